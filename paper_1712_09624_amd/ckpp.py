@@ -1,0 +1,307 @@
+"""Python binding of ``libckpp.so`` (the C ABI declared in ``include/ckpp.h``).
+
+Argument marshalling only: every step of every operation runs in the HIP
+library.  Device buffers are torch tensors (PyTorch provides device memory
+and streams); there is no CPU fallback -- without the built library every
+call raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libckpp.so")
+
+OK, EINVAL, ENOMEM, EDEVICE = 0, 1, 2, 3
+INSERTED, UPDATED, FAILED = 0, 1, 2
+PLAIN = 1
+LOOKUP_DEFAULT, LOOKUP_BOTH, LOOKUP_OPTIMISTIC = 0, 1, 2
+MODES = {"cuckoopp": LOOKUP_DEFAULT, "default": LOOKUP_DEFAULT, "both": LOOKUP_BOTH,
+         "plain": LOOKUP_BOTH, "pessimistic": LOOKUP_BOTH, "optimistic": LOOKUP_OPTIMISTIC}
+MOVED_BINS = 66
+DEFAULT_HASH_SEED = 0x243F6A8885A308D3
+
+
+class CkppError(RuntimeError):
+    pass
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [
+        ("nbuckets", ctypes.c_uint64),
+        ("live", ctypes.c_uint64),
+        ("in_secondary", ctypes.c_uint64),
+        ("bloom_pc_sum", ctypes.c_uint64),
+        ("bloom_pc2_sum", ctypes.c_uint64),
+        ("locked", ctypes.c_uint64),
+        ("retry_exhausted", ctypes.c_uint64),
+        ("moved_hist", ctypes.c_uint64 * MOVED_BINS),
+    ]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [
+        ("log2_buckets", ctypes.c_uint32),
+        ("max_kicks", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("device", ctypes.c_int),
+        ("hash_seed", ctypes.c_uint64),
+        ("bucket_bytes", ctypes.c_uint64),
+        ("kv_bytes", ctypes.c_uint64),
+        ("d_buckets", ctypes.c_void_p),
+        ("d_kv", ctypes.c_void_p),
+    ]
+
+
+class _Launch(ctypes.Structure):
+    _fields_ = [
+        ("lanes_per_lookup", ctypes.c_uint32),
+        ("lookups_per_lane", ctypes.c_uint32),
+        ("block", ctypes.c_uint32),
+        ("blocks_per_cu", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_VP, _U32, _U64, _I = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+SIGNATURES = [
+    ("ckpp_create", _I, [ctypes.POINTER(_VP), _U32, _U64, _U32, _U32, _I]),
+    ("ckpp_destroy", _I, [_VP]),
+    ("ckpp_clear", _I, [_VP, _VP]),
+    ("ckpp_insert_batch", _I, [_VP, _VP, _VP, _U64, _VP, _VP, _VP]),
+    ("ckpp_lookup_batch", _I, [_VP, _VP, _U64, _U32, _VP, _VP, _VP]),
+    ("ckpp_delete_batch", _I, [_VP, _VP, _U64, _VP, _VP]),
+    ("ckpp_export", _I, [_VP, _VP, _VP, _VP]),
+    ("ckpp_import", _I, [_VP, _VP, _VP, _VP]),
+    ("ckpp_stats", _I, [_VP, ctypes.POINTER(_Stats), _VP]),
+    ("ckpp_hash_batch", _I, [_VP, _VP, _U64, _VP, _VP]),
+    ("ckpp_info", _I, [_VP, ctypes.POINTER(_Info)]),
+    ("ckpp_set_lookup_launch", _I, [_VP, ctypes.POINTER(_Launch)]),
+    ("ckpp_get_lookup_launch", _I, [_VP, ctypes.POINTER(_Launch)]),
+    ("ckpp_probe_random_reads", _I, [_VP, _U64, _U32, _U64, _U32, _U32, _U32, _U64, _VP, _VP]),
+    ("ckpp_strerror", ctypes.c_char_p, [_I]),
+]
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Loads the HIP library; raises when it has not been built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise CkppError(f"{p} is not built: run `python -m paper_1712_09624_amd.build` "
+                        "(there is no CPU fallback)")
+    lib = ctypes.CDLL(p)
+    for name, res, args in SIGNATURES:
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        msg = load().ckpp_strerror(rc).decode()
+        raise CkppError(f"{what}: {msg} (status {rc})")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _keys_ptr(keys) -> tuple[int, int]:
+    """(device pointer, n) of a contiguous (n, 16) byte tensor (any 16-byte
+    row dtype view is accepted)."""
+    torch = _torch()
+    if not keys.is_cuda:
+        raise CkppError("keys must be a device tensor")
+    if not keys.is_contiguous():
+        raise CkppError("keys must be contiguous")
+    nbytes = keys.numel() * keys.element_size()
+    if nbytes % 16:
+        raise CkppError("keys must be a whole number of 16-byte rows")
+    if keys.data_ptr() % 16:
+        raise CkppError("keys must be 16-byte aligned")
+    del torch
+    return keys.data_ptr(), nbytes // 16
+
+
+class Table:
+    """A Cuckoo++ hash table in device memory (see include/ckpp.h)."""
+
+    def __init__(self, log2_buckets: int, hash_seed: int = DEFAULT_HASH_SEED,
+                 max_kicks: int = 500, plain: bool = False, device: int | None = None):
+        torch = _torch()
+        self.lib = load()
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = int(device)
+        self.log2_buckets = int(log2_buckets)
+        self.nbuckets = 1 << self.log2_buckets
+        self.hash_seed = int(hash_seed)
+        self.plain = bool(plain)
+        h = ctypes.c_void_p()
+        rc = self.lib.ckpp_create(ctypes.byref(h), self.log2_buckets,
+                                  ctypes.c_uint64(self.hash_seed), int(max_kicks),
+                                  PLAIN if plain else 0, self.device)
+        _check(rc, "ckpp_create")
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.ckpp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> int:
+        return self._h.value
+
+    def _dev(self):
+        return _torch().device("cuda", self.device)
+
+    # -- batches
+    def insert(self, keys, values, status=None, nfailed=None, stream=None):
+        """Enqueues an insert batch; returns (status u8[n], nfailed i64[1])."""
+        torch = _torch()
+        kp, n = _keys_ptr(keys)
+        if values.numel() != n or values.element_size() != 8 or not values.is_contiguous():
+            raise CkppError("values must be n contiguous 64-bit integers")
+        if status is None:
+            status = torch.empty(n, dtype=torch.uint8, device=self._dev())
+        if nfailed is None:
+            nfailed = torch.zeros(1, dtype=torch.int64, device=self._dev())
+        rc = self.lib.ckpp_insert_batch(self._h, kp, values.data_ptr(), n, status.data_ptr(),
+                                        nfailed.data_ptr(), _stream_handle(stream))
+        _check(rc, "ckpp_insert_batch")
+        return status, nfailed
+
+    def lookup(self, keys, mode="cuckoopp", found=None, values=None, stream=None):
+        """Enqueues a lookup batch; returns (found u8[n], values i64[n])."""
+        torch = _torch()
+        kp, n = _keys_ptr(keys)
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        if found is None:
+            found = torch.empty(n, dtype=torch.uint8, device=self._dev())
+        if values is None:
+            values = torch.empty(n, dtype=torch.int64, device=self._dev())
+        rc = self.lib.ckpp_lookup_batch(self._h, kp, n, m, found.data_ptr(), values.data_ptr(),
+                                        _stream_handle(stream))
+        _check(rc, "ckpp_lookup_batch")
+        return found, values
+
+    def delete(self, keys, found=None, stream=None):
+        """Enqueues a delete batch; returns found u8[n]."""
+        torch = _torch()
+        kp, n = _keys_ptr(keys)
+        if found is None:
+            found = torch.empty(n, dtype=torch.uint8, device=self._dev())
+        rc = self.lib.ckpp_delete_batch(self._h, kp, n, found.data_ptr(), _stream_handle(stream))
+        _check(rc, "ckpp_delete_batch")
+        return found
+
+    def hash(self, keys, stream=None):
+        torch = _torch()
+        kp, n = _keys_ptr(keys)
+        out = torch.empty(n, dtype=torch.int64, device=self._dev())
+        rc = self.lib.ckpp_hash_batch(self._h, kp, n, out.data_ptr(), _stream_handle(stream))
+        _check(rc, "ckpp_hash_batch")
+        return out
+
+    def clear(self, stream=None):
+        _check(self.lib.ckpp_clear(self._h, _stream_handle(stream)), "ckpp_clear")
+
+    # -- inspection
+    def export(self, stream=None):
+        """Host copies (numpy uint8) of the bucket and key/value arrays."""
+        b = np.empty(64 * self.nbuckets, dtype=np.uint8)
+        k = np.empty(256 * self.nbuckets, dtype=np.uint8)
+        rc = self.lib.ckpp_export(self._h, b.ctypes.data, k.ctypes.data, _stream_handle(stream))
+        _check(rc, "ckpp_export")
+        return b, k
+
+    def import_image(self, buckets: np.ndarray, kv: np.ndarray, stream=None):
+        b = np.ascontiguousarray(buckets, dtype=np.uint8).reshape(-1)
+        k = np.ascontiguousarray(kv, dtype=np.uint8).reshape(-1)
+        if b.size != 64 * self.nbuckets or k.size != 256 * self.nbuckets:
+            raise CkppError("image size does not match the table")
+        rc = self.lib.ckpp_import(self._h, b.ctypes.data, k.ctypes.data, _stream_handle(stream))
+        _check(rc, "ckpp_import")
+
+    def stats(self, stream=None) -> dict:
+        st = _Stats()
+        _check(self.lib.ckpp_stats(self._h, ctypes.byref(st), _stream_handle(stream)),
+               "ckpp_stats")
+        nb = int(st.nbuckets)
+        live = int(st.live)
+        hist = [int(x) for x in st.moved_hist]
+        return {
+            "nbuckets": nb,
+            "live": live,
+            "in_secondary": int(st.in_secondary),
+            "f_sec": int(st.in_secondary) / live if live else 0.0,
+            "bloom_pc_sum": int(st.bloom_pc_sum),
+            "bloom_pc2_sum": int(st.bloom_pc2_sum),
+            "expected_fpr": int(st.bloom_pc2_sum) / (4096.0 * nb),
+            "locked": int(st.locked),
+            "retry_exhausted": int(st.retry_exhausted),
+            "moved_hist": hist,
+            "moved_zero_fraction": hist[0] / nb,
+        }
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(self.lib.ckpp_info(self._h, ctypes.byref(inf)), "ckpp_info")
+        return {f: getattr(inf, f) for f, _ in _Info._fields_}
+
+    def set_lookup_launch(self, lanes_per_lookup=1, lookups_per_lane=2, block=256,
+                          blocks_per_cu=0):
+        cfg = _Launch(lanes_per_lookup, lookups_per_lane, block, blocks_per_cu)
+        _check(self.lib.ckpp_set_lookup_launch(self._h, ctypes.byref(cfg)),
+               "ckpp_set_lookup_launch")
+
+    def get_lookup_launch(self) -> dict:
+        cfg = _Launch()
+        _check(self.lib.ckpp_get_lookup_launch(self._h, ctypes.byref(cfg)),
+               "ckpp_get_lookup_launch")
+        return {f: getattr(cfg, f) for f, _ in _Launch._fields_}
+
+
+def probe_random_reads(buf, granule: int, nreads: int, per_lane: int, block: int, grid: int,
+                       seed: int, sink, stream=None):
+    """Launches the random-read probe over the device tensor ``buf``."""
+    lib = load()
+    nbytes = buf.numel() * buf.element_size()
+    rc = lib.ckpp_probe_random_reads(buf.data_ptr(), nbytes, granule, nreads, per_lane, block,
+                                     grid, ctypes.c_uint64(seed), sink.data_ptr(),
+                                     _stream_handle(stream))
+    _check(rc, "ckpp_probe_random_reads")

@@ -1,0 +1,283 @@
+// ckpp_api.hip -- the C ABI: argument checks, device memory, dispatch.
+
+#include <new>
+#include <stdint.h>
+#include <string.h>
+
+#include "ckpp_internal.h"
+
+namespace {
+
+constexpr uint32_t kMaxLog2Buckets = 24;
+constexpr uint32_t kMaxKicksLimit = 4096;
+constexpr uint32_t kMaxPathLanes = 65536;
+constexpr uint32_t kAccWords = 128;   // device accumulator words
+constexpr uint32_t kAccStats = 6 + CKPP_MOVED_BINS;
+constexpr uint32_t kAccRetry = 127;   // retry-bound counter (never cleared)
+
+// Makes the table's device current for the duration of a call.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) : prev_(-1), ok_(true) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    else prev_ = -1;
+  }
+  ~DeviceGuard() {
+    if (prev_ >= 0) (void)hipSetDevice(prev_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_;
+  bool ok_;
+};
+
+bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int dev_status(hipError_t e) { return e == hipSuccess ? CKPP_OK : CKPP_EDEVICE; }
+
+uint64_t bucket_bytes(const ckpp_table *t) { return 64ull << t->log2_buckets; }
+uint64_t kv_bytes(const ckpp_table *t) { return 256ull << t->log2_buckets; }
+
+}  // namespace
+
+extern "C" {
+
+const char *ckpp_strerror(int code) {
+  switch (code) {
+    case CKPP_OK: return "ok";
+    case CKPP_EINVAL: return "invalid argument";
+    case CKPP_ENOMEM: return "out of device memory";
+    case CKPP_EDEVICE: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uint32_t max_kicks,
+                uint32_t flags, int device) {
+  if (!out) return CKPP_EINVAL;
+  *out = nullptr;
+  if (log2_buckets < 1 || log2_buckets > kMaxLog2Buckets) return CKPP_EINVAL;
+  if (max_kicks > kMaxKicksLimit) return CKPP_EINVAL;
+  if (flags & ~CKPP_PLAIN) return CKPP_EINVAL;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess) return CKPP_EDEVICE;
+  if (device < 0 || device >= ndev) return CKPP_EINVAL;
+  DeviceGuard g(device);
+  if (!g.ok()) return CKPP_EDEVICE;
+
+  ckpp_table *t = new (std::nothrow) ckpp_table();
+  if (!t) return CKPP_ENOMEM;
+  memset(t, 0, sizeof(*t));
+  t->log2_buckets = log2_buckets;
+  t->max_kicks = max_kicks;
+  t->flags = flags;
+  t->device = device;
+  t->seed = hash_seed;
+  t->lookup_launch.lanes_per_lookup = 1;
+  t->lookup_launch.lookups_per_lane = 2;
+  t->lookup_launch.block = 256;
+  t->lookup_launch.blocks_per_cu = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete t;
+    return CKPP_EDEVICE;
+  }
+  t->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 1;
+  // lanes of the persistent insert/delete grid: enough to keep every CU busy
+  // on large tables, fewer on small ones (they would only contend)
+  uint64_t lanes = 8ull << log2_buckets;
+  if (lanes < 256) lanes = 256;
+  if (lanes > kMaxPathLanes) lanes = kMaxPathLanes;
+  t->path_lanes = (uint32_t)lanes;
+  const uint64_t path_words = lanes * (uint64_t)(max_kicks ? max_kicks : 1u);
+
+  int rc = CKPP_OK;
+  if (hipMalloc(&t->d_buckets, bucket_bytes(t)) != hipSuccess ||
+      hipMalloc(&t->d_kv, kv_bytes(t)) != hipSuccess ||
+      hipMalloc(&t->d_paths, path_words * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&t->d_stats, kAccWords * sizeof(uint64_t)) != hipSuccess) {
+    rc = CKPP_ENOMEM;
+  } else if (hipMemset(t->d_buckets, 0, bucket_bytes(t)) != hipSuccess ||
+             hipMemset(t->d_kv, 0, kv_bytes(t)) != hipSuccess ||
+             hipMemset(t->d_stats, 0, kAccWords * sizeof(uint64_t)) != hipSuccess ||
+             hipDeviceSynchronize() != hipSuccess) {
+    rc = CKPP_EDEVICE;
+  }
+  if (rc != CKPP_OK) {
+    (void)hipGetLastError();
+    if (t->d_buckets) (void)hipFree(t->d_buckets);
+    if (t->d_kv) (void)hipFree(t->d_kv);
+    if (t->d_paths) (void)hipFree(t->d_paths);
+    if (t->d_stats) (void)hipFree(t->d_stats);
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return CKPP_OK;
+}
+
+int ckpp_destroy(ckpp_table *t) {
+  if (!t) return CKPP_OK;
+  DeviceGuard g(t->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(t->d_buckets);
+  (void)hipFree(t->d_kv);
+  (void)hipFree(t->d_paths);
+  (void)hipFree(t->d_stats);
+  delete t;
+  return CKPP_OK;
+}
+
+int ckpp_clear(ckpp_table *t, void *stream) {
+  if (!t) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = ckpp::launch_fill_zero(t->d_buckets, bucket_bytes(t), s);
+  if (e == hipSuccess) e = ckpp::launch_fill_zero(t->d_kv, kv_bytes(t), s);
+  return dev_status(e);
+}
+
+int ckpp_insert_batch(ckpp_table *t, const void *d_keys, const uint64_t *d_values, uint64_t n,
+                      uint8_t *d_status, uint64_t *d_nfailed, void *stream) {
+  if (!t) return CKPP_EINVAL;
+  if (n == 0) return CKPP_OK;
+  if (!d_keys || !d_values || !aligned(d_keys, 16) || !aligned(d_values, 8)) return CKPP_EINVAL;
+  if (d_nfailed && !aligned(d_nfailed, 8)) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  return dev_status(ckpp::launch_insert(t, d_keys, d_values, n, d_status, d_nfailed,
+                                        reinterpret_cast<hipStream_t>(stream)));
+}
+
+int ckpp_lookup_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
+                      uint8_t *d_found, uint64_t *d_values, void *stream) {
+  if (!t) return CKPP_EINVAL;
+  if (mode > CKPP_LOOKUP_OPTIMISTIC) return CKPP_EINVAL;
+  if (n == 0) return CKPP_OK;
+  if (!d_keys || !d_found || !d_values) return CKPP_EINVAL;
+  if (!aligned(d_keys, 16) || !aligned(d_values, 8)) return CKPP_EINVAL;
+  // a plain table keeps no filter: its default lookup reads both buckets
+  if (mode == CKPP_LOOKUP_DEFAULT && (t->flags & CKPP_PLAIN)) mode = CKPP_LOOKUP_BOTH;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  return dev_status(ckpp::launch_lookup(t, d_keys, n, mode, d_found, d_values,
+                                        reinterpret_cast<hipStream_t>(stream)));
+}
+
+int ckpp_delete_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_found,
+                      void *stream) {
+  if (!t) return CKPP_EINVAL;
+  if (n == 0) return CKPP_OK;
+  if (!d_keys || !aligned(d_keys, 16)) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  return dev_status(
+      ckpp::launch_delete(t, d_keys, n, d_found, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int ckpp_export(const ckpp_table *t, void *h_buckets, void *h_kv, void *stream) {
+  if (!t) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (h_buckets) e = hipMemcpyAsync(h_buckets, t->d_buckets, bucket_bytes(t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && h_kv) e = hipMemcpyAsync(h_kv, t->d_kv, kv_bytes(t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return dev_status(e);
+}
+
+int ckpp_import(ckpp_table *t, const void *h_buckets, const void *h_kv, void *stream) {
+  if (!t || !h_buckets || !h_kv) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(t->d_buckets, h_buckets, bucket_bytes(t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(t->d_kv, h_kv, kv_bytes(t), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return dev_status(e);
+}
+
+int ckpp_stats(const ckpp_table *t, ckpp_stats_t *h_out, void *stream) {
+  if (!t || !h_out) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  uint64_t acc[kAccWords];
+  hipError_t e = ckpp::launch_fill_zero(t->d_stats, 16 * ((kAccStats * 8 + 15) / 16), s);
+  if (e == hipSuccess) e = ckpp::launch_stats(t, t->d_stats, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(acc, t->d_stats, sizeof(acc), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return CKPP_EDEVICE;
+  memset(h_out, 0, sizeof(*h_out));
+  h_out->nbuckets = 1ull << t->log2_buckets;
+  h_out->live = acc[0];
+  h_out->in_secondary = acc[1];
+  h_out->bloom_pc_sum = acc[2];
+  h_out->bloom_pc2_sum = acc[3];
+  h_out->locked = acc[4];
+  h_out->retry_exhausted = acc[kAccRetry];
+  for (int i = 0; i < CKPP_MOVED_BINS; ++i) h_out->moved_hist[i] = acc[6 + i];
+  return CKPP_OK;
+}
+
+int ckpp_hash_batch(const ckpp_table *t, const void *d_keys, uint64_t n, uint64_t *d_hash,
+                    void *stream) {
+  if (!t) return CKPP_EINVAL;
+  if (n == 0) return CKPP_OK;
+  if (!d_keys || !d_hash || !aligned(d_keys, 16) || !aligned(d_hash, 8)) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  return dev_status(ckpp::launch_hash(t, d_keys, n, d_hash, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int ckpp_info(const ckpp_table *t, ckpp_info_t *out) {
+  if (!t || !out) return CKPP_EINVAL;
+  out->log2_buckets = t->log2_buckets;
+  out->max_kicks = t->max_kicks;
+  out->flags = t->flags;
+  out->device = t->device;
+  out->hash_seed = t->seed;
+  out->bucket_bytes = bucket_bytes(t);
+  out->kv_bytes = kv_bytes(t);
+  out->d_buckets = t->d_buckets;
+  out->d_kv = t->d_kv;
+  return CKPP_OK;
+}
+
+int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg) {
+  if (!t || !cfg) return CKPP_EINVAL;
+  if (cfg->lanes_per_lookup != 1 && cfg->lanes_per_lookup != 2) return CKPP_EINVAL;
+  if (cfg->lookups_per_lane != 1 && cfg->lookups_per_lane != 2 && cfg->lookups_per_lane != 4)
+    return CKPP_EINVAL;
+  if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return CKPP_EINVAL;
+  if (cfg->blocks_per_cu > 4096) return CKPP_EINVAL;
+  t->lookup_launch = *cfg;
+  return CKPP_OK;
+}
+
+int ckpp_get_lookup_launch(const ckpp_table *t, ckpp_launch_t *cfg) {
+  if (!t || !cfg) return CKPP_EINVAL;
+  *cfg = t->lookup_launch;
+  return CKPP_OK;
+}
+
+int ckpp_probe_random_reads(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t nreads,
+                            uint32_t per_lane, uint32_t block, uint32_t grid, uint64_t seed,
+                            uint64_t *d_sink, void *stream) {
+  if (!d_buf || !d_sink) return CKPP_EINVAL;
+  if (granule != 32 && granule != 64 && granule != 128) return CKPP_EINVAL;
+  if (!aligned(d_buf, granule) || bytes < granule || bytes % granule) return CKPP_EINVAL;
+  if (per_lane != 1 && per_lane != 2 && per_lane != 4 && per_lane != 8) return CKPP_EINVAL;
+  if (block != 64 && block != 128 && block != 256) return CKPP_EINVAL;
+  if (grid == 0 || !aligned(d_sink, 8)) return CKPP_EINVAL;
+  if (nreads == 0) return CKPP_OK;
+  return dev_status(ckpp::launch_probe(d_buf, bytes, granule, nreads, per_lane, block, grid, seed,
+                                       d_sink, reinterpret_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,149 @@
+// ckpp_aux.hip -- statistics, hashing, zero-fill and the random-read probe.
+
+#include "ckpp_device.h"
+#include "ckpp_internal.h"
+
+namespace ckpp {
+namespace {
+
+// Accumulator layout (u64 words) shared with the host side:
+//   0 live, 1 in_secondary, 2 bloom_pc_sum, 3 bloom_pc2_sum, 4 locked,
+//   5 unused, 6 .. 6+CKPP_MOVED_BINS-1 moved histogram.
+constexpr uint32_t kHistBase = 6;
+
+__global__ void __launch_bounds__(256)
+    stats_kernel(const uint4 *__restrict__ bk, uint64_t nbuckets, unsigned long long *acc) {
+  __shared__ unsigned int hist[CKPP_MOVED_BINS];
+  __shared__ unsigned long long part[5];
+  for (uint32_t i = threadIdx.x; i < CKPP_MOVED_BINS; i += blockDim.x) hist[i] = 0u;
+  if (threadIdx.x < 5) part[threadIdx.x] = 0ull;
+  __syncthreads();
+  unsigned long long live = 0, insec = 0, pc = 0, pc2 = 0, locked = 0;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nbuckets;
+       b += (uint64_t)gridDim.x * blockDim.x) {
+    const uint4 q1 = bk[b * kQuartersPerBucket + 1];
+    const uint32_t meta = q1.z;
+    live += (unsigned long long)__builtin_popcount(meta_busy(meta));
+    insec += (unsigned long long)__builtin_popcount(meta_sec(meta));
+    const unsigned long long c =
+        (unsigned long long)(__builtin_popcount(q1.x) + __builtin_popcount(q1.y));
+    pc += c;
+    pc2 += c * c;
+    locked += q1.w != 0u ? 1ull : 0ull;
+    const uint32_t m = meta_moved(meta);
+    atomicAdd(&hist[m < CKPP_MOVED_BINS - 1 ? m : CKPP_MOVED_BINS - 1], 1u);
+  }
+  atomicAdd(&part[0], live);
+  atomicAdd(&part[1], insec);
+  atomicAdd(&part[2], pc);
+  atomicAdd(&part[3], pc2);
+  atomicAdd(&part[4], locked);
+  __syncthreads();
+  if (threadIdx.x < 5) atomicAdd(&acc[threadIdx.x], part[threadIdx.x]);
+  for (uint32_t i = threadIdx.x; i < CKPP_MOVED_BINS; i += blockDim.x)
+    if (hist[i]) atomicAdd(&acc[kHistBase + i], (unsigned long long)hist[i]);
+}
+
+__global__ void __launch_bounds__(256)
+    hash_kernel(const uint4 *__restrict__ keys, uint64_t n, uint64_t seed,
+                uint64_t *__restrict__ out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = key_hash(keys[i], seed);
+}
+
+__global__ void __launch_bounds__(256) fill_zero_kernel(uint4 *d, uint64_t n16) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    d[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Random-read probe: read i of the launch reads the granule at index
+// mix64(seed + i) * units >> 64 (uniform over the buffer); each lane keeps
+// PL reads of Q 16-byte quarters in flight and folds them into its sink.
+template <int Q, int PL>
+__global__ void __launch_bounds__(256)
+    probe_kernel(const uint4 *__restrict__ buf, uint64_t units, uint64_t nreads, uint64_t seed,
+                 unsigned long long *__restrict__ sink) {
+  const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t nl = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t acc = 0u;
+  for (uint64_t r0 = lane * PL; r0 < nreads; r0 += nl * PL) {
+    uint4 v[PL][Q];
+#pragma unroll
+    for (int j = 0; j < PL; ++j) {
+      const uint64_t i = r0 + j;
+      if (i < nreads) {
+        const uint64_t u = __umul64hi(mix64(seed + i), units);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[j][q] = buf[u * Q + q];
+      } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) v[j][q] = make_uint4(0u, 0u, 0u, 0u);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PL; ++j)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) acc ^= v[j][q].x ^ v[j][q].y ^ v[j][q].z ^ v[j][q].w;
+  }
+  sink[lane] = acc;
+}
+
+template <int Q>
+hipError_t probe_q(const void *d_buf, uint64_t units, uint64_t nreads, uint32_t per_lane,
+                   uint32_t block, uint32_t grid, uint64_t seed, uint64_t *d_sink,
+                   hipStream_t s) {
+  const uint4 *b = reinterpret_cast<const uint4 *>(d_buf);
+  unsigned long long *k = reinterpret_cast<unsigned long long *>(d_sink);
+  switch (per_lane) {
+    case 1: hipLaunchKernelGGL((probe_kernel<Q, 1>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
+    case 2: hipLaunchKernelGGL((probe_kernel<Q, 2>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
+    case 4: hipLaunchKernelGGL((probe_kernel<Q, 4>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
+    default: hipLaunchKernelGGL((probe_kernel<Q, 8>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stats(const ckpp_table *t, uint64_t *d_acc, hipStream_t s) {
+  const uint64_t nb = 1ull << t->log2_buckets;
+  uint64_t grid = (nb + 255) / 256;
+  const uint64_t cap = (uint64_t)t->num_cus * 8;
+  if (grid > cap) grid = cap;
+  hipLaunchKernelGGL(stats_kernel, dim3((uint32_t)grid), dim3(256), 0, s,
+                     reinterpret_cast<const uint4 *>(t->d_buckets), nb,
+                     reinterpret_cast<unsigned long long *>(d_acc));
+  return hipGetLastError();
+}
+
+hipError_t launch_hash(const ckpp_table *t, const void *d_keys, uint64_t n, uint64_t *d_hash,
+                       hipStream_t s) {
+  uint64_t grid = (n + 255) / 256;
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(hash_kernel, dim3((uint32_t)grid), dim3(256), 0, s,
+                     reinterpret_cast<const uint4 *>(d_keys), n, t->seed, d_hash);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void *d, uint64_t bytes, hipStream_t s) {
+  const uint64_t n16 = bytes / 16;
+  uint64_t grid = (n16 + 255) / 256;
+  if (grid > 65536) grid = 65536;
+  if (grid == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((uint32_t)grid), dim3(256), 0, s,
+                     reinterpret_cast<uint4 *>(d), n16);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t nreads,
+                        uint32_t per_lane, uint32_t block, uint32_t grid, uint64_t seed,
+                        uint64_t *d_sink, hipStream_t s) {
+  const uint64_t units = bytes / granule;
+  if (granule == 32) return probe_q<2>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
+  if (granule == 64) return probe_q<4>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
+  return probe_q<8>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
+}
+
+}  // namespace ckpp

@@ -1,0 +1,108 @@
+// ckpp_device.h -- device-side view of a Cuckoo++ table (gfx950).
+//
+// Bucket: one 64-byte line (Sec. 4.3), read by the kernels as four 16-byte
+// quarters:
+//   q0  tags of slots 0..7, u16 each (slot 2i in the low half of word i)
+//   q1  .x,.y bloom filter (u64, Sec. 4.1)
+//       .z    moved counter (bits 0..15) | busy mask (16..23) | sec mask (24..31)
+//       .w    lock word (zero outside a running insert or delete batch)
+//   q2  other bucket of slots 0..3 (u32 each)
+//   q3  other bucket of slots 4..7
+// A lookup needs q0 and q1 only (the first 32 bytes); q2, q3 serve the
+// cuckoo-path search of inserts, which then reads no keys (Sec. 4.3).
+// Key/value record of slot s of bucket b: 32 bytes at index 8*b+s of the
+// record array (implicit index, Sec. 4.3): key (16) | value (8) | zero (8).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ckpp {
+
+constexpr uint32_t kSlots = 8;
+constexpr uint32_t kQuartersPerBucket = 4;  // 64-byte bucket = 4 x uint4
+constexpr uint32_t kQuartersPerRecord = 2;  // 32-byte record = 2 x uint4
+constexpr uint32_t kMetaOffset = 24;        // byte offset of the meta word
+constexpr uint32_t kLockOffset = 28;        // byte offset of the lock word
+constexpr uint32_t kOtherOffset = 32;       // byte offset of other[0]
+
+// SplitMix64 output finalizer (Steele, Lea, Flood, OOPSLA 2014).
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+// Hash of a key held as four little-endian u32 words:
+// h = mix(mix(lo ^ seed) ^ hi), lo = w0 | w1 << 32, hi = w2 | w3 << 32.
+__device__ __forceinline__ uint64_t key_hash(uint4 k, uint64_t seed) {
+  const uint64_t lo = (uint64_t)k.x | ((uint64_t)k.y << 32);
+  const uint64_t hi = (uint64_t)k.z | ((uint64_t)k.w << 32);
+  return mix64(mix64(lo ^ seed) ^ hi);
+}
+
+// Fields of a key derived from its hash for 2^log2b buckets (log2b <= 24):
+// primary p, alternate a (never equal to p), 16-bit tag, and the two bloom
+// bits taken from the alternate-bucket field (Sec. 4.1).
+struct KeyFields {
+  uint32_t p;
+  uint32_t a;
+  uint32_t tag;
+  uint64_t bloom_bits;
+};
+
+__device__ __forceinline__ KeyFields key_fields(uint64_t h, uint32_t log2b) {
+  const uint32_t mask = (1u << log2b) - 1u;
+  KeyFields f;
+  f.p = (uint32_t)h & mask;
+  uint32_t a = (uint32_t)(h >> 24) & mask;
+  f.a = (a == f.p) ? (a ^ 1u) : a;
+  f.tag = (uint32_t)(h >> 48);
+  const uint32_t sh = (uint32_t)(h >> 24);
+  f.bloom_bits = (1ull << (sh & 63u)) | (1ull << ((sh >> 6) & 63u));
+  return f;
+}
+
+// Exact per-slot equality of the eight 16-bit tags with t: bit s of the
+// result is set iff tag[s] == t.
+__device__ __forceinline__ uint32_t tag_eq_mask(uint4 q0, uint32_t t) {
+  uint32_t r = 0;
+  r |= ((q0.x & 0xffffu) == t) ? 0x01u : 0u;
+  r |= ((q0.x >> 16) == t) ? 0x02u : 0u;
+  r |= ((q0.y & 0xffffu) == t) ? 0x04u : 0u;
+  r |= ((q0.y >> 16) == t) ? 0x08u : 0u;
+  r |= ((q0.z & 0xffffu) == t) ? 0x10u : 0u;
+  r |= ((q0.z >> 16) == t) ? 0x20u : 0u;
+  r |= ((q0.w & 0xffffu) == t) ? 0x40u : 0u;
+  r |= ((q0.w >> 16) == t) ? 0x80u : 0u;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t meta_busy(uint32_t meta) { return (meta >> 16) & 0xffu; }
+__device__ __forceinline__ uint32_t meta_sec(uint32_t meta) { return meta >> 24; }
+__device__ __forceinline__ uint32_t meta_moved(uint32_t meta) { return meta & 0xffffu; }
+__device__ __forceinline__ uint32_t make_meta(uint32_t moved, uint32_t busy, uint32_t sec) {
+  return (moved & 0xffffu) | ((busy & 0xffu) << 16) | ((sec & 0xffu) << 24);
+}
+
+// The filter passes iff both of the key's bits are set (Sec. 6: an equal
+// and a bitwise and).
+__device__ __forceinline__ bool bloom_pass(uint4 q1, uint64_t bits) {
+  const uint64_t bloom = (uint64_t)q1.x | ((uint64_t)q1.y << 32);
+  return (bloom & bits) == bits;
+}
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Streaming (non-temporal) 16-byte load: data read once, kept out of the
+// caches that hold table lines.
+__device__ __forceinline__ uint4 load_stream(const uint4 *p) {
+  const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ bool key_eq(uint4 a, uint4 b) {
+  return ((a.x ^ b.x) | (a.y ^ b.y) | (a.z ^ b.z) | (a.w ^ b.w)) == 0u;
+}
+
+}  // namespace ckpp
