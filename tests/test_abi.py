@@ -1,0 +1,97 @@
+"""The C ABI library loads on a machine without a GPU and exports every
+entry point include/ckpp.h declares; the binding covers each of them and its
+structures match the header's (checked by compiling the header with gcc).
+No compute call is made here."""
+
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1712_09624_amd import ckpp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ckpp.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ckpp_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ckpp.LIB_PATH):
+        from paper_1712_09624_amd import build
+        build.build()
+    return ckpp.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ckpp_create", "ckpp_insert_batch", "ckpp_lookup_batch",
+                     "ckpp_delete_batch", "ckpp_destroy"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), f"{name} declared in ckpp.h but not exported"
+
+
+def test_binding_covers_every_declared_symbol():
+    bound = {s[0] for s in ckpp.SIGNATURES}
+    assert set(declared_functions()) == bound
+
+
+def test_strerror_needs_no_device(lib):
+    assert lib.ckpp_strerror(0) == b"ok"
+    assert lib.ckpp_strerror(1) == b"invalid argument"
+
+
+def test_argument_checks_need_no_device(lib):
+    # invalid arguments are rejected before any device work
+    h = ctypes.c_void_p()
+    assert lib.ckpp_create(None, 10, 1, 500, 0, 0) == ckpp.EINVAL
+    assert lib.ckpp_create(ctypes.byref(h), 0, 1, 500, 0, 0) == ckpp.EINVAL
+    assert lib.ckpp_create(ctypes.byref(h), 25, 1, 500, 0, 0) == ckpp.EINVAL
+    assert lib.ckpp_create(ctypes.byref(h), 10, 1, 500, 4, 0) == ckpp.EINVAL
+    assert lib.ckpp_insert_batch(None, None, None, 5, None, None, None) == ckpp.EINVAL
+    assert lib.ckpp_lookup_batch(None, None, 5, 0, None, None, None) == ckpp.EINVAL
+    assert lib.ckpp_delete_batch(None, None, 5, None, None) == ckpp.EINVAL
+    assert lib.ckpp_destroy(None) == ckpp.OK
+    assert lib.ckpp_probe_random_reads(None, 64, 64, 1, 1, 256, 1, 0, None, None) == ckpp.EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    with pytest.raises(ckpp.CkppError):
+        ckpp.load(str(tmp_path / "absent.so"))
+
+
+def test_struct_layouts_match_header():
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "ckpp.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\n", sizeof(ckpp_stats_t), offsetof(ckpp_stats_t, moved_hist),
+         sizeof(ckpp_info_t), sizeof(ckpp_launch_t));
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "t.c")
+        exe = os.path.join(d, "t")
+        open(c, "w").write(prog)
+        subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), "-o", exe, c],
+                       check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
+    sz_stats, off_hist, sz_info, sz_launch = map(int, out)
+    assert sz_stats == ctypes.sizeof(ckpp._Stats)
+    assert off_hist == ckpp._Stats.moved_hist.offset
+    assert sz_info == ctypes.sizeof(ckpp._Info)
+    assert sz_launch == ctypes.sizeof(ckpp._Launch)
