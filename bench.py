@@ -1,0 +1,427 @@
+"""Benchmark of the Cuckoo++ hot path on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic input, on a
+2^24-bucket x 8-slot table (134M slots, ~5 GiB of buckets and records,
+HBM-resident) filled to load 0.9:
+    insert_batch  65536 fresh keys (churn)
+    lookup_batch  2^26 positive lookups   (Cuckoo++)
+    lookup_batch  2^26 negative lookups   (Cuckoo++)
+    delete_batch  the 65536 churn keys    (load back to 0.9)
+value = lookups per second over the timed steps (Glookups/s), inputs resident
+in device memory.  Around it (untimed): the plain-cuckoo and optimistic
+lookups on the same table, a 2^20-bucket table (cache-resident bucket array),
+the random-read line rate of the device (the lookups' roofline), single
+burst latencies, and the oracle timed on the host.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1712_09624_amd import workload as W  # noqa: E402
+
+METRIC = "Glookups/s @load 0.9 (pos & neg), % random-64B HBM peak; p99 burst latency"
+HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
+LINE = 64
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2-buckets", type=int, default=24)
+    ap.add_argument("--load", type=float, default=0.9)
+    ap.add_argument("--lookups", type=int, default=1 << 26)
+    ap.add_argument("--churn", type=int, default=65536)
+    ap.add_argument("--core-only", action="store_true",
+                    help="only the timed steps (for profiler runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--tune", action="store_true",
+                    help="time every lookup launch shape, print them, keep the fastest")
+    ap.add_argument("--lanes", type=int, default=None)
+    ap.add_argument("--per-lane", type=int, default=None)
+    ap.add_argument("--block", type=int, default=None)
+    ap.add_argument("--blocks-per-cu", type=int, default=None)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def to_dev(a, dev):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def lookup_source_digest() -> str:
+    h = hashlib.sha256()
+    for f in ("ckpp_lookup.hip", "ckpp_device.h"):
+        with open(os.path.join(ROOT, "paper_1712_09624_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def expected_lines(stats: dict) -> dict:
+    """Algorithmic 64-byte lines per lookup (Sec. 2 and 4.1): a positive
+    Cuckoo++ lookup reads its primary bucket, its record, and the secondary
+    bucket when the key sits there (fraction f_sec); a negative one reads its
+    primary bucket and, when the filter passes (rate FPR), the secondary.  A
+    probed bucket adds a record line per false tag match (occupancy x
+    2^-16).  The plain lookup reads both buckets always."""
+    occ = stats["live"] / stats["nbuckets"]
+    eps = occ / 65536.0
+    f_sec, fpr = stats["f_sec"], stats["expected_fpr"]
+    return {
+        "cuckoopp_pos": 2.0 + f_sec + eps * (1.0 + f_sec) / 2.0,
+        "cuckoopp_neg": 1.0 + fpr + eps * (1.0 + fpr),
+        "plain_pos": 3.0 + eps,
+        "plain_neg": 2.0 + 2.0 * eps,
+        "optimistic_pos": 2.0 + f_sec + eps * (1.0 + f_sec) / 2.0,
+        "optimistic_neg": 2.0 + 2.0 * eps,
+    }
+
+
+STREAM_BYTES = 16 + 1 + 8  # key in, found + value out, per lookup
+
+
+def build_table(B, load, seed, dev, batch=1 << 22):
+    import torch
+    from paper_1712_09624_amd.ckpp import Table
+    n = W.keys_at_load(B, load)
+    log(f"generating {n} keys for 2^{B} buckets at load {load}")
+    keys = W.distinct_five_tuples(n, seed)
+    vals = W.insertion_values(n)
+    t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=dev.index)
+    nfail = torch.zeros(1, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(0, n, batch):
+        dk = to_dev(keys[s:s + batch], dev)
+        dv = to_dev(vals[s:s + batch].view(np.int64), dev)
+        t.insert(dk, dv, nfailed=nfail)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    nf = int(nfail.item())
+    if nf:
+        raise RuntimeError(f"{nf} inserts failed while building the table")
+    log(f"built in {dt:.2f}s ({n / dt / 1e6:.0f} M inserts/s incl. transfers)")
+    return t, keys, vals, dt
+
+
+def timed(fn, reps, dev):
+    """Mean ms of fn() measured with events on the current stream."""
+    import torch
+    s = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fn()
+    e0.record(s)
+    for _ in range(reps):
+        fn()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def probe_rand_peak(dev, gib=8, nreads=1 << 26):
+    """Measured random-read rate: aligned 32/64/128-byte reads at uniformly
+    random positions of a buffer far larger than every cache, read either by
+    one lane (16-byte loads) or cooperatively (one 16-byte piece per lane,
+    one coalesced request per granule); several reads in flight per lane;
+    best launch shape per granule and form."""
+    import torch
+    from paper_1712_09624_amd import ckpp
+    nbytes = gib << 30
+    buf = torch.empty(nbytes // 8, dtype=torch.int64, device=dev)
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    best = {}
+    for coop in (False, True):
+        for granule in (32, 64, 128):
+            rates = []
+            for per_lane in (2, 4, 8):
+                for bpc in (8, 16):
+                    grid = ncu * bpc
+                    sink = torch.empty(grid * 256, dtype=torch.int64, device=dev)
+                    ms = timed(lambda: ckpp.probe_random_reads(buf, granule, nreads, per_lane, 256,
+                                                               grid, 12345, sink, coop), 3, dev)
+                    rates.append((nreads / (ms * 1e-3), per_lane, bpc))
+            r = max(rates)
+            key = f"{granule}{'_coop' if coop else '_lane'}"
+            best[key] = {"reads_per_s": r[0], "GBps": r[0] * granule / 1e9,
+                         "per_lane": r[1], "blocks_per_cu": r[2]}
+            log(f"random {key} reads: {r[0] / 1e9:.2f} G/s = {r[0] * granule / 1e9:.0f} GB/s")
+    del buf
+    torch.cuda.empty_cache()
+    return best
+
+
+def cache_resident_table(dev, lookups):
+    """2^20 buckets (64 MiB bucket array, which fits the 256 MiB last-level
+    cache; the 256 MiB record array only partly) at load 0.9."""
+    import torch
+    t, keys, _, _ = build_table(20, 0.9, 77, dev)
+    n = min(lookups, 1 << 24)
+    pos, _, _ = W.lookup_mix(keys, n, 0.0, 78)
+    neg = W.five_tuples(n, 79, stream=W.STREAM_NEGATIVE)
+    dp, dn = to_dev(pos, dev), to_dev(neg, dev)
+    f = torch.empty(n, dtype=torch.uint8, device=dev)
+    v = torch.empty(n, dtype=torch.int64, device=dev)
+    out = {"log2_buckets": 20, "load": 0.9, "lookups": n}
+    st = t.stats()
+    out["f_sec"] = st["f_sec"]
+    for mode in ("cuckoopp", "both"):
+        for name, d in (("pos", dp), ("neg", dn)):
+            ms = timed(lambda: t.lookup(d, mode, found=f, values=v), 5, dev)
+            out[f"{mode}_{name}_glookups"] = n / (ms * 1e-3) / 1e9
+    t.close()
+    return out
+
+
+def burst_latency(t, pos_keys_dev, neg_keys_dev, dev, nbursts=2000):
+    """Submit-to-completion time of single synchronous lookup bursts, sizes
+    log-uniform in [1, 2048], each half positive and half negative."""
+    import torch
+    sizes = W.log_uniform_sizes(nbursts, 1, 2048, 5, 0)
+    f = torch.empty(4096, dtype=torch.uint8, device=dev)
+    v = torch.empty(4096, dtype=torch.int64, device=dev)
+    lat = []
+    for i, s in enumerate(sizes):
+        s = int(s)
+        src = pos_keys_dev if i % 2 == 0 else neg_keys_dev
+        off = (i * 4096) % (src.shape[0] - 4096)
+        q = src[off:off + s]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.lookup(q, "cuckoopp", found=f[:s], values=v[:s])
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat = np.array(lat[50:]) * 1e6
+    return {"p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+            "bursts": int(len(lat)), "sizes": "log-uniform [1, 2048]"}
+
+
+def cpu_baseline(B=22, load=0.9, n=1 << 22):
+    """The oracle (single-threaded C, as it stands) timed on the host."""
+    from oracle import oracle as O
+    nk = W.keys_at_load(B, load)
+    keys = W.distinct_five_tuples(nk, 1, check=False)
+    t = O.OracleTable(B, W.HASH_SEED, W.MAX_KICKS)
+    t0 = time.perf_counter()
+    st = t.insert(keys, W.insertion_values(nk))
+    t_ins = time.perf_counter() - t0
+    assert (st == O.INSERTED).all()
+    pos, _, _ = W.lookup_mix(keys, n, 0.0, 2)
+    neg = W.five_tuples(n, 3, stream=W.STREAM_NEGATIVE)
+    t0 = time.perf_counter()
+    t.lookup(pos)
+    t.lookup(neg)
+    dt = time.perf_counter() - t0
+    t.close()
+    return {"value": 2 * n / dt / 1e9, "unit": "Glookups/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle table of 2^{B} buckets x 8 slots at load {load} "
+                      f"({nk} keys, the paper's 32M-entry size; built in {t_ins:.1f}s), "
+                      f"{n} positive + {n} negative Cuckoo++ lookups, single thread",
+            "insert_per_s": nk / t_ins}
+
+
+def copy_calibration(dev):
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.int64, device=dev)  # 1 GiB
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 1 << 30, "dispatches": 5}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the table is "
+                                   "sharded one-per-GPU by design but no multi-GPU path is "
+                                   "built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_1712_09624_amd import ckpp
+    ckpp.load()
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    if args.copy_calib:
+        copy_calibration(dev)
+        return
+
+    B, load, n = args.log2_buckets, args.load, args.lookups
+    t, keys, vals, build_s = build_table(B, load, 1, dev)
+    cfg = t.get_lookup_launch()
+    if args.lanes or args.per_lane or args.block or args.blocks_per_cu is not None:
+        t.set_lookup_launch(args.lanes or cfg["lanes_per_lookup"],
+                            args.per_lane or cfg["lookups_per_lane"],
+                            args.block or cfg["block"],
+                            cfg["blocks_per_cu"] if args.blocks_per_cu is None else args.blocks_per_cu)
+    launch = t.get_lookup_launch()
+    stats = t.stats()
+    lines = expected_lines(stats)
+    log(f"table: live {stats['live']} f_sec {stats['f_sec']:.4f} "
+        f"fpr {stats['expected_fpr']:.5f} moved0 {stats['moved_zero_fraction']:.3f}")
+
+    log(f"generating {n} positive and {n} negative lookups")
+    pos, _, pos_idx = W.lookup_mix(keys, n, 0.0, 2)
+    neg = W.five_tuples(n, 3, stream=W.STREAM_NEGATIVE)
+    churn = W.distinct_five_tuples(args.churn, 4, stream=W.STREAM_FRESH)
+    dpos, dneg = to_dev(pos, dev), to_dev(neg, dev)
+    dchurn = to_dev(churn, dev)
+    dchurn_v = to_dev(W.insertion_values(args.churn, 1 << 40).view(np.int64), dev)
+    if args.tune:
+        from paper_1712_09624_amd import tune
+        sweep = {}
+        for mode in ("both", "cuckoopp"):
+            res = tune.tune(t, [dpos, dneg], mode)
+            sweep[mode] = [{"ms_total": r[0], "ms_pos": r[2][0], "ms_neg": r[2][1], **r[1]}
+                           for r in res]
+            for r in res:
+                log(f"tune {mode}: {r[1]} pos {r[2][0]:.3f} ms neg {r[2][1]:.3f} ms")
+        print(json.dumps({"tune": sweep}), flush=True)
+        launch = t.get_lookup_launch()
+    f_pos = torch.empty(n, dtype=torch.uint8, device=dev)
+    v_pos = torch.empty(n, dtype=torch.int64, device=dev)
+    f_neg = torch.empty(n, dtype=torch.uint8, device=dev)
+    v_neg = torch.empty(n, dtype=torch.int64, device=dev)
+    st_churn = torch.empty(args.churn, dtype=torch.uint8, device=dev)
+    nf_churn = torch.zeros(1, dtype=torch.int64, device=dev)
+    d_churn = torch.empty(args.churn, dtype=torch.uint8, device=dev)
+    s = torch.cuda.current_stream(dev)
+
+    ev = {k: [] for k in ("ins", "pos", "neg", "del")}
+
+    def step(record):
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(5)] if record else None
+        if record:
+            marks[0].record(s)
+        t.insert(dchurn, dchurn_v, status=st_churn, nfailed=nf_churn)
+        if record:
+            marks[1].record(s)
+        t.lookup(dpos, "cuckoopp", found=f_pos, values=v_pos)
+        if record:
+            marks[2].record(s)
+        t.lookup(dneg, "cuckoopp", found=f_neg, values=v_neg)
+        if record:
+            marks[3].record(s)
+        t.delete(dchurn, found=d_churn)
+        if record:
+            marks[4].record(s)
+            for i, k in enumerate(("ins", "pos", "neg", "del")):
+                ev[k].append((marks[i], marks[i + 1]))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    # exactness spot check of the warm-up results (the tests check it fully)
+    chk = np.arange(0, n, max(1, n // 65536))
+    fp = f_pos.cpu().numpy()
+    vp = v_pos.cpu().numpy().view(np.uint64)
+    if not (fp[chk].all() and np.array_equal(vp[chk], vals[pos_idx[chk]])):
+        raise RuntimeError("positive lookups returned a wrong answer")
+    if f_neg.cpu().numpy()[chk].any() or int(nf_churn.item()):
+        raise RuntimeError("negative lookup hit, or churn insert failed")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = {k: float(np.mean([a.elapsed_time(b) for a, b in v])) for k, v in ev.items()}
+    if not bool(d_churn.all().item()) or int(nf_churn.item()):
+        raise RuntimeError("churn keys were not all inserted and deleted")
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = 2.0 * n / (ms_per_step * 1e-3) / 1e9
+
+    # roofline of the dominant kernel (the Cuckoo++ lookup: two launches/step)
+    bytes_pos = n * (LINE * lines["cuckoopp_pos"] + STREAM_BYTES)
+    bytes_neg = n * (LINE * lines["cuckoopp_neg"] + STREAM_BYTES)
+    achieved = (bytes_pos + bytes_neg) / ((ms["pos"] + ms["neg"]) * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": (f"lookup_{'lane' if launch['lanes_per_lookup'] == 1 else 'pair'}"
+                           f"<K={launch['lookups_per_lane']}, Cuckoo++>"),
+                "algorithmic_bytes_per_launch": (bytes_pos + bytes_neg) / 2,
+                "avg_launch_ms": (ms["pos"] + ms["neg"]) / 2}
+    tf = os.path.join(ROOT, "profiles", "lookup_traffic.json")
+    if os.path.exists(tf):
+        with open(tf) as fh:
+            tr = json.load(fh)
+        if tr.get("source_digest") == lookup_source_digest() and tr.get("launch") == launch:
+            roofline["traffic"] = tr["hbm_bytes_per_launch"]
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "Glookups/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"Cuckoo++ table 2^{B} buckets x 8 slots, load {load}; step = "
+                               f"insert {args.churn} + lookup {n} positive + lookup {n} "
+                               f"negative + delete {args.churn}",
+                   "log2_buckets": B, "load": load, "lookups_per_launch": n,
+                   "churn_batch": args.churn, "key_bytes": 16, "value_bytes": 8,
+                   "launch": launch, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "ms": ms,
+        "lookups": {
+            "cuckoopp_pos_glookups": n / (ms["pos"] * 1e-3) / 1e9,
+            "cuckoopp_neg_glookups": n / (ms["neg"] * 1e-3) / 1e9,
+            "lines_per_lookup": lines,
+        },
+        "table": {"live": stats["live"], "f_sec": stats["f_sec"],
+                  "expected_fpr": stats["expected_fpr"],
+                  "moved_zero_fraction": stats["moved_zero_fraction"],
+                  "build_s": build_s},
+    }
+    if not args.core_only:
+        lk = out["lookups"]
+        for mode in ("both", "optimistic"):
+            for name, d, fo, vo in (("pos", dpos, f_pos, v_pos), ("neg", dneg, f_neg, v_neg)):
+                tms = timed(lambda: t.lookup(d, mode, found=fo, values=vo), 5, dev)
+                lk[f"{'plain' if mode == 'both' else mode}_{name}_glookups"] = n / (tms * 1e-3) / 1e9
+        for name in ("pos", "neg"):
+            lk[f"cuckoopp_over_plain_{name}"] = (lk[f"cuckoopp_{name}_glookups"]
+                                                 / lk[f"plain_{name}_glookups"])
+        out["burst_latency"] = burst_latency(t, dpos, dneg, dev)
+        t.close()
+        del dpos, dneg, f_pos, v_pos, f_neg, v_neg
+        torch.cuda.empty_cache()
+        peak = probe_rand_peak(dev)
+        out["random_read_peak"] = peak
+        p64 = max(peak["64_coop"]["reads_per_s"], peak["64_lane"]["reads_per_s"])
+        out["random_read_peak_64"] = p64
+        lk["cuckoopp_pos_frac_rand64_peak"] = lk["cuckoopp_pos_glookups"] * 1e9 * lines["cuckoopp_pos"] / p64
+        lk["cuckoopp_neg_frac_rand64_peak"] = lk["cuckoopp_neg_glookups"] * 1e9 * lines["cuckoopp_neg"] / p64
+        lk["plain_pos_frac_rand64_peak"] = lk["plain_pos_glookups"] * 1e9 * lines["plain_pos"] / p64
+        lk["plain_neg_frac_rand64_peak"] = lk["plain_neg_glookups"] * 1e9 * lines["plain_neg"] / p64
+        out["cache_resident_table"] = cache_resident_table(dev, n)
+        if not args.no_cpu_baseline:
+            log("timing the oracle on the host")
+            out["cpu_baseline"] = cpu_baseline()
+    else:
+        t.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

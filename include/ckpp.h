@@ -207,14 +207,18 @@ int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg);
 int ckpp_get_lookup_launch(const ckpp_table *t, ckpp_launch_t *cfg);
 
 /* Measurement kernel for the roofline of the lookups: reads `nreads`
- * granules of `granule` bytes (32, 64 or 128, aligned) at pseudo-random
- * positions of the device buffer d_buf (`bytes` long, a multiple of the
- * granule), `per_lane` independent reads in flight per lane, and folds the
- * data into d_sink (one u64 per launched lane, grid*block entries).  The
- * caller times it; nreads / time is the random-access line rate. */
+ * granules of `granule` bytes (16, 32, 64 or 128, aligned) at uniformly
+ * random positions of the device buffer d_buf (`bytes` long, a multiple of
+ * the granule) and folds the data into d_sink (one u64 per launched lane:
+ * grid * block entries).  per_lane (1, 2, 4, 8) granules are kept in flight
+ * per lane (or lane group).  cooperative = 0: each lane reads whole
+ * granules with 16-byte loads; cooperative = 1: granule/16 neighbouring
+ * lanes read one granule together, one 16-byte piece each (one coalesced
+ * request per granule).  block: 64, 128 or 256.  The caller times it;
+ * nreads / time is the random-access rate. */
 int ckpp_probe_random_reads(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t nreads,
-                            uint32_t per_lane, uint32_t block, uint32_t grid, uint64_t seed,
-                            uint64_t *d_sink, void *stream);
+                            uint32_t per_lane, uint32_t cooperative, uint32_t block, uint32_t grid,
+                            uint64_t seed, uint64_t *d_sink, void *stream);
 
 /* Human-readable name of a status code. */
 const char *ckpp_strerror(int code);

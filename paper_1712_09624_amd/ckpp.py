@@ -84,7 +84,8 @@ SIGNATURES = [
     ("ckpp_info", _I, [_VP, ctypes.POINTER(_Info)]),
     ("ckpp_set_lookup_launch", _I, [_VP, ctypes.POINTER(_Launch)]),
     ("ckpp_get_lookup_launch", _I, [_VP, ctypes.POINTER(_Launch)]),
-    ("ckpp_probe_random_reads", _I, [_VP, _U64, _U32, _U64, _U32, _U32, _U32, _U64, _VP, _VP]),
+    ("ckpp_probe_random_reads", _I, [_VP, _U64, _U32, _U64, _U32, _U32, _U32, _U32, _U64, _VP,
+                                     _VP]),
     ("ckpp_strerror", ctypes.c_char_p, [_I]),
 ]
 
@@ -297,11 +298,12 @@ class Table:
 
 
 def probe_random_reads(buf, granule: int, nreads: int, per_lane: int, block: int, grid: int,
-                       seed: int, sink, stream=None):
+                       seed: int, sink, cooperative: bool = False, stream=None):
     """Launches the random-read probe over the device tensor ``buf``."""
     lib = load()
     nbytes = buf.numel() * buf.element_size()
-    rc = lib.ckpp_probe_random_reads(buf.data_ptr(), nbytes, granule, nreads, per_lane, block,
-                                     grid, ctypes.c_uint64(seed), sink.data_ptr(),
+    rc = lib.ckpp_probe_random_reads(buf.data_ptr(), nbytes, granule, nreads, per_lane,
+                                     1 if cooperative else 0, block, grid,
+                                     ctypes.c_uint64(seed), sink.data_ptr(),
                                      _stream_handle(stream))
     _check(rc, "ckpp_probe_random_reads")

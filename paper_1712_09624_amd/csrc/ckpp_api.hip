@@ -267,17 +267,18 @@ int ckpp_get_lookup_launch(const ckpp_table *t, ckpp_launch_t *cfg) {
 }
 
 int ckpp_probe_random_reads(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t nreads,
-                            uint32_t per_lane, uint32_t block, uint32_t grid, uint64_t seed,
-                            uint64_t *d_sink, void *stream) {
+                            uint32_t per_lane, uint32_t cooperative, uint32_t block, uint32_t grid,
+                            uint64_t seed, uint64_t *d_sink, void *stream) {
   if (!d_buf || !d_sink) return CKPP_EINVAL;
-  if (granule != 32 && granule != 64 && granule != 128) return CKPP_EINVAL;
+  if (granule != 16 && granule != 32 && granule != 64 && granule != 128) return CKPP_EINVAL;
   if (!aligned(d_buf, granule) || bytes < granule || bytes % granule) return CKPP_EINVAL;
   if (per_lane != 1 && per_lane != 2 && per_lane != 4 && per_lane != 8) return CKPP_EINVAL;
+  if (cooperative > 1) return CKPP_EINVAL;
   if (block != 64 && block != 128 && block != 256) return CKPP_EINVAL;
   if (grid == 0 || !aligned(d_sink, 8)) return CKPP_EINVAL;
   if (nreads == 0) return CKPP_OK;
-  return dev_status(ckpp::launch_probe(d_buf, bytes, granule, nreads, per_lane, block, grid, seed,
-                                       d_sink, reinterpret_cast<hipStream_t>(stream)));
+  return dev_status(ckpp::launch_probe(d_buf, bytes, granule, nreads, per_lane, cooperative, block,
+                                       grid, seed, d_sink, reinterpret_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

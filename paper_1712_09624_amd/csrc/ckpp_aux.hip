@@ -59,50 +59,67 @@ __global__ void __launch_bounds__(256) fill_zero_kernel(uint4 *d, uint64_t n16) 
 }
 
 // Random-read probe: read i of the launch reads the granule at index
-// mix64(seed + i) * units >> 64 (uniform over the buffer); each lane keeps
-// PL reads of Q 16-byte quarters in flight and folds them into its sink.
-template <int Q, int PL>
+// mix64(seed + i) * units >> 64 (uniform over the buffer).  Lane form: each
+// lane reads whole granules (Q 16-byte loads each), PL granules in flight.
+// Cooperative form: Q neighbouring lanes read one granule together, one
+// 16-byte piece each, so a granule is a single coalesced request.
+template <int Q, int PL, bool COOP>
 __global__ void __launch_bounds__(256)
     probe_kernel(const uint4 *__restrict__ buf, uint64_t units, uint64_t nreads, uint64_t seed,
                  unsigned long long *__restrict__ sink) {
   const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nl = (uint64_t)gridDim.x * blockDim.x;
+  constexpr int QL = COOP ? 1 : Q;  // loads per granule per lane
+  const uint64_t group = COOP ? lane / Q : lane;
+  const uint64_t ngroups = COOP ? nl / Q : nl;
+  const uint32_t part = COOP ? (uint32_t)(threadIdx.x % Q) : 0u;
   uint32_t acc = 0u;
-  for (uint64_t r0 = lane * PL; r0 < nreads; r0 += nl * PL) {
-    uint4 v[PL][Q];
+  for (uint64_t r0 = group * PL; r0 < nreads; r0 += ngroups * PL) {
+    uint4 v[PL][QL];
 #pragma unroll
     for (int j = 0; j < PL; ++j) {
       const uint64_t i = r0 + j;
       if (i < nreads) {
         const uint64_t u = __umul64hi(mix64(seed + i), units);
 #pragma unroll
-        for (int q = 0; q < Q; ++q) v[j][q] = buf[u * Q + q];
+        for (int q = 0; q < QL; ++q) v[j][q] = buf[u * Q + part + q];
       } else {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) v[j][q] = make_uint4(0u, 0u, 0u, 0u);
+        for (int q = 0; q < QL; ++q) v[j][q] = make_uint4(0u, 0u, 0u, 0u);
       }
     }
 #pragma unroll
     for (int j = 0; j < PL; ++j)
 #pragma unroll
-      for (int q = 0; q < Q; ++q) acc ^= v[j][q].x ^ v[j][q].y ^ v[j][q].z ^ v[j][q].w;
+      for (int q = 0; q < QL; ++q) acc ^= v[j][q].x ^ v[j][q].y ^ v[j][q].z ^ v[j][q].w;
   }
   sink[lane] = acc;
 }
 
-template <int Q>
+template <int Q, bool COOP>
 hipError_t probe_q(const void *d_buf, uint64_t units, uint64_t nreads, uint32_t per_lane,
                    uint32_t block, uint32_t grid, uint64_t seed, uint64_t *d_sink,
                    hipStream_t s) {
   const uint4 *b = reinterpret_cast<const uint4 *>(d_buf);
   unsigned long long *k = reinterpret_cast<unsigned long long *>(d_sink);
   switch (per_lane) {
-    case 1: hipLaunchKernelGGL((probe_kernel<Q, 1>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
-    case 2: hipLaunchKernelGGL((probe_kernel<Q, 2>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
-    case 4: hipLaunchKernelGGL((probe_kernel<Q, 4>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
-    default: hipLaunchKernelGGL((probe_kernel<Q, 8>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
+    case 1: hipLaunchKernelGGL((probe_kernel<Q, 1, COOP>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
+    case 2: hipLaunchKernelGGL((probe_kernel<Q, 2, COOP>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
+    case 4: hipLaunchKernelGGL((probe_kernel<Q, 4, COOP>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
+    default: hipLaunchKernelGGL((probe_kernel<Q, 8, COOP>), dim3(grid), dim3(block), 0, s, b, units, nreads, seed, k); break;
   }
   return hipGetLastError();
+}
+
+template <bool COOP>
+hipError_t probe_g(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t nreads,
+                   uint32_t per_lane, uint32_t block, uint32_t grid, uint64_t seed,
+                   uint64_t *d_sink, hipStream_t s) {
+  const uint64_t units = bytes / granule;
+  if (granule == 16) return probe_q<1, COOP>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
+  if (granule == 32) return probe_q<2, COOP>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
+  if (granule == 64) return probe_q<4, COOP>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
+  return probe_q<8, COOP>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
 }
 
 }  // namespace
@@ -138,12 +155,11 @@ hipError_t launch_fill_zero(void *d, uint64_t bytes, hipStream_t s) {
 }
 
 hipError_t launch_probe(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t nreads,
-                        uint32_t per_lane, uint32_t block, uint32_t grid, uint64_t seed,
-                        uint64_t *d_sink, hipStream_t s) {
-  const uint64_t units = bytes / granule;
-  if (granule == 32) return probe_q<2>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
-  if (granule == 64) return probe_q<4>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
-  return probe_q<8>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
+                        uint32_t per_lane, uint32_t cooperative, uint32_t block, uint32_t grid,
+                        uint64_t seed, uint64_t *d_sink, hipStream_t s) {
+  if (cooperative)
+    return probe_g<true>(d_buf, bytes, granule, nreads, per_lane, block, grid, seed, d_sink, s);
+  return probe_g<false>(d_buf, bytes, granule, nreads, per_lane, block, grid, seed, d_sink, s);
 }
 
 }  // namespace ckpp

@@ -38,7 +38,7 @@ hipError_t launch_hash(const ckpp_table *t, const void *d_keys, uint64_t n, uint
                        hipStream_t s);
 hipError_t launch_fill_zero(void *d, uint64_t bytes, hipStream_t s);
 hipError_t launch_probe(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t nreads,
-                        uint32_t per_lane, uint32_t block, uint32_t grid, uint64_t seed,
-                        uint64_t *d_sink, hipStream_t s);
+                        uint32_t per_lane, uint32_t cooperative, uint32_t block, uint32_t grid,
+                        uint64_t seed, uint64_t *d_sink, hipStream_t s);
 
 }  // namespace ckpp

@@ -1,0 +1,56 @@
+"""Launch-shape autotuner of the lookup kernels.
+
+Times every lookup launch shape (lanes per lookup, lookups in flight per
+lane, block size, grid cap) on a caller's table and key batches, and returns
+the shapes ranked by lookups per second.  Timing uses device events on the
+current stream; the answers do not depend on the shape (the parity tests
+check every shape), only the speed does.
+"""
+
+from __future__ import annotations
+
+import itertools
+
+SHAPES = [
+    {"lanes_per_lookup": lanes, "lookups_per_lane": per, "block": block, "blocks_per_cu": bpc}
+    for lanes, per, block, bpc in itertools.product((1, 2), (1, 2, 4), (128, 256), (0,))
+]
+
+
+def time_lookup(table, keys, mode, found, values, reps=3):
+    import torch
+    s = torch.cuda.current_stream()
+    table.lookup(keys, mode, found=found, values=values)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        table.lookup(keys, mode, found=found, values=values)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(table, batches, mode="cuckoopp", shapes=None, reps=3, apply=True):
+    """batches: list of device key tensors (e.g. a positive and a negative
+    batch).  The score of a shape is the total time over the batches.
+    Returns [(total_ms, shape, [ms per batch])] sorted fastest first, and
+    sets the fastest shape on the table when apply is true."""
+    import torch
+    shapes = shapes or SHAPES
+    n = max(int(b.shape[0]) for b in batches)
+    found = torch.empty(n, dtype=torch.uint8, device=batches[0].device)
+    values = torch.empty(n, dtype=torch.int64, device=batches[0].device)
+    before = table.get_lookup_launch()
+    results = []
+    for sh in shapes:
+        table.set_lookup_launch(sh["lanes_per_lookup"], sh["lookups_per_lane"], sh["block"],
+                                sh["blocks_per_cu"])
+        per = [time_lookup(table, b, mode, found[: b.shape[0]], values[: b.shape[0]], reps)
+               for b in batches]
+        results.append((sum(per), dict(sh), per))
+    results.sort(key=lambda r: r[0])
+    best = results[0][1] if apply else before
+    table.set_lookup_launch(best["lanes_per_lookup"], best["lookups_per_lane"], best["block"],
+                            best["blocks_per_cu"])
+    return results

@@ -64,7 +64,7 @@ def test_argument_checks_need_no_device(lib):
     assert lib.ckpp_lookup_batch(None, None, 5, 0, None, None, None) == ckpp.EINVAL
     assert lib.ckpp_delete_batch(None, None, 5, None, None) == ckpp.EINVAL
     assert lib.ckpp_destroy(None) == ckpp.OK
-    assert lib.ckpp_probe_random_reads(None, 64, 64, 1, 1, 256, 1, 0, None, None) == ckpp.EINVAL
+    assert lib.ckpp_probe_random_reads(None, 64, 64, 1, 1, 0, 256, 1, 0, None, None) == ckpp.EINVAL
 
 
 def test_missing_library_fails_loudly(tmp_path):
