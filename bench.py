@@ -34,7 +34,7 @@ from paper_1712_09624_amd import workload as W  # noqa: E402
 
 METRIC = "Glookups/s @load 0.9 (pos & neg), % random-64B HBM peak; p99 burst latency"
 HBM_PEAK_GBS = 8000.0  # MI355X published HBM3E bandwidth
-LINE = 64
+LINE = 128  # bytes of one bucket line (half of a 256-byte device bucket)
 
 
 def parse():
@@ -78,21 +78,28 @@ def lookup_source_digest() -> str:
 
 
 def expected_lines(stats: dict) -> dict:
-    """Algorithmic 64-byte lines per lookup (Sec. 2 and 4.1): a positive
-    Cuckoo++ lookup reads its primary bucket, its record, and the secondary
-    bucket when the key sits there (fraction f_sec); a negative one reads its
-    primary bucket and, when the filter passes (rate FPR), the secondary.  A
-    probed bucket adds a record line per false tag match (occupancy x
-    2^-16).  The plain lookup reads both buckets always."""
-    occ = stats["live"] / stats["nbuckets"]
-    eps = occ / 65536.0
+    """Algorithmic 128-byte lines read per lookup (Sec. 2 and 4.1 on the
+    device layout: a bucket's first line holds its metadata and slots 0..3,
+    its second line slots 4..7).  A positive Cuckoo++ lookup reads the first
+    line of its primary bucket, plus the second line when the key sits in a
+    slot 4..7, plus the secondary bucket's line(s) when the key was displaced
+    there: per key 1 + f_high + f_sec, f_high = share of entries in slots
+    4..7, f_sec = share in their secondary bucket.  A negative Cuckoo++
+    lookup reads one line, plus a line of the secondary when the filter
+    passes (rate FPR).  A busy slot 4..7 whose tag matches by chance
+    (2^-16 per slot) costs one more line.  The pessimistic lookup reads the
+    first lines of both buckets always; the optimistic one reads the
+    secondary whenever the key is not in the primary."""
+    nb, live = stats["nbuckets"], max(1, stats["live"])
     f_sec, fpr = stats["f_sec"], stats["expected_fpr"]
+    f_high = stats["high_slots"] / live
+    eps = (stats["high_slots"] / nb) / 65536.0  # false tag matches in slots 4..7 per bucket
     return {
-        "cuckoopp_pos": 2.0 + f_sec + eps * (1.0 + f_sec) / 2.0,
+        "cuckoopp_pos": 1.0 + f_high + f_sec + eps * f_sec,
         "cuckoopp_neg": 1.0 + fpr + eps * (1.0 + fpr),
-        "plain_pos": 3.0 + eps,
+        "plain_pos": 2.0 + f_high + eps,
         "plain_neg": 2.0 + 2.0 * eps,
-        "optimistic_pos": 2.0 + f_sec + eps * (1.0 + f_sec) / 2.0,
+        "optimistic_pos": 1.0 + f_high + f_sec + eps * f_sec,
         "optimistic_neg": 2.0 + 2.0 * eps,
     }
 
@@ -359,8 +366,7 @@ def main():
     achieved = (bytes_pos + bytes_neg) / ((ms["pos"] + ms["neg"]) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": (f"lookup_{'lane' if launch['lanes_per_lookup'] == 1 else 'pair'}"
-                           f"<K={launch['lookups_per_lane']}, Cuckoo++>"),
+                "kernel": f"lookup_group8<K={launch['lookups_per_lane']}, Cuckoo++>",
                 "algorithmic_bytes_per_launch": (bytes_pos + bytes_neg) / 2,
                 "avg_launch_ms": (ms["pos"] + ms["neg"]) / 2}
     tf = os.path.join(ROOT, "profiles", "lookup_traffic.json")
@@ -370,6 +376,7 @@ def main():
         if tr.get("source_digest") == lookup_source_digest() and tr.get("launch") == launch:
             roofline["traffic"] = tr["hbm_bytes_per_launch"]
 
+    stats["f_high"] = stats["high_slots"] / max(1, stats["live"])
     out = {
         "metric": METRIC, "value": value, "unit": "Glookups/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -388,7 +395,7 @@ def main():
             "cuckoopp_neg_glookups": n / (ms["neg"] * 1e-3) / 1e9,
             "lines_per_lookup": lines,
         },
-        "table": {"live": stats["live"], "f_sec": stats["f_sec"],
+        "table": {"live": stats["live"], "f_sec": stats["f_sec"], "f_high": stats["f_high"],
                   "expected_fpr": stats["expected_fpr"],
                   "moved_zero_fraction": stats["moved_zero_fraction"],
                   "build_s": build_s},
@@ -408,12 +415,11 @@ def main():
         torch.cuda.empty_cache()
         peak = probe_rand_peak(dev)
         out["random_read_peak"] = peak
-        p64 = max(peak["64_coop"]["reads_per_s"], peak["64_lane"]["reads_per_s"])
-        out["random_read_peak_64"] = p64
-        lk["cuckoopp_pos_frac_rand64_peak"] = lk["cuckoopp_pos_glookups"] * 1e9 * lines["cuckoopp_pos"] / p64
-        lk["cuckoopp_neg_frac_rand64_peak"] = lk["cuckoopp_neg_glookups"] * 1e9 * lines["cuckoopp_neg"] / p64
-        lk["plain_pos_frac_rand64_peak"] = lk["plain_pos_glookups"] * 1e9 * lines["plain_pos"] / p64
-        lk["plain_neg_frac_rand64_peak"] = lk["plain_neg_glookups"] * 1e9 * lines["plain_neg"] / p64
+        p128 = peak["128_coop"]["reads_per_s"]
+        out["random_line_peak_per_s"] = p128
+        for k in ("cuckoopp_pos", "cuckoopp_neg", "plain_pos", "plain_neg", "optimistic_pos",
+                  "optimistic_neg"):
+            lk[f"{k}_frac_random_line_peak"] = lk[f"{k}_glookups"] * 1e9 * lines[k] / p128
         out["cache_resident_table"] = cache_resident_table(dev, n)
         if not args.no_cpu_baseline:
             log("timing the oracle on the host")

@@ -23,11 +23,12 @@
  *  - Every call validates its arguments first and returns CKPP_OK or an
  *    error code without enqueueing anything; n == 0 is a no-op returning
  *    CKPP_OK.  A failed kernel launch returns CKPP_EDEVICE.
- *  - The table's device memory is owned by the library: 64 * 2^B bytes of
- *    buckets and 256 * 2^B bytes of key/value records (40 bytes per slot),
- *    plus a small working area.
+ *  - The table's device memory is owned by the library: 256 * 2^B bytes
+ *    (32 bytes per slot: bucket b holds its metadata and the keys and values
+ *    of its 8 slots in two 128-byte lines), plus a small working area.
  *
- * Image layout (used by export/import; fixed, little-endian):
+ * Image layout (the interchange format of export/import, independent of the
+ * device layout; fixed, little-endian):
  *   bucket b, 64 bytes at offset 64*b (one cache line, Sec. 4.3):
  *     0..15  tag[8]   u16  16-bit tag of each slot, from the key's hash
  *     16..23 bloom    u64  bloom filter of keys displaced from b (Sec. 4.1)
@@ -152,7 +153,9 @@ int ckpp_import(ckpp_table *t, const void *h_buckets, const void *h_kv, void *st
 /* Table statistics (Sec. 3 entries in secondary; Sec. 4.1 moved counters;
  * Sec. 5.3 filter false-positive rate).  The rate a uniformly random absent
  * key passes bucket b's filter is (popcount(bloom_b)/64)^2, so the mean rate
- * is bloom_pc2_sum / (4096 * nbuckets). */
+ * is bloom_pc2_sum / (4096 * nbuckets).  Slots 4..7 of a bucket sit in its
+ * second 128-byte line: a lookup of a key stored there reads two lines of
+ * that bucket. */
 #define CKPP_MOVED_BINS 66 /* moved counter values 0..64, then "> 64" */
 typedef struct {
     uint64_t nbuckets;
@@ -161,6 +164,8 @@ typedef struct {
     uint64_t bloom_pc_sum;  /* sum of popcount(bloom) over buckets */
     uint64_t bloom_pc2_sum; /* sum of popcount(bloom)^2 over buckets */
     uint64_t locked;        /* buckets whose lock word is non-zero */
+    uint64_t high_slots;    /* occupied slots 4..7 */
+    uint64_t high_slots_secondary; /* of which entries in their secondary */
     uint64_t retry_exhausted; /* keys of earlier insert/delete batches that
                                  gave up after the retry bound on contended
                                  locks (reported FAILED / not found) */
@@ -181,21 +186,21 @@ typedef struct {
     uint32_t flags;
     int device;
     uint64_t hash_seed;
-    uint64_t bucket_bytes;
-    uint64_t kv_bytes;
-    void *d_buckets; /* device address of the bucket array */
-    void *d_kv;      /* device address of the key/value array */
+    uint64_t image_bucket_bytes; /* sizes of the export/import arrays */
+    uint64_t image_kv_bytes;
+    uint64_t device_bytes;       /* device memory of the table */
+    void *d_table;               /* device address of the table */
 } ckpp_info_t;
 
 int ckpp_info(const ckpp_table *t, ckpp_info_t *out);
 
-/* Launch shape of the lookup kernels.  lanes_per_lookup: 1 (one lane reads
- * a 32-byte bucket head with two 16-byte loads) or 2 (two neighbouring lanes
- * read its two 16-byte halves in one coalesced request and combine the tag
- * match across lanes); lookups_per_lane: 1, 2 or 4 lookups kept in flight by
- * each lane (or lane pair); block: 64, 128 or 256;
- * blocks_per_cu: grid size in blocks per compute unit (0: enough blocks to
- * cover the batch in one pass).  Applies to every later lookup on t. */
+/* Launch shape of the lookup kernel.  lanes_per_lookup: 8 (a group of 8
+ * neighbouring lanes reads a bucket's 128-byte first line in one request,
+ * 16 bytes per lane, and combines the verdicts across the group);
+ * lookups_per_lane: 1, 2 or 4 lookups kept in flight by each group; block:
+ * 64, 128 or 256; blocks_per_cu: grid size in blocks per compute unit (0:
+ * enough blocks to cover the batch in one pass).  Applies to every later
+ * lookup on t. */
 typedef struct {
     uint32_t lanes_per_lookup;
     uint32_t lookups_per_lane;

@@ -38,6 +38,8 @@ class _Stats(ctypes.Structure):
         ("bloom_pc_sum", ctypes.c_uint64),
         ("bloom_pc2_sum", ctypes.c_uint64),
         ("locked", ctypes.c_uint64),
+        ("high_slots", ctypes.c_uint64),
+        ("high_slots_secondary", ctypes.c_uint64),
         ("retry_exhausted", ctypes.c_uint64),
         ("moved_hist", ctypes.c_uint64 * MOVED_BINS),
     ]
@@ -50,10 +52,10 @@ class _Info(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("device", ctypes.c_int),
         ("hash_seed", ctypes.c_uint64),
-        ("bucket_bytes", ctypes.c_uint64),
-        ("kv_bytes", ctypes.c_uint64),
-        ("d_buckets", ctypes.c_void_p),
-        ("d_kv", ctypes.c_void_p),
+        ("image_bucket_bytes", ctypes.c_uint64),
+        ("image_kv_bytes", ctypes.c_uint64),
+        ("device_bytes", ctypes.c_uint64),
+        ("d_table", ctypes.c_void_p),
     ]
 
 
@@ -274,6 +276,8 @@ class Table:
             "bloom_pc2_sum": int(st.bloom_pc2_sum),
             "expected_fpr": int(st.bloom_pc2_sum) / (4096.0 * nb),
             "locked": int(st.locked),
+            "high_slots": int(st.high_slots),
+            "high_slots_secondary": int(st.high_slots_secondary),
             "retry_exhausted": int(st.retry_exhausted),
             "moved_hist": hist,
             "moved_zero_fraction": hist[0] / nb,
@@ -284,7 +288,7 @@ class Table:
         _check(self.lib.ckpp_info(self._h, ctypes.byref(inf)), "ckpp_info")
         return {f: getattr(inf, f) for f, _ in _Info._fields_}
 
-    def set_lookup_launch(self, lanes_per_lookup=1, lookups_per_lane=2, block=256,
+    def set_lookup_launch(self, lanes_per_lookup=8, lookups_per_lane=2, block=256,
                           blocks_per_cu=0):
         cfg = _Launch(lanes_per_lookup, lookups_per_lane, block, blocks_per_cu)
         _check(self.lib.ckpp_set_lookup_launch(self._h, ctypes.byref(cfg)),

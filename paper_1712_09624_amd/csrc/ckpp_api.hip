@@ -1,8 +1,11 @@
 // ckpp_api.hip -- the C ABI: argument checks, device memory, dispatch.
 
+#include <algorithm>
 #include <new>
 #include <stdint.h>
 #include <string.h>
+#include <thread>
+#include <vector>
 
 #include "ckpp_internal.h"
 
@@ -12,7 +15,7 @@ constexpr uint32_t kMaxLog2Buckets = 24;
 constexpr uint32_t kMaxKicksLimit = 4096;
 constexpr uint32_t kMaxPathLanes = 65536;
 constexpr uint32_t kAccWords = 128;   // device accumulator words
-constexpr uint32_t kAccStats = 6 + CKPP_MOVED_BINS;
+constexpr uint32_t kAccStats = 7 + CKPP_MOVED_BINS;
 constexpr uint32_t kAccRetry = 127;   // retry-bound counter (never cleared)
 
 // Makes the table's device current for the duration of a call.
@@ -37,8 +40,68 @@ bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p
 
 int dev_status(hipError_t e) { return e == hipSuccess ? CKPP_OK : CKPP_EDEVICE; }
 
-uint64_t bucket_bytes(const ckpp_table *t) { return 64ull << t->log2_buckets; }
-uint64_t kv_bytes(const ckpp_table *t) { return 256ull << t->log2_buckets; }
+uint64_t nbuckets(const ckpp_table *t) { return 1ull << t->log2_buckets; }
+uint64_t table_bytes(const ckpp_table *t) { return 256ull << t->log2_buckets; }
+uint64_t image_bucket_bytes(const ckpp_table *t) { return 64ull << t->log2_buckets; }
+uint64_t image_kv_bytes(const ckpp_table *t) { return 256ull << t->log2_buckets; }
+
+// Byte offsets of slot s's key and value within a 256-byte device bucket
+// (the layout documented in ckpp_device.h).
+uint32_t dev_key_offset(uint32_t s) { return s < 4 ? 32 + 16 * s : 128 + 16 * (s - 4); }
+uint32_t dev_value_offset(uint32_t s) { return s < 4 ? 96 + 8 * s : 192 + 8 * (s - 4); }
+constexpr uint32_t kDevOther = 224;
+
+// Runs f(lo, hi) over [0, n) split across host threads.
+template <class F>
+void parallel_range(uint64_t n, F f) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (n < (1u << 16)) nt = 1;
+  std::vector<std::thread> th;
+  const uint64_t chunk = (n + nt - 1) / nt;
+  for (unsigned i = 0; i < nt; ++i) {
+    const uint64_t lo = i * chunk, hi = std::min(n, lo + chunk);
+    if (lo < hi) th.emplace_back(f, lo, hi);
+  }
+  for (auto &x : th) x.join();
+}
+
+// image (64-byte buckets + 32-byte records) -> device layout
+void image_to_device(const uint8_t *hb, const uint8_t *hk, uint8_t *dev, uint64_t nb) {
+  parallel_range(nb, [=](uint64_t lo, uint64_t hi) {
+    for (uint64_t b = lo; b < hi; ++b) {
+      uint8_t *d = dev + 256 * b;
+      const uint8_t *src = hb + 64 * b;
+      memcpy(d, src, 32);               // tags, filter, masks, lock
+      memcpy(d + kDevOther, src + 32, 32);  // other[8]
+      for (uint32_t s = 0; s < 8; ++s) {
+        const uint8_t *r = hk + 32 * (8 * b + s);
+        memcpy(d + dev_key_offset(s), r, 16);
+        memcpy(d + dev_value_offset(s), r + 16, 8);
+      }
+    }
+  });
+}
+
+// device layout -> image (the records' reserved 8 bytes are written as 0)
+void device_to_image(const uint8_t *dev, uint8_t *hb, uint8_t *hk, uint64_t nb) {
+  parallel_range(nb, [=](uint64_t lo, uint64_t hi) {
+    for (uint64_t b = lo; b < hi; ++b) {
+      const uint8_t *d = dev + 256 * b;
+      if (hb) {
+        memcpy(hb + 64 * b, d, 32);
+        memcpy(hb + 64 * b + 32, d + kDevOther, 32);
+      }
+      if (hk) {
+        for (uint32_t s = 0; s < 8; ++s) {
+          uint8_t *r = hk + 32 * (8 * b + s);
+          memcpy(r, d + dev_key_offset(s), 16);
+          memcpy(r + 16, d + dev_value_offset(s), 8);
+          memset(r + 24, 0, 8);
+        }
+      }
+    }
+  });
+}
 
 }  // namespace
 
@@ -75,7 +138,7 @@ int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uin
   t->flags = flags;
   t->device = device;
   t->seed = hash_seed;
-  t->lookup_launch.lanes_per_lookup = 1;
+  t->lookup_launch.lanes_per_lookup = 8;
   t->lookup_launch.lookups_per_lane = 2;
   t->lookup_launch.block = 256;
   t->lookup_launch.blocks_per_cu = 0;
@@ -94,21 +157,18 @@ int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uin
   const uint64_t path_words = lanes * (uint64_t)(max_kicks ? max_kicks : 1u);
 
   int rc = CKPP_OK;
-  if (hipMalloc(&t->d_buckets, bucket_bytes(t)) != hipSuccess ||
-      hipMalloc(&t->d_kv, kv_bytes(t)) != hipSuccess ||
+  if (hipMalloc(&t->d_table, table_bytes(t)) != hipSuccess ||
       hipMalloc(&t->d_paths, path_words * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&t->d_stats, kAccWords * sizeof(uint64_t)) != hipSuccess) {
     rc = CKPP_ENOMEM;
-  } else if (hipMemset(t->d_buckets, 0, bucket_bytes(t)) != hipSuccess ||
-             hipMemset(t->d_kv, 0, kv_bytes(t)) != hipSuccess ||
+  } else if (hipMemset(t->d_table, 0, table_bytes(t)) != hipSuccess ||
              hipMemset(t->d_stats, 0, kAccWords * sizeof(uint64_t)) != hipSuccess ||
              hipDeviceSynchronize() != hipSuccess) {
     rc = CKPP_EDEVICE;
   }
   if (rc != CKPP_OK) {
     (void)hipGetLastError();
-    if (t->d_buckets) (void)hipFree(t->d_buckets);
-    if (t->d_kv) (void)hipFree(t->d_kv);
+    if (t->d_table) (void)hipFree(t->d_table);
     if (t->d_paths) (void)hipFree(t->d_paths);
     if (t->d_stats) (void)hipFree(t->d_stats);
     delete t;
@@ -122,8 +182,7 @@ int ckpp_destroy(ckpp_table *t) {
   if (!t) return CKPP_OK;
   DeviceGuard g(t->device);
   (void)hipDeviceSynchronize();
-  (void)hipFree(t->d_buckets);
-  (void)hipFree(t->d_kv);
+  (void)hipFree(t->d_table);
   (void)hipFree(t->d_paths);
   (void)hipFree(t->d_stats);
   delete t;
@@ -135,9 +194,7 @@ int ckpp_clear(ckpp_table *t, void *stream) {
   DeviceGuard g(t->device);
   if (!g.ok()) return CKPP_EDEVICE;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = ckpp::launch_fill_zero(t->d_buckets, bucket_bytes(t), s);
-  if (e == hipSuccess) e = ckpp::launch_fill_zero(t->d_kv, kv_bytes(t), s);
-  return dev_status(e);
+  return dev_status(ckpp::launch_fill_zero(t->d_table, table_bytes(t), s));
 }
 
 int ckpp_insert_batch(ckpp_table *t, const void *d_keys, const uint64_t *d_values, uint64_t n,
@@ -180,13 +237,18 @@ int ckpp_delete_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_
 
 int ckpp_export(const ckpp_table *t, void *h_buckets, void *h_kv, void *stream) {
   if (!t) return CKPP_EINVAL;
+  if (!h_buckets && !h_kv) return CKPP_OK;
   DeviceGuard g(t->device);
   if (!g.ok()) return CKPP_EDEVICE;
+  uint8_t *stage = new (std::nothrow) uint8_t[table_bytes(t)];
+  if (!stage) return CKPP_ENOMEM;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = hipSuccess;
-  if (h_buckets) e = hipMemcpyAsync(h_buckets, t->d_buckets, bucket_bytes(t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess && h_kv) e = hipMemcpyAsync(h_kv, t->d_kv, kv_bytes(t), hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(stage, t->d_table, table_bytes(t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess)
+    device_to_image(stage, static_cast<uint8_t *>(h_buckets), static_cast<uint8_t *>(h_kv),
+                    nbuckets(t));
+  delete[] stage;
   return dev_status(e);
 }
 
@@ -194,10 +256,14 @@ int ckpp_import(ckpp_table *t, const void *h_buckets, const void *h_kv, void *st
   if (!t || !h_buckets || !h_kv) return CKPP_EINVAL;
   DeviceGuard g(t->device);
   if (!g.ok()) return CKPP_EDEVICE;
+  uint8_t *stage = new (std::nothrow) uint8_t[table_bytes(t)];
+  if (!stage) return CKPP_ENOMEM;
+  image_to_device(static_cast<const uint8_t *>(h_buckets), static_cast<const uint8_t *>(h_kv),
+                  stage, nbuckets(t));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  hipError_t e = hipMemcpyAsync(t->d_buckets, h_buckets, bucket_bytes(t), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(t->d_kv, h_kv, kv_bytes(t), hipMemcpyHostToDevice, s);
+  hipError_t e = hipMemcpyAsync(t->d_table, stage, table_bytes(t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  delete[] stage;
   return dev_status(e);
 }
 
@@ -220,8 +286,10 @@ int ckpp_stats(const ckpp_table *t, ckpp_stats_t *h_out, void *stream) {
   h_out->bloom_pc_sum = acc[2];
   h_out->bloom_pc2_sum = acc[3];
   h_out->locked = acc[4];
+  h_out->high_slots = acc[5];
+  h_out->high_slots_secondary = acc[6];
   h_out->retry_exhausted = acc[kAccRetry];
-  for (int i = 0; i < CKPP_MOVED_BINS; ++i) h_out->moved_hist[i] = acc[6 + i];
+  for (int i = 0; i < CKPP_MOVED_BINS; ++i) h_out->moved_hist[i] = acc[7 + i];
   return CKPP_OK;
 }
 
@@ -242,16 +310,16 @@ int ckpp_info(const ckpp_table *t, ckpp_info_t *out) {
   out->flags = t->flags;
   out->device = t->device;
   out->hash_seed = t->seed;
-  out->bucket_bytes = bucket_bytes(t);
-  out->kv_bytes = kv_bytes(t);
-  out->d_buckets = t->d_buckets;
-  out->d_kv = t->d_kv;
+  out->image_bucket_bytes = image_bucket_bytes(t);
+  out->image_kv_bytes = image_kv_bytes(t);
+  out->device_bytes = table_bytes(t);
+  out->d_table = t->d_table;
   return CKPP_OK;
 }
 
 int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg) {
   if (!t || !cfg) return CKPP_EINVAL;
-  if (cfg->lanes_per_lookup != 1 && cfg->lanes_per_lookup != 2) return CKPP_EINVAL;
+  if (cfg->lanes_per_lookup != 8) return CKPP_EINVAL;
   if (cfg->lookups_per_lane != 1 && cfg->lookups_per_lane != 2 && cfg->lookups_per_lane != 4)
     return CKPP_EINVAL;
   if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return CKPP_EINVAL;

@@ -8,17 +8,19 @@ namespace {
 
 // Accumulator layout (u64 words) shared with the host side:
 //   0 live, 1 in_secondary, 2 bloom_pc_sum, 3 bloom_pc2_sum, 4 locked,
-//   5 unused, 6 .. 6+CKPP_MOVED_BINS-1 moved histogram.
-constexpr uint32_t kHistBase = 6;
+//   5 busy slots 4..7, 6 secondary entries in slots 4..7,
+//   7 .. 7+CKPP_MOVED_BINS-1 moved histogram.
+constexpr uint32_t kHistBase = 7;
+constexpr uint32_t kSums = 7;
 
 __global__ void __launch_bounds__(256)
     stats_kernel(const uint4 *__restrict__ bk, uint64_t nbuckets, unsigned long long *acc) {
   __shared__ unsigned int hist[CKPP_MOVED_BINS];
-  __shared__ unsigned long long part[5];
+  __shared__ unsigned long long part[kSums];
   for (uint32_t i = threadIdx.x; i < CKPP_MOVED_BINS; i += blockDim.x) hist[i] = 0u;
-  if (threadIdx.x < 5) part[threadIdx.x] = 0ull;
+  if (threadIdx.x < kSums) part[threadIdx.x] = 0ull;
   __syncthreads();
-  unsigned long long live = 0, insec = 0, pc = 0, pc2 = 0, locked = 0;
+  unsigned long long live = 0, insec = 0, pc = 0, pc2 = 0, locked = 0, hi = 0, hisec = 0;
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nbuckets;
        b += (uint64_t)gridDim.x * blockDim.x) {
     const uint4 q1 = bk[b * kQuartersPerBucket + 1];
@@ -30,6 +32,8 @@ __global__ void __launch_bounds__(256)
     pc += c;
     pc2 += c * c;
     locked += q1.w != 0u ? 1ull : 0ull;
+    hi += (unsigned long long)__builtin_popcount(meta_busy(meta) & 0xf0u);
+    hisec += (unsigned long long)__builtin_popcount(meta_sec(meta) & 0xf0u);
     const uint32_t m = meta_moved(meta);
     atomicAdd(&hist[m < CKPP_MOVED_BINS - 1 ? m : CKPP_MOVED_BINS - 1], 1u);
   }
@@ -38,8 +42,10 @@ __global__ void __launch_bounds__(256)
   atomicAdd(&part[2], pc);
   atomicAdd(&part[3], pc2);
   atomicAdd(&part[4], locked);
+  atomicAdd(&part[5], hi);
+  atomicAdd(&part[6], hisec);
   __syncthreads();
-  if (threadIdx.x < 5) atomicAdd(&acc[threadIdx.x], part[threadIdx.x]);
+  if (threadIdx.x < kSums) atomicAdd(&acc[threadIdx.x], part[threadIdx.x]);
   for (uint32_t i = threadIdx.x; i < CKPP_MOVED_BINS; i += blockDim.x)
     if (hist[i]) atomicAdd(&acc[kHistBase + i], (unsigned long long)hist[i]);
 }
@@ -130,7 +136,7 @@ hipError_t launch_stats(const ckpp_table *t, uint64_t *d_acc, hipStream_t s) {
   const uint64_t cap = (uint64_t)t->num_cus * 8;
   if (grid > cap) grid = cap;
   hipLaunchKernelGGL(stats_kernel, dim3((uint32_t)grid), dim3(256), 0, s,
-                     reinterpret_cast<const uint4 *>(t->d_buckets), nb,
+                     reinterpret_cast<const uint4 *>(t->d_table), nb,
                      reinterpret_cast<unsigned long long *>(d_acc));
   return hipGetLastError();
 }

@@ -1,17 +1,22 @@
 // ckpp_device.h -- device-side view of a Cuckoo++ table (gfx950).
 //
-// Bucket: one 64-byte line (Sec. 4.3), read by the kernels as four 16-byte
-// quarters:
-//   q0  tags of slots 0..7, u16 each (slot 2i in the low half of word i)
-//   q1  .x,.y bloom filter (u64, Sec. 4.1)
-//       .z    moved counter (bits 0..15) | busy mask (16..23) | sec mask (24..31)
-//       .w    lock word (zero outside a running insert or delete batch)
-//   q2  other bucket of slots 0..3 (u32 each)
-//   q3  other bucket of slots 4..7
-// A lookup needs q0 and q1 only (the first 32 bytes); q2, q3 serve the
-// cuckoo-path search of inserts, which then reads no keys (Sec. 4.3).
-// Key/value record of slot s of bucket b: 32 bytes at index 8*b+s of the
-// record array (implicit index, Sec. 4.3): key (16) | value (8) | zero (8).
+// Device layout: bucket b owns 256 bytes (two 128-byte L2 lines) at byte
+// 256*b of one array.  A random 128-byte read costs one memory request, the
+// same as a 64-byte one, so a bucket's metadata (Sec. 4.3) shares its first
+// line with the keys and values of slots 0..3; the implicit index of the
+// paper (record position derived from bucket and slot, Sec. 4.3) is kept.
+//   line 0:   0..15  tag[8]   u16, slot s at bytes 2s
+//            16..23  bloom    u64  (Sec. 4.1)
+//            24..27  meta     moved u16 | busy u8 << 16 | sec u8 << 24
+//            28..31  lock     u32  (zero outside a running insert/delete)
+//            32..95  key[0..3]   16 bytes each
+//            96..127 value[0..3]  8 bytes each
+//   line 1: 128..191 key[4..7]
+//           192..223 value[4..7]
+//           224..255 other[0..7] u32: the entry's other bucket, so a cuckoo
+//                    path is searched without reading keys (Sec. 4.3)
+// Viewed as uint4 quarters: 16 per bucket; quarter r of line 0 is read by
+// lane r of an 8-lane lookup group.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,11 +25,19 @@
 namespace ckpp {
 
 constexpr uint32_t kSlots = 8;
-constexpr uint32_t kQuartersPerBucket = 4;  // 64-byte bucket = 4 x uint4
-constexpr uint32_t kQuartersPerRecord = 2;  // 32-byte record = 2 x uint4
-constexpr uint32_t kMetaOffset = 24;        // byte offset of the meta word
-constexpr uint32_t kLockOffset = 28;        // byte offset of the lock word
-constexpr uint32_t kOtherOffset = 32;       // byte offset of other[0]
+constexpr uint32_t kBucketBytes = 256;
+constexpr uint32_t kQuartersPerBucket = 16;  // 256-byte bucket = 16 x uint4
+constexpr uint32_t kMetaOffset = 24;         // byte offset of the meta word
+constexpr uint32_t kLockOffset = 28;         // byte offset of the lock word
+constexpr uint32_t kOtherOffset = 224;       // byte offset of other[0]
+
+// Byte offsets of the key and value of slot s within a bucket.
+__device__ __forceinline__ uint32_t key_offset(uint32_t s) {
+  return s < 4u ? 32u + 16u * s : 128u + 16u * (s - 4u);
+}
+__device__ __forceinline__ uint32_t value_offset(uint32_t s) {
+  return s < 4u ? 96u + 8u * s : 192u + 8u * (s - 4u);
+}
 
 // SplitMix64 output finalizer (Steele, Lea, Flood, OOPSLA 2014).
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {

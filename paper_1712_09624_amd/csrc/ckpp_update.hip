@@ -42,8 +42,15 @@ constexpr uint32_t kSpinLimit = 1u << 20;  // loop iterations per key
 constexpr uint32_t kMaxWalks = 64;         // path searches per key
 constexpr uint32_t kNoBucket = 0xffffffffu;
 
+__device__ __forceinline__ uint8_t *bucket_ptr(uint8_t *bk, uint32_t b) {
+  return bk + (uint64_t)b * kBucketBytes;
+}
+__device__ __forceinline__ const uint8_t *bucket_ptr(const uint8_t *bk, uint32_t b) {
+  return bk + (uint64_t)b * kBucketBytes;
+}
+
 __device__ __forceinline__ uint32_t *lock_word(uint8_t *bk, uint32_t b) {
-  return reinterpret_cast<uint32_t *>(bk + (uint64_t)b * 64 + kLockOffset);
+  return reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kLockOffset);
 }
 
 __device__ __forceinline__ bool try_lock(uint8_t *bk, uint32_t b) {
@@ -83,7 +90,7 @@ struct Head {
 };
 
 __device__ __forceinline__ Head read_head(const uint8_t *bk, uint32_t b) {
-  const uint4 *q = reinterpret_cast<const uint4 *>(bk + (uint64_t)b * 64);
+  const uint4 *q = reinterpret_cast<const uint4 *>(bucket_ptr(bk, b));
   Head h;
   h.q0 = q[0];
   h.q1 = q[1];
@@ -91,39 +98,40 @@ __device__ __forceinline__ Head read_head(const uint8_t *bk, uint32_t b) {
 }
 
 __device__ __forceinline__ uint32_t *meta_ptr(uint8_t *bk, uint32_t b) {
-  return reinterpret_cast<uint32_t *>(bk + (uint64_t)b * 64 + kMetaOffset);
+  return reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kMetaOffset);
 }
 __device__ __forceinline__ uint64_t *bloom_ptr(uint8_t *bk, uint32_t b) {
-  return reinterpret_cast<uint64_t *>(bk + (uint64_t)b * 64 + 16);
+  return reinterpret_cast<uint64_t *>(bucket_ptr(bk, b) + 16);
 }
 __device__ __forceinline__ uint16_t *tag_ptr(uint8_t *bk, uint32_t b) {
-  return reinterpret_cast<uint16_t *>(bk + (uint64_t)b * 64);
+  return reinterpret_cast<uint16_t *>(bucket_ptr(bk, b));
 }
 __device__ __forceinline__ uint32_t *other_ptr(uint8_t *bk, uint32_t b) {
-  return reinterpret_cast<uint32_t *>(bk + (uint64_t)b * 64 + kOtherOffset);
+  return reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kOtherOffset);
 }
-__device__ __forceinline__ uint4 *record_ptr(uint8_t *kv, uint32_t b, uint32_t s) {
-  return reinterpret_cast<uint4 *>(kv + ((uint64_t)b * kSlots + s) * 32);
+__device__ __forceinline__ uint4 *key_ptr(uint8_t *bk, uint32_t b, uint32_t s) {
+  return reinterpret_cast<uint4 *>(bucket_ptr(bk, b) + key_offset(s));
+}
+__device__ __forceinline__ uint64_t *value_ptr(uint8_t *bk, uint32_t b, uint32_t s) {
+  return reinterpret_cast<uint64_t *>(bucket_ptr(bk, b) + value_offset(s));
 }
 
 // Slot of `key` in a bucket whose head is h (bucket locked), or -1.
-__device__ __forceinline__ int find_slot(uint8_t *kv, uint32_t b, const Head &h, uint4 key,
+__device__ __forceinline__ int find_slot(uint8_t *bk, uint32_t b, const Head &h, uint4 key,
                                          uint32_t tag) {
   uint32_t cand = tag_eq_mask(h.q0, tag) & meta_busy(h.q1.z);
   while (cand) {
     const uint32_t s = (uint32_t)__builtin_ctz(cand);
     cand &= cand - 1u;
-    if (key_eq(record_ptr(kv, b, s)[0], key)) return (int)s;
+    if (key_eq(*key_ptr(bk, b, s), key)) return (int)s;
   }
   return -1;
 }
 
-__device__ __forceinline__ void write_entry(uint8_t *bk, uint8_t *kv, uint32_t b, uint32_t s,
-                                            uint4 key, uint64_t value, uint32_t tag,
-                                            uint32_t other) {
-  uint4 *r = record_ptr(kv, b, s);
-  r[0] = key;
-  r[1] = make_uint4((uint32_t)value, (uint32_t)(value >> 32), 0u, 0u);
+__device__ __forceinline__ void write_entry(uint8_t *bk, uint32_t b, uint32_t s, uint4 key,
+                                            uint64_t value, uint32_t tag, uint32_t other) {
+  *key_ptr(bk, b, s) = key;
+  *value_ptr(bk, b, s) = value;
   tag_ptr(bk, b)[s] = (uint16_t)tag;
   other_ptr(bk, b)[s] = other;
 }
@@ -131,33 +139,32 @@ __device__ __forceinline__ void write_entry(uint8_t *bk, uint8_t *kv, uint32_t b
 constexpr int kBusy = -2;    // a lock was taken by another lane: retry
 constexpr int kNeedPath = -1;
 
-__device__ int insert_direct(uint8_t *bk, uint8_t *kv, uint4 key, uint64_t value,
+__device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value,
                              const KeyFields &f, bool plain) {
   if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   const Head ha = read_head(bk, f.a);
   int r;
-  int s = find_slot(kv, f.p, hp, key, f.tag);
+  int s = find_slot(bk, f.p, hp, key, f.tag);
   uint32_t b = f.p;
   if (s < 0 && (plain || bloom_pass(hp.q1, f.bloom_bits))) {
-    s = find_slot(kv, f.a, ha, key, f.tag);
+    s = find_slot(bk, f.a, ha, key, f.tag);
     b = f.a;
   }
   if (s >= 0) {
-    uint4 *rec = record_ptr(kv, b, (uint32_t)s);
-    rec[1] = make_uint4((uint32_t)value, (uint32_t)(value >> 32), 0u, 0u);
+    *value_ptr(bk, b, (uint32_t)s) = value;
     r = CKPP_UPDATED;
   } else {
     const uint32_t mp = hp.q1.z, ma = ha.q1.z;
     const uint32_t busy_p = meta_busy(mp), busy_a = meta_busy(ma);
     if (busy_p != 0xffu) {
       const uint32_t fs = (uint32_t)__builtin_ctz(~busy_p & 0xffu);
-      write_entry(bk, kv, f.p, fs, key, value, f.tag, f.a);
+      write_entry(bk, f.p, fs, key, value, f.tag, f.a);
       *meta_ptr(bk, f.p) = make_meta(meta_moved(mp), busy_p | (1u << fs), meta_sec(mp) & ~(1u << fs));
       r = CKPP_INSERTED;
     } else if (busy_a != 0xffu && (plain || meta_moved(mp) < 0xffffu)) {
       const uint32_t fs = (uint32_t)__builtin_ctz(~busy_a & 0xffu);
-      write_entry(bk, kv, f.a, fs, key, value, f.tag, f.p);
+      write_entry(bk, f.a, fs, key, value, f.tag, f.p);
       *meta_ptr(bk, f.a) = make_meta(meta_moved(ma), busy_a | (1u << fs), meta_sec(ma) | (1u << fs));
       if (!plain) {
         *bloom_ptr(bk, f.p) |= f.bloom_bits;
@@ -190,7 +197,7 @@ __device__ int walk(const uint8_t *bk, uint32_t start, uint64_t rbase, uint32_t 
                     bool plain, uint32_t *path, uint32_t *last) {
   uint32_t cur = start, prev = kNoBucket;
   for (uint32_t step = 0; step < max_kicks; ++step) {
-    const uint8_t *base = bk + (uint64_t)cur * 64;
+    const uint8_t *base = bucket_ptr(bk, cur);
     const uint32_t meta = (uint32_t)load_relaxed(base + kMetaOffset);
     uint32_t other[kSlots];
 #pragma unroll
@@ -218,7 +225,7 @@ __device__ int walk(const uint8_t *bk, uint32_t start, uint64_t rbase, uint32_t 
     const uint32_t v = nth_bit(pick, (uint32_t)(r % (uint64_t)__builtin_popcount(pick)));
     path[step] = cur | (v << 24);
     const uint32_t nxt = other[v];
-    const uint32_t nmeta = (uint32_t)load_relaxed(bk + (uint64_t)nxt * 64 + kMetaOffset);
+    const uint32_t nmeta = (uint32_t)load_relaxed(bucket_ptr(bk, nxt) + kMetaOffset);
     if (meta_busy(nmeta) != 0xffu) {
       *last = nxt;
       return (int)step + 1;
@@ -232,26 +239,21 @@ __device__ int walk(const uint8_t *bk, uint32_t start, uint64_t rbase, uint32_t 
 // Moves the entry of slot s of bucket x to a free slot of bucket y, its
 // other bucket.  Returns 1 when done, 0 when the state no longer matches
 // the path, kBusy when a lock was taken.
-__device__ int move_entry(uint8_t *bk, uint8_t *kv, uint32_t x, uint32_t s, uint32_t y,
+__device__ int move_entry(uint8_t *bk, uint32_t x, uint32_t s, uint32_t y,
                           uint32_t log2b, uint64_t seed, bool plain) {
   if (x == y || !lock_two(bk, x, y)) return kBusy;
   int r = 0;
   const uint32_t mx = *meta_ptr(bk, x), my = *meta_ptr(bk, y);
   const uint32_t busy_x = meta_busy(mx), busy_y = meta_busy(my);
   if (((busy_x >> s) & 1u) && other_ptr(bk, x)[s] == y && busy_y != 0xffu) {
-    const uint4 *src = record_ptr(kv, x, s);
-    const uint4 key = src[0];
-    const uint4 val = src[1];
+    const uint4 key = *key_ptr(bk, x, s);
+    const uint64_t val = *value_ptr(bk, x, s);
     const KeyFields fe = key_fields(key_hash(key, seed), log2b);
     const bool from_primary = fe.p == x;
     const bool consistent = from_primary ? (fe.a == y) : (fe.a == x && fe.p == y);
     if (consistent && (plain || !from_primary || meta_moved(mx) < 0xffffu)) {
       const uint32_t fs = (uint32_t)__builtin_ctz(~busy_y & 0xffu);
-      uint4 *dst = record_ptr(kv, y, fs);
-      dst[0] = key;
-      dst[1] = make_uint4(val.x, val.y, 0u, 0u);
-      tag_ptr(bk, y)[fs] = tag_ptr(bk, x)[s];
-      other_ptr(bk, y)[fs] = x;
+      write_entry(bk, y, fs, key, val, tag_ptr(bk, x)[s], x);
       uint32_t moved_x = meta_moved(mx), moved_y = meta_moved(my);
       const uint32_t sec_y =
           from_primary ? (meta_sec(my) | (1u << fs)) : (meta_sec(my) & ~(1u << fs));
@@ -274,7 +276,7 @@ __device__ int move_entry(uint8_t *bk, uint8_t *kv, uint32_t x, uint32_t s, uint
 }
 
 __global__ void __launch_bounds__(256)
-    insert_kernel(uint8_t *bk, uint8_t *kv, const uint4 *__restrict__ keys,
+    insert_kernel(uint8_t *bk, const uint4 *__restrict__ keys,
                   const uint64_t *__restrict__ vals, uint64_t n, uint32_t log2b, uint64_t seed,
                   uint32_t max_kicks, uint32_t plain_flag, uint32_t *paths,
                   uint8_t *__restrict__ status, unsigned long long *nfailed,
@@ -299,7 +301,7 @@ __global__ void __launch_bounds__(256)
         break;
       }
       if (state == DIRECT) {
-        const int r = insert_direct(bk, kv, key, value, f, plain);
+        const int r = insert_direct(bk, key, value, f, plain);
         if (r >= 0)
           result = r;
         else if (r == kNeedPath)
@@ -323,7 +325,7 @@ __global__ void __launch_bounds__(256)
         const uint32_t e = path[next - 1];
         const uint32_t x = e & 0xffffffu, s = e >> 24;
         const uint32_t y = (next == len) ? last : (path[next] & 0xffffffu);
-        const int r = move_entry(bk, kv, x, s, y, log2b, seed, plain);
+        const int r = move_entry(bk, x, s, y, log2b, seed, plain);
         if (r == 1) {
           if (--next == 0) state = DIRECT;
         } else if (r == 0) {
@@ -338,11 +340,11 @@ __global__ void __launch_bounds__(256)
 }
 
 // Returns 1 if the key was removed, 0 if absent, kBusy to retry.
-__device__ int delete_direct(uint8_t *bk, uint8_t *kv, uint4 key, const KeyFields &f, bool plain) {
+__device__ int delete_direct(uint8_t *bk, uint4 key, const KeyFields &f, bool plain) {
   if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   int r = 0;
-  int s = find_slot(kv, f.p, hp, key, f.tag);
+  int s = find_slot(bk, f.p, hp, key, f.tag);
   const uint32_t mp = hp.q1.z;
   if (s >= 0) {
     const uint32_t bit = 1u << s;
@@ -350,7 +352,7 @@ __device__ int delete_direct(uint8_t *bk, uint8_t *kv, uint4 key, const KeyField
     r = 1;
   } else if (plain || bloom_pass(hp.q1, f.bloom_bits)) {
     const Head ha = read_head(bk, f.a);
-    s = find_slot(kv, f.a, ha, key, f.tag);
+    s = find_slot(bk, f.a, ha, key, f.tag);
     if (s >= 0) {
       const uint32_t bit = 1u << s, ma = ha.q1.z;
       *meta_ptr(bk, f.a) = make_meta(meta_moved(ma), meta_busy(ma) & ~bit, meta_sec(ma) & ~bit);
@@ -367,7 +369,7 @@ __device__ int delete_direct(uint8_t *bk, uint8_t *kv, uint4 key, const KeyField
 }
 
 __global__ void __launch_bounds__(256)
-    delete_kernel(uint8_t *bk, uint8_t *kv, const uint4 *__restrict__ keys, uint64_t n,
+    delete_kernel(uint8_t *bk, const uint4 *__restrict__ keys, uint64_t n,
                   uint32_t log2b, uint64_t seed, uint32_t plain_flag,
                   uint8_t *__restrict__ found, unsigned long long *nspin) {
   const bool plain = plain_flag != 0u;
@@ -380,7 +382,7 @@ __global__ void __launch_bounds__(256)
     uint32_t iters = 0;
     while (r == kBusy && iters < kSpinLimit) {
       ++iters;
-      r = delete_direct(bk, kv, key, f, plain);
+      r = delete_direct(bk, key, f, plain);
     }
     if (r == kBusy) {
       r = 0;
@@ -398,7 +400,7 @@ hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t
   const uint32_t block = 256;
   const uint32_t grid = (uint32_t)((lanes + block - 1) / block);
   unsigned long long *nspin = reinterpret_cast<unsigned long long *>(t->d_stats) + 127;
-  hipLaunchKernelGGL(insert_kernel, dim3(grid), dim3(block), 0, s, t->d_buckets, t->d_kv,
+  hipLaunchKernelGGL(insert_kernel, dim3(grid), dim3(block), 0, s, t->d_table,
                      reinterpret_cast<const uint4 *>(d_keys), d_values, n, t->log2_buckets,
                      t->seed, t->max_kicks, (t->flags & CKPP_PLAIN) ? 1u : 0u, t->d_paths,
                      d_status, reinterpret_cast<unsigned long long *>(d_nfailed), nspin);
@@ -411,7 +413,7 @@ hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n, ui
   const uint32_t block = 256;
   const uint32_t grid = (uint32_t)((lanes + block - 1) / block);
   unsigned long long *nspin = reinterpret_cast<unsigned long long *>(t->d_stats) + 127;
-  hipLaunchKernelGGL(delete_kernel, dim3(grid), dim3(block), 0, s, t->d_buckets, t->d_kv,
+  hipLaunchKernelGGL(delete_kernel, dim3(grid), dim3(block), 0, s, t->d_table,
                      reinterpret_cast<const uint4 *>(d_keys), n, t->log2_buckets, t->seed,
                      (t->flags & CKPP_PLAIN) ? 1u : 0u, d_found, nspin);
   return hipGetLastError();
