@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
+                    help="write profiles/ summaries from rocprofv3 CSV output under DIR")
     ap.add_argument("--tune", action="store_true",
                     help="time every lookup launch shape, print them, keep the fastest")
     ap.add_argument("--lanes", type=int, default=None)
@@ -258,8 +260,108 @@ def copy_calibration(dev):
     print(json.dumps({"copy_calibration_bytes": 1 << 30, "dispatches": 5}))
 
 
+PROFILE_CMDS = {
+    "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d DIR/p4_trace -o core -- "
+             "python3 bench.py --core-only --steps 5 --warmup 2",
+    "fetch": "rocprofv3 --pmc FETCH_SIZE --output-format csv -d DIR/p4_fetch -o core -- "
+             "python3 bench.py --core-only --steps 5 --warmup 2",
+    "write": "rocprofv3 --pmc WRITE_SIZE --output-format csv -d DIR/p4_write -o core -- "
+             "python3 bench.py --core-only --steps 5 --warmup 2",
+    "req": "rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum "
+           "TCC_EA0_RDREQ_128B_sum --output-format csv -d DIR/p4_req -o core -- "
+           "python3 bench.py --core-only --steps 5 --warmup 2",
+    "copy": "the same three --pmc runs with -d DIR/p4_copy_{fetch,write,req} -o copy -- "
+            "python3 bench.py --copy-calib",
+}
+
+
+def _pmc(path, kernel_part):
+    import csv
+    per = {}
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if kernel_part in r["Kernel_Name"]:
+                per.setdefault(int(r["Dispatch_Id"]), {})[r["Counter_Name"]] = float(r["Counter_Value"])
+    return [per[k] for k in sorted(per)]
+
+
+def summarize_profiles(d):
+    """Writes profiles/ summaries from the rocprofv3 CSV output of the
+    commands in PROFILE_CMDS (run from the repository root with DIR = d)."""
+    import csv
+    prof = os.path.join(ROOT, "profiles")
+    # kernel trace
+    rows = list(csv.DictReader(open(os.path.join(d, "p4_trace", "core_kernel_stats.csv"))))
+    out = ["# rocprofv3 kernel-trace summary: Cuckoo++ step on a 2^24-bucket table at load 0.9",
+           "# (bench.py --core-only: table build in 4M-key insert batches, then per step",
+           "#  insert 65536 + lookup 2^26 positive + lookup 2^26 negative + delete 65536)",
+           "# device layout: 256-byte buckets, two 128-byte lines; lookup kernel lookup_lds",
+           "# command (repository root, TMPDIR=/tmp): " + PROFILE_CMDS["trace"].replace("DIR", d),
+           f"{'kernel':<40} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
+    for r in rows:
+        name = r["Name"].replace("void ", "", 1).replace("ckpp::(anonymous namespace)::", "")
+        depth, cut = 0, len(name)
+        for i, ch in enumerate(name):
+            if ch == "<":
+                depth += 1
+            elif ch == ">":
+                depth -= 1
+            elif ch == "(" and depth == 0 and i > 0 and name[i - 1] != " ":
+                cut = i
+                break
+        out.append(f"{name[:cut][:40]:<40} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
+                   f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} "
+                   f"{float(r['Percentage']):>6.2f}")
+    out.append("# lookup_lds launches alternate positive (the longer) and negative batches;")
+    out.append("# their average is the avg_launch_ms bench.py reports in roofline.")
+    with open(os.path.join(prof, "lookup_lds_b24_load0.9_kernel_trace.txt"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    # traffic
+    lk = {k: _pmc(os.path.join(d, f"p4_{k}", "core_counter_collection.csv"), "lookup_lds")
+          for k in ("fetch", "write", "req")}
+    cp = {k: _pmc(os.path.join(d, f"p4_copy_{k}", "copy_counter_collection.csv"), "copyBuffer")
+          for k in ("fetch", "write", "req")}
+    copy_bytes = 1 << 30
+    f_fetch = copy_bytes / (cp["fetch"][0]["FETCH_SIZE"] * 1024)
+    f_write = copy_bytes / (cp["write"][0]["WRITE_SIZE"] * 1024)
+    def exact(v):
+        return (v["TCC_EA0_RDREQ_32B_sum"] * 32 + v["TCC_EA0_RDREQ_64B_sum"] * 64 +
+                v["TCC_EA0_RDREQ_128B_sum"] * 128)
+    f_req = copy_bytes / exact(cp["req"][0])
+    fetch = [v["FETCH_SIZE"] * 1024 * f_fetch for v in lk["fetch"]]
+    write = [v["WRITE_SIZE"] * 1024 * f_write for v in lk["write"]]
+    reqb = [exact(v) * f_req for v in lk["req"]]
+    nreq = [v["TCC_EA0_RDREQ_sum"] for v in lk["req"]]
+    per_launch = (sum(fetch) + sum(write)) / len(fetch)
+    lines = ["# HBM traffic of the Cuckoo++ lookup kernel (lookup_lds), 2^24 buckets at load 0.9,",
+             "# 2^26 lookups per launch, launches alternating positive / negative batches",
+             "# commands (repository root, TMPDIR=/tmp, one counter group per run):"]
+    for k in ("fetch", "write", "req", "copy"):
+        lines.append("#   " + PROFILE_CMDS[k].replace("DIR", d))
+    lines += [f"# calibration on a 1 GiB device copy: FETCH_SIZE x {f_fetch:.4f}, WRITE_SIZE x {f_write:.4f},",
+              f"#   request-size bytes (32*RDREQ_32B + 64*RDREQ_64B + 128*RDREQ_128B) x {f_req:.4f}",
+              f"{'dispatch':>8} {'fetch_GB':>10} {'write_GB':>10} {'reqsize_GB':>11} {'rd_requests':>13}"]
+    for i in range(len(fetch)):
+        lines.append(f"{i:>8} {fetch[i] / 1e9:>10.3f} {write[i] / 1e9:>10.3f} {reqb[i] / 1e9:>11.3f} "
+                     f"{nreq[i]:>13.0f}")
+    lines.append(f"# mean HBM bytes per launch (calibrated fetch + write): {per_launch / 1e9:.3f} GB")
+    with open(os.path.join(prof, "lookup_lds_b24_load0.9_hbm_traffic.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    with open(os.path.join(prof, "lookup_traffic.json"), "w") as fh:
+        json.dump({"source_digest": lookup_source_digest(),
+                   "launch": {"lanes_per_lookup": 8, "lookups_per_lane": 1, "block": 128,
+                              "blocks_per_cu": 0},
+                   "hbm_bytes_per_launch": per_launch,
+                   "fetch_factor": f_fetch, "write_factor": f_write,
+                   "dispatches": len(fetch)}, fh, indent=1)
+    print("\n".join(out + lines))
+
+
 def main():
     args = parse()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the table is "
                                    "sharded one-per-GPU by design but no multi-GPU path is "
@@ -366,7 +468,7 @@ def main():
     achieved = (bytes_pos + bytes_neg) / ((ms["pos"] + ms["neg"]) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": f"lookup_group8<K={launch['lookups_per_lane']}, Cuckoo++>",
+                "kernel": f"lookup_lds<waves={launch['block'] // 64}, Cuckoo++>",
                 "algorithmic_bytes_per_launch": (bytes_pos + bytes_neg) / 2,
                 "avg_launch_ms": (ms["pos"] + ms["neg"]) / 2}
     tf = os.path.join(ROOT, "profiles", "lookup_traffic.json")

@@ -194,13 +194,14 @@ typedef struct {
 
 int ckpp_info(const ckpp_table *t, ckpp_info_t *out);
 
-/* Launch shape of the lookup kernel.  lanes_per_lookup: 8 (a group of 8
- * neighbouring lanes reads a bucket's 128-byte first line in one request,
- * 16 bytes per lane, and combines the verdicts across the group);
- * lookups_per_lane: 1, 2 or 4 lookups kept in flight by each group; block:
- * 64, 128 or 256; blocks_per_cu: grid size in blocks per compute unit (0:
- * enough blocks to cover the batch in one pass).  Applies to every later
- * lookup on t. */
+/* Launch shape of the lookup kernel.  Each lane owns one lookup; the line
+ * of a bucket is read by a group of lanes_per_lookup = 8 neighbouring lanes
+ * (16 bytes each, one 128-byte request) straight into LDS, and each lane
+ * then analyses its own line there.  lookups_per_lane: 1; block: 64, 128 or
+ * 256 (1, 2 or 4 wavefronts, 8 KiB of LDS each, 16 KiB for the pessimistic
+ * mode); blocks_per_cu: grid size in blocks per compute unit (0: enough
+ * blocks to cover the batch in one pass).  Applies to every later lookup
+ * on t. */
 typedef struct {
     uint32_t lanes_per_lookup;
     uint32_t lookups_per_lane;

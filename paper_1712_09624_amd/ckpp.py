@@ -288,7 +288,7 @@ class Table:
         _check(self.lib.ckpp_info(self._h, ctypes.byref(inf)), "ckpp_info")
         return {f: getattr(inf, f) for f, _ in _Info._fields_}
 
-    def set_lookup_launch(self, lanes_per_lookup=8, lookups_per_lane=2, block=256,
+    def set_lookup_launch(self, lanes_per_lookup=8, lookups_per_lane=1, block=256,
                           blocks_per_cu=0):
         cfg = _Launch(lanes_per_lookup, lookups_per_lane, block, blocks_per_cu)
         _check(self.lib.ckpp_set_lookup_launch(self._h, ctypes.byref(cfg)),

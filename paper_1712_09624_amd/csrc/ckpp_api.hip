@@ -139,8 +139,8 @@ int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uin
   t->device = device;
   t->seed = hash_seed;
   t->lookup_launch.lanes_per_lookup = 8;
-  t->lookup_launch.lookups_per_lane = 2;
-  t->lookup_launch.block = 256;
+  t->lookup_launch.lookups_per_lane = 1;
+  t->lookup_launch.block = 128;
   t->lookup_launch.blocks_per_cu = 0;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
@@ -320,8 +320,7 @@ int ckpp_info(const ckpp_table *t, ckpp_info_t *out) {
 int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg) {
   if (!t || !cfg) return CKPP_EINVAL;
   if (cfg->lanes_per_lookup != 8) return CKPP_EINVAL;
-  if (cfg->lookups_per_lane != 1 && cfg->lookups_per_lane != 2 && cfg->lookups_per_lane != 4)
-    return CKPP_EINVAL;
+  if (cfg->lookups_per_lane != 1) return CKPP_EINVAL;
   if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return CKPP_EINVAL;
   if (cfg->blocks_per_cu > 4096) return CKPP_EINVAL;
   t->lookup_launch = *cfg;

@@ -3,22 +3,28 @@
 // One lookup (Sec. 2 lookup procedure, Sec. 4.1 pruning):
 //   hash the key -> primary bucket p, alternate a, tag, two bloom bits;
 //   read p; a slot holds the key iff it is busy and its full 16-byte key
-//   equals the searched key (its tag is only a hint that selects which
-//   record to fetch); if not found, Cuckoo++ reads a only when both bloom
-//   bits are set in p's filter, the pessimistic mode reads a together with
-//   p, the optimistic mode reads a whenever the key was not in p;
+//   equals the searched key (its tag is only a hint that selects which keys
+//   to compare); if not found, Cuckoo++ reads a only when both bloom bits
+//   are set in p's filter, the pessimistic mode reads a together with p, the
+//   optimistic mode reads a whenever the key was not in p;
 //   write found (u8) and the value (u64, 0 on a miss).
 //
-// GPU form: a group of 8 neighbouring lanes owns a lookup.  Lane r of the
-// group reads 16-byte quarter r of the bucket's first 128-byte line, so the
-// whole line -- tags, filter, masks, and the keys and values of slots 0..3
-// -- arrives in ONE memory request (a random 128-byte read costs the same
-// request as a 64-byte one on MI355X).  The group combines per-lane verdicts
-// with three cross-lane exchanges: lane 0 the tag matches, lane 1 the busy
-// mask and the filter verdict, lanes 2..5 the full-key equality of slots
-// 0..3.  Only if a busy slot 4..7 carries the key's tag is the second line
-// (keys and values of slots 4..7) read.  Each group keeps K lookups in
-// flight; keys stream in and results stream out with non-temporal accesses.
+// GPU form.  On MI355X every random read that misses the L2 costs one
+// 128-byte line request, a later second access to the same line costs
+// another, and the request rate -- not the byte rate -- bounds random reads.
+// So a bucket line is read exactly once, in one instruction, by 8 lanes (16
+// bytes each), straight into LDS (global_load_lds_dwordx4: the data in
+// flight occupies no registers, so a wave keeps 64 line requests in flight
+// at once).  Each lane owns one lookup: it hashes its key once, hands its
+// bucket index to the fetching group (ds_bpermute), and after the lines
+// have landed it analyses its own line from LDS: tags and busy mask, then
+// the full keys of the candidate slots and the value.  The first line of a
+// bucket holds the metadata and slots 0..3, so most lookups need one
+// request; the second line (slots 4..7) and the secondary bucket are
+// fetched, in the same cooperative way, only for the lookups of the wave
+// that need them, and skipped when none does.  Keys for the next tile are
+// loaded while the current tile is processed; keys stream in and results
+// stream out with non-temporal accesses.
 
 #include "ckpp_device.h"
 #include "ckpp_internal.h"
@@ -26,181 +32,149 @@
 namespace ckpp {
 namespace {
 
-// Group word of a bucket's first line:
-//   bits 0..7   tag equality of slots 0..7       (lane 0)
-//   bits 8..15  busy mask                        (lane 1)
-//   bit  16     both bloom bits set              (lane 1)
-//   bits 24..27 key equality of slots 0..3       (lanes 2..5)
-__device__ __forceinline__ uint32_t line0_word(uint32_t r, uint4 q, const KeyFields &f,
-                                               uint4 key) {
-  if (r == 0u) return tag_eq_mask(q, f.tag);
-  if (r == 1u) return (meta_busy(q.z) << 8) | (bloom_pass(q, f.bloom_bits) ? 0x10000u : 0u);
-  if (r < 6u) return key_eq(q, key) ? (1u << (22u + r)) : 0u;
-  return 0u;
+constexpr uint32_t kNoFetch = 0xffffffffu;  // bucket indices are < 2^24
+
+// Lines of one wave: 64 lines x 8 quarters; lookup j's line at [8j, 8j+8).
+constexpr uint32_t kWaveQuarters = 64 * 8;
+
+// Cooperative fetch of one 128-byte line (half `half` of the bucket) for
+// every lookup of the wave whose `bucket` is not kNoFetch: in round k the
+// lanes 8g..8g+7 read the line of lookup 8k+g, lane r its quarter r, and
+// the line lands at lines[8(8k+g) .. 8(8k+g)+8).
+__device__ __forceinline__ void fetch_lines(uint4 *lines, const uint4 *tab, uint32_t bucket,
+                                            uint32_t half, uint32_t g, uint32_t r) {
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) {
+    const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
+    if (b != kNoFetch) {
+      const uint4 *src = tab + (uint64_t)b * kQuartersPerBucket + 8u * half + r;
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1))) *)src,
+          (void __attribute__((address_space(3))) *)(lines + 64u * k), 16, 0, 0);
+    }
+  }
 }
 
-// Group word of a bucket's second line: bits 4..7 key equality of slots
-// 4..7 (lanes 0..3).
-__device__ __forceinline__ uint32_t line1_word(uint32_t r, uint4 q, uint4 key) {
-  return (r < 4u && key_eq(q, key)) ? (1u << (4u + r)) : 0u;
+// Waits until the lines requested by this wave have landed in LDS (the
+// loads' counter drains once the data is written there); the compiler may
+// not move LDS reads above this point.
+__device__ __forceinline__ void lines_landed() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// OR of w over the 8 lanes of the group.
-__device__ __forceinline__ uint32_t group_or(uint32_t w) {
-  w |= (uint32_t)__shfl_xor((int)w, 1);
-  w |= (uint32_t)__shfl_xor((int)w, 2);
-  w |= (uint32_t)__shfl_xor((int)w, 4);
-  return w;
-}
-
-// The 64-bit value of slot s (slot parity selects the half) from the
-// quarter that holds it.
 __device__ __forceinline__ uint64_t quarter_value(uint4 q, uint32_t s) {
   return (s & 1u) ? ((uint64_t)q.z | ((uint64_t)q.w << 32))
                   : ((uint64_t)q.x | ((uint64_t)q.y << 32));
 }
 
-// Search state of one lookup, identical in the 8 lanes of its group except
-// `val`, which is meaningful in lane `owner` only.
-struct Probe {
-  bool hit;
-  uint32_t owner;
-  uint64_t val;
-};
-
-// Analyses the first line of a bucket (quarter q of this lane): a hit in
-// slots 0..3 resolves here; returns the group word (busy mask, tag
-// matches, filter verdict).
-__device__ __forceinline__ uint32_t analyse_line0(uint32_t r, uint4 q, const KeyFields &f,
-                                                  uint4 key, Probe &pr) {
-  const uint32_t w = group_or(line0_word(r, q, f, key));
-  const uint32_t m = (w >> 8) & (w >> 24) & 0xfu;  // busy and equal, slots 0..3
-  if (m) {
-    const uint32_t s = (uint32_t)__builtin_ctz(m);
-    pr.hit = true;
-    pr.owner = 6u + (s >> 1);
-    pr.val = quarter_value(q, s);
-  }
-  return w;
-}
-
-// After the second line of a bucket (quarter q) arrived: a hit in 4..7.
-__device__ __forceinline__ void analyse_line1(uint32_t r, uint4 q, uint32_t w0, uint4 key,
-                                              Probe &pr) {
-  const uint32_t w = group_or(line1_word(r, q, key));
-  const uint32_t m = (w0 >> 8) & w & 0xf0u;
-  if (m) {
-    const uint32_t s = (uint32_t)__builtin_ctz(m);
-    pr.hit = true;
-    pr.owner = 4u + ((s - 4u) >> 1);
-    pr.val = quarter_value(q, s);
+// Compares the key with the candidate slots `cand` (ascending) of a first
+// line (mine[0..7]); on a hit sets hit/val.
+__device__ __forceinline__ void match_line0(const uint4 *mine, uint32_t cand, uint4 key, bool &hit,
+                                            uint64_t &val) {
+  while (cand != 0u && !hit) {
+    const uint32_t s = (uint32_t)__builtin_ctz(cand);
+    cand &= cand - 1u;
+    if (key_eq(mine[2u + s], key)) {
+      hit = true;
+      val = quarter_value(mine[6u + (s >> 1)], s);
+    }
   }
 }
 
-// Whether the second line must be read: no hit yet and a busy slot 4..7
-// carries the key's tag.
-__device__ __forceinline__ bool needs_line1(uint32_t w0, const Probe &pr) {
-  return !pr.hit && (((w0 >> 8) & w0 & 0xf0u) != 0u);
+// Same for slots 4..7 on a second line (mine[0..7]).
+__device__ __forceinline__ void match_line1(const uint4 *mine, uint32_t cand, uint4 key, bool &hit,
+                                            uint64_t &val) {
+  while (cand != 0u && !hit) {
+    const uint32_t s = (uint32_t)__builtin_ctz(cand);
+    cand &= cand - 1u;
+    if (key_eq(mine[s - 4u], key)) {
+      hit = true;
+      val = quarter_value(mine[4u + ((s - 4u) >> 1)], s);
+    }
+  }
 }
 
-template <int K, uint32_t MODE>
-__global__ void __launch_bounds__(256)
-    lookup_group8(const uint4 *__restrict__ tab, const uint4 *__restrict__ keys, uint64_t n,
-                  uint32_t log2b, uint64_t seed, uint8_t *__restrict__ found,
-                  uint64_t *__restrict__ vals) {
-  const uint32_t r = threadIdx.x & 7u;
-  const uint32_t groups = blockDim.x >> 3;
-  const uint32_t gid = threadIdx.x >> 3;
-  const uint64_t tile_sz = (uint64_t)groups * K;
-  for (uint64_t tile = (uint64_t)blockIdx.x * tile_sz; tile < n;
-       tile += (uint64_t)gridDim.x * tile_sz) {
-    uint4 key[K];
-    bool ok[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const uint64_t i = tile + (uint64_t)j * groups + gid;
-      ok[j] = i < n;
-      key[j] = ok[j] ? load_stream(keys + i) : make_uint4(0u, 0u, 0u, 0u);
+template <uint32_t WAVES, uint32_t MODE>
+__global__ void __launch_bounds__(64 * WAVES)
+    lookup_lds(const uint4 *__restrict__ tab, const uint4 *__restrict__ keys, uint64_t n,
+               uint32_t log2b, uint64_t seed, uint8_t *__restrict__ found,
+               uint64_t *__restrict__ vals) {
+  constexpr uint32_t NB = MODE == kModeBoth ? 2 : 1;  // line buffers per wave
+  __shared__ uint4 s_lines[WAVES * NB * kWaveQuarters];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t g = lane >> 3, r = lane & 7u;
+  uint4 *lines = s_lines + (threadIdx.x >> 6) * NB * kWaveQuarters;
+  uint4 *lines_a = lines + (NB - 1) * kWaveQuarters;  // pessimistic: secondary lines
+  const uint4 *mine = lines + 8u * lane;
+  const uint4 *mine_a = lines_a + 8u * lane;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint4 key = i < n ? load_stream(keys + i) : make_uint4(0u, 0u, 0u, 0u);
+  // the wave stays together: its loop condition is the wave's first lookup
+  for (; i - lane < n; i += stride) {
+    const bool ok = i < n;
+    const uint64_t h = key_hash(key, seed);
+    const KeyFields f = key_fields(h, log2b);
+    // first line of the primary (and, pessimistic mode, the secondary)
+    fetch_lines(lines, tab, ok ? f.p : kNoFetch, 0u, g, r);
+    if (MODE == kModeBoth) fetch_lines(lines_a, tab, ok ? f.a : kNoFetch, 0u, g, r);
+    const uint64_t inext = i + stride;
+    const uint4 knext = inext < n ? load_stream(keys + inext) : make_uint4(0u, 0u, 0u, 0u);
+    lines_landed();
+    bool hit = false;
+    uint64_t val = 0;
+    const uint4 t0 = mine[0], t1 = mine[1];
+    const uint32_t cand = ok ? (tag_eq_mask(t0, f.tag) & meta_busy(t1.z)) : 0u;
+    const bool pass = MODE != kModeCuckoopp || bloom_pass(t1, f.bloom_bits);
+    match_line0(mine, cand & 0xfu, key, hit, val);
+    // second line of the primary, for keys whose tag sits in slots 4..7
+    bool need = !hit && (cand & 0xf0u);
+    if (__builtin_amdgcn_ballot_w64(need)) {
+      fetch_lines(lines, tab, need ? f.p : kNoFetch, 1u, g, r);
+      lines_landed();
+      if (need) match_line1(mine, cand & 0xf0u, key, hit, val);
     }
-    KeyFields f[K];
-    uint4 qp[K], qa[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      f[j] = key_fields(key_hash(key[j], seed), log2b);
-      qp[j] = qa[j] = make_uint4(0u, 0u, 0u, 0u);
-    }
-    // first lines: one 128-byte request per lookup (two for pessimistic)
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      if (ok[j]) {
-        qp[j] = tab[(uint64_t)f[j].p * kQuartersPerBucket + r];
-        if (MODE == kModeBoth) qa[j] = tab[(uint64_t)f[j].a * kQuartersPerBucket + r];
-      }
-    }
-    Probe pr[K];
-    uint32_t wp[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      pr[j].hit = false;
-      pr[j].owner = 0u;
-      pr[j].val = 0ull;
-      wp[j] = ok[j] ? analyse_line0(r, qp[j], f[j], key[j], pr[j]) : 0u;
-    }
-    // second line of the primary bucket, only on a tag match in slots 4..7
-    bool need[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      need[j] = ok[j] && needs_line1(wp[j], pr[j]);
-      if (need[j]) qp[j] = tab[(uint64_t)f[j].p * kQuartersPerBucket + 8u + r];
-    }
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-      if (need[j]) analyse_line1(r, qp[j], wp[j], key[j], pr[j]);
     // secondary bucket
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      need[j] = ok[j] && !pr[j].hit && (MODE != kModeCuckoopp || ((wp[j] >> 16) & 1u));
-      if (MODE != kModeBoth && need[j]) qa[j] = tab[(uint64_t)f[j].a * kQuartersPerBucket + r];
-    }
-    uint32_t wa[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-      wa[j] = need[j] ? analyse_line0(r, qa[j], f[j], key[j], pr[j]) : 0u;
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      need[j] = need[j] && needs_line1(wa[j], pr[j]);
-      if (need[j]) qa[j] = tab[(uint64_t)f[j].a * kQuartersPerBucket + 8u + r];
-    }
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-      if (need[j]) analyse_line1(r, qa[j], wa[j], key[j], pr[j]);
-    // results: lane 0 writes the found flag; the value is written by the
-    // lane that holds it (lane 0 writes 0 on a miss)
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-      const uint64_t i = tile + (uint64_t)j * groups + gid;
-      if (ok[j]) {
-        if (r == 0u) __builtin_nontemporal_store((uint8_t)(pr[j].hit ? 1 : 0), found + i);
-        if (pr[j].hit ? (r == pr[j].owner) : (r == 0u))
-          __builtin_nontemporal_store(pr[j].hit ? pr[j].val : 0ull, vals + i);
+    need = ok && !hit && pass;
+    if (__builtin_amdgcn_ballot_w64(need)) {
+      if (MODE != kModeBoth) {
+        fetch_lines(lines, tab, need ? f.a : kNoFetch, 0u, g, r);
+        lines_landed();
+      }
+      uint32_t cand2 = 0u;
+      if (need) {
+        const uint4 u0 = mine_a[0], u1 = mine_a[1];
+        cand2 = tag_eq_mask(u0, f.tag) & meta_busy(u1.z);
+        match_line0(mine_a, cand2 & 0xfu, key, hit, val);
+      }
+      need = need && !hit && (cand2 & 0xf0u);
+      if (__builtin_amdgcn_ballot_w64(need)) {
+        fetch_lines(lines_a, tab, need ? f.a : kNoFetch, 1u, g, r);
+        lines_landed();
+        if (need) match_line1(mine_a, cand2 & 0xf0u, key, hit, val);
       }
     }
+    if (ok) {
+      __builtin_nontemporal_store((uint8_t)(hit ? 1 : 0), found + i);
+      __builtin_nontemporal_store(hit ? val : 0ull, vals + i);
+    }
+    key = knext;
   }
 }
 
-template <int K, uint32_t MODE>
+template <uint32_t WAVES, uint32_t MODE>
 hipError_t launch_shape(const ckpp_table *t, const uint4 *keys, uint64_t n, uint8_t *found,
                         uint64_t *vals, hipStream_t s) {
   const ckpp_launch_t &L = t->lookup_launch;
-  const uint32_t block = L.block;
-  const uint64_t per_block = (uint64_t)(block / 8u) * K;
+  const uint64_t per_block = 64ull * WAVES;
   uint64_t grid = (n + per_block - 1) / per_block;
   if (L.blocks_per_cu) {
     const uint64_t cap = (uint64_t)L.blocks_per_cu * (uint64_t)t->num_cus;
     if (grid > cap) grid = cap;
   }
   if (grid > 0x7fffffffull) grid = 0x7fffffffull;
-  hipLaunchKernelGGL((lookup_group8<K, MODE>), dim3((uint32_t)grid), dim3(block), 0, s,
+  hipLaunchKernelGGL((lookup_lds<WAVES, MODE>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, s,
                      reinterpret_cast<const uint4 *>(t->d_table), keys, n, t->log2_buckets,
                      t->seed, found, vals);
   return hipGetLastError();
@@ -209,9 +183,9 @@ hipError_t launch_shape(const ckpp_table *t, const uint4 *keys, uint64_t n, uint
 template <uint32_t MODE>
 hipError_t launch_mode(const ckpp_table *t, const uint4 *keys, uint64_t n, uint8_t *found,
                        uint64_t *vals, hipStream_t s) {
-  switch (t->lookup_launch.lookups_per_lane) {
-    case 1: return launch_shape<1, MODE>(t, keys, n, found, vals, s);
-    case 2: return launch_shape<2, MODE>(t, keys, n, found, vals, s);
+  switch (t->lookup_launch.block) {
+    case 64: return launch_shape<1, MODE>(t, keys, n, found, vals, s);
+    case 128: return launch_shape<2, MODE>(t, keys, n, found, vals, s);
     default: return launch_shape<4, MODE>(t, keys, n, found, vals, s);
   }
 }
