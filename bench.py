@@ -51,6 +51,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="lookup rate over loads x negative rates x modes (2^24 and 2^20 buckets)")
+    ap.add_argument("--insert-workload", action="store_true",
+                    help="insert rate vs load in 65536-key batches, then delete 20%% and re-insert")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSV output under DIR")
     ap.add_argument("--tune", action="store_true",
@@ -260,6 +264,120 @@ def copy_calibration(dev):
     print(json.dumps({"copy_calibration_bytes": 1 << 30, "dispatches": 5}))
 
 
+def sweep(dev, lookups, probe_peak):
+    """Lookup rate of Cuckoo++ and plain lookups over loads {0.6 .. 0.95} and
+    negative rates {0 .. 1}, on a 2^24-bucket (HBM-resident) and a
+    2^20-bucket (256 MiB, cache-sized) table built incrementally."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Table
+    loads = (0.6, 0.7, 0.8, 0.9, 0.95)
+    rates = (0.0, 0.25, 0.5, 0.75, 1.0)
+    rows = []
+    for B, nlook in ((24, lookups), (20, min(lookups, 1 << 24))):
+        nmax = W.keys_at_load(B, max(loads))
+        keys = W.distinct_five_tuples(nmax, 21 + B, check=False)
+        t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=dev.index)
+        nf = torch.zeros(1, dtype=torch.int64, device=dev)
+        done = 0
+        neg_pool = to_dev(W.five_tuples(nlook, 40 + B, stream=W.STREAM_NEGATIVE), dev)
+        f = torch.empty(nlook, dtype=torch.uint8, device=dev)
+        v = torch.empty(nlook, dtype=torch.int64, device=dev)
+        for ld in loads:
+            n = W.keys_at_load(B, ld)
+            for s0 in range(done, n, 1 << 22):
+                s1 = min(n, s0 + (1 << 22))
+                t.insert(to_dev(keys[s0:s1], dev),
+                         to_dev(W.insertion_values(s1 - s0, s0).view(np.int64), dev), nfailed=nf)
+            done = n
+            torch.cuda.synchronize()
+            st = t.stats()
+            lines = expected_lines(st)
+            pick = W.raw_u64(50 + B, int(ld * 100), nlook) % np.uint64(n)
+            pos_pool = to_dev(keys[pick.astype(np.int64)], dev)
+            for r in rates:
+                neg = torch.from_numpy(W.bernoulli(nlook, r, 60 + B, int(r * 100))).to(dev)
+                q = torch.where(neg[:, None], neg_pool, pos_pool).contiguous()
+                for mode, lk in (("cuckoopp", "cuckoopp"), ("both", "plain")):
+                    ms = timed(lambda: t.lookup(q, mode, found=f, values=v), 3, dev)
+                    req = (1 - r) * lines[f"{lk}_pos"] + r * lines[f"{lk}_neg"]
+                    rate = nlook / (ms * 1e-3)
+                    rows.append({"log2_buckets": B, "load": ld, "neg_rate": r, "mode": lk,
+                                 "glookups": rate / 1e9, "lines_per_lookup": req,
+                                 "frac_random_line_peak": rate * req / probe_peak,
+                                 "failed_inserts": int(nf.item())})
+            del pos_pool
+            log(f"sweep B={B} load={ld}: " + " ".join(
+                f"{x['mode'][0]}{x['neg_rate']}:{x['glookups']:.1f}" for x in rows[-10:]))
+        t.close()
+        del neg_pool
+        torch.cuda.empty_cache()
+    return rows
+
+
+def insert_workload(dev, B=24, batch=65536):
+    """Insert rate vs load (empty table -> load 0.95 in batches of 65536
+    keys), then delete of a random 20% and re-insert of as many fresh keys."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Table
+    n = W.keys_at_load(B, 0.95)
+    keys = W.distinct_five_tuples(n, 11, check=False)
+    vals = W.insertion_values(n)
+    t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=dev.index)
+    dk, dv = to_dev(keys, dev), to_dev(vals.view(np.int64), dev)
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+    nf = torch.zeros(1, dtype=torch.int64, device=dev)
+    s = torch.cuda.current_stream(dev)
+    nb = (n + batch - 1) // batch
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nb + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(s)
+    for b in range(nb):
+        lo, hi = b * batch, min(n, (b + 1) * batch)
+        t.insert(dk[lo:hi], dv[lo:hi], status=st[lo:hi], nfailed=nf)
+        ev[b + 1].record(s)
+    torch.cuda.synchronize()
+    ms = np.array([ev[b].elapsed_time(ev[b + 1]) for b in range(nb)])
+    slots = 8 << B
+    per_load = []
+    for lo_ld in np.arange(0.0, 0.95, 0.05):
+        sel = [b for b in range(nb) if lo_ld <= (b * batch) / slots < lo_ld + 0.05]
+        if sel:
+            k = sum(min(n, (b + 1) * batch) - b * batch for b in sel)
+            per_load.append({"load_from": round(float(lo_ld), 2),
+                             "minserts_per_s": k / (ms[sel].sum() * 1e-3) / 1e6})
+    fails = int(nf.item())
+    nd = n // 5
+    rows = W.choose_rows(n, nd, 12)
+    dd = to_dev(keys[rows], dev)
+    fo = torch.empty(nd, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(0, nd, batch):
+        t.delete(dd[b:b + batch], found=fo[b:b + batch])
+    torch.cuda.synchronize()
+    del_s = time.perf_counter() - t0
+    fresh = to_dev(W.distinct_five_tuples(nd, 13, stream=W.STREAM_FRESH, check=False), dev)
+    fv = to_dev(W.insertion_values(nd, n).view(np.int64), dev)
+    st2 = torch.empty(nd, dtype=torch.uint8, device=dev)
+    nf2 = torch.zeros(1, dtype=torch.int64, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(0, nd, batch):
+        t.insert(fresh[b:b + batch], fv[b:b + batch], status=st2[b:b + batch], nfailed=nf2)
+    torch.cuda.synchronize()
+    re_s = time.perf_counter() - t0
+    stats = t.stats()
+    t.close()
+    return {"log2_buckets": B, "batch": batch, "keys": n, "build_ms": float(ms.sum()),
+            "build_minserts_per_s": n / (ms.sum() * 1e-3) / 1e6, "build_failed": fails,
+            "per_load": per_load, "deleted": nd, "deleted_found": int(fo.sum().item()),
+            "delete_minserts_per_s": nd / del_s / 1e6,
+            "reinserted": nd, "reinsert_failed": int(nf2.item()),
+            "reinsert_minserts_per_s": nd / re_s / 1e6,
+            "final_live": stats["live"], "f_sec": stats["f_sec"],
+            "retry_exhausted": stats["retry_exhausted"]}
+
+
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d DIR/p4_trace -o core -- "
              "python3 bench.py --core-only --steps 5 --warmup 2",
@@ -375,6 +493,14 @@ def main():
     if args.copy_calib:
         copy_calibration(dev)
         return
+    if args.insert_workload:
+        print(json.dumps({"insert_workload": insert_workload(dev)}), flush=True)
+        return
+    if args.sweep:
+        peak = probe_rand_peak(dev)["128_coop"]["reads_per_s"]
+        print(json.dumps({"sweep": sweep(dev, args.lookups, peak), "random_line_peak_per_s": peak}),
+              flush=True)
+        return
 
     B, load, n = args.log2_buckets, args.load, args.lookups
     t, keys, vals, build_s = build_table(B, load, 1, dev)
@@ -399,14 +525,14 @@ def main():
     dchurn_v = to_dev(W.insertion_values(args.churn, 1 << 40).view(np.int64), dev)
     if args.tune:
         from paper_1712_09624_amd import tune
-        sweep = {}
+        tuned = {}
         for mode in ("both", "cuckoopp"):
             res = tune.tune(t, [dpos, dneg], mode)
-            sweep[mode] = [{"ms_total": r[0], "ms_pos": r[2][0], "ms_neg": r[2][1], **r[1]}
+            tuned[mode] = [{"ms_total": r[0], "ms_pos": r[2][0], "ms_neg": r[2][1], **r[1]}
                            for r in res]
             for r in res:
                 log(f"tune {mode}: {r[1]} pos {r[2][0]:.3f} ms neg {r[2][1]:.3f} ms")
-        print(json.dumps({"tune": sweep}), flush=True)
+        print(json.dumps({"tune": tuned}), flush=True)
         launch = t.get_lookup_launch()
     f_pos = torch.empty(n, dtype=torch.uint8, device=dev)
     v_pos = torch.empty(n, dtype=torch.int64, device=dev)
