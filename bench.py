@@ -408,12 +408,15 @@ def summarize_profiles(d):
     commands in PROFILE_CMDS (run from the repository root with DIR = d)."""
     import csv
     prof = os.path.join(ROOT, "profiles")
+    from paper_1712_09624_amd import ckpp
+    # the profiled runs use the default launch shape
+    kname = ckpp.lookup_kernel_name(ckpp.DEFAULT_LAUNCH)
     # kernel trace
     rows = list(csv.DictReader(open(os.path.join(d, "p4_trace", "core_kernel_stats.csv"))))
     out = ["# rocprofv3 kernel-trace summary: Cuckoo++ step on a 2^24-bucket table at load 0.9",
            "# (bench.py --core-only: table build in 4M-key insert batches, then per step",
            "#  insert 65536 + lookup 2^26 positive + lookup 2^26 negative + delete 65536)",
-           "# device layout: 256-byte buckets, two 128-byte lines; lookup kernel lookup_lds",
+           "# device layout: 256-byte buckets, two 128-byte lines; lookup kernel " + kname,
            "# command (repository root, TMPDIR=/tmp): " + PROFILE_CMDS["trace"].replace("DIR", d),
            f"{'kernel':<40} {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'pct':>6}"]
     for r in rows:
@@ -430,12 +433,12 @@ def summarize_profiles(d):
         out.append(f"{name[:cut][:40]:<40} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
                    f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} "
                    f"{float(r['Percentage']):>6.2f}")
-    out.append("# lookup_lds launches alternate positive (the longer) and negative batches;")
+    out.append(f"# {kname} launches alternate positive (the longer) and negative batches;")
     out.append("# their average is the avg_launch_ms bench.py reports in roofline.")
-    with open(os.path.join(prof, "lookup_lds_b24_load0.9_kernel_trace.txt"), "w") as fh:
+    with open(os.path.join(prof, f"{kname}_b24_load0.9_kernel_trace.txt"), "w") as fh:
         fh.write("\n".join(out) + "\n")
     # traffic
-    lk = {k: _pmc(os.path.join(d, f"p4_{k}", "core_counter_collection.csv"), "lookup_lds")
+    lk = {k: _pmc(os.path.join(d, f"p4_{k}", "core_counter_collection.csv"), kname)
           for k in ("fetch", "write", "req")}
     cp = {k: _pmc(os.path.join(d, f"p4_copy_{k}", "copy_counter_collection.csv"), "copyBuffer")
           for k in ("fetch", "write", "req")}
@@ -451,7 +454,7 @@ def summarize_profiles(d):
     reqb = [exact(v) * f_req for v in lk["req"]]
     nreq = [v["TCC_EA0_RDREQ_sum"] for v in lk["req"]]
     per_launch = (sum(fetch) + sum(write)) / len(fetch)
-    lines = ["# HBM traffic of the Cuckoo++ lookup kernel (lookup_lds), 2^24 buckets at load 0.9,",
+    lines = [f"# HBM traffic of the Cuckoo++ lookup kernel ({kname}), 2^24 buckets at load 0.9,",
              "# 2^26 lookups per launch, launches alternating positive / negative batches",
              "# commands (repository root, TMPDIR=/tmp, one counter group per run):"]
     for k in ("fetch", "write", "req", "copy"):
@@ -463,12 +466,11 @@ def summarize_profiles(d):
         lines.append(f"{i:>8} {fetch[i] / 1e9:>10.3f} {write[i] / 1e9:>10.3f} {reqb[i] / 1e9:>11.3f} "
                      f"{nreq[i]:>13.0f}")
     lines.append(f"# mean HBM bytes per launch (calibrated fetch + write): {per_launch / 1e9:.3f} GB")
-    with open(os.path.join(prof, "lookup_lds_b24_load0.9_hbm_traffic.txt"), "w") as fh:
+    with open(os.path.join(prof, f"{kname}_b24_load0.9_hbm_traffic.txt"), "w") as fh:
         fh.write("\n".join(lines) + "\n")
     with open(os.path.join(prof, "lookup_traffic.json"), "w") as fh:
         json.dump({"source_digest": lookup_source_digest(),
-                   "launch": {"lanes_per_lookup": 8, "lookups_per_lane": 1, "block": 128,
-                              "blocks_per_cu": 0},
+                   "launch": dict(ckpp.DEFAULT_LAUNCH), "kernel": kname,
                    "hbm_bytes_per_launch": per_launch,
                    "fetch_factor": f_fetch, "write_factor": f_write,
                    "dispatches": len(fetch)}, fh, indent=1)
@@ -594,7 +596,7 @@ def main():
     achieved = (bytes_pos + bytes_neg) / ((ms["pos"] + ms["neg"]) * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": f"lookup_lds<waves={launch['block'] // 64}, Cuckoo++>",
+                "kernel": f"{ckpp.lookup_kernel_name(launch)}<waves={launch['block'] // 64}, Cuckoo++>",
                 "algorithmic_bytes_per_launch": (bytes_pos + bytes_neg) / 2,
                 "avg_launch_ms": (ms["pos"] + ms["neg"]) / 2}
     tf = os.path.join(ROOT, "profiles", "lookup_traffic.json")

@@ -116,7 +116,11 @@ int ckpp_clear(ckpp_table *t, void *stream);
  * batch must be pairwise distinct (the result is unspecified otherwise).
  * d_status (n bytes, nullable) receives CKPP_INSERTED / UPDATED / FAILED;
  * d_nfailed (one u64, nullable) is incremented by the number of FAILED keys.
- * Errors: CKPP_EINVAL (null table/keys/values with n > 0, misaligned keys). */
+ * The cuckoo-path scratch of the call (at most 4 * max_kicks bytes per
+ * launched lane, at most 2^16 lanes) comes from the device's stream-ordered
+ * memory pool and is returned to it on `stream`.
+ * Errors: CKPP_EINVAL (null table/keys/values with n > 0, misaligned keys),
+ * CKPP_ENOMEM (scratch allocation failed). */
 int ckpp_insert_batch(ckpp_table *t, const void *d_keys, const uint64_t *d_values, uint64_t n,
                       uint8_t *d_status, uint64_t *d_nfailed, void *stream);
 
@@ -197,11 +201,15 @@ int ckpp_info(const ckpp_table *t, ckpp_info_t *out);
 /* Launch shape of the lookup kernel.  Each lane owns one lookup; the line
  * of a bucket is read by a group of lanes_per_lookup = 8 neighbouring lanes
  * (16 bytes each, one 128-byte request) straight into LDS, and each lane
- * then analyses its own line there.  lookups_per_lane: 1; block: 64, 128 or
- * 256 (1, 2 or 4 wavefronts, 8 KiB of LDS each, 16 KiB for the pessimistic
- * mode); blocks_per_cu: grid size in blocks per compute unit (0: enough
- * blocks to cover the batch in one pass).  Applies to every later lookup
- * on t. */
+ * then analyses its own line there.  lookups_per_lane: 1, or 2 (each lane
+ * owns two lookups; the lines of the second half land in registers and are
+ * parked in LDS after the first half is analysed: twice the requests in
+ * flight; the pessimistic mode always uses 1); block: 64, 128 or 256 (1, 2
+ * or 4 wavefronts, 8 KiB of LDS each, 16 KiB for the pessimistic mode);
+ * blocks_per_cu: grid size in blocks per compute unit (0: enough blocks to
+ * cover the batch in one pass).  Applies to every later lookup on t.  A new
+ * table starts with {8, 2, 128, 0}, the fastest shape on 2^20..2^24-bucket
+ * tables at load 0.9. */
 typedef struct {
     uint32_t lanes_per_lookup;
     uint32_t lookups_per_lane;

@@ -24,6 +24,15 @@ MODES = {"cuckoopp": LOOKUP_DEFAULT, "default": LOOKUP_DEFAULT, "both": LOOKUP_B
          "plain": LOOKUP_BOTH, "pessimistic": LOOKUP_BOTH, "optimistic": LOOKUP_OPTIMISTIC}
 MOVED_BINS = 66
 DEFAULT_HASH_SEED = 0x243F6A8885A308D3
+# lookup launch shape a new table starts with (ckpp_create sets the same)
+DEFAULT_LAUNCH = {"lanes_per_lookup": 8, "lookups_per_lane": 2, "block": 128, "blocks_per_cu": 0}
+
+
+def lookup_kernel_name(launch: dict, mode: str = "cuckoopp") -> str:
+    """Name of the lookup kernel a launch shape selects for a lookup mode."""
+    if launch["lookups_per_lane"] == 2 and mode != "both":
+        return "lookup_dual"
+    return "lookup_lds"
 
 
 class CkppError(RuntimeError):
@@ -288,8 +297,10 @@ class Table:
         _check(self.lib.ckpp_info(self._h, ctypes.byref(inf)), "ckpp_info")
         return {f: getattr(inf, f) for f, _ in _Info._fields_}
 
-    def set_lookup_launch(self, lanes_per_lookup=8, lookups_per_lane=1, block=256,
-                          blocks_per_cu=0):
+    def set_lookup_launch(self, lanes_per_lookup=DEFAULT_LAUNCH["lanes_per_lookup"],
+                          lookups_per_lane=DEFAULT_LAUNCH["lookups_per_lane"],
+                          block=DEFAULT_LAUNCH["block"],
+                          blocks_per_cu=DEFAULT_LAUNCH["blocks_per_cu"]):
         cfg = _Launch(lanes_per_lookup, lookups_per_lane, block, blocks_per_cu)
         _check(self.lib.ckpp_set_lookup_launch(self._h, ctypes.byref(cfg)),
                "ckpp_set_lookup_launch")

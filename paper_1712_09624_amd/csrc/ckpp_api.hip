@@ -38,7 +38,10 @@ class DeviceGuard {
 
 bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-int dev_status(hipError_t e) { return e == hipSuccess ? CKPP_OK : CKPP_EDEVICE; }
+int dev_status(hipError_t e) {
+  if (e == hipSuccess) return CKPP_OK;
+  return e == hipErrorOutOfMemory ? CKPP_ENOMEM : CKPP_EDEVICE;
+}
 
 uint64_t nbuckets(const ckpp_table *t) { return 1ull << t->log2_buckets; }
 uint64_t table_bytes(const ckpp_table *t) { return 256ull << t->log2_buckets; }
@@ -139,7 +142,7 @@ int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uin
   t->device = device;
   t->seed = hash_seed;
   t->lookup_launch.lanes_per_lookup = 8;
-  t->lookup_launch.lookups_per_lane = 1;
+  t->lookup_launch.lookups_per_lane = 2;
   t->lookup_launch.block = 128;
   t->lookup_launch.blocks_per_cu = 0;
   hipDeviceProp_t prop;
@@ -154,11 +157,9 @@ int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uin
   if (lanes < 256) lanes = 256;
   if (lanes > kMaxPathLanes) lanes = kMaxPathLanes;
   t->path_lanes = (uint32_t)lanes;
-  const uint64_t path_words = lanes * (uint64_t)(max_kicks ? max_kicks : 1u);
 
   int rc = CKPP_OK;
   if (hipMalloc(&t->d_table, table_bytes(t)) != hipSuccess ||
-      hipMalloc(&t->d_paths, path_words * sizeof(uint32_t)) != hipSuccess ||
       hipMalloc(&t->d_stats, kAccWords * sizeof(uint64_t)) != hipSuccess) {
     rc = CKPP_ENOMEM;
   } else if (hipMemset(t->d_table, 0, table_bytes(t)) != hipSuccess ||
@@ -169,7 +170,6 @@ int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uin
   if (rc != CKPP_OK) {
     (void)hipGetLastError();
     if (t->d_table) (void)hipFree(t->d_table);
-    if (t->d_paths) (void)hipFree(t->d_paths);
     if (t->d_stats) (void)hipFree(t->d_stats);
     delete t;
     return rc;
@@ -183,7 +183,6 @@ int ckpp_destroy(ckpp_table *t) {
   DeviceGuard g(t->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(t->d_table);
-  (void)hipFree(t->d_paths);
   (void)hipFree(t->d_stats);
   delete t;
   return CKPP_OK;
@@ -320,7 +319,7 @@ int ckpp_info(const ckpp_table *t, ckpp_info_t *out) {
 int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg) {
   if (!t || !cfg) return CKPP_EINVAL;
   if (cfg->lanes_per_lookup != 8) return CKPP_EINVAL;
-  if (cfg->lookups_per_lane != 1) return CKPP_EINVAL;
+  if (cfg->lookups_per_lane != 1 && cfg->lookups_per_lane != 2) return CKPP_EINVAL;
   if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return CKPP_EINVAL;
   if (cfg->blocks_per_cu > 4096) return CKPP_EINVAL;
   t->lookup_launch = *cfg;

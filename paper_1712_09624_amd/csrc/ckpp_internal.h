@@ -13,7 +13,6 @@ struct ckpp_table {
   int device;
   uint64_t seed;
   uint8_t *d_table;     // 256 * 2^B bytes: bucket b at 256 * b (ckpp_device.h)
-  uint32_t *d_paths;    // cuckoo-path scratch: path_lanes * max(1, max_kicks) u32
   uint32_t path_lanes;  // lanes of the persistent insert grid
   uint64_t *d_stats;    // device accumulator of ckpp_stats_t
   ckpp_launch_t lookup_launch;

@@ -163,9 +163,154 @@ __global__ void __launch_bounds__(64 * WAVES)
   }
 }
 
+// Register-landing counterpart of fetch_lines: the same rounds, but the
+// quarter arrives in q[k] of the fetching lane; park_lines() later writes
+// the quarters to LDS in exactly the layout fetch_lines produces.
+__device__ __forceinline__ void fetch_lines_reg(uint4 (&q)[8], const uint4 *tab, uint32_t bucket,
+                                                uint32_t half, uint32_t g, uint32_t r) {
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) {
+    const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
+    q[k] = make_uint4(0u, 0u, 0u, 0u);
+    if (b != kNoFetch) q[k] = tab[(uint64_t)b * kQuartersPerBucket + 8u * half + r];
+  }
+}
+
+__device__ __forceinline__ void park_lines(uint4 *lines, const uint4 (&q)[8], uint32_t lane) {
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) lines[64u * k + lane] = q[k];
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Lookup state of one lookup owned by a lane.
+struct Look {
+  uint4 key;
+  KeyFields f;
+  bool ok, hit, pass;
+  uint32_t cand;
+  uint64_t val;
+};
+
+__device__ __forceinline__ void first_line(const uint4 *mine, Look &L, uint32_t mode) {
+  const uint4 t0 = mine[0], t1 = mine[1];
+  L.cand = L.ok ? (tag_eq_mask(t0, L.f.tag) & meta_busy(t1.z)) : 0u;
+  L.pass = mode != kModeCuckoopp || bloom_pass(t1, L.f.bloom_bits);
+  match_line0(mine, L.cand & 0xfu, L.key, L.hit, L.val);
+}
+
+// Two lookups per lane (lookups tile + lane and tile + 64 + lane): for each
+// phase the lines of the first 64 land in LDS directly, those of the other
+// 64 in registers, which are parked in LDS once the first 64 have been
+// analysed -- twice the line requests in flight for the same LDS.
+template <uint32_t WAVES, uint32_t MODE>
+__global__ void __launch_bounds__(64 * WAVES)
+    lookup_dual(const uint4 *__restrict__ tab, const uint4 *__restrict__ keys, uint64_t n,
+                uint32_t log2b, uint64_t seed, uint8_t *__restrict__ found,
+                uint64_t *__restrict__ vals) {
+  static_assert(MODE != kModeBoth, "the pessimistic mode uses lookup_lds");
+  __shared__ uint4 s_lines[WAVES * kWaveQuarters];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t g = lane >> 3, r = lane & 7u;
+  uint4 *lines = s_lines + (threadIdx.x >> 6) * kWaveQuarters;
+  const uint4 *mine = lines + 8u * lane;
+  const uint64_t wave0 = ((uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 128u;
+  const uint64_t stride = (uint64_t)gridDim.x * WAVES * 128u;
+  uint4 ka = wave0 + lane < n ? load_stream(keys + wave0 + lane) : make_uint4(0u, 0u, 0u, 0u);
+  uint4 kb = wave0 + 64u + lane < n ? load_stream(keys + wave0 + 64u + lane)
+                                    : make_uint4(0u, 0u, 0u, 0u);
+  for (uint64_t w0 = wave0; w0 < n; w0 += stride) {
+    Look A, Bq;
+    A.key = ka;
+    Bq.key = kb;
+    A.ok = w0 + lane < n;
+    Bq.ok = w0 + 64u + lane < n;
+    A.f = key_fields(key_hash(A.key, seed), log2b);
+    Bq.f = key_fields(key_hash(Bq.key, seed), log2b);
+    A.hit = Bq.hit = false;
+    A.val = Bq.val = 0ull;
+    uint4 q[8];
+    // phase 1: primary first lines
+    fetch_lines(lines, tab, A.ok ? A.f.p : kNoFetch, 0u, g, r);
+    fetch_lines_reg(q, tab, Bq.ok ? Bq.f.p : kNoFetch, 0u, g, r);
+    const uint64_t nx = w0 + stride;
+    ka = nx + lane < n ? load_stream(keys + nx + lane) : make_uint4(0u, 0u, 0u, 0u);
+    kb = nx + 64u + lane < n ? load_stream(keys + nx + 64u + lane) : make_uint4(0u, 0u, 0u, 0u);
+    lines_landed();
+    first_line(mine, A, MODE);
+    park_lines(lines, q, lane);
+    first_line(mine, Bq, MODE);
+    // phase 2: primary second lines
+    bool na = !A.hit && (A.cand & 0xf0u), nb = !Bq.hit && (Bq.cand & 0xf0u);
+    if (__builtin_amdgcn_ballot_w64(na || nb)) {
+      fetch_lines(lines, tab, na ? A.f.p : kNoFetch, 1u, g, r);
+      fetch_lines_reg(q, tab, nb ? Bq.f.p : kNoFetch, 1u, g, r);
+      lines_landed();
+      if (na) match_line1(mine, A.cand & 0xf0u, A.key, A.hit, A.val);
+      park_lines(lines, q, lane);
+      if (nb) match_line1(mine, Bq.cand & 0xf0u, Bq.key, Bq.hit, Bq.val);
+    }
+    // phase 3: secondary first lines
+    na = A.ok && !A.hit && A.pass;
+    nb = Bq.ok && !Bq.hit && Bq.pass;
+    if (__builtin_amdgcn_ballot_w64(na || nb)) {
+      fetch_lines(lines, tab, na ? A.f.a : kNoFetch, 0u, g, r);
+      fetch_lines_reg(q, tab, nb ? Bq.f.a : kNoFetch, 0u, g, r);
+      lines_landed();
+      uint32_t ca = 0u, cb = 0u;
+      if (na) {
+        ca = tag_eq_mask(mine[0], A.f.tag) & meta_busy(mine[1].z);
+        match_line0(mine, ca & 0xfu, A.key, A.hit, A.val);
+      }
+      park_lines(lines, q, lane);
+      if (nb) {
+        cb = tag_eq_mask(mine[0], Bq.f.tag) & meta_busy(mine[1].z);
+        match_line0(mine, cb & 0xfu, Bq.key, Bq.hit, Bq.val);
+      }
+      // phase 4: secondary second lines
+      na = na && !A.hit && (ca & 0xf0u);
+      nb = nb && !Bq.hit && (cb & 0xf0u);
+      if (__builtin_amdgcn_ballot_w64(na || nb)) {
+        fetch_lines(lines, tab, na ? A.f.a : kNoFetch, 1u, g, r);
+        fetch_lines_reg(q, tab, nb ? Bq.f.a : kNoFetch, 1u, g, r);
+        lines_landed();
+        if (na) match_line1(mine, ca & 0xf0u, A.key, A.hit, A.val);
+        park_lines(lines, q, lane);
+        if (nb) match_line1(mine, cb & 0xf0u, Bq.key, Bq.hit, Bq.val);
+      }
+    }
+    if (A.ok) {
+      __builtin_nontemporal_store((uint8_t)(A.hit ? 1 : 0), found + w0 + lane);
+      __builtin_nontemporal_store(A.hit ? A.val : 0ull, vals + w0 + lane);
+    }
+    if (Bq.ok) {
+      __builtin_nontemporal_store((uint8_t)(Bq.hit ? 1 : 0), found + w0 + 64u + lane);
+      __builtin_nontemporal_store(Bq.hit ? Bq.val : 0ull, vals + w0 + 64u + lane);
+    }
+  }
+}
+
+template <uint32_t WAVES, uint32_t MODE>
+hipError_t launch_dual(const ckpp_table *t, const uint4 *keys, uint64_t n, uint8_t *found,
+                       uint64_t *vals, hipStream_t s) {
+  const ckpp_launch_t &L = t->lookup_launch;
+  const uint64_t per_block = 128ull * WAVES;
+  uint64_t grid = (n + per_block - 1) / per_block;
+  if (L.blocks_per_cu) {
+    const uint64_t cap = (uint64_t)L.blocks_per_cu * (uint64_t)t->num_cus;
+    if (grid > cap) grid = cap;
+  }
+  if (grid > 0x7fffffffull) grid = 0x7fffffffull;
+  hipLaunchKernelGGL((lookup_dual<WAVES, MODE>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, s,
+                     reinterpret_cast<const uint4 *>(t->d_table), keys, n, t->log2_buckets,
+                     t->seed, found, vals);
+  return hipGetLastError();
+}
+
 template <uint32_t WAVES, uint32_t MODE>
 hipError_t launch_shape(const ckpp_table *t, const uint4 *keys, uint64_t n, uint8_t *found,
                         uint64_t *vals, hipStream_t s) {
+  if (MODE != kModeBoth && t->lookup_launch.lookups_per_lane == 2)
+    return launch_dual<WAVES, (MODE == kModeBoth ? kModeCuckoopp : MODE)>(t, keys, n, found, vals, s);
   const ckpp_launch_t &L = t->lookup_launch;
   const uint64_t per_block = 64ull * WAVES;
   uint64_t grid = (n + per_block - 1) / per_block;

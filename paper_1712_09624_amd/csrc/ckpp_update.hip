@@ -399,12 +399,20 @@ hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t
   const uint64_t lanes = n < t->path_lanes ? n : t->path_lanes;
   const uint32_t block = 256;
   const uint32_t grid = (uint32_t)((lanes + block - 1) / block);
+  // cuckoo-path scratch of this batch, stream-ordered from the device's pool:
+  // one path of max_kicks entries per launched lane
+  const uint64_t words = (uint64_t)grid * block * (uint64_t)(t->max_kicks ? t->max_kicks : 1u);
+  uint32_t *paths = nullptr;
+  hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&paths), words * sizeof(uint32_t), s);
+  if (e != hipSuccess) return e;
   unsigned long long *nspin = reinterpret_cast<unsigned long long *>(t->d_stats) + 127;
   hipLaunchKernelGGL(insert_kernel, dim3(grid), dim3(block), 0, s, t->d_table,
                      reinterpret_cast<const uint4 *>(d_keys), d_values, n, t->log2_buckets,
-                     t->seed, t->max_kicks, (t->flags & CKPP_PLAIN) ? 1u : 0u, t->d_paths,
+                     t->seed, t->max_kicks, (t->flags & CKPP_PLAIN) ? 1u : 0u, paths,
                      d_status, reinterpret_cast<unsigned long long *>(d_nfailed), nspin);
-  return hipGetLastError();
+  e = hipGetLastError();
+  const hipError_t f = hipFreeAsync(paths, s);
+  return e != hipSuccess ? e : f;
 }
 
 hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_found,

@@ -13,7 +13,7 @@ import itertools
 
 SHAPES = [
     {"lanes_per_lookup": lanes, "lookups_per_lane": per, "block": block, "blocks_per_cu": bpc}
-    for lanes, per, block, bpc in itertools.product((8,), (1,), (64, 128, 256), (0, 4, 8, 16))
+    for lanes, per, block, bpc in itertools.product((8,), (1, 2), (64, 128, 256), (0, 5, 10))
 ]
 
 

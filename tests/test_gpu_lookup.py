@@ -14,7 +14,7 @@ from paper_1712_09624_amd import workload as W
 pytestmark = pytest.mark.gpu
 
 MODES = [("cuckoopp", O.MODE_CUCKOOPP), ("both", O.MODE_BOTH), ("optimistic", O.MODE_OPTIMISTIC)]
-SHAPES = [(8, 1, block, bpc) for block in (64, 128, 256) for bpc in (0, 1, 3)]
+SHAPES = [(8, per, block, bpc) for per in (1, 2) for block in (64, 128, 256) for bpc in (0, 1, 3)]
 
 
 @pytest.fixture(scope="module")
@@ -107,6 +107,16 @@ def test_empty_batch_is_noop(cfg1):
     torch.cuda.synchronize()
     assert f.numel() == 0 and v.numel() == 0 and st.numel() == 0 and d.numel() == 0
     assert int(nf.item()) == 0
+    t.close()
+
+
+def test_default_launch_shape():
+    from paper_1712_09624_amd import ckpp
+    t = ckpp.Table(8, W.HASH_SEED, device=0)
+    assert t.get_lookup_launch() == ckpp.DEFAULT_LAUNCH
+    t.set_lookup_launch(8, 1, 256, 3)
+    assert t.get_lookup_launch() == {"lanes_per_lookup": 8, "lookups_per_lane": 1, "block": 256,
+                                     "blocks_per_cu": 3}
     t.close()
 
 
