@@ -53,6 +53,8 @@ def parse():
                     help="run only a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sweep", action="store_true",
                     help="lookup rate over loads x negative rates x modes (2^24 and 2^20 buckets)")
+    ap.add_argument("--many-tables", type=int, default=0, metavar="N",
+                    help="batching workload over N tables: per-table calls vs one plan launch")
     ap.add_argument("--insert-workload", action="store_true",
                     help="insert rate vs load in 65536-key batches, then delete 20%% and re-insert")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
@@ -77,7 +79,7 @@ def to_dev(a, dev):
 
 def lookup_source_digest() -> str:
     h = hashlib.sha256()
-    for f in ("ckpp_lookup.hip", "ckpp_device.h"):
+    for f in ("ckpp_lookup.hip", "ckpp_lookup_dev.h", "ckpp_device.h"):
         with open(os.path.join(ROOT, "paper_1712_09624_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -378,6 +380,128 @@ def insert_workload(dev, B=24, batch=65536):
             "retry_exhausted": stats["retry_exhausted"]}
 
 
+def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
+    """Batching workload: ntables independent tables (bucket counts
+    log-uniform over 2^10..2^18, loads U[0.6, 0.95], lookup batches
+    U[32, 4096], negative rates U[0, 1]), every table's batch served
+    (a) by one lookup call per table, eagerly and captured in a HIP graph,
+    and (b) by one plan launch, eagerly and captured in a HIP graph, after
+    the plan's launch shape is autotuned.  All four give the same answers,
+    checked against the workload's ground truth."""
+    import torch
+    from paper_1712_09624_amd import tune
+    from paper_1712_09624_amd.ckpp import Plan, Table
+    cfg = W.many_tables(ntables, seed)
+    tables, offsets, counts, chunks, want_f, want_v, lines = [], [], [], [], [], [], []
+    nkeys = 0
+    t0 = time.perf_counter()
+    nfail = torch.zeros(1, dtype=torch.int64, device=dev)
+    pos = 0
+    for i in range(ntables):
+        B, load = int(cfg["log2_buckets"][i]), float(cfg["load"][i])
+        n = W.keys_at_load(B, load)
+        keys = W.distinct_five_tuples(n, seed * 10000 + i, check=False)
+        vals = W.insertion_values(n, i << 32)
+        t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=dev.index)
+        t.insert(to_dev(keys, dev), to_dev(vals.view(np.int64), dev), nfailed=nfail)
+        look, neg, idx = W.lookup_mix(keys, int(cfg["batch"][i]), float(cfg["neg_rate"][i]),
+                                      seed * 10000 + i)
+        want_f.append((~neg).astype(np.uint8))
+        want_v.append(np.where(neg, np.uint64(0), vals[np.maximum(idx, 0)]))
+        tables.append(t)
+        offsets.append(pos)
+        counts.append(len(look))
+        chunks.append(look)
+        pos += len(look)
+        nkeys += n
+        if i % 128 == 127:
+            log(f"many tables: built {i + 1}/{ntables} ({nkeys} keys, {time.perf_counter() - t0:.1f}s)")
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    if int(nfail.item()):
+        raise RuntimeError(f"{int(nfail.item())} inserts failed while building the tables")
+    # algorithmic lines per lookup of each table, from its own statistics
+    neg_rate = np.array([1.0 - float(f.mean()) if len(f) else 0.0 for f in want_f])
+    for i, t in enumerate(tables):
+        el = expected_lines(t.stats())
+        lines.append(counts[i] * ((1.0 - neg_rate[i]) * el["cuckoopp_pos"]
+                                  + neg_rate[i] * el["cuckoopp_neg"]))
+    total = int(sum(counts))
+    alg_bytes = LINE * float(sum(lines)) + STREAM_BYTES * total
+    keys_d = to_dev(np.concatenate(chunks), dev)
+    wf, wv = np.concatenate(want_f), np.concatenate(want_v)
+    found = torch.empty(total, dtype=torch.uint8, device=dev)
+    vals_d = torch.empty(total, dtype=torch.int64, device=dev)
+    views = [(keys_d[o:o + c], found[o:o + c], vals_d[o:o + c]) for o, c in zip(offsets, counts)]
+
+    def check(what):
+        torch.cuda.synchronize()
+        if not (np.array_equal(found.cpu().numpy(), wf)
+                and np.array_equal(vals_d.cpu().numpy().view(np.uint64), wv)):
+            raise RuntimeError(f"{what}: wrong answers")
+        found.fill_(0xAB)
+        vals_d.fill_(-1)
+
+    def per_table():
+        for t, (k, f, v) in zip(tables, views):
+            t.lookup(k, "cuckoopp", found=f, values=v)
+
+    out = {"tables": ntables, "keys": nkeys, "lookups": total, "build_s": build_s,
+           "device_table_bytes": int(sum(256 << int(b) for b in cfg["log2_buckets"])),
+           "algorithmic_bytes": alg_bytes}
+    s = torch.cuda.current_stream(dev)
+    # (a) one call per table
+    per_table()
+    check("per-table calls")
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    ms = timed(per_table, reps, dev)
+    out["per_table_eager_us"] = ms * 1e3
+    out["per_table_eager_wall_us"] = (time.perf_counter() - w0) * 1e6 / (reps + 1)
+    g_tab = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_tab):
+        per_table()
+    g_tab.replay()
+    check("per-table graph")
+    out["per_table_graph_us"] = timed(g_tab.replay, reps, dev) * 1e3
+    # (b) one plan launch
+    plan = Plan(tables, offsets, counts)
+    plan.lookup(keys_d, found, vals_d)
+    check("plan (default shape)")
+    out["plan_default_shape"] = plan.get_launch()
+    out["plan_default_us"] = timed(lambda: plan.lookup(keys_d, found, vals_d), reps, dev) * 1e3
+    ranked = tune.tune_plan(plan, keys_d, found, vals_d, reps=tune_reps)
+    out["plan_tuned_shape"] = ranked[0][1]
+    out["plan_tune_top"] = [{"us": r[0] * 1e3, **r[1]} for r in ranked[:8]]
+    best_of = {}
+    for ms_, sh in ranked:  # fastest shape per (lookups per lane, schedule)
+        best_of.setdefault(f"per{sh['lookups_per_lane']}_sched{sh['schedule']}",
+                           {"us": ms_ * 1e3, **sh})
+    out["plan_tune_best_of"] = best_of
+    plan.lookup(keys_d, found, vals_d)
+    check("plan (tuned shape)")
+    out["plan_eager_us"] = timed(lambda: plan.lookup(keys_d, found, vals_d), reps, dev) * 1e3
+    g_plan = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_plan):
+        plan.lookup(keys_d, found, vals_d)
+    for _ in range(3):  # every replay is checked
+        g_plan.replay()
+        check("plan graph replay")
+    out["plan_graph_us"] = timed(g_plan.replay, reps, dev) * 1e3
+    del s
+    for k in ("per_table_eager", "per_table_graph", "plan_eager", "plan_graph"):
+        out[k + "_glookups"] = total / (out[k + "_us"] * 1e-6) / 1e9
+    out["plan_graph_over_per_table_graph"] = out["per_table_graph_us"] / out["plan_graph_us"]
+    out["plan_graph_over_per_table_eager"] = out["per_table_eager_us"] / out["plan_graph_us"]
+    out["plan_achieved_GBps"] = alg_bytes / (out["plan_eager_us"] * 1e-6) / 1e9
+    out["plan_frac_hbm_peak"] = out["plan_achieved_GBps"] / HBM_PEAK_GBS
+    del g_plan, g_tab
+    plan.close()
+    for t in tables:
+        t.close()
+    return out
+
+
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d DIR/p4_trace -o core -- "
              "python3 bench.py --core-only --steps 5 --warmup 2",
@@ -494,6 +618,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_calib:
         copy_calibration(dev)
+        return
+    if args.many_tables:
+        print(json.dumps({"many_tables": many_table_bench(dev, args.many_tables)}), flush=True)
         return
     if args.insert_workload:
         print(json.dumps({"insert_workload": insert_workload(dev)}), flush=True)

@@ -64,6 +64,9 @@ enum {
     CKPP_EINVAL = 1,  /* bad argument: null, misaligned, out of range */
     CKPP_ENOMEM = 2,  /* device allocation failed */
     CKPP_EDEVICE = 3, /* HIP runtime error (launch, copy, device) */
+    CKPP_EBUSY = 4,   /* not admitted now (serving budget or queue full):
+                         retry after completions */
+    CKPP_ETIMEOUT = 5 /* a wait ran out of time */
 };
 
 /* Per-key insert status (written to d_status). */
@@ -219,6 +222,197 @@ typedef struct {
 
 int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg);
 int ckpp_get_lookup_launch(const ckpp_table *t, ckpp_launch_t *cfg);
+
+/* ---- Many tables, one launch -------------------------------------------
+ * A plan serves the lookup batches of many tables (each one a Sec. 2 /
+ * Sec. 4.1 lookup batch, exactly as ckpp_lookup_batch computes it) in a
+ * single launch of a persistent kernel: the batches are cut into work items
+ * of at most passes_per_item * 64 * lookups_per_lane lookups of one table,
+ * and each wavefront takes the next item from a device counter until none
+ * is left.  The grouping is this library's scheduling, not the paper's; the
+ * results are those of one ckpp_lookup_batch call per table. */
+typedef struct ckpp_plan ckpp_plan;
+
+/* Launch shape of a plan's kernel.  lookups_per_lane: 1 or 2 (as in
+ * ckpp_launch_t); block: 64, 128 or 256; blocks_per_cu: 1..64, the
+ * persistent grid is blocks_per_cu blocks per compute unit (at most one
+ * wavefront per work item); passes_per_item: 1..64; schedule:
+ * CKPP_PLAN_STATIC (wavefront w runs items w, w + W, ... for W wavefronts)
+ * or CKPP_PLAN_DYNAMIC (each wavefront takes the next item from a device
+ * counter). */
+enum { CKPP_PLAN_STATIC = 0, CKPP_PLAN_DYNAMIC = 1 };
+
+typedef struct {
+    uint32_t lookups_per_lane;
+    uint32_t block;
+    uint32_t blocks_per_cu;
+    uint32_t passes_per_item;
+    uint32_t schedule;
+} ckpp_plan_launch_t;
+
+typedef struct {
+    uint32_t ntables;
+    uint32_t nitems;       /* work items under the current launch shape */
+    uint64_t lookups;      /* sum of the batch sizes */
+    uint64_t key_span;     /* max over tables of offset + count */
+} ckpp_plan_info_t;
+
+/* Builds a plan over ntables >= 1 tables, all on one device: table i's
+ * batch is keys [h_offsets[i], h_offsets[i] + h_counts[i]) of the key
+ * array later passed to ckpp_plan_lookup, and its results go to the same
+ * positions of the output arrays; the ranges must not overlap (a count may
+ * be 0).  h_modes (nullable: all CKPP_LOOKUP_DEFAULT) gives each table's
+ * lookup mode; CKPP_LOOKUP_DEFAULT on a plain table is CKPP_LOOKUP_BOTH.
+ * The plan keeps the tables' device addresses, not the tables: it must be
+ * destroyed before any of them, and inserts and deletes between plan
+ * lookups are seen by the next one.  Host arrays are read during the call
+ * only.  Starts with the launch shape {1, 128, 8, 1, CKPP_PLAN_STATIC}.
+ * Errors: CKPP_EINVAL (null arguments, ntables 0, overlapping ranges, bad
+ * mode, tables on different devices), CKPP_ENOMEM, CKPP_EDEVICE. */
+int ckpp_plan_create(ckpp_plan **out, ckpp_table *const *tables, uint32_t ntables,
+                     const uint64_t *h_offsets, const uint64_t *h_counts,
+                     const uint32_t *h_modes);
+
+/* Frees the plan after its device is idle.  A null plan is a no-op. */
+int ckpp_plan_destroy(ckpp_plan *p);
+
+/* Runs every table's batch: d_keys holds key_span 16-byte keys (16-byte
+ * aligned), d_found key_span bytes and d_values key_span u64 (8-byte
+ * aligned); positions outside every range are neither read nor written.
+ * One kernel launch on `stream`, no allocation, no memory set: the call may
+ * be captured in a HIP graph.  The dynamic schedule's work counter lives in
+ * the plan's device memory, so two launches of one plan must not overlap in
+ * time (order them on one stream).  Must not run concurrently with inserts or deletes on its
+ * tables.  Errors: CKPP_EINVAL (null or misaligned pointers). */
+int ckpp_plan_lookup(ckpp_plan *p, const void *d_keys, uint8_t *d_found, uint64_t *d_values,
+                     void *stream);
+
+/* Sets the launch shape (rebuilds the work items: synchronizes the device,
+ * not for use under graph capture).  Errors: CKPP_EINVAL (out of range). */
+int ckpp_plan_set_launch(ckpp_plan *p, const ckpp_plan_launch_t *cfg);
+int ckpp_plan_get_launch(const ckpp_plan *p, ckpp_plan_launch_t *cfg);
+int ckpp_plan_info(const ckpp_plan *p, ckpp_plan_info_t *out);
+
+/* ---- Serving: a device-resident request loop --------------------------
+ * A server runs one persistent kernel over a table that stays in device
+ * memory.  Producers place the operations of a burst in three device rings
+ * (lookups: 16-byte keys; inserts: keys and u64 values; deletes: keys) at
+ * the positions following the previous burst's, then submit the burst's
+ * three counts.  The loop gathers every burst submitted before it starts a
+ * round (continuous batching: bursts that arrive while a round runs join
+ * the next one) and runs the round's lookups, then its inserts, then its
+ * deletes, each phase over all of the round's bursts at once, with grid-wide
+ * barriers between the phases; rounds run in submission order.  So a lookup
+ * sees every insert and delete of the bursts of earlier rounds and none of
+ * its own round's, and a burst's results do not depend on which other
+ * bursts share its round as long as their writes concern other keys.  Each
+ * operation is the Sec. 2 / Sec. 4.1 operation of ckpp_lookup_batch,
+ * ckpp_insert_batch or ckpp_delete_batch; results land in the rings at the
+ * operation's position.  Admission: a burst is accepted only while the
+ * operations submitted and not completed stay within the budget of each
+ * ring (and fewer than 4096 bursts are in flight); otherwise CKPP_EBUSY.
+ * Ring position of operation number i of a kind: i mod capacity.
+ * When no burst arrives for idle_ms the kernel exits; the next submit
+ * relaunches it. */
+typedef struct ckpp_server ckpp_server;
+
+typedef struct {
+    uint64_t capacity;      /* slots of each ring: a power of two, 2^6..2^30 */
+    uint64_t budget;        /* ops of one kind in flight at most (<= capacity) */
+    uint32_t mode;          /* lookup mode, CKPP_LOOKUP_* (DEFAULT: Cuckoo++,
+                               both buckets on a plain table) */
+    uint32_t blocks_per_cu; /* persistent grid: 1..4 blocks of 256 threads
+                               per compute unit, all co-resident */
+    uint32_t idle_ms;       /* 1..60000 */
+    uint32_t reserved;      /* 0 */
+} ckpp_server_config_t;
+
+/* Device rings owned by the server (freed by ckpp_server_destroy). */
+typedef struct {
+    void *d_lookup_keys;        /* capacity x 16 bytes */
+    uint8_t *d_lookup_found;    /* capacity bytes */
+    uint64_t *d_lookup_values;  /* capacity u64 */
+    void *d_insert_keys;        /* capacity x 16 bytes */
+    uint64_t *d_insert_values;  /* capacity u64 */
+    uint8_t *d_insert_status;   /* capacity bytes (CKPP_INSERTED/UPDATED/FAILED) */
+    void *d_delete_keys;        /* capacity x 16 bytes */
+    uint8_t *d_delete_found;    /* capacity bytes */
+    uint64_t capacity;
+} ckpp_server_rings_t;
+
+enum {
+    CKPP_SERVER_STOPPED = 0, /* no loop kernel running */
+    CKPP_SERVER_RUNNING = 1,
+    CKPP_SERVER_EXITING = 2, /* the loop is deciding to exit for idleness */
+    CKPP_SERVER_ABORTED = 3  /* a grid barrier ran out of time: the loop
+                                stopped; the server is unusable */
+};
+
+typedef struct {
+    uint64_t submitted;   /* bursts */
+    uint64_t completed;   /* bursts whose results are in the rings */
+    uint64_t lookup_tail, insert_tail, delete_tail; /* ops submitted per kind */
+    uint64_t rounds;      /* rounds the loop ran */
+    uint64_t launches;    /* loop kernel launches (1 + restarts) */
+    uint32_t state;       /* CKPP_SERVER_* */
+    uint32_t grid;        /* blocks of the loop kernel */
+} ckpp_server_status_t;
+
+/* Creates a server on table t (the table must not be used by other calls
+ * while the server exists) and launches its loop.
+ * Errors: CKPP_EINVAL (bad config), CKPP_ENOMEM, CKPP_EDEVICE. */
+int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_config_t *cfg);
+
+int ckpp_server_rings(const ckpp_server *s, ckpp_server_rings_t *out);
+
+/* Kinds of operations (ring selectors). */
+enum { CKPP_OP_LOOKUP = 0, CKPP_OP_INSERT = 1, CKPP_OP_DELETE = 2 };
+
+/* Copies n operations of one kind from the caller's device buffers into the
+ * ring slots of operation numbers pos .. pos + n - 1 (slot = number mod
+ * capacity), ordered on `stream` (device-to-device copies; the caller
+ * synchronizes before submitting).  d_values: the insert values (inserts
+ * only, else null).  Errors: CKPP_EINVAL (n > capacity, null pointers). */
+int ckpp_server_put(ckpp_server *s, uint32_t kind, uint64_t pos, const void *d_keys,
+                    const uint64_t *d_values, uint32_t n, void *stream);
+
+/* Copies the results of operations pos .. pos + n - 1 of one kind out of the
+ * rings, ordered on `stream`: lookups -> d_flags (found) and d_values;
+ * inserts -> d_flags (status); deletes -> d_flags (found).  Valid once the
+ * operations' bursts are complete and before their slots are reused. */
+int ckpp_server_get(ckpp_server *s, uint32_t kind, uint64_t pos, uint32_t n, uint8_t *d_flags,
+                    uint64_t *d_values, void *stream);
+
+/* Submits the next burst: its ops are at ring positions tail .. tail + n - 1
+ * (mod capacity) of each kind, tail as ckpp_server_status reports before the
+ * call, already written (and the writes complete) by the caller.  *burst
+ * (nullable) receives the burst's number.  Errors: CKPP_EBUSY (over the
+ * budget or too many bursts in flight: nothing was submitted),
+ * CKPP_EDEVICE (the loop aborted or could not be relaunched). */
+int ckpp_server_submit(ckpp_server *s, uint32_t n_lookup, uint32_t n_insert, uint32_t n_delete,
+                       uint64_t *burst);
+
+int ckpp_server_status(ckpp_server *s, ckpp_server_status_t *out);
+
+/* Waits until bursts 0..burst are complete.  Errors: CKPP_ETIMEOUT,
+ * CKPP_EDEVICE (the loop aborted). */
+int ckpp_server_wait(ckpp_server *s, uint64_t burst, uint32_t timeout_ms);
+
+/* Open-loop replay (measurement): submits burst i of a pre-staged stream at
+ * h_arrival_s[i] seconds after the call (later if the budget does not admit
+ * it yet, in order), and records when it was admitted and when the host saw
+ * it complete, in seconds after the call (h_admit_s, h_done_s: nbursts
+ * each).  The stream's ops must already be in the rings at the positions
+ * the bursts will take.  Errors: CKPP_ETIMEOUT (not all done within
+ * timeout_s), CKPP_EDEVICE. */
+int ckpp_server_replay(ckpp_server *s, uint64_t nbursts, const uint32_t *h_nlookup,
+                       const uint32_t *h_ninsert, const uint32_t *h_ndelete,
+                       const double *h_arrival_s, double *h_admit_s, double *h_done_s,
+                       double timeout_s);
+
+/* Stops the loop (after the bursts already submitted complete), frees the
+ * server.  A null server is a no-op. */
+int ckpp_server_destroy(ckpp_server *s);
 
 /* Measurement kernel for the roofline of the lookups: reads `nreads`
  * granules of `granule` bytes (16, 32, 64 or 128, aligned) at uniformly

@@ -14,7 +14,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libckpp.so")
-SOURCES = ["ckpp_api.hip", "ckpp_lookup.hip", "ckpp_update.hip", "ckpp_aux.hip"]
+SOURCES = ["ckpp_api.hip", "ckpp_lookup.hip", "ckpp_plan.hip", "ckpp_serve.hip", "ckpp_update.hip",
+           "ckpp_aux.hip"]
 ARCH = os.environ.get("CKPP_OFFLOAD_ARCH", "gfx950")
 
 

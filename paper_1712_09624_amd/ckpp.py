@@ -77,6 +77,72 @@ class _Launch(ctypes.Structure):
     ]
 
 
+class _PlanLaunch(ctypes.Structure):
+    _fields_ = [
+        ("lookups_per_lane", ctypes.c_uint32),
+        ("block", ctypes.c_uint32),
+        ("blocks_per_cu", ctypes.c_uint32),
+        ("passes_per_item", ctypes.c_uint32),
+        ("schedule", ctypes.c_uint32),
+    ]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("ntables", ctypes.c_uint32),
+        ("nitems", ctypes.c_uint32),
+        ("lookups", ctypes.c_uint64),
+        ("key_span", ctypes.c_uint64),
+    ]
+
+
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("capacity", ctypes.c_uint64),
+        ("budget", ctypes.c_uint64),
+        ("mode", ctypes.c_uint32),
+        ("blocks_per_cu", ctypes.c_uint32),
+        ("idle_ms", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class _ServerRings(ctypes.Structure):
+    _fields_ = [
+        ("d_lookup_keys", ctypes.c_void_p),
+        ("d_lookup_found", ctypes.c_void_p),
+        ("d_lookup_values", ctypes.c_void_p),
+        ("d_insert_keys", ctypes.c_void_p),
+        ("d_insert_values", ctypes.c_void_p),
+        ("d_insert_status", ctypes.c_void_p),
+        ("d_delete_keys", ctypes.c_void_p),
+        ("d_delete_found", ctypes.c_void_p),
+        ("capacity", ctypes.c_uint64),
+    ]
+
+
+class _ServerStatus(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64),
+        ("lookup_tail", ctypes.c_uint64),
+        ("insert_tail", ctypes.c_uint64),
+        ("delete_tail", ctypes.c_uint64),
+        ("rounds", ctypes.c_uint64),
+        ("launches", ctypes.c_uint64),
+        ("state", ctypes.c_uint32),
+        ("grid", ctypes.c_uint32),
+    ]
+
+
+EBUSY, ETIMEOUT = 4, 5
+SERVER_STOPPED, SERVER_RUNNING, SERVER_EXITING, SERVER_ABORTED = 0, 1, 2, 3
+
+# launch shape a new plan starts with (ckpp_plan_create sets the same)
+PLAN_STATIC, PLAN_DYNAMIC = 0, 1
+DEFAULT_PLAN_LAUNCH = {"lookups_per_lane": 1, "block": 128, "blocks_per_cu": 8,
+                       "passes_per_item": 1, "schedule": PLAN_STATIC}
+
 _lib = None
 
 # (name, restype, argtypes) of every exported entry point
@@ -95,6 +161,21 @@ SIGNATURES = [
     ("ckpp_info", _I, [_VP, ctypes.POINTER(_Info)]),
     ("ckpp_set_lookup_launch", _I, [_VP, ctypes.POINTER(_Launch)]),
     ("ckpp_get_lookup_launch", _I, [_VP, ctypes.POINTER(_Launch)]),
+    ("ckpp_plan_create", _I, [ctypes.POINTER(_VP), ctypes.POINTER(_VP), _U32, _VP, _VP, _VP]),
+    ("ckpp_plan_destroy", _I, [_VP]),
+    ("ckpp_plan_lookup", _I, [_VP, _VP, _VP, _VP, _VP]),
+    ("ckpp_plan_set_launch", _I, [_VP, ctypes.POINTER(_PlanLaunch)]),
+    ("ckpp_plan_get_launch", _I, [_VP, ctypes.POINTER(_PlanLaunch)]),
+    ("ckpp_plan_info", _I, [_VP, ctypes.POINTER(_PlanInfo)]),
+    ("ckpp_server_create", _I, [ctypes.POINTER(_VP), _VP, ctypes.POINTER(_ServerConfig)]),
+    ("ckpp_server_rings", _I, [_VP, ctypes.POINTER(_ServerRings)]),
+    ("ckpp_server_put", _I, [_VP, _U32, _U64, _VP, _VP, _U32, _VP]),
+    ("ckpp_server_get", _I, [_VP, _U32, _U64, _U32, _VP, _VP, _VP]),
+    ("ckpp_server_submit", _I, [_VP, _U32, _U32, _U32, ctypes.POINTER(_U64)]),
+    ("ckpp_server_status", _I, [_VP, ctypes.POINTER(_ServerStatus)]),
+    ("ckpp_server_wait", _I, [_VP, _U64, _U32]),
+    ("ckpp_server_replay", _I, [_VP, _U64, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double]),
+    ("ckpp_server_destroy", _I, [_VP]),
     ("ckpp_probe_random_reads", _I, [_VP, _U64, _U32, _U64, _U32, _U32, _U32, _U32, _U64, _VP,
                                      _VP]),
     ("ckpp_strerror", ctypes.c_char_p, [_I]),
@@ -310,6 +391,209 @@ class Table:
         _check(self.lib.ckpp_get_lookup_launch(self._h, ctypes.byref(cfg)),
                "ckpp_get_lookup_launch")
         return {f: getattr(cfg, f) for f, _ in _Launch._fields_}
+
+
+class Plan:
+    """Lookup batches of many tables served by one persistent launch (see
+    ckpp_plan_create in include/ckpp.h).  ``offsets[i]``/``counts[i]`` place
+    table i's batch in the concatenated key array; ``modes`` (names or
+    numbers, default Cuckoo++) gives each table's lookup mode."""
+
+    def __init__(self, tables, offsets, counts, modes=None):
+        self.lib = load()
+        self.tables = list(tables)  # kept alive for the plan's lifetime
+        nt = len(self.tables)
+        handles = (ctypes.c_void_p * nt)(*[t.handle for t in self.tables])
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        cnt = np.ascontiguousarray(counts, dtype=np.uint64)
+        if off.size != nt or cnt.size != nt:
+            raise CkppError("one offset and one count per table")
+        md = None
+        if modes is not None:
+            md = np.ascontiguousarray([MODES[m] if isinstance(m, str) else int(m) for m in modes],
+                                      dtype=np.uint32)
+            if md.size != nt:
+                raise CkppError("one mode per table")
+        h = ctypes.c_void_p()
+        rc = self.lib.ckpp_plan_create(ctypes.byref(h), handles, nt, off.ctypes.data,
+                                       cnt.ctypes.data, md.ctypes.data if md is not None else None)
+        _check(rc, "ckpp_plan_create")
+        self._h = h
+        self.device = self.tables[0].device
+        self.key_span = self.info()["key_span"]
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.ckpp_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def lookup(self, keys, found=None, values=None, stream=None):
+        """Enqueues the plan's lookups; returns (found u8[span], values i64[span])."""
+        torch = _torch()
+        kp, n = _keys_ptr(keys)
+        if n < self.key_span:
+            raise CkppError(f"the plan reads {self.key_span} keys, got {n}")
+        dev = torch.device("cuda", self.device)
+        if found is None:
+            found = torch.zeros(self.key_span, dtype=torch.uint8, device=dev)
+        if values is None:
+            values = torch.zeros(self.key_span, dtype=torch.int64, device=dev)
+        if found.numel() < self.key_span or values.numel() < self.key_span:
+            raise CkppError("output arrays shorter than the plan's key span")
+        rc = self.lib.ckpp_plan_lookup(self._h, kp, found.data_ptr(), values.data_ptr(),
+                                       _stream_handle(stream))
+        _check(rc, "ckpp_plan_lookup")
+        return found, values
+
+    def set_launch(self, lookups_per_lane=DEFAULT_PLAN_LAUNCH["lookups_per_lane"],
+                   block=DEFAULT_PLAN_LAUNCH["block"],
+                   blocks_per_cu=DEFAULT_PLAN_LAUNCH["blocks_per_cu"],
+                   passes_per_item=DEFAULT_PLAN_LAUNCH["passes_per_item"],
+                   schedule=DEFAULT_PLAN_LAUNCH["schedule"]):
+        cfg = _PlanLaunch(lookups_per_lane, block, blocks_per_cu, passes_per_item, schedule)
+        _check(self.lib.ckpp_plan_set_launch(self._h, ctypes.byref(cfg)), "ckpp_plan_set_launch")
+
+    def get_launch(self) -> dict:
+        cfg = _PlanLaunch()
+        _check(self.lib.ckpp_plan_get_launch(self._h, ctypes.byref(cfg)), "ckpp_plan_get_launch")
+        return {f: getattr(cfg, f) for f, _ in _PlanLaunch._fields_}
+
+    def info(self) -> dict:
+        inf = _PlanInfo()
+        _check(self.lib.ckpp_plan_info(self._h, ctypes.byref(inf)), "ckpp_plan_info")
+        return {f: getattr(inf, f) for f, _ in _PlanInfo._fields_}
+
+
+class Server:
+    """A device-resident serving loop over one table (see ckpp_server_create
+    in include/ckpp.h).  ``put`` copies a burst's operations into the rings
+    at the next positions, ``submit`` hands the burst to the loop, ``get``
+    copies results out once the burst is complete."""
+
+    KINDS = {"lookup": 0, "insert": 1, "delete": 2}
+
+    def __init__(self, table, capacity=1 << 20, budget=None, mode="cuckoopp", blocks_per_cu=1,
+                 idle_ms=200):
+        self.lib = load()
+        self.table = table
+        cfg = _ServerConfig(int(capacity), int(budget or capacity),
+                            MODES[mode] if isinstance(mode, str) else int(mode),
+                            int(blocks_per_cu), int(idle_ms), 0)
+        h = ctypes.c_void_p()
+        _check(self.lib.ckpp_server_create(ctypes.byref(h), table.handle, ctypes.byref(cfg)),
+               "ckpp_server_create")
+        self._h = h
+        r = _ServerRings()
+        _check(self.lib.ckpp_server_rings(self._h, ctypes.byref(r)), "ckpp_server_rings")
+        self.capacity = int(r.capacity)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self.lib.ckpp_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def status(self) -> dict:
+        st = _ServerStatus()
+        _check(self.lib.ckpp_server_status(self._h, ctypes.byref(st)), "ckpp_server_status")
+        return {f: int(getattr(st, f)) for f, _ in _ServerStatus._fields_}
+
+    def put(self, kind: str, pos: int, keys, values=None, stream=None):
+        """Copies ops (device tensors) into the ring slots of op numbers
+        pos .. pos + n - 1 of a kind, then waits for the copies."""
+        kp, n = _keys_ptr(keys)
+        vp = None
+        if values is not None:
+            if values.numel() != n or values.element_size() != 8 or not values.is_contiguous():
+                raise CkppError("values must be n contiguous 64-bit integers")
+            vp = values.data_ptr()
+        torch = _torch()
+        if stream is None:
+            stream = torch.cuda.current_stream(self.table.device)
+        _check(self.lib.ckpp_server_put(self._h, self.KINDS[kind], int(pos), kp, vp, n,
+                                        _stream_handle(stream)), "ckpp_server_put")
+        stream.synchronize()
+
+    def put_burst(self, lookup_keys=None, insert_keys=None, insert_values=None,
+                  delete_keys=None):
+        """Puts one burst's operations at the next positions; returns the
+        counts and the first op number of each kind."""
+        st = self.status()
+        counts, first = [], []
+        for kind, keys, vals in (("lookup", lookup_keys, None), ("insert", insert_keys,
+                                                                 insert_values),
+                                 ("delete", delete_keys, None)):
+            n = 0 if keys is None else int(keys.shape[0])
+            pos = st[f"{kind}_tail"]
+            if n:
+                self.put(kind, pos, keys, vals)
+            counts.append(n)
+            first.append(pos)
+        return counts, first
+
+    def submit(self, n_lookup, n_insert=0, n_delete=0):
+        """Returns the burst number, or None when the budget does not admit it."""
+        b = ctypes.c_uint64()
+        rc = self.lib.ckpp_server_submit(self._h, int(n_lookup), int(n_insert), int(n_delete),
+                                         ctypes.byref(b))
+        if rc == EBUSY:
+            return None
+        _check(rc, "ckpp_server_submit")
+        return int(b.value)
+
+    def wait(self, burst, timeout_ms=10000):
+        _check(self.lib.ckpp_server_wait(self._h, int(burst), int(timeout_ms)), "ckpp_server_wait")
+
+    def get(self, kind: str, pos: int, n: int, stream=None):
+        """Results of ops pos .. pos + n - 1 of a kind: (found, values) for
+        lookups, status for inserts, found for deletes (device tensors,
+        ready once the stream is synchronized)."""
+        torch = _torch()
+        dev = torch.device("cuda", self.table.device)
+        flags = torch.empty(int(n), dtype=torch.uint8, device=dev)
+        vals = torch.empty(int(n), dtype=torch.int64, device=dev) if kind == "lookup" else None
+        _check(self.lib.ckpp_server_get(self._h, self.KINDS[kind], int(pos), int(n),
+                                        flags.data_ptr(), vals.data_ptr() if vals is not None
+                                        else None, _stream_handle(stream)), "ckpp_server_get")
+        return (flags, vals) if kind == "lookup" else flags
+
+    def replay(self, nlookup, ninsert, ndelete, arrival_s, timeout_s=60.0):
+        """Open-loop replay of a pre-staged stream; returns (admit_s, done_s)."""
+        n = len(arrival_s)
+        nl = np.ascontiguousarray(nlookup, dtype=np.uint32)
+        ni = np.ascontiguousarray(ninsert, dtype=np.uint32)
+        nd = np.ascontiguousarray(ndelete, dtype=np.uint32)
+        ar = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        adm = np.zeros(n, np.float64)
+        done = np.zeros(n, np.float64)
+        _check(self.lib.ckpp_server_replay(self._h, n, nl.ctypes.data, ni.ctypes.data,
+                                           nd.ctypes.data, ar.ctypes.data, adm.ctypes.data,
+                                           done.ctypes.data, float(timeout_s)),
+               "ckpp_server_replay")
+        return adm, done
 
 
 def probe_random_reads(buf, granule: int, nreads: int, per_lane: int, block: int, grid: int,

@@ -11,6 +11,9 @@
 
 namespace {
 
+using ckpp::DeviceGuard;
+using ckpp::dev_status;
+
 constexpr uint32_t kMaxLog2Buckets = 24;
 constexpr uint32_t kMaxKicksLimit = 4096;
 constexpr uint32_t kMaxPathLanes = 65536;
@@ -18,30 +21,7 @@ constexpr uint32_t kAccWords = 128;   // device accumulator words
 constexpr uint32_t kAccStats = 7 + CKPP_MOVED_BINS;
 constexpr uint32_t kAccRetry = 127;   // retry-bound counter (never cleared)
 
-// Makes the table's device current for the duration of a call.
-class DeviceGuard {
- public:
-  explicit DeviceGuard(int dev) : prev_(-1), ok_(true) {
-    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
-    if (prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
-    else prev_ = -1;
-  }
-  ~DeviceGuard() {
-    if (prev_ >= 0) (void)hipSetDevice(prev_);
-  }
-  bool ok() const { return ok_; }
-
- private:
-  int prev_;
-  bool ok_;
-};
-
 bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
-
-int dev_status(hipError_t e) {
-  if (e == hipSuccess) return CKPP_OK;
-  return e == hipErrorOutOfMemory ? CKPP_ENOMEM : CKPP_EDEVICE;
-}
 
 uint64_t nbuckets(const ckpp_table *t) { return 1ull << t->log2_buckets; }
 uint64_t table_bytes(const ckpp_table *t) { return 256ull << t->log2_buckets; }

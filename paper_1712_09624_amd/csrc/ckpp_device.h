@@ -98,8 +98,9 @@ __device__ __forceinline__ uint32_t make_meta(uint32_t moved, uint32_t busy, uin
   return (moved & 0xffffu) | ((busy & 0xffu) << 16) | ((sec & 0xffu) << 24);
 }
 
-// The filter passes iff both of the key's bits are set (Sec. 6: an equal
-// and a bitwise and).
+// The filter passes iff both of the key's bits are set: one AND of the
+// 64-bit filter with the key's two-bit mask and one comparison (the test
+// Sec. 6 counts as the whole run-time cost of the filter).
 __device__ __forceinline__ bool bloom_pass(uint4 q1, uint64_t bits) {
   const uint64_t bloom = (uint64_t)q1.x | ((uint64_t)q1.y << 32);
   return (bloom & bits) == bits;

@@ -21,12 +21,32 @@ struct ckpp_table {
 
 namespace ckpp {
 
+// One work item of a plan: lookups [start, start + count) of the
+// concatenated key batch, all of one table, with that table's parameters
+// (so a wave needs a single descriptor load per item).
+struct PlanItem {
+  const uint4 *tab;  // the table's buckets
+  uint64_t seed;     // its hash seed
+  uint64_t start;
+  uint32_t count;
+  uint32_t log2b;    // log2 of its bucket count
+  uint32_t mode;     // kMode* of its lookups
+  uint32_t table;    // index of the table in the plan
+};
+
 constexpr uint32_t kModeCuckoopp = 0;
 constexpr uint32_t kModeBoth = 1;
 constexpr uint32_t kModeOptimistic = 2;
 
 hipError_t launch_lookup(const ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
                          uint8_t *d_found, uint64_t *d_values, hipStream_t s);
+// One launch of the plan's persistent lookup kernel over its items.
+// d_ctr: two u32 counters (next item, finished waves), zero before the
+// launch and zero again after it.  two_buffers: some table uses the
+// pessimistic mode.
+hipError_t launch_plan(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr, bool two_buffers,
+                       const ckpp_plan_launch_t &L, int num_cus, const void *d_keys,
+                       uint8_t *d_found, uint64_t *d_values, hipStream_t s);
 hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t *d_values,
                          uint64_t n, uint8_t *d_status, uint64_t *d_nfailed, hipStream_t s);
 hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_found,
@@ -38,5 +58,28 @@ hipError_t launch_fill_zero(void *d, uint64_t bytes, hipStream_t s);
 hipError_t launch_probe(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t nreads,
                         uint32_t per_lane, uint32_t cooperative, uint32_t block, uint32_t grid,
                         uint64_t seed, uint64_t *d_sink, hipStream_t s);
+
+// Makes a device current for the duration of a call.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) : prev_(-1), ok_(true) {
+    if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
+    if (prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    else prev_ = -1;
+  }
+  ~DeviceGuard() {
+    if (prev_ >= 0) (void)hipSetDevice(prev_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_;
+  bool ok_;
+};
+
+inline int dev_status(hipError_t e) {
+  if (e == hipSuccess) return CKPP_OK;
+  return e == hipErrorOutOfMemory ? CKPP_ENOMEM : CKPP_EDEVICE;
+}
 
 }  // namespace ckpp

@@ -26,302 +26,204 @@
 // loaded while the current tile is processed; keys stream in and results
 // stream out with non-temporal accesses.
 
-#include "ckpp_device.h"
-#include "ckpp_internal.h"
+#include "ckpp_lookup_dev.h"
 
 namespace ckpp {
 namespace {
 
-constexpr uint32_t kNoFetch = 0xffffffffu;  // bucket indices are < 2^24
-
-// Lines of one wave: 64 lines x 8 quarters; lookup j's line at [8j, 8j+8).
-constexpr uint32_t kWaveQuarters = 64 * 8;
-
-// Cooperative fetch of one 128-byte line (half `half` of the bucket) for
-// every lookup of the wave whose `bucket` is not kNoFetch: in round k the
-// lanes 8g..8g+7 read the line of lookup 8k+g, lane r its quarter r, and
-// the line lands at lines[8(8k+g) .. 8(8k+g)+8).
-__device__ __forceinline__ void fetch_lines(uint4 *lines, const uint4 *tab, uint32_t bucket,
-                                            uint32_t half, uint32_t g, uint32_t r) {
-#pragma unroll
-  for (uint32_t k = 0; k < 8; ++k) {
-    const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
-    if (b != kNoFetch) {
-      const uint4 *src = tab + (uint64_t)b * kQuartersPerBucket + 8u * half + r;
-      __builtin_amdgcn_global_load_lds(
-          (const void __attribute__((address_space(1))) *)src,
-          (void __attribute__((address_space(3))) *)(lines + 64u * k), 16, 0, 0);
-    }
-  }
-}
-
-// Waits until the lines requested by this wave have landed in LDS (the
-// loads' counter drains once the data is written there); the compiler may
-// not move LDS reads above this point.
-__device__ __forceinline__ void lines_landed() {
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-__device__ __forceinline__ uint64_t quarter_value(uint4 q, uint32_t s) {
-  return (s & 1u) ? ((uint64_t)q.z | ((uint64_t)q.w << 32))
-                  : ((uint64_t)q.x | ((uint64_t)q.y << 32));
-}
-
-// Compares the key with the candidate slots `cand` (ascending) of a first
-// line (mine[0..7]); on a hit sets hit/val.
-__device__ __forceinline__ void match_line0(const uint4 *mine, uint32_t cand, uint4 key, bool &hit,
-                                            uint64_t &val) {
-  while (cand != 0u && !hit) {
-    const uint32_t s = (uint32_t)__builtin_ctz(cand);
-    cand &= cand - 1u;
-    if (key_eq(mine[2u + s], key)) {
-      hit = true;
-      val = quarter_value(mine[6u + (s >> 1)], s);
-    }
-  }
-}
-
-// Same for slots 4..7 on a second line (mine[0..7]).
-__device__ __forceinline__ void match_line1(const uint4 *mine, uint32_t cand, uint4 key, bool &hit,
-                                            uint64_t &val) {
-  while (cand != 0u && !hit) {
-    const uint32_t s = (uint32_t)__builtin_ctz(cand);
-    cand &= cand - 1u;
-    if (key_eq(mine[s - 4u], key)) {
-      hit = true;
-      val = quarter_value(mine[4u + ((s - 4u) >> 1)], s);
-    }
-  }
-}
-
+// One table's batch, one lookup per lane per pass; the grid strides over
+// the batch and each wave loads its next keys while its lines are in flight.
 template <uint32_t WAVES, uint32_t MODE>
 __global__ void __launch_bounds__(64 * WAVES)
-    lookup_lds(const uint4 *__restrict__ tab, const uint4 *__restrict__ keys, uint64_t n,
-               uint32_t log2b, uint64_t seed, uint8_t *__restrict__ found,
-               uint64_t *__restrict__ vals) {
+    lookup_lds(TableRef T, const uint4 *__restrict__ keys, uint64_t n,
+               uint8_t *__restrict__ found, uint64_t *__restrict__ vals) {
   constexpr uint32_t NB = MODE == kModeBoth ? 2 : 1;  // line buffers per wave
   __shared__ uint4 s_lines[WAVES * NB * kWaveQuarters];
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t g = lane >> 3, r = lane & 7u;
-  uint4 *lines = s_lines + (threadIdx.x >> 6) * NB * kWaveQuarters;
-  uint4 *lines_a = lines + (NB - 1) * kWaveQuarters;  // pessimistic: secondary lines
-  const uint4 *mine = lines + 8u * lane;
-  const uint4 *mine_a = lines_a + 8u * lane;
+  const Wave w = wave_lines<NB>(s_lines);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint4 key = i < n ? load_stream(keys + i) : make_uint4(0u, 0u, 0u, 0u);
+  uint4 key = i < n ? load_stream(keys + i) : zero4();
   // the wave stays together: its loop condition is the wave's first lookup
-  for (; i - lane < n; i += stride) {
-    const bool ok = i < n;
-    const uint64_t h = key_hash(key, seed);
-    const KeyFields f = key_fields(h, log2b);
-    // first line of the primary (and, pessimistic mode, the secondary)
-    fetch_lines(lines, tab, ok ? f.p : kNoFetch, 0u, g, r);
-    if (MODE == kModeBoth) fetch_lines(lines_a, tab, ok ? f.a : kNoFetch, 0u, g, r);
-    const uint64_t inext = i + stride;
-    const uint4 knext = inext < n ? load_stream(keys + inext) : make_uint4(0u, 0u, 0u, 0u);
-    lines_landed();
-    bool hit = false;
-    uint64_t val = 0;
-    const uint4 t0 = mine[0], t1 = mine[1];
-    const uint32_t cand = ok ? (tag_eq_mask(t0, f.tag) & meta_busy(t1.z)) : 0u;
-    const bool pass = MODE != kModeCuckoopp || bloom_pass(t1, f.bloom_bits);
-    match_line0(mine, cand & 0xfu, key, hit, val);
-    // second line of the primary, for keys whose tag sits in slots 4..7
-    bool need = !hit && (cand & 0xf0u);
-    if (__builtin_amdgcn_ballot_w64(need)) {
-      fetch_lines(lines, tab, need ? f.p : kNoFetch, 1u, g, r);
-      lines_landed();
-      if (need) match_line1(mine, cand & 0xf0u, key, hit, val);
-    }
-    // secondary bucket
-    need = ok && !hit && pass;
-    if (__builtin_amdgcn_ballot_w64(need)) {
-      if (MODE != kModeBoth) {
-        fetch_lines(lines, tab, need ? f.a : kNoFetch, 0u, g, r);
-        lines_landed();
-      }
-      uint32_t cand2 = 0u;
-      if (need) {
-        const uint4 u0 = mine_a[0], u1 = mine_a[1];
-        cand2 = tag_eq_mask(u0, f.tag) & meta_busy(u1.z);
-        match_line0(mine_a, cand2 & 0xfu, key, hit, val);
-      }
-      need = need && !hit && (cand2 & 0xf0u);
-      if (__builtin_amdgcn_ballot_w64(need)) {
-        fetch_lines(lines_a, tab, need ? f.a : kNoFetch, 1u, g, r);
-        lines_landed();
-        if (need) match_line1(mine_a, cand2 & 0xf0u, key, hit, val);
-      }
-    }
-    if (ok) {
-      __builtin_nontemporal_store((uint8_t)(hit ? 1 : 0), found + i);
-      __builtin_nontemporal_store(hit ? val : 0ull, vals + i);
-    }
+  for (; i - w.lane < n; i += stride) {
+    uint4 knext;
+    lds_pass<MODE>(w, T, key, i < n, found + i, vals + i, [&] {
+      const uint64_t inext = i + stride;
+      knext = inext < n ? load_stream(keys + inext) : zero4();
+    });
     key = knext;
   }
 }
 
-// Register-landing counterpart of fetch_lines: the same rounds, but the
-// quarter arrives in q[k] of the fetching lane; park_lines() later writes
-// the quarters to LDS in exactly the layout fetch_lines produces.
-__device__ __forceinline__ void fetch_lines_reg(uint4 (&q)[8], const uint4 *tab, uint32_t bucket,
-                                                uint32_t half, uint32_t g, uint32_t r) {
-#pragma unroll
-  for (uint32_t k = 0; k < 8; ++k) {
-    const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
-    q[k] = make_uint4(0u, 0u, 0u, 0u);
-    if (b != kNoFetch) q[k] = tab[(uint64_t)b * kQuartersPerBucket + 8u * half + r];
-  }
-}
-
-__device__ __forceinline__ void park_lines(uint4 *lines, const uint4 (&q)[8], uint32_t lane) {
-#pragma unroll
-  for (uint32_t k = 0; k < 8; ++k) lines[64u * k + lane] = q[k];
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-}
-
-// Lookup state of one lookup owned by a lane.
-struct Look {
-  uint4 key;
-  KeyFields f;
-  bool ok, hit, pass;
-  uint32_t cand;
-  uint64_t val;
-};
-
-__device__ __forceinline__ void first_line(const uint4 *mine, Look &L, uint32_t mode) {
-  const uint4 t0 = mine[0], t1 = mine[1];
-  L.cand = L.ok ? (tag_eq_mask(t0, L.f.tag) & meta_busy(t1.z)) : 0u;
-  L.pass = mode != kModeCuckoopp || bloom_pass(t1, L.f.bloom_bits);
-  match_line0(mine, L.cand & 0xfu, L.key, L.hit, L.val);
-}
-
-// Two lookups per lane (lookups tile + lane and tile + 64 + lane): for each
-// phase the lines of the first 64 land in LDS directly, those of the other
-// 64 in registers, which are parked in LDS once the first 64 have been
-// analysed -- twice the line requests in flight for the same LDS.
+// One table's batch, two lookups per lane per pass (lookups w0 + lane and
+// w0 + 64 + lane of the wave's 128-lookup tile).
 template <uint32_t WAVES, uint32_t MODE>
 __global__ void __launch_bounds__(64 * WAVES)
-    lookup_dual(const uint4 *__restrict__ tab, const uint4 *__restrict__ keys, uint64_t n,
-                uint32_t log2b, uint64_t seed, uint8_t *__restrict__ found,
-                uint64_t *__restrict__ vals) {
-  static_assert(MODE != kModeBoth, "the pessimistic mode uses lookup_lds");
+    lookup_dual(TableRef T, const uint4 *__restrict__ keys, uint64_t n,
+                uint8_t *__restrict__ found, uint64_t *__restrict__ vals) {
   __shared__ uint4 s_lines[WAVES * kWaveQuarters];
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t g = lane >> 3, r = lane & 7u;
-  uint4 *lines = s_lines + (threadIdx.x >> 6) * kWaveQuarters;
-  const uint4 *mine = lines + 8u * lane;
+  const Wave w = wave_lines<1>(s_lines);
+  const uint32_t lane = w.lane;
   const uint64_t wave0 = ((uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 128u;
   const uint64_t stride = (uint64_t)gridDim.x * WAVES * 128u;
-  uint4 ka = wave0 + lane < n ? load_stream(keys + wave0 + lane) : make_uint4(0u, 0u, 0u, 0u);
-  uint4 kb = wave0 + 64u + lane < n ? load_stream(keys + wave0 + 64u + lane)
-                                    : make_uint4(0u, 0u, 0u, 0u);
+  uint4 ka = wave0 + lane < n ? load_stream(keys + wave0 + lane) : zero4();
+  uint4 kb = wave0 + 64u + lane < n ? load_stream(keys + wave0 + 64u + lane) : zero4();
   for (uint64_t w0 = wave0; w0 < n; w0 += stride) {
-    Look A, Bq;
-    A.key = ka;
-    Bq.key = kb;
-    A.ok = w0 + lane < n;
-    Bq.ok = w0 + 64u + lane < n;
-    A.f = key_fields(key_hash(A.key, seed), log2b);
-    Bq.f = key_fields(key_hash(Bq.key, seed), log2b);
-    A.hit = Bq.hit = false;
-    A.val = Bq.val = 0ull;
-    uint4 q[8];
-    // phase 1: primary first lines
-    fetch_lines(lines, tab, A.ok ? A.f.p : kNoFetch, 0u, g, r);
-    fetch_lines_reg(q, tab, Bq.ok ? Bq.f.p : kNoFetch, 0u, g, r);
-    const uint64_t nx = w0 + stride;
-    ka = nx + lane < n ? load_stream(keys + nx + lane) : make_uint4(0u, 0u, 0u, 0u);
-    kb = nx + 64u + lane < n ? load_stream(keys + nx + 64u + lane) : make_uint4(0u, 0u, 0u, 0u);
-    lines_landed();
-    first_line(mine, A, MODE);
-    park_lines(lines, q, lane);
-    first_line(mine, Bq, MODE);
-    // phase 2: primary second lines
-    bool na = !A.hit && (A.cand & 0xf0u), nb = !Bq.hit && (Bq.cand & 0xf0u);
-    if (__builtin_amdgcn_ballot_w64(na || nb)) {
-      fetch_lines(lines, tab, na ? A.f.p : kNoFetch, 1u, g, r);
-      fetch_lines_reg(q, tab, nb ? Bq.f.p : kNoFetch, 1u, g, r);
-      lines_landed();
-      if (na) match_line1(mine, A.cand & 0xf0u, A.key, A.hit, A.val);
-      park_lines(lines, q, lane);
-      if (nb) match_line1(mine, Bq.cand & 0xf0u, Bq.key, Bq.hit, Bq.val);
-    }
-    // phase 3: secondary first lines
-    na = A.ok && !A.hit && A.pass;
-    nb = Bq.ok && !Bq.hit && Bq.pass;
-    if (__builtin_amdgcn_ballot_w64(na || nb)) {
-      fetch_lines(lines, tab, na ? A.f.a : kNoFetch, 0u, g, r);
-      fetch_lines_reg(q, tab, nb ? Bq.f.a : kNoFetch, 0u, g, r);
-      lines_landed();
-      uint32_t ca = 0u, cb = 0u;
-      if (na) {
-        ca = tag_eq_mask(mine[0], A.f.tag) & meta_busy(mine[1].z);
-        match_line0(mine, ca & 0xfu, A.key, A.hit, A.val);
+    const uint64_t ia = w0 + lane, ib = w0 + 64u + lane;
+    uint4 na, nb;
+    dual_pass<MODE>(w, T, ka, ia < n, kb, ib < n, found + ia, vals + ia, found + ib, vals + ib,
+                    [&] {
+                      const uint64_t nx = w0 + stride;
+                      na = nx + lane < n ? load_stream(keys + nx + lane) : zero4();
+                      nb = nx + 64u + lane < n ? load_stream(keys + nx + 64u + lane) : zero4();
+                    });
+    ka = na;
+    kb = nb;
+  }
+}
+
+// The wave's next work item: lane 0 takes a ticket from the plan's counter
+// and the wave shares it.
+__device__ __forceinline__ uint32_t take_item(uint32_t *ctr, uint32_t lane) {
+  uint32_t v = 0u;
+  if (lane == 0u) v = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+// The item after `prev` for this wave: the wave's own stride through the
+// list (static schedule) or the next ticket (dynamic schedule); once past
+// the end, it stays there.
+template <bool DYN>
+__device__ __forceinline__ uint32_t next_item(uint32_t prev, uint32_t stride, uint32_t nitems,
+                                              uint32_t *ctr, uint32_t lane) {
+  if (prev >= nitems) return prev;
+  return DYN ? take_item(ctr, lane) : prev + stride;
+}
+
+// Keys of one pass of an item: lookups off + lane (and off + 64 + lane).
+template <uint32_t PER>
+__device__ __forceinline__ void item_keys(const uint4 *keys, const PlanItem &I, uint32_t off,
+                                          uint32_t lane, uint4 &ka, uint4 &kb) {
+  const uint32_t o = off + lane;
+  ka = o < I.count ? load_stream(keys + I.start + o) : zero4();
+  if (PER == 2) kb = o + 64u < I.count ? load_stream(keys + I.start + o + 64u) : zero4();
+}
+
+// A plan's batches in one persistent launch.  Each wave runs work items (a
+// range of one table's batch, in passes of PER * 64 lookups) in a
+// three-deep pipeline: while item `cur` runs, the descriptor of the next
+// item is already loaded and the index of the one after is known; the last
+// pass of `cur` loads the next item's first keys, the descriptor after it
+// and the next index, all independent loads issued while that pass's lines
+// are in flight.  DYN: items are handed out by a device counter (the wave
+// that finishes last rewinds it, so the next launch or graph replay starts
+// from zero without a memory set); else wave w runs items w, w + W, ...
+// NB = 2 gives each wave the second line buffer of the pessimistic mode;
+// with NB = 1 the host passes no pessimistic item.
+template <uint32_t WAVES, uint32_t NB, uint32_t PER, bool DYN>
+__global__ void __launch_bounds__(64 * WAVES)
+    lookup_plan(const PlanItem *__restrict__ items, uint32_t nitems,
+                const uint4 *__restrict__ keys, uint8_t *__restrict__ found,
+                uint64_t *__restrict__ vals, uint32_t *__restrict__ ctr) {
+  constexpr uint32_t P = 64u * PER;  // lookups per pass
+  __shared__ uint4 s_lines[WAVES * NB * kWaveQuarters];
+  const Wave w = wave_lines<NB>(s_lines);
+  const uint32_t lane = w.lane;
+  const uint32_t stride = gridDim.x * WAVES;
+  const uint32_t wave_id =
+      (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * WAVES + (threadIdx.x >> 6)));
+  uint32_t cur = DYN ? take_item(ctr, lane) : wave_id;
+  uint32_t n1 = next_item<DYN>(cur, stride, nitems, ctr, lane);
+  uint32_t n2 = next_item<DYN>(n1, stride, nitems, ctr, lane);
+  const PlanItem none{nullptr, 0ull, 0ull, 0u, 0u, 0u, 0u};
+  PlanItem I = cur < nitems ? items[cur] : none;
+  PlanItem I1 = n1 < nitems ? items[n1] : none;
+  uint4 ka = zero4(), kb = zero4();
+  if (cur < nitems) item_keys<PER>(keys, I, 0u, lane, ka, kb);
+  while (cur < nitems) {
+    const TableRef T{I.tab, I.seed, I.log2b};
+    PlanItem I2 = none;
+    uint32_t n3 = n2;
+    for (uint32_t off = 0u; off < I.count; off += P) {
+      const bool last = off + P >= I.count;
+      uint4 na = zero4(), nb = zero4();
+      auto pre = [&] {
+        if (!last) {
+          item_keys<PER>(keys, I, off + P, lane, na, nb);
+        } else {
+          if (n1 < nitems) item_keys<PER>(keys, I1, 0u, lane, na, nb);
+          if (n2 < nitems) I2 = items[n2];
+          n3 = next_item<DYN>(n2, stride, nitems, ctr, lane);
+        }
+      };
+      const uint64_t ia = I.start + off + lane;
+      const bool oka = off + lane < I.count;
+      if (PER == 1) {
+        if (I.mode == kModeCuckoopp) {
+          lds_pass<kModeCuckoopp>(w, T, ka, oka, found + ia, vals + ia, pre);
+        } else if (I.mode == kModeOptimistic) {
+          lds_pass<kModeOptimistic>(w, T, ka, oka, found + ia, vals + ia, pre);
+        } else if (NB == 2) {
+          lds_pass<kModeBoth>(w, T, ka, oka, found + ia, vals + ia, pre);
+        }
+      } else {
+        const uint64_t ib = ia + 64u;
+        const bool okb = off + 64u + lane < I.count;
+        if (I.mode == kModeCuckoopp) {
+          dual_pass<kModeCuckoopp>(w, T, ka, oka, kb, okb, found + ia, vals + ia, found + ib,
+                                   vals + ib, pre);
+        } else if (I.mode == kModeOptimistic) {
+          dual_pass<kModeOptimistic>(w, T, ka, oka, kb, okb, found + ia, vals + ia, found + ib,
+                                     vals + ib, pre);
+        } else if (NB == 2) {
+          lds_pass<kModeBoth>(w, T, ka, oka, found + ia, vals + ia, [] {});
+          lds_pass<kModeBoth>(w, T, kb, okb, found + ib, vals + ib, pre);
+        }
       }
-      park_lines(lines, q, lane);
-      if (nb) {
-        cb = tag_eq_mask(mine[0], Bq.f.tag) & meta_busy(mine[1].z);
-        match_line0(mine, cb & 0xfu, Bq.key, Bq.hit, Bq.val);
-      }
-      // phase 4: secondary second lines
-      na = na && !A.hit && (ca & 0xf0u);
-      nb = nb && !Bq.hit && (cb & 0xf0u);
-      if (__builtin_amdgcn_ballot_w64(na || nb)) {
-        fetch_lines(lines, tab, na ? A.f.a : kNoFetch, 1u, g, r);
-        fetch_lines_reg(q, tab, nb ? Bq.f.a : kNoFetch, 1u, g, r);
-        lines_landed();
-        if (na) match_line1(mine, ca & 0xf0u, A.key, A.hit, A.val);
-        park_lines(lines, q, lane);
-        if (nb) match_line1(mine, cb & 0xf0u, Bq.key, Bq.hit, Bq.val);
-      }
+      ka = na;
+      kb = nb;
     }
-    if (A.ok) {
-      __builtin_nontemporal_store((uint8_t)(A.hit ? 1 : 0), found + w0 + lane);
-      __builtin_nontemporal_store(A.hit ? A.val : 0ull, vals + w0 + lane);
-    }
-    if (Bq.ok) {
-      __builtin_nontemporal_store((uint8_t)(Bq.hit ? 1 : 0), found + w0 + 64u + lane);
-      __builtin_nontemporal_store(Bq.hit ? Bq.val : 0ull, vals + w0 + 64u + lane);
+    cur = n1;
+    I = I1;
+    n1 = n2;
+    I1 = I2;
+    n2 = n3;
+  }
+  if (DYN && lane == 0u) {
+    // every ticket this wave will ever take is taken: count the wave out;
+    // the last one (which sees every other wave's tickets) rewinds both
+    const uint32_t out = __hip_atomic_fetch_add(ctr + 1, 1u, __ATOMIC_ACQ_REL,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (out == gridDim.x * WAVES - 1u) {
+      __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(ctr + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
 
-template <uint32_t WAVES, uint32_t MODE>
-hipError_t launch_dual(const ckpp_table *t, const uint4 *keys, uint64_t n, uint8_t *found,
-                       uint64_t *vals, hipStream_t s) {
-  const ckpp_launch_t &L = t->lookup_launch;
-  const uint64_t per_block = 128ull * WAVES;
+uint64_t capped_grid(uint64_t n, uint64_t per_block, uint32_t blocks_per_cu, int num_cus) {
   uint64_t grid = (n + per_block - 1) / per_block;
-  if (L.blocks_per_cu) {
-    const uint64_t cap = (uint64_t)L.blocks_per_cu * (uint64_t)t->num_cus;
+  if (blocks_per_cu) {
+    const uint64_t cap = (uint64_t)blocks_per_cu * (uint64_t)num_cus;
     if (grid > cap) grid = cap;
   }
-  if (grid > 0x7fffffffull) grid = 0x7fffffffull;
-  hipLaunchKernelGGL((lookup_dual<WAVES, MODE>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, s,
-                     reinterpret_cast<const uint4 *>(t->d_table), keys, n, t->log2_buckets,
-                     t->seed, found, vals);
-  return hipGetLastError();
+  return grid > 0x7fffffffull ? 0x7fffffffull : grid;
 }
 
 template <uint32_t WAVES, uint32_t MODE>
 hipError_t launch_shape(const ckpp_table *t, const uint4 *keys, uint64_t n, uint8_t *found,
                         uint64_t *vals, hipStream_t s) {
-  if (MODE != kModeBoth && t->lookup_launch.lookups_per_lane == 2)
-    return launch_dual<WAVES, (MODE == kModeBoth ? kModeCuckoopp : MODE)>(t, keys, n, found, vals, s);
   const ckpp_launch_t &L = t->lookup_launch;
-  const uint64_t per_block = 64ull * WAVES;
-  uint64_t grid = (n + per_block - 1) / per_block;
-  if (L.blocks_per_cu) {
-    const uint64_t cap = (uint64_t)L.blocks_per_cu * (uint64_t)t->num_cus;
-    if (grid > cap) grid = cap;
+  const TableRef T{reinterpret_cast<const uint4 *>(t->d_table), t->seed, t->log2_buckets};
+  if (MODE != kModeBoth && L.lookups_per_lane == 2) {
+    constexpr uint32_t M = MODE == kModeBoth ? kModeCuckoopp : MODE;
+    const uint64_t grid = capped_grid(n, 128ull * WAVES, L.blocks_per_cu, t->num_cus);
+    hipLaunchKernelGGL((lookup_dual<WAVES, M>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, s, T,
+                       keys, n, found, vals);
+  } else {
+    const uint64_t grid = capped_grid(n, 64ull * WAVES, L.blocks_per_cu, t->num_cus);
+    hipLaunchKernelGGL((lookup_lds<WAVES, MODE>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, s, T,
+                       keys, n, found, vals);
   }
-  if (grid > 0x7fffffffull) grid = 0x7fffffffull;
-  hipLaunchKernelGGL((lookup_lds<WAVES, MODE>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, s,
-                     reinterpret_cast<const uint4 *>(t->d_table), keys, n, t->log2_buckets,
-                     t->seed, found, vals);
   return hipGetLastError();
 }
 
@@ -335,7 +237,55 @@ hipError_t launch_mode(const ckpp_table *t, const uint4 *keys, uint64_t n, uint8
   }
 }
 
+template <uint32_t WAVES, uint32_t NB, uint32_t PER>
+hipError_t launch_plan_shape(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr,
+                             const ckpp_plan_launch_t &L, int num_cus, const uint4 *keys,
+                             uint8_t *found, uint64_t *vals, hipStream_t s) {
+  // persistent grid: blocks_per_cu per CU, but no more waves than items
+  const uint64_t grid = capped_grid(nitems, WAVES, L.blocks_per_cu, num_cus);
+  if (L.schedule == CKPP_PLAN_DYNAMIC)
+    hipLaunchKernelGGL((lookup_plan<WAVES, NB, PER, true>), dim3((uint32_t)grid), dim3(64 * WAVES),
+                       0, s, d_items, nitems, keys, found, vals, d_ctr);
+  else
+    hipLaunchKernelGGL((lookup_plan<WAVES, NB, PER, false>), dim3((uint32_t)grid),
+                       dim3(64 * WAVES), 0, s, d_items, nitems, keys, found, vals, d_ctr);
+  return hipGetLastError();
+}
+
+template <uint32_t WAVES>
+hipError_t launch_plan_waves(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr,
+                             bool two_buffers, const ckpp_plan_launch_t &L, int num_cus,
+                             const uint4 *keys, uint8_t *found, uint64_t *vals, hipStream_t s) {
+  if (two_buffers) {
+    if (L.lookups_per_lane == 2)
+      return launch_plan_shape<WAVES, 2, 2>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals,
+                                            s);
+    return launch_plan_shape<WAVES, 2, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals, s);
+  }
+  if (L.lookups_per_lane == 2)
+    return launch_plan_shape<WAVES, 1, 2>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals, s);
+  return launch_plan_shape<WAVES, 1, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals, s);
+}
+
 }  // namespace
+
+hipError_t launch_plan(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr, bool two_buffers,
+                       const ckpp_plan_launch_t &L, int num_cus, const void *d_keys,
+                       uint8_t *d_found, uint64_t *d_values, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  const uint4 *keys = reinterpret_cast<const uint4 *>(d_keys);
+  switch (L.block) {
+    case 64:
+      return launch_plan_waves<1>(d_items, nitems, d_ctr, two_buffers, L, num_cus, keys, d_found,
+                                  d_values, s);
+    case 128:
+      return launch_plan_waves<2>(d_items, nitems, d_ctr, two_buffers, L, num_cus, keys, d_found,
+                                  d_values, s);
+    default:
+      return launch_plan_waves<4>(d_items, nitems, d_ctr, two_buffers, L, num_cus, keys, d_found,
+                                  d_values, s);
+  }
+}
 
 hipError_t launch_lookup(const ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
                          uint8_t *d_found, uint64_t *d_values, hipStream_t s) {

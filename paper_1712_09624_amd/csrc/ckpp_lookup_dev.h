@@ -1,0 +1,280 @@
+// ckpp_lookup_dev.h -- the lookup passes shared by every lookup kernel
+// (one table, a plan of many tables, the serving loop).  See ckpp_lookup.hip
+// for the lookup procedure and its GPU form.
+#pragma once
+
+#include "ckpp_device.h"
+#include "ckpp_internal.h"
+
+namespace ckpp {
+namespace {
+
+constexpr uint32_t kNoFetch = 0xffffffffu;  // bucket indices are < 2^24
+
+// Lines of one wave: 64 lines x 8 quarters; lookup j's line at [8j, 8j+8).
+constexpr uint32_t kWaveQuarters = 64 * 8;
+
+// Cooperative fetch of one 128-byte line (half `half` of the bucket) for
+// every lookup of the wave whose `bucket` is not kNoFetch: in round k the
+// lanes 8g..8g+7 read the line of lookup 8k+g, lane r its quarter r, and
+// the line lands at lines[8(8k+g) .. 8(8k+g)+8).
+__device__ __forceinline__ void fetch_lines(uint4 *lines, const uint4 *tab, uint32_t bucket,
+                                            uint32_t half, uint32_t g, uint32_t r) {
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) {
+    const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
+    if (b != kNoFetch) {
+      const uint4 *src = tab + (uint64_t)b * kQuartersPerBucket + 8u * half + r;
+      __builtin_amdgcn_global_load_lds(
+          (const void __attribute__((address_space(1))) *)src,
+          (void __attribute__((address_space(3))) *)(lines + 64u * k), 16, 0, 0);
+    }
+  }
+}
+
+// Waits until the lines requested by this wave have landed in LDS (the
+// loads' counter drains once the data is written there); the compiler may
+// not move LDS reads above this point.
+__device__ __forceinline__ void lines_landed() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+__device__ __forceinline__ uint64_t quarter_value(uint4 q, uint32_t s) {
+  return (s & 1u) ? ((uint64_t)q.z | ((uint64_t)q.w << 32))
+                  : ((uint64_t)q.x | ((uint64_t)q.y << 32));
+}
+
+// Compares the key with the candidate slots `cand` (ascending) of a first
+// line (mine[0..7]); on a hit sets hit/val.
+__device__ __forceinline__ void match_line0(const uint4 *mine, uint32_t cand, uint4 key, bool &hit,
+                                            uint64_t &val) {
+  while (cand != 0u && !hit) {
+    const uint32_t s = (uint32_t)__builtin_ctz(cand);
+    cand &= cand - 1u;
+    if (key_eq(mine[2u + s], key)) {
+      hit = true;
+      val = quarter_value(mine[6u + (s >> 1)], s);
+    }
+  }
+}
+
+// Same for slots 4..7 on a second line (mine[0..7]).
+__device__ __forceinline__ void match_line1(const uint4 *mine, uint32_t cand, uint4 key, bool &hit,
+                                            uint64_t &val) {
+  while (cand != 0u && !hit) {
+    const uint32_t s = (uint32_t)__builtin_ctz(cand);
+    cand &= cand - 1u;
+    if (key_eq(mine[s - 4u], key)) {
+      hit = true;
+      val = quarter_value(mine[4u + ((s - 4u) >> 1)], s);
+    }
+  }
+}
+
+// LDS line buffers of one wave and the lane's place in them: `lines` holds
+// the wave's first (or only) buffer, lookup j's line at quarters 8j..8j+7;
+// `lines_a` the secondary lines of the pessimistic mode, which fetches both
+// buckets at once (the same buffer when the kernel keeps one per wave).
+struct Wave {
+  uint4 *lines, *lines_a;
+  const uint4 *mine, *mine_a;
+  uint32_t lane, g, r;
+};
+
+template <uint32_t NB>
+__device__ __forceinline__ Wave wave_lines(uint4 *s_lines) {
+  Wave w;
+  w.lane = threadIdx.x & 63u;
+  w.g = w.lane >> 3;
+  w.r = w.lane & 7u;
+  w.lines = s_lines + (threadIdx.x >> 6) * NB * kWaveQuarters;
+  w.lines_a = w.lines + (NB - 1) * kWaveQuarters;
+  w.mine = w.lines + 8u * w.lane;
+  w.mine_a = w.lines_a + 8u * w.lane;
+  return w;
+}
+
+// What a lookup needs of its table.
+struct TableRef {
+  const uint4 *tab;
+  uint64_t seed;
+  uint32_t log2b;
+};
+
+__device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
+
+// One pass of a wave over 64 lookups, one per lane (the lane's `key`, a
+// real lookup iff `ok`), in mode MODE; the result goes to *found / *val.
+// `pre` runs once the first lines are requested and before they are waited
+// for: the caller loads its next keys there.  The pessimistic mode needs a
+// wave with two line buffers; the other modes use the first one only.
+template <uint32_t MODE, class Pre>
+__device__ __forceinline__ void lds_pass(const Wave &w, const TableRef &T, uint4 key, bool ok,
+                                         uint8_t *found, uint64_t *val_out, Pre &&pre) {
+  // the secondary's lines: the second buffer in the pessimistic mode (fetched
+  // with the primary), else the first one again (fetched after it)
+  uint4 *const lines_a = MODE == kModeBoth ? w.lines_a : w.lines;
+  const uint4 *const mine_a = MODE == kModeBoth ? w.mine_a : w.mine;
+  const KeyFields f = key_fields(key_hash(key, T.seed), T.log2b);
+  // first line of the primary (and, pessimistic mode, the secondary)
+  fetch_lines(w.lines, T.tab, ok ? f.p : kNoFetch, 0u, w.g, w.r);
+  if (MODE == kModeBoth) fetch_lines(lines_a, T.tab, ok ? f.a : kNoFetch, 0u, w.g, w.r);
+  pre();
+  lines_landed();
+  bool hit = false;
+  uint64_t val = 0;
+  const uint4 t0 = w.mine[0], t1 = w.mine[1];
+  const uint32_t cand = ok ? (tag_eq_mask(t0, f.tag) & meta_busy(t1.z)) : 0u;
+  const bool pass = MODE != kModeCuckoopp || bloom_pass(t1, f.bloom_bits);
+  match_line0(w.mine, cand & 0xfu, key, hit, val);
+  // second line of the primary, for keys whose tag sits in slots 4..7
+  bool need = !hit && (cand & 0xf0u);
+  if (__builtin_amdgcn_ballot_w64(need)) {
+    fetch_lines(w.lines, T.tab, need ? f.p : kNoFetch, 1u, w.g, w.r);
+    lines_landed();
+    if (need) match_line1(w.mine, cand & 0xf0u, key, hit, val);
+  }
+  // secondary bucket
+  need = ok && !hit && pass;
+  if (__builtin_amdgcn_ballot_w64(need)) {
+    if (MODE != kModeBoth) {
+      fetch_lines(w.lines, T.tab, need ? f.a : kNoFetch, 0u, w.g, w.r);
+      lines_landed();
+    }
+    uint32_t cand2 = 0u;
+    if (need) {
+      const uint4 u0 = mine_a[0], u1 = mine_a[1];
+      cand2 = tag_eq_mask(u0, f.tag) & meta_busy(u1.z);
+      match_line0(mine_a, cand2 & 0xfu, key, hit, val);
+    }
+    need = need && !hit && (cand2 & 0xf0u);
+    if (__builtin_amdgcn_ballot_w64(need)) {
+      fetch_lines(lines_a, T.tab, need ? f.a : kNoFetch, 1u, w.g, w.r);
+      lines_landed();
+      if (need) match_line1(mine_a, cand2 & 0xf0u, key, hit, val);
+    }
+  }
+  if (ok) {
+    __builtin_nontemporal_store((uint8_t)(hit ? 1 : 0), found);
+    __builtin_nontemporal_store(hit ? val : 0ull, val_out);
+  }
+}
+
+// Register-landing counterpart of fetch_lines: the same rounds, but the
+// quarter arrives in q[k] of the fetching lane; park_lines() later writes
+// the quarters to LDS in exactly the layout fetch_lines produces.
+__device__ __forceinline__ void fetch_lines_reg(uint4 (&q)[8], const uint4 *tab, uint32_t bucket,
+                                                uint32_t half, uint32_t g, uint32_t r) {
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) {
+    const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
+    q[k] = zero4();
+    if (b != kNoFetch) q[k] = tab[(uint64_t)b * kQuartersPerBucket + 8u * half + r];
+  }
+}
+
+__device__ __forceinline__ void park_lines(uint4 *lines, const uint4 (&q)[8], uint32_t lane) {
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k) lines[64u * k + lane] = q[k];
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Lookup state of one lookup owned by a lane.
+struct Look {
+  uint4 key;
+  KeyFields f;
+  bool ok, hit, pass;
+  uint32_t cand;
+  uint64_t val;
+};
+
+__device__ __forceinline__ void first_line(const uint4 *mine, Look &L, uint32_t mode) {
+  const uint4 t0 = mine[0], t1 = mine[1];
+  L.cand = L.ok ? (tag_eq_mask(t0, L.f.tag) & meta_busy(t1.z)) : 0u;
+  L.pass = mode != kModeCuckoopp || bloom_pass(t1, L.f.bloom_bits);
+  match_line0(mine, L.cand & 0xfu, L.key, L.hit, L.val);
+}
+
+// One pass of a wave over 128 lookups, two per lane (A and B): for each
+// phase the lines of the A lookups land in LDS directly, those of the B
+// lookups in registers, which are parked in LDS once the A lookups have been
+// analysed -- twice the line requests in flight for the same LDS.  `pre` as
+// in lds_pass.  Not for the pessimistic mode.
+template <uint32_t MODE, class Pre>
+__device__ __forceinline__ void dual_pass(const Wave &w, const TableRef &T, uint4 ka, bool oka,
+                                          uint4 kb, bool okb, uint8_t *fa, uint64_t *va,
+                                          uint8_t *fb, uint64_t *vb, Pre &&pre) {
+  static_assert(MODE != kModeBoth, "the pessimistic mode runs in lds_pass");
+  const uint32_t lane = w.lane, g = w.g, r = w.r;
+  uint4 *lines = w.lines;
+  const uint4 *mine = w.mine;
+  Look A, Bq;
+  A.key = ka;
+  Bq.key = kb;
+  A.ok = oka;
+  Bq.ok = okb;
+  A.f = key_fields(key_hash(A.key, T.seed), T.log2b);
+  Bq.f = key_fields(key_hash(Bq.key, T.seed), T.log2b);
+  A.hit = Bq.hit = false;
+  A.val = Bq.val = 0ull;
+  uint4 q[8];
+  // phase 1: primary first lines
+  fetch_lines(lines, T.tab, A.ok ? A.f.p : kNoFetch, 0u, g, r);
+  fetch_lines_reg(q, T.tab, Bq.ok ? Bq.f.p : kNoFetch, 0u, g, r);
+  pre();
+  lines_landed();
+  first_line(mine, A, MODE);
+  park_lines(lines, q, lane);
+  first_line(mine, Bq, MODE);
+  // phase 2: primary second lines
+  bool na = !A.hit && (A.cand & 0xf0u), nb = !Bq.hit && (Bq.cand & 0xf0u);
+  if (__builtin_amdgcn_ballot_w64(na || nb)) {
+    fetch_lines(lines, T.tab, na ? A.f.p : kNoFetch, 1u, g, r);
+    fetch_lines_reg(q, T.tab, nb ? Bq.f.p : kNoFetch, 1u, g, r);
+    lines_landed();
+    if (na) match_line1(mine, A.cand & 0xf0u, A.key, A.hit, A.val);
+    park_lines(lines, q, lane);
+    if (nb) match_line1(mine, Bq.cand & 0xf0u, Bq.key, Bq.hit, Bq.val);
+  }
+  // phase 3: secondary first lines
+  na = A.ok && !A.hit && A.pass;
+  nb = Bq.ok && !Bq.hit && Bq.pass;
+  if (__builtin_amdgcn_ballot_w64(na || nb)) {
+    fetch_lines(lines, T.tab, na ? A.f.a : kNoFetch, 0u, g, r);
+    fetch_lines_reg(q, T.tab, nb ? Bq.f.a : kNoFetch, 0u, g, r);
+    lines_landed();
+    uint32_t ca = 0u, cb = 0u;
+    if (na) {
+      ca = tag_eq_mask(mine[0], A.f.tag) & meta_busy(mine[1].z);
+      match_line0(mine, ca & 0xfu, A.key, A.hit, A.val);
+    }
+    park_lines(lines, q, lane);
+    if (nb) {
+      cb = tag_eq_mask(mine[0], Bq.f.tag) & meta_busy(mine[1].z);
+      match_line0(mine, cb & 0xfu, Bq.key, Bq.hit, Bq.val);
+    }
+    // phase 4: secondary second lines
+    na = na && !A.hit && (ca & 0xf0u);
+    nb = nb && !Bq.hit && (cb & 0xf0u);
+    if (__builtin_amdgcn_ballot_w64(na || nb)) {
+      fetch_lines(lines, T.tab, na ? A.f.a : kNoFetch, 1u, g, r);
+      fetch_lines_reg(q, T.tab, nb ? Bq.f.a : kNoFetch, 1u, g, r);
+      lines_landed();
+      if (na) match_line1(mine, ca & 0xf0u, A.key, A.hit, A.val);
+      park_lines(lines, q, lane);
+      if (nb) match_line1(mine, cb & 0xf0u, Bq.key, Bq.hit, Bq.val);
+    }
+  }
+  if (A.ok) {
+    __builtin_nontemporal_store((uint8_t)(A.hit ? 1 : 0), fa);
+    __builtin_nontemporal_store(A.hit ? A.val : 0ull, va);
+  }
+  if (Bq.ok) {
+    __builtin_nontemporal_store((uint8_t)(Bq.hit ? 1 : 0), fb);
+    __builtin_nontemporal_store(Bq.hit ? Bq.val : 0ull, vb);
+  }
+}
+
+}  // namespace
+}  // namespace ckpp

@@ -1,0 +1,640 @@
+// ckpp_serve.hip -- the serving loop: one persistent kernel that takes
+// bursts of lookups, inserts and deletes from device rings as the host
+// submits them, in rounds (continuous batching).
+//
+// Host and loop talk through a small block of pinned, coherent host memory:
+// the host writes each burst's cumulative ring tails and then the number of
+// submitted bursts; the loop's leader (block 0, thread 0) polls that number
+// and publishes the number of completed bursts there.  A round:
+//
+//   boundary  every block arrives at the leader's barrier; once all have
+//             arrived the leader publishes the previous round's completion,
+//             waits for submitted bursts (or exits after idle_ms without
+//             any), writes the round's op ranges and releases the barrier
+//   lookups   every wave runs 64-lookup passes over the round's lookup range
+//             (the lookup passes of the batch kernels, unchanged)
+//   inserts   after a barrier, one lane per key (the batch insert's state
+//             machine, unchanged), at most `path_lanes` lanes
+//   deletes   after a barrier, one lane per key
+//   end       each block makes its results visible to the host (system-
+//             scope release) before it arrives at the next boundary
+//
+// Every wait is bounded by the real-time counter: a block that waits too
+// long for a barrier sets `abort`, every other wait sees it, and the whole
+// grid leaves the loop, so the kernel always ends.  The grid is launched
+// cooperatively, so all of its blocks are resident at once.
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <new>
+#include <stdint.h>
+#include <string.h>
+#include <thread>
+#include <vector>
+
+#include "ckpp_lookup_dev.h"
+#include "ckpp_update_dev.h"
+
+namespace ckpp {
+namespace {
+
+constexpr uint32_t kQueue = 4096;        // bursts in flight at most
+constexpr uint32_t kBlock = 256;         // threads per block of the loop
+constexpr uint32_t kWaves = kBlock / 64;
+constexpr uint64_t kTicksPerMs = 100000; // real-time counter: 100 MHz
+constexpr uint64_t kPhaseMs = 20000;     // a phase may take this long at most
+constexpr uint32_t kMaxPathLanes = 65536;
+
+constexpr uint32_t kCmdRun = 1, kCmdExit = 2;
+
+// Pinned host memory shared by the host and the loop.
+struct ServeHost {
+  uint64_t submitted;  // host -> loop: bursts submitted
+  uint64_t completed;  // loop -> host: bursts whose results are visible
+  uint64_t rounds;     // loop -> host
+  uint32_t stop;       // host -> loop: exit once idle
+  uint32_t state;      // loop -> host: CKPP_SERVER_*
+  uint64_t tails[kQueue][4];  // after burst k, at k % kQueue: lookup, insert, delete tails
+};
+
+// Device memory of the loop (survives relaunches).
+struct ServeDev {
+  uint64_t done;              // bursts taken into rounds so far
+  uint64_t lk0, lk1, in0, in1, de0, de1;  // the round's op ranges
+  uint32_t cmd;               // kCmdRun / kCmdExit for the blocks
+  uint32_t abort;             // a wait ran out of time
+  uint32_t arrived;           // barrier: blocks arrived
+  uint32_t gen;               // barrier: generation, bumped by the leader
+};
+
+struct ServeArgs {
+  TableRef T;
+  uint8_t *bk;
+  uint32_t max_kicks;
+  uint32_t plain;
+  ServeHost *host;
+  ServeDev *dev;
+  uint64_t mask;  // capacity - 1
+  const uint4 *lk_keys;
+  uint8_t *lk_found;
+  uint64_t *lk_vals;
+  const uint4 *in_keys;
+  const uint64_t *in_vals;
+  uint8_t *in_status;
+  const uint4 *de_keys;
+  uint8_t *de_found;
+  uint32_t *paths;
+  uint32_t path_lanes;
+  uint64_t idle_ticks;
+  unsigned long long *nspin;
+};
+
+__device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
+
+__device__ __forceinline__ uint64_t sys_load64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t sys_load32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void sys_store64(uint64_t *p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void sys_store32(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t agent_load32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Non-leader side of a barrier (thread 0 of the block): arrive, then wait
+// until the leader bumps the generation.  Returns false when the wait ran
+// out of time or another block gave up.
+__device__ bool arrive_and_wait(ServeDev *d, uint64_t limit_ticks) {
+  const uint32_t g = agent_load32(&d->gen);
+  __hip_atomic_fetch_add(&d->arrived, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t t0 = now_ticks();
+  while (agent_load32(&d->gen) == g) {
+    if (agent_load32(&d->abort)) return false;
+    if (now_ticks() - t0 > limit_ticks) {
+      __hip_atomic_store(&d->abort, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+// Leader side: arrive and wait until every block has arrived.
+__device__ bool leader_gather(ServeDev *d, uint32_t nblocks, uint64_t limit_ticks) {
+  __hip_atomic_fetch_add(&d->arrived, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  const uint64_t t0 = now_ticks();
+  while (agent_load32(&d->arrived) != nblocks) {
+    if (agent_load32(&d->abort)) return false;
+    if (now_ticks() - t0 > limit_ticks) {
+      __hip_atomic_store(&d->abort, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return true;
+}
+
+// Leader: releases the blocks waiting at the barrier.
+__device__ void leader_release(ServeDev *d) {
+  __hip_atomic_store(&d->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_add(&d->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Leader at a round boundary (every block has arrived): publish the round
+// that just ended, wait for work, set the next round.  Returns the command.
+__device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
+  ServeHost *h = a.host;
+  ServeDev *d = a.dev;
+  if (ran_round) {
+    sys_store64(&h->completed, d->done);
+    sys_store64(&h->rounds, sys_load64(&h->rounds) + 1u);
+  }
+  const uint64_t t0 = now_ticks();
+  uint64_t s = 0;
+  for (;;) {
+    s = sys_load64(&h->submitted);
+    if (s > d->done) break;
+    if (sys_load32(&h->stop)) return kCmdExit;
+    if (now_ticks() - t0 > a.idle_ticks) {
+      // tell the host the loop is leaving, then look once more: a burst
+      // submitted before the host saw EXITING is still taken
+      sys_store32(&h->state, CKPP_SERVER_EXITING);
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "");
+      s = sys_load64(&h->submitted);
+      if (s > d->done) {
+        sys_store32(&h->state, CKPP_SERVER_RUNNING);
+        break;
+      }
+      return kCmdExit;
+    }
+    __builtin_amdgcn_s_sleep(4);
+  }
+  const uint64_t *t = h->tails[(s - 1u) % kQueue];
+  d->lk0 = d->lk1;
+  d->in0 = d->in1;
+  d->de0 = d->de1;
+  d->lk1 = __hip_atomic_load(t + 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  d->in1 = __hip_atomic_load(t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  d->de1 = __hip_atomic_load(t + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  d->done = s;
+  return kCmdRun;
+}
+
+template <uint32_t MODE>
+__device__ void lookup_phase(const ServeArgs &a, const Wave &w, uint64_t l0, uint64_t l1) {
+  const uint64_t nwaves = (uint64_t)gridDim.x * kWaves;
+  const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
+  uint64_t i = l0 + wave * 64u + w.lane;
+  uint4 key = i < l1 ? load_stream(a.lk_keys + (i & a.mask)) : zero4();
+  for (; i - w.lane < l1; i += nwaves * 64u) {
+    const uint64_t slot = i & a.mask;
+    uint4 knext;
+    lds_pass<MODE>(w, a.T, key, i < l1, a.lk_found + slot, a.lk_vals + slot, [&] {
+      const uint64_t in = i + nwaves * 64u;
+      knext = in < l1 ? load_stream(a.lk_keys + (in & a.mask)) : zero4();
+    });
+    key = knext;
+  }
+}
+
+__device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1) {
+  const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (g >= a.path_lanes) return;
+  uint32_t *path = a.paths + g * (uint64_t)(a.max_kicks ? a.max_kicks : 1u);
+  for (uint64_t j = i0 + g; j < i1; j += a.path_lanes) {
+    const uint64_t slot = j & a.mask;
+    const InsertOutcome o = insert_one(a.bk, a.in_keys[slot], a.in_vals[slot], a.T.log2b, a.T.seed,
+                                       a.max_kicks, a.plain != 0u, path);
+    a.in_status[slot] = (uint8_t)o.status;
+    if (o.spun) atomicAdd(a.nspin, 1ull);
+  }
+}
+
+__device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1) {
+  const uint64_t nlanes = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t j = d0 + (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < d1; j += nlanes) {
+    const uint64_t slot = j & a.mask;
+    bool spun = false;
+    a.de_found[slot] = (uint8_t)delete_one(a.bk, a.de_keys[slot], a.T.log2b, a.T.seed,
+                                           a.plain != 0u, &spun);
+    if (spun) atomicAdd(a.nspin, 1ull);
+  }
+}
+
+// Grid-wide barrier inside a round (every thread of every block calls it).
+__device__ bool phase_barrier(const ServeArgs &a, uint32_t *s_ok) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    bool ok;
+    if (blockIdx.x == 0) {
+      ok = leader_gather(a.dev, gridDim.x, kPhaseMs * kTicksPerMs);
+      leader_release(a.dev);
+    } else {
+      ok = arrive_and_wait(a.dev, kPhaseMs * kTicksPerMs);
+    }
+    *s_ok = ok ? 1u : 0u;
+  }
+  __syncthreads();
+  return *s_ok != 0u;
+}
+
+template <uint32_t NB, uint32_t MODE>
+__global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
+  __shared__ uint4 s_lines[kWaves * NB * kWaveQuarters];
+  __shared__ uint64_t s_range[6];
+  __shared__ uint32_t s_cmd, s_ok;
+  const Wave w = wave_lines<NB>(s_lines);
+  const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+  ServeDev *d = a.dev;
+  bool ran = false;
+  for (;;) {
+    // round boundary
+    if (threadIdx.x == 0) {
+      uint32_t cmd = kCmdExit;
+      if (blockIdx.x == 0) {
+        if (leader_gather(d, gridDim.x, kPhaseMs * kTicksPerMs)) cmd = leader_next_round(a, ran);
+        d->cmd = cmd;
+        leader_release(d);
+      } else if (arrive_and_wait(d, a.idle_ticks + kPhaseMs * kTicksPerMs)) {
+        cmd = __hip_atomic_load(&d->cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (agent_load32(&d->abort)) cmd = kCmdExit;
+      // the round's ring entries were written by the host or a copy engine
+      // while the kernel ran: drop any cached copy of them
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      s_cmd = cmd;
+      if (cmd == kCmdRun) {
+        s_range[0] = d->lk0;
+        s_range[1] = d->lk1;
+        s_range[2] = d->in0;
+        s_range[3] = d->in1;
+        s_range[4] = d->de0;
+        s_range[5] = d->de1;
+      }
+    }
+    __syncthreads();
+    if (s_cmd != kCmdRun) break;
+    const uint64_t l0 = s_range[0], l1 = s_range[1], i0 = s_range[2], i1 = s_range[3];
+    const uint64_t d0 = s_range[4], d1 = s_range[5];
+    lookup_phase<MODE>(a, w, l0, l1);
+    if (i1 > i0 || d1 > d0) {
+      if (!phase_barrier(a, &s_ok)) break;
+      insert_phase(a, i0, i1);
+      if (d1 > d0) {
+        if (!phase_barrier(a, &s_ok)) break;
+        delete_phase(a, d0, d1);
+      }
+    }
+    // every wave's results become visible to the host and the copy engines
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    __syncthreads();
+    ran = true;
+  }
+  if (leader) {
+    const uint32_t aborted = agent_load32(&d->abort);
+    sys_store32(&a.host->state, aborted ? CKPP_SERVER_ABORTED : CKPP_SERVER_STOPPED);
+  }
+}
+
+}  // namespace
+}  // namespace ckpp
+
+using ckpp::ServeArgs;
+using ckpp::ServeDev;
+using ckpp::ServeHost;
+
+struct ckpp_server {
+  ckpp_table *t;
+  int device;
+  ckpp_server_config_t cfg;
+  uint32_t mode;
+  uint32_t grid;
+  hipStream_t stream;
+  ServeHost *host;
+  ServeDev *dev;
+  uint32_t *paths;
+  ckpp_server_rings_t rings;
+  ServeArgs args;
+  uint64_t submitted;
+  uint64_t tails[3];
+  std::vector<uint64_t> burst_tails;  // kQueue x 3: cumulative tails after burst k
+  uint64_t launches;
+  bool launched;
+};
+
+namespace {
+
+using ckpp::DeviceGuard;
+using ckpp::dev_status;
+
+std::atomic<uint64_t> *host_u64(uint64_t *p) { return reinterpret_cast<std::atomic<uint64_t> *>(p); }
+std::atomic<uint32_t> *host_u32(uint32_t *p) { return reinterpret_cast<std::atomic<uint32_t> *>(p); }
+
+hipError_t launch_loop(ckpp_server *s) {
+  void *kargs[] = {&s->args};
+  const void *fn;
+  const bool two = s->mode == ckpp::kModeBoth;
+  if (two)
+    fn = reinterpret_cast<const void *>(&ckpp::serve_loop<2, ckpp::kModeBoth>);
+  else if (s->mode == ckpp::kModeOptimistic)
+    fn = reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeOptimistic>);
+  else
+    fn = reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeCuckoopp>);
+  host_u32(&s->host->state)->store(CKPP_SERVER_RUNNING, std::memory_order_seq_cst);
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(s->grid), dim3(ckpp::kBlock), kargs, 0,
+                                            s->stream);
+  if (e != hipSuccess) {
+    host_u32(&s->host->state)->store(CKPP_SERVER_STOPPED, std::memory_order_seq_cst);
+    return e;
+  }
+  s->launches += 1;
+  s->launched = true;
+  return hipSuccess;
+}
+
+// Makes sure a loop is running after a submit (see the exit protocol in
+// leader_next_round).
+int ensure_running(ckpp_server *s) {
+  for (;;) {
+    const uint32_t st = host_u32(&s->host->state)->load(std::memory_order_seq_cst);
+    if (st == CKPP_SERVER_RUNNING) return CKPP_OK;
+    if (st == CKPP_SERVER_ABORTED) return CKPP_EDEVICE;
+    if (st == CKPP_SERVER_EXITING) {
+      std::this_thread::yield();
+      continue;
+    }
+    // stopped: the previous kernel has left (or is leaving) the loop
+    if (hipStreamSynchronize(s->stream) != hipSuccess) return CKPP_EDEVICE;
+    if (host_u32(&s->host->state)->load(std::memory_order_seq_cst) == CKPP_SERVER_ABORTED)
+      return CKPP_EDEVICE;
+    return dev_status(launch_loop(s));
+  }
+}
+
+void free_server(ckpp_server *s) {
+  (void)hipFree(s->rings.d_lookup_keys);
+  (void)hipFree(s->rings.d_lookup_found);
+  (void)hipFree(s->rings.d_lookup_values);
+  (void)hipFree(s->rings.d_insert_keys);
+  (void)hipFree(s->rings.d_insert_values);
+  (void)hipFree(s->rings.d_insert_status);
+  (void)hipFree(s->rings.d_delete_keys);
+  (void)hipFree(s->rings.d_delete_found);
+  (void)hipFree(s->paths);
+  (void)hipFree(s->dev);
+  if (s->host) (void)hipHostFree(s->host);
+  if (s->stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+}  // namespace
+
+extern "C" {
+
+int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_config_t *cfg) {
+  if (!out) return CKPP_EINVAL;
+  *out = nullptr;
+  if (!t || !cfg) return CKPP_EINVAL;
+  const ckpp_server_config_t &c = *cfg;
+  if (!pow2(c.capacity) || c.capacity < 64 || c.capacity > (1ull << 30)) return CKPP_EINVAL;
+  if (c.budget == 0 || c.budget > c.capacity) return CKPP_EINVAL;
+  if (c.mode > CKPP_LOOKUP_OPTIMISTIC || c.blocks_per_cu < 1 || c.blocks_per_cu > 4) return CKPP_EINVAL;
+  if (c.idle_ms < 1 || c.idle_ms > 60000 || c.reserved != 0) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  ckpp_server *s = new (std::nothrow) ckpp_server();
+  if (!s) return CKPP_ENOMEM;
+  s->t = t;
+  s->device = t->device;
+  s->cfg = c;
+  s->mode = c.mode;
+  if (s->mode == CKPP_LOOKUP_DEFAULT && (t->flags & CKPP_PLAIN)) s->mode = CKPP_LOOKUP_BOTH;
+  s->burst_tails.assign(3ull * ckpp::kQueue, 0ull);
+  const uint64_t C = c.capacity;
+  ckpp_server_rings_t &r = s->rings;
+  r.capacity = C;
+  hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipMalloc(&r.d_lookup_keys, C * 16);
+  if (e == hipSuccess) e = hipMalloc(&r.d_lookup_found, C);
+  if (e == hipSuccess) e = hipMalloc(&r.d_lookup_values, C * 8);
+  if (e == hipSuccess) e = hipMalloc(&r.d_insert_keys, C * 16);
+  if (e == hipSuccess) e = hipMalloc(&r.d_insert_values, C * 8);
+  if (e == hipSuccess) e = hipMalloc(&r.d_insert_status, C);
+  if (e == hipSuccess) e = hipMalloc(&r.d_delete_keys, C * 16);
+  if (e == hipSuccess) e = hipMalloc(&r.d_delete_found, C);
+  // the loop kernel's grid: co-resident blocks only
+  int per_cu = 0;
+  const void *fn = s->mode == CKPP_LOOKUP_BOTH
+                       ? reinterpret_cast<const void *>(&ckpp::serve_loop<2, ckpp::kModeBoth>)
+                       : reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeCuckoopp>);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, ckpp::kBlock, 0);
+  if (e == hipSuccess && per_cu < 1) e = hipErrorInvalidConfiguration;
+  const uint32_t bpc = std::min<uint32_t>(c.blocks_per_cu, (uint32_t)std::max(per_cu, 1));
+  s->grid = bpc * (uint32_t)t->num_cus;
+  const uint32_t path_lanes = std::min<uint32_t>(ckpp::kMaxPathLanes, s->grid * ckpp::kBlock);
+  const uint64_t path_words = (uint64_t)path_lanes * (t->max_kicks ? t->max_kicks : 1u);
+  if (e == hipSuccess) e = hipMalloc(&s->paths, path_words * 4);
+  if (e == hipSuccess) e = hipMalloc(&s->dev, sizeof(ServeDev));
+  if (e == hipSuccess) e = hipMemset(s->dev, 0, sizeof(ServeDev));
+  if (e == hipSuccess) e = hipHostMalloc(&s->host, sizeof(ServeHost), hipHostMallocCoherent);
+  if (e == hipSuccess) memset(s->host, 0, sizeof(ServeHost));
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_server(s);
+    return dev_status(e);
+  }
+  ServeArgs &a = s->args;
+  a.T = ckpp::TableRef{reinterpret_cast<const uint4 *>(t->d_table), t->seed, t->log2_buckets};
+  a.bk = t->d_table;
+  a.max_kicks = t->max_kicks;
+  a.plain = (t->flags & CKPP_PLAIN) ? 1u : 0u;
+  a.host = s->host;
+  a.dev = s->dev;
+  a.mask = C - 1u;
+  a.lk_keys = reinterpret_cast<const uint4 *>(r.d_lookup_keys);
+  a.lk_found = r.d_lookup_found;
+  a.lk_vals = r.d_lookup_values;
+  a.in_keys = reinterpret_cast<const uint4 *>(r.d_insert_keys);
+  a.in_vals = r.d_insert_values;
+  a.in_status = r.d_insert_status;
+  a.de_keys = reinterpret_cast<const uint4 *>(r.d_delete_keys);
+  a.de_found = r.d_delete_found;
+  a.paths = s->paths;
+  a.path_lanes = path_lanes;
+  a.idle_ticks = (uint64_t)c.idle_ms * ckpp::kTicksPerMs;
+  a.nspin = reinterpret_cast<unsigned long long *>(t->d_stats) + 127;
+  e = launch_loop(s);
+  if (e != hipSuccess) {
+    free_server(s);
+    return dev_status(e);
+  }
+  *out = s;
+  return CKPP_OK;
+}
+
+int ckpp_server_rings(const ckpp_server *s, ckpp_server_rings_t *out) {
+  if (!s || !out) return CKPP_EINVAL;
+  *out = s->rings;
+  return CKPP_OK;
+}
+
+int ckpp_server_put(ckpp_server *s, uint32_t kind, uint64_t pos, const void *d_keys,
+                    const uint64_t *d_values, uint32_t n, void *stream) {
+  if (!s || kind > CKPP_OP_DELETE || n > s->rings.capacity) return CKPP_EINVAL;
+  if (n == 0) return CKPP_OK;
+  if (!d_keys || (kind == CKPP_OP_INSERT) != (d_values != nullptr)) return CKPP_EINVAL;
+  DeviceGuard g(s->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  const ckpp_server_rings_t &r = s->rings;
+  uint8_t *keys = static_cast<uint8_t *>(kind == CKPP_OP_LOOKUP   ? r.d_lookup_keys
+                                         : kind == CKPP_OP_INSERT ? r.d_insert_keys
+                                                                  : r.d_delete_keys);
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const uint64_t C = r.capacity, first = pos % C, n1 = std::min<uint64_t>(n, C - first);
+  const uint8_t *src = static_cast<const uint8_t *>(d_keys);
+  hipError_t e = hipMemcpyAsync(keys + first * 16, src, n1 * 16, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && n1 < n)
+    e = hipMemcpyAsync(keys, src + n1 * 16, (n - n1) * 16, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && d_values) {
+    e = hipMemcpyAsync(r.d_insert_values + first, d_values, n1 * 8, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && n1 < n)
+      e = hipMemcpyAsync(r.d_insert_values, d_values + n1, (n - n1) * 8, hipMemcpyDeviceToDevice,
+                         st);
+  }
+  return dev_status(e);
+}
+
+int ckpp_server_get(ckpp_server *s, uint32_t kind, uint64_t pos, uint32_t n, uint8_t *d_flags,
+                    uint64_t *d_values, void *stream) {
+  if (!s || kind > CKPP_OP_DELETE || n > s->rings.capacity) return CKPP_EINVAL;
+  if (n == 0) return CKPP_OK;
+  if (!d_flags || (kind == CKPP_OP_LOOKUP) != (d_values != nullptr)) return CKPP_EINVAL;
+  DeviceGuard g(s->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  const ckpp_server_rings_t &r = s->rings;
+  const uint8_t *flags = kind == CKPP_OP_LOOKUP   ? r.d_lookup_found
+                         : kind == CKPP_OP_INSERT ? r.d_insert_status
+                                                  : r.d_delete_found;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const uint64_t C = r.capacity, first = pos % C, n1 = std::min<uint64_t>(n, C - first);
+  hipError_t e = hipMemcpyAsync(d_flags, flags + first, n1, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && n1 < n)
+    e = hipMemcpyAsync(d_flags + n1, flags, n - n1, hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess && d_values) {
+    e = hipMemcpyAsync(d_values, r.d_lookup_values + first, n1 * 8, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess && n1 < n)
+      e = hipMemcpyAsync(d_values + n1, r.d_lookup_values, (n - n1) * 8, hipMemcpyDeviceToDevice,
+                         st);
+  }
+  return dev_status(e);
+}
+
+int ckpp_server_status(ckpp_server *s, ckpp_server_status_t *out) {
+  if (!s || !out) return CKPP_EINVAL;
+  out->submitted = s->submitted;
+  out->completed = host_u64(&s->host->completed)->load(std::memory_order_acquire);
+  out->lookup_tail = s->tails[0];
+  out->insert_tail = s->tails[1];
+  out->delete_tail = s->tails[2];
+  out->rounds = host_u64(&s->host->rounds)->load(std::memory_order_acquire);
+  out->launches = s->launches;
+  out->state = host_u32(&s->host->state)->load(std::memory_order_acquire);
+  out->grid = s->grid;
+  return CKPP_OK;
+}
+
+int ckpp_server_submit(ckpp_server *s, uint32_t n_lookup, uint32_t n_insert, uint32_t n_delete,
+                       uint64_t *burst) {
+  if (!s) return CKPP_EINVAL;
+  const uint64_t done = host_u64(&s->host->completed)->load(std::memory_order_acquire);
+  if (s->submitted - done >= ckpp::kQueue) return CKPP_EBUSY;
+  // ops in flight of each kind after this burst
+  const uint64_t *dt = done ? &s->burst_tails[3 * ((done - 1) % ckpp::kQueue)] : nullptr;
+  const uint64_t n[3] = {n_lookup, n_insert, n_delete};
+  uint64_t nt[3];
+  for (int k = 0; k < 3; ++k) {
+    nt[k] = s->tails[k] + n[k];
+    if (nt[k] - (dt ? dt[k] : 0ull) > s->cfg.budget) return CKPP_EBUSY;
+  }
+  const uint64_t b = s->submitted;
+  uint64_t *slot = s->host->tails[b % ckpp::kQueue];
+  for (int k = 0; k < 3; ++k) {
+    host_u64(&slot[k])->store(nt[k], std::memory_order_relaxed);
+    s->burst_tails[3 * (b % ckpp::kQueue) + k] = nt[k];
+    s->tails[k] = nt[k];
+  }
+  s->submitted = b + 1;
+  host_u64(&s->host->submitted)->store(b + 1, std::memory_order_seq_cst);
+  if (burst) *burst = b;
+  DeviceGuard g(s->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  return ensure_running(s);
+}
+
+int ckpp_server_wait(ckpp_server *s, uint64_t burst, uint32_t timeout_ms) {
+  if (!s || burst >= s->submitted) return CKPP_EINVAL;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    if (host_u64(&s->host->completed)->load(std::memory_order_acquire) > burst) return CKPP_OK;
+    const uint32_t st = host_u32(&s->host->state)->load(std::memory_order_acquire);
+    if (st == CKPP_SERVER_ABORTED) return CKPP_EDEVICE;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(timeout_ms))
+      return CKPP_ETIMEOUT;
+    std::this_thread::yield();
+  }
+}
+
+int ckpp_server_replay(ckpp_server *s, uint64_t nbursts, const uint32_t *h_nlookup,
+                       const uint32_t *h_ninsert, const uint32_t *h_ndelete,
+                       const double *h_arrival_s, double *h_admit_s, double *h_done_s,
+                       double timeout_s) {
+  if (!s || (nbursts && (!h_nlookup || !h_ninsert || !h_ndelete || !h_arrival_s || !h_admit_s ||
+                         !h_done_s)))
+    return CKPP_EINVAL;
+  using clk = std::chrono::steady_clock;
+  const auto t0 = clk::now();
+  auto since = [&](clk::time_point t) { return std::chrono::duration<double>(t - t0).count(); };
+  const uint64_t first = s->submitted;  // burst number of stream entry 0
+  uint64_t next = 0, seen = 0;
+  while (seen < nbursts) {
+    const auto now = clk::now();
+    const double ts = since(now);
+    while (next < nbursts && h_arrival_s[next] <= ts) {
+      const int rc = ckpp_server_submit(s, h_nlookup[next], h_ninsert[next], h_ndelete[next],
+                                        nullptr);
+      if (rc == CKPP_EBUSY) break;
+      if (rc != CKPP_OK) return rc;
+      h_admit_s[next] = since(clk::now());
+      ++next;
+    }
+    const uint64_t c = host_u64(&s->host->completed)->load(std::memory_order_acquire);
+    if (c > first + seen) {
+      const double td = since(clk::now());
+      while (seen < nbursts && first + seen < c) h_done_s[seen++] = td;
+    }
+    if (host_u32(&s->host->state)->load(std::memory_order_acquire) == CKPP_SERVER_ABORTED)
+      return CKPP_EDEVICE;
+    if (ts > timeout_s) return CKPP_ETIMEOUT;
+  }
+  return CKPP_OK;
+}
+
+int ckpp_server_destroy(ckpp_server *s) {
+  if (!s) return CKPP_OK;
+  DeviceGuard g(s->device);
+  host_u32(&s->host->stop)->store(1u, std::memory_order_seq_cst);
+  (void)hipStreamSynchronize(s->stream);
+  free_server(s);
+  return CKPP_OK;
+}
+
+}  // extern "C"

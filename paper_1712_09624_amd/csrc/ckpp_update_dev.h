@@ -1,0 +1,388 @@
+// ckpp_update_dev.h -- per-key insert and delete (device functions shared by
+// the batch kernels and the serving loop).
+//
+// Insert (Sec. 2 insertion procedure, Sec. 4.1 filter maintenance) and
+// delete (Sec. 4.1) run as many independent lanes, one key at a time per
+// lane, on a persistent grid.  Each bucket's lock word (bytes 28..31) is
+// taken with a single compare-and-swap and never waited on: a lane that
+// misses a lock drops every lock it holds and retries in its next loop
+// iteration, so no lane ever spins on a lock that a lane of its own
+// wavefront holds.  A lane holds the locks of at most two buckets, taken in
+// ascending bucket order, always the two buckets an entry may live in, so
+// every bloom-filter and moved-counter update -- which concerns the primary
+// bucket of the entry that moves -- happens under the lock of that bucket.
+//
+// A key's state machine:
+//   DIRECT  lock p and a; if the key is present, replace its value
+//           (UPDATED); else take the lowest free slot of p, else of a (set
+//           the key's two bits in p's filter, moved[p] += 1) (INSERTED);
+//           else go to WALK.
+//   WALK    random walk over full buckets starting at p, reading without
+//           locks: at each bucket pick a victim -- preferably an entry that
+//           sits in its secondary bucket (it would move back home), then one
+//           whose other bucket is not the bucket just left -- and continue
+//           at the victim's other bucket, until one with a free slot, at most
+//           max_kicks steps; no (bucket, slot) twice.  No path: FAILED.
+//   MOVE    apply the path backwards, one displacement per iteration, each
+//           under the locks of its two buckets and re-validated there; a
+//           move from primary to secondary adds the entry to the source's
+//           filter, a move back decrements the destination's counter and
+//           resets its filter at zero (Sec. 4.1).  A stale path returns to
+//           DIRECT (the moves done so far are valid moves); when the path is
+//           applied, p has a free slot and the key returns to DIRECT.
+// Every loop is bounded: walks by max_kicks, retries by a fixed limit whose
+// exhaustion reports FAILED and is counted separately.
+
+#pragma once
+
+#include "ckpp_device.h"
+#include "ckpp_internal.h"
+
+namespace ckpp {
+namespace {
+
+constexpr uint32_t kSpinLimit = 1u << 20;  // loop iterations per key
+constexpr uint32_t kMaxWalks = 64;         // path searches per key
+constexpr uint32_t kNoBucket = 0xffffffffu;
+
+__device__ __forceinline__ uint8_t *bucket_ptr(uint8_t *bk, uint32_t b) {
+  return bk + (uint64_t)b * kBucketBytes;
+}
+__device__ __forceinline__ const uint8_t *bucket_ptr(const uint8_t *bk, uint32_t b) {
+  return bk + (uint64_t)b * kBucketBytes;
+}
+
+__device__ __forceinline__ uint32_t *lock_word(uint8_t *bk, uint32_t b) {
+  return reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kLockOffset);
+}
+
+__device__ __forceinline__ bool try_lock(uint8_t *bk, uint32_t b) {
+  uint32_t expected = 0u;
+  return __hip_atomic_compare_exchange_strong(lock_word(bk, b), &expected, 1u, __ATOMIC_RELAXED,
+                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void unlock(uint8_t *bk, uint32_t b) {
+  __hip_atomic_store(lock_word(bk, b), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Takes the locks of buckets x != y in ascending order, or none.  On
+// success the caller's later reads see every write made under these locks
+// by earlier holders.
+__device__ __forceinline__ bool lock_two(uint8_t *bk, uint32_t x, uint32_t y) {
+  const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
+  if (!try_lock(bk, lo)) return false;
+  if (!try_lock(bk, hi)) {
+    unlock(bk, lo);
+    return false;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
+}
+
+// Publishes the writes made under the locks, then drops both locks.
+__device__ __forceinline__ void unlock_two(uint8_t *bk, uint32_t x, uint32_t y) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  unlock(bk, x);
+  unlock(bk, y);
+}
+
+struct Head {
+  uint4 q0;  // tags
+  uint4 q1;  // bloom lo, bloom hi, meta, lock
+};
+
+__device__ __forceinline__ Head read_head(const uint8_t *bk, uint32_t b) {
+  const uint4 *q = reinterpret_cast<const uint4 *>(bucket_ptr(bk, b));
+  Head h;
+  h.q0 = q[0];
+  h.q1 = q[1];
+  return h;
+}
+
+__device__ __forceinline__ uint32_t *meta_ptr(uint8_t *bk, uint32_t b) {
+  return reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kMetaOffset);
+}
+__device__ __forceinline__ uint64_t *bloom_ptr(uint8_t *bk, uint32_t b) {
+  return reinterpret_cast<uint64_t *>(bucket_ptr(bk, b) + 16);
+}
+__device__ __forceinline__ uint16_t *tag_ptr(uint8_t *bk, uint32_t b) {
+  return reinterpret_cast<uint16_t *>(bucket_ptr(bk, b));
+}
+__device__ __forceinline__ uint32_t *other_ptr(uint8_t *bk, uint32_t b) {
+  return reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kOtherOffset);
+}
+__device__ __forceinline__ uint4 *key_ptr(uint8_t *bk, uint32_t b, uint32_t s) {
+  return reinterpret_cast<uint4 *>(bucket_ptr(bk, b) + key_offset(s));
+}
+__device__ __forceinline__ uint64_t *value_ptr(uint8_t *bk, uint32_t b, uint32_t s) {
+  return reinterpret_cast<uint64_t *>(bucket_ptr(bk, b) + value_offset(s));
+}
+
+// Slot of `key` in a bucket whose head is h (bucket locked), or -1.
+__device__ __forceinline__ int find_slot(uint8_t *bk, uint32_t b, const Head &h, uint4 key,
+                                         uint32_t tag) {
+  uint32_t cand = tag_eq_mask(h.q0, tag) & meta_busy(h.q1.z);
+  while (cand) {
+    const uint32_t s = (uint32_t)__builtin_ctz(cand);
+    cand &= cand - 1u;
+    if (key_eq(*key_ptr(bk, b, s), key)) return (int)s;
+  }
+  return -1;
+}
+
+__device__ __forceinline__ void write_entry(uint8_t *bk, uint32_t b, uint32_t s, uint4 key,
+                                            uint64_t value, uint32_t tag, uint32_t other) {
+  *key_ptr(bk, b, s) = key;
+  *value_ptr(bk, b, s) = value;
+  tag_ptr(bk, b)[s] = (uint16_t)tag;
+  other_ptr(bk, b)[s] = other;
+}
+
+constexpr int kBusy = -2;    // a lock was taken by another lane: retry
+constexpr int kNeedPath = -1;
+
+__device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value,
+                             const KeyFields &f, bool plain) {
+  if (!lock_two(bk, f.p, f.a)) return kBusy;
+  const Head hp = read_head(bk, f.p);
+  const Head ha = read_head(bk, f.a);
+  int r;
+  int s = find_slot(bk, f.p, hp, key, f.tag);
+  uint32_t b = f.p;
+  if (s < 0 && (plain || bloom_pass(hp.q1, f.bloom_bits))) {
+    s = find_slot(bk, f.a, ha, key, f.tag);
+    b = f.a;
+  }
+  if (s >= 0) {
+    *value_ptr(bk, b, (uint32_t)s) = value;
+    r = CKPP_UPDATED;
+  } else {
+    const uint32_t mp = hp.q1.z, ma = ha.q1.z;
+    const uint32_t busy_p = meta_busy(mp), busy_a = meta_busy(ma);
+    if (busy_p != 0xffu) {
+      const uint32_t fs = (uint32_t)__builtin_ctz(~busy_p & 0xffu);
+      write_entry(bk, f.p, fs, key, value, f.tag, f.a);
+      *meta_ptr(bk, f.p) = make_meta(meta_moved(mp), busy_p | (1u << fs), meta_sec(mp) & ~(1u << fs));
+      r = CKPP_INSERTED;
+    } else if (busy_a != 0xffu && (plain || meta_moved(mp) < 0xffffu)) {
+      const uint32_t fs = (uint32_t)__builtin_ctz(~busy_a & 0xffu);
+      write_entry(bk, f.a, fs, key, value, f.tag, f.p);
+      *meta_ptr(bk, f.a) = make_meta(meta_moved(ma), busy_a | (1u << fs), meta_sec(ma) | (1u << fs));
+      if (!plain) {
+        *bloom_ptr(bk, f.p) |= f.bloom_bits;
+        *meta_ptr(bk, f.p) = make_meta(meta_moved(mp) + 1u, busy_p, meta_sec(mp));
+      }
+      r = CKPP_INSERTED;
+    } else {
+      r = kNeedPath;
+    }
+  }
+  unlock_two(bk, f.p, f.a);
+  return r;
+}
+
+// Index of the k-th set bit of m (k < popcount(m)).
+__device__ __forceinline__ uint32_t nth_bit(uint32_t m, uint32_t k) {
+  for (uint32_t i = 0; i < k; ++i) m &= m - 1u;
+  return (uint32_t)__builtin_ctz(m);
+}
+
+__device__ __forceinline__ uint64_t load_relaxed(const uint8_t *p) {
+  return __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Random walk from bucket `start` (read without locks).  path[i] holds
+// bucket | slot << 24 of the i-th victim; *last receives the bucket with a
+// free slot that ends the path.  Returns the path length, or -1.
+__device__ int walk(const uint8_t *bk, uint32_t start, uint64_t rbase, uint32_t max_kicks,
+                    bool plain, uint32_t *path, uint32_t *last) {
+  uint32_t cur = start, prev = kNoBucket;
+  for (uint32_t step = 0; step < max_kicks; ++step) {
+    const uint8_t *base = bucket_ptr(bk, cur);
+    const uint32_t meta = (uint32_t)load_relaxed(base + kMetaOffset);
+    uint32_t other[kSlots];
+#pragma unroll
+    for (uint32_t w = 0; w < 4; ++w) {
+      const uint64_t o = load_relaxed(base + kOtherOffset + 8 * w);
+      other[2 * w] = (uint32_t)o;
+      other[2 * w + 1] = (uint32_t)(o >> 32);
+    }
+    uint32_t used = 0;
+    for (uint32_t i = 0; i < step; ++i) {
+      const uint32_t e = path[i];
+      if ((e & 0xffffffu) == cur) used |= 1u << (e >> 24);
+    }
+    const uint32_t sec = meta_sec(meta);
+    uint32_t cand = meta_busy(meta) & ~used;
+    if (!plain && meta_moved(meta) >= 0xffffu) cand &= sec;  // no owner may leave
+    uint32_t pref = 0;
+#pragma unroll
+    for (uint32_t s = 0; s < kSlots; ++s)
+      if (((cand >> s) & 1u) && other[s] != prev) pref |= 1u << s;
+    const uint32_t home = pref & sec;
+    const uint32_t pick = home ? home : (pref ? pref : cand);
+    if (!pick) return -1;
+    const uint64_t r = mix64(rbase + (uint64_t)(step + 1) * 0x9e3779b97f4a7c15ull);
+    const uint32_t v = nth_bit(pick, (uint32_t)(r % (uint64_t)__builtin_popcount(pick)));
+    path[step] = cur | (v << 24);
+    const uint32_t nxt = other[v];
+    const uint32_t nmeta = (uint32_t)load_relaxed(bucket_ptr(bk, nxt) + kMetaOffset);
+    if (meta_busy(nmeta) != 0xffu) {
+      *last = nxt;
+      return (int)step + 1;
+    }
+    prev = cur;
+    cur = nxt;
+  }
+  return -1;
+}
+
+// Moves the entry of slot s of bucket x to a free slot of bucket y, its
+// other bucket.  Returns 1 when done, 0 when the state no longer matches
+// the path, kBusy when a lock was taken.
+__device__ int move_entry(uint8_t *bk, uint32_t x, uint32_t s, uint32_t y,
+                          uint32_t log2b, uint64_t seed, bool plain) {
+  if (x == y || !lock_two(bk, x, y)) return kBusy;
+  int r = 0;
+  const uint32_t mx = *meta_ptr(bk, x), my = *meta_ptr(bk, y);
+  const uint32_t busy_x = meta_busy(mx), busy_y = meta_busy(my);
+  if (((busy_x >> s) & 1u) && other_ptr(bk, x)[s] == y && busy_y != 0xffu) {
+    const uint4 key = *key_ptr(bk, x, s);
+    const uint64_t val = *value_ptr(bk, x, s);
+    const KeyFields fe = key_fields(key_hash(key, seed), log2b);
+    const bool from_primary = fe.p == x;
+    const bool consistent = from_primary ? (fe.a == y) : (fe.a == x && fe.p == y);
+    if (consistent && (plain || !from_primary || meta_moved(mx) < 0xffffu)) {
+      const uint32_t fs = (uint32_t)__builtin_ctz(~busy_y & 0xffu);
+      write_entry(bk, y, fs, key, val, tag_ptr(bk, x)[s], x);
+      uint32_t moved_x = meta_moved(mx), moved_y = meta_moved(my);
+      const uint32_t sec_y =
+          from_primary ? (meta_sec(my) | (1u << fs)) : (meta_sec(my) & ~(1u << fs));
+      if (!plain) {
+        if (from_primary) {
+          *bloom_ptr(bk, x) |= fe.bloom_bits;
+          moved_x += 1u;
+        } else if (moved_y > 0u) {
+          moved_y -= 1u;
+          if (moved_y == 0u) *bloom_ptr(bk, y) = 0ull;
+        }
+      }
+      *meta_ptr(bk, y) = make_meta(moved_y, busy_y | (1u << fs), sec_y);
+      *meta_ptr(bk, x) = make_meta(moved_x, busy_x & ~(1u << s), meta_sec(mx) & ~(1u << s));
+      r = 1;
+    }
+  }
+  unlock_two(bk, x, y);
+  return r;
+}
+
+// Outcome of one key's insert: its status, and whether the retry bound ran
+// out (then the status is CKPP_FAILED).
+struct InsertOutcome {
+  int status;
+  bool spun;
+};
+
+// Runs one key through the DIRECT / WALK / MOVE state machine until it is
+// placed, updated or fails.  path: this lane's scratch, max(1, max_kicks)
+// words.
+__device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint32_t log2b,
+                                    uint64_t seed, uint32_t max_kicks, bool plain,
+                                    uint32_t *path) {
+  const uint64_t h = key_hash(key, seed);
+  const KeyFields f = key_fields(h, log2b);
+  enum { DIRECT, WALK, MOVE };
+  int state = DIRECT, result = -1;
+  uint32_t len = 0, next = 0, last = 0, walks = 0, iters = 0;
+  bool spun = false;
+  while (result < 0) {
+    if (++iters > kSpinLimit) {
+      result = CKPP_FAILED;
+      spun = true;
+      break;
+    }
+    if (state == DIRECT) {
+      const int r = insert_direct(bk, key, value, f, plain);
+      if (r >= 0)
+        result = r;
+      else if (r == kNeedPath)
+        state = WALK;
+    } else if (state == WALK) {
+      if (walks >= kMaxWalks) {
+        result = CKPP_FAILED;
+        break;
+      }
+      const int L = walk(bk, f.p, h ^ ((uint64_t)walks * 0xd1b54a32d192ed03ull), max_kicks, plain,
+                         path, &last);
+      ++walks;
+      if (L <= 0) {
+        result = CKPP_FAILED;
+      } else {
+        len = (uint32_t)L;
+        next = len;
+        state = MOVE;
+      }
+    } else {
+      const uint32_t e = path[next - 1];
+      const uint32_t x = e & 0xffffffu, s = e >> 24;
+      const uint32_t y = (next == len) ? last : (path[next] & 0xffffffu);
+      const int r = move_entry(bk, x, s, y, log2b, seed, plain);
+      if (r == 1) {
+        if (--next == 0) state = DIRECT;
+      } else if (r == 0) {
+        state = DIRECT;
+      }
+    }
+  }
+  return InsertOutcome{result, spun};
+}
+
+// Returns 1 if the key was removed, 0 if absent, kBusy to retry.
+__device__ int delete_direct(uint8_t *bk, uint4 key, const KeyFields &f, bool plain) {
+  if (!lock_two(bk, f.p, f.a)) return kBusy;
+  const Head hp = read_head(bk, f.p);
+  int r = 0;
+  int s = find_slot(bk, f.p, hp, key, f.tag);
+  const uint32_t mp = hp.q1.z;
+  if (s >= 0) {
+    const uint32_t bit = 1u << s;
+    *meta_ptr(bk, f.p) = make_meta(meta_moved(mp), meta_busy(mp) & ~bit, meta_sec(mp) & ~bit);
+    r = 1;
+  } else if (plain || bloom_pass(hp.q1, f.bloom_bits)) {
+    const Head ha = read_head(bk, f.a);
+    s = find_slot(bk, f.a, ha, key, f.tag);
+    if (s >= 0) {
+      const uint32_t bit = 1u << s, ma = ha.q1.z;
+      *meta_ptr(bk, f.a) = make_meta(meta_moved(ma), meta_busy(ma) & ~bit, meta_sec(ma) & ~bit);
+      if (!plain && meta_moved(mp) > 0u) {
+        const uint32_t moved = meta_moved(mp) - 1u;
+        if (moved == 0u) *bloom_ptr(bk, f.p) = 0ull;
+        *meta_ptr(bk, f.p) = make_meta(moved, meta_busy(mp), meta_sec(mp));
+      }
+      r = 1;
+    }
+  }
+  unlock_two(bk, f.p, f.a);
+  return r;
+}
+
+
+// Deletes one key: 1 if it was removed, 0 if absent; *spun is set when the
+// retry bound ran out (then 0 is returned).
+__device__ int delete_one(uint8_t *bk, uint4 key, uint32_t log2b, uint64_t seed, bool plain,
+                          bool *spun) {
+  const KeyFields f = key_fields(key_hash(key, seed), log2b);
+  int r = kBusy;
+  uint32_t iters = 0;
+  while (r == kBusy && iters < kSpinLimit) {
+    ++iters;
+    r = delete_direct(bk, key, f, plain);
+  }
+  *spun = r == kBusy;
+  return r == kBusy ? 0 : r;
+}
+
+}  // namespace
+}  // namespace ckpp

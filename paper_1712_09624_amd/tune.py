@@ -1,4 +1,4 @@
-"""Launch-shape autotuner of the lookup kernels.
+"""Launch-shape autotuner of the lookup kernels and of plans.
 
 Times every lookup launch shape (lanes per lookup, lookups in flight per
 lane, block size, grid cap) on a caller's table and key batches, and returns
@@ -53,4 +53,47 @@ def tune(table, batches, mode="cuckoopp", shapes=None, reps=3, apply=True):
     best = results[0][1] if apply else before
     table.set_lookup_launch(best["lanes_per_lookup"], best["lookups_per_lane"], best["block"],
                             best["blocks_per_cu"])
+    return results
+
+
+# Launch shapes of a plan's persistent kernel: lookups per lane, block size,
+# blocks per compute unit (persistent grid), lookup passes per work item and
+# schedule (0 static, 1 dynamic).
+PLAN_SHAPES = [
+    {"lookups_per_lane": per, "block": block, "blocks_per_cu": bpc, "passes_per_item": passes,
+     "schedule": sched}
+    for per, block, bpc, passes, sched in itertools.product((1, 2), (64, 128, 256), (2, 4, 8, 16),
+                                                            (1, 2, 4), (0, 1))
+]
+
+
+def time_plan(plan, keys, found, values, reps=5):
+    import torch
+    s = torch.cuda.current_stream()
+    plan.lookup(keys, found, values)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(reps):
+        plan.lookup(keys, found, values)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune_plan(plan, keys, found, values, shapes=None, reps=5, apply=True):
+    """Times every plan launch shape on the plan's own batches.  Returns
+    [(ms, shape)] sorted fastest first, and keeps the fastest shape on the
+    plan when apply is true (else restores the shape it had)."""
+    shapes = shapes or PLAN_SHAPES
+    before = plan.get_launch()
+    results = []
+    for sh in shapes:
+        plan.set_launch(sh["lookups_per_lane"], sh["block"], sh["blocks_per_cu"],
+                        sh["passes_per_item"], sh["schedule"])
+        results.append((time_plan(plan, keys, found, values, reps), dict(sh)))
+    results.sort(key=lambda r: r[0])
+    best = results[0][1] if apply else before
+    plan.set_launch(best["lookups_per_lane"], best["block"], best["blocks_per_cu"],
+                    best["passes_per_item"], best["schedule"])
     return results

@@ -35,6 +35,7 @@ STREAM_MIX = 1
 STREAM_DELETE = 2
 STREAM_FRESH = 3
 STREAM_NEGATIVE = 4
+STREAM_TABLES = 5
 
 
 def raw_u64(seed: int, stream: int, n: int) -> np.ndarray:
@@ -149,3 +150,27 @@ def log_uniform_sizes(n: int, lo: int, hi: int, seed: int, stream: int) -> np.nd
     u = (raw_u64(seed, stream, n) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
     v = np.exp(np.log(lo) + u * (np.log(hi + 1) - np.log(lo)))
     return np.clip(np.floor(v).astype(np.int64), lo, hi)
+
+
+def uniform01(n: int, seed: int, stream: int) -> np.ndarray:
+    """n doubles uniform in [0, 1) (53-bit)."""
+    return (raw_u64(seed, stream, n) >> np.uint64(11)).astype(np.float64) / float(1 << 53)
+
+
+def many_tables(ntables: int, seed: int, log2_lo: int = 10, log2_hi: int = 18,
+                load_lo: float = 0.6, load_hi: float = 0.95, batch_lo: int = 32,
+                batch_hi: int = 4096) -> dict:
+    """Parameters of a many-table batching workload: per table, a bucket
+    count log-uniform over the powers of two 2^log2_lo..2^log2_hi (the
+    exponent uniform), a load uniform in [load_lo, load_hi], a lookup batch
+    size uniform in [batch_lo, batch_hi] and a negative-lookup rate uniform
+    in [0, 1].  Returns arrays log2_buckets, load, batch, neg_rate."""
+    n = int(ntables)
+    u = uniform01(4 * n, seed, STREAM_TABLES).reshape(4, n) if n else np.zeros((4, 0))
+    span = log2_hi - log2_lo + 1
+    return {
+        "log2_buckets": (log2_lo + np.floor(u[0] * span)).astype(np.int64),
+        "load": load_lo + u[1] * (load_hi - load_lo),
+        "batch": (batch_lo + np.floor(u[2] * (batch_hi - batch_lo + 1))).astype(np.int64),
+        "neg_rate": u[3],
+    }

@@ -65,6 +65,16 @@ def test_argument_checks_need_no_device(lib):
     assert lib.ckpp_delete_batch(None, None, 5, None, None) == ckpp.EINVAL
     assert lib.ckpp_destroy(None) == ckpp.OK
     assert lib.ckpp_probe_random_reads(None, 64, 64, 1, 1, 0, 256, 1, 0, None, None) == ckpp.EINVAL
+    offs = (ctypes.c_uint64 * 1)(0)
+    cnts = (ctypes.c_uint64 * 1)(1)
+    tabs = (ctypes.c_void_p * 1)(None)
+    assert lib.ckpp_plan_create(None, tabs, 1, offs, cnts, None) == ckpp.EINVAL
+    assert lib.ckpp_plan_create(ctypes.byref(h), None, 1, offs, cnts, None) == ckpp.EINVAL
+    assert lib.ckpp_plan_create(ctypes.byref(h), tabs, 0, offs, cnts, None) == ckpp.EINVAL
+    assert lib.ckpp_plan_create(ctypes.byref(h), tabs, 1, offs, cnts, None) == ckpp.EINVAL
+    assert lib.ckpp_plan_lookup(None, None, None, None, None) == ckpp.EINVAL
+    assert lib.ckpp_plan_set_launch(None, None) == ckpp.EINVAL
+    assert lib.ckpp_plan_destroy(None) == ckpp.OK
 
 
 def test_missing_library_fails_loudly(tmp_path):
@@ -78,8 +88,9 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "ckpp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\n", sizeof(ckpp_stats_t), offsetof(ckpp_stats_t, moved_hist),
-         sizeof(ckpp_info_t), sizeof(ckpp_launch_t));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(ckpp_stats_t), offsetof(ckpp_stats_t, moved_hist),
+         sizeof(ckpp_info_t), sizeof(ckpp_launch_t), sizeof(ckpp_plan_launch_t),
+         sizeof(ckpp_plan_info_t), offsetof(ckpp_plan_info_t, key_span));
   return 0;
 }
 """
@@ -90,8 +101,11 @@ int main(void) {
         subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), "-o", exe, c],
                        check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
-    sz_stats, off_hist, sz_info, sz_launch = map(int, out)
+    sz_stats, off_hist, sz_info, sz_launch, sz_pl, sz_pi, off_span = map(int, out)
     assert sz_stats == ctypes.sizeof(ckpp._Stats)
     assert off_hist == ckpp._Stats.moved_hist.offset
     assert sz_info == ctypes.sizeof(ckpp._Info)
     assert sz_launch == ctypes.sizeof(ckpp._Launch)
+    assert sz_pl == ctypes.sizeof(ckpp._PlanLaunch)
+    assert sz_pi == ctypes.sizeof(ckpp._PlanInfo)
+    assert off_span == ckpp._PlanInfo.key_span.offset
