@@ -498,6 +498,7 @@ class Server:
         r = _ServerRings()
         _check(self.lib.ckpp_server_rings(self._h, ctypes.byref(r)), "ckpp_server_rings")
         self.capacity = int(r.capacity)
+        self._stage = [0, 0, 0]  # op numbers where put_burst stages next
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -539,17 +540,20 @@ class Server:
 
     def put_burst(self, lookup_keys=None, insert_keys=None, insert_values=None,
                   delete_keys=None):
-        """Puts one burst's operations at the next positions; returns the
-        counts and the first op number of each kind."""
+        """Stages one burst's operations after those already staged or
+        submitted (bursts may be staged ahead of their submission, in
+        submission order, as long as they fit the rings); returns the counts
+        for submit() and the first op number of each kind."""
         st = self.status()
         counts, first = [], []
-        for kind, keys, vals in (("lookup", lookup_keys, None), ("insert", insert_keys,
-                                                                 insert_values),
-                                 ("delete", delete_keys, None)):
+        for k, (kind, keys, vals) in enumerate((("lookup", lookup_keys, None),
+                                                ("insert", insert_keys, insert_values),
+                                                ("delete", delete_keys, None))):
             n = 0 if keys is None else int(keys.shape[0])
-            pos = st[f"{kind}_tail"]
+            pos = max(self._stage[k], st[f"{kind}_tail"])
             if n:
                 self.put(kind, pos, keys, vals)
+            self._stage[k] = pos + n
             counts.append(n)
             first.append(pos)
         return counts, first

@@ -45,6 +45,9 @@ constexpr uint32_t kWaves = kBlock / 64;
 constexpr uint64_t kTicksPerMs = 100000; // real-time counter: 100 MHz
 constexpr uint64_t kPhaseMs = 20000;     // a phase may take this long at most
 constexpr uint32_t kMaxPathLanes = 65536;
+// second bound on every spin loop, in iterations (each one sleeps and reads
+// memory, so this is tens of seconds)
+constexpr uint64_t kMaxSpins = 1ull << 26;
 
 constexpr uint32_t kCmdRun = 1, kCmdExit = 2;
 
@@ -115,9 +118,9 @@ __device__ bool arrive_and_wait(ServeDev *d, uint64_t limit_ticks) {
   const uint32_t g = agent_load32(&d->gen);
   __hip_atomic_fetch_add(&d->arrived, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   const uint64_t t0 = now_ticks();
-  while (agent_load32(&d->gen) == g) {
+  for (uint64_t it = 0; agent_load32(&d->gen) == g; ++it) {
     if (agent_load32(&d->abort)) return false;
-    if (now_ticks() - t0 > limit_ticks) {
+    if (now_ticks() - t0 > limit_ticks || it > kMaxSpins) {
       __hip_atomic_store(&d->abort, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -130,9 +133,9 @@ __device__ bool arrive_and_wait(ServeDev *d, uint64_t limit_ticks) {
 __device__ bool leader_gather(ServeDev *d, uint32_t nblocks, uint64_t limit_ticks) {
   __hip_atomic_fetch_add(&d->arrived, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   const uint64_t t0 = now_ticks();
-  while (agent_load32(&d->arrived) != nblocks) {
+  for (uint64_t it = 0; agent_load32(&d->arrived) != nblocks; ++it) {
     if (agent_load32(&d->abort)) return false;
-    if (now_ticks() - t0 > limit_ticks) {
+    if (now_ticks() - t0 > limit_ticks || it > kMaxSpins) {
       __hip_atomic_store(&d->abort, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -158,11 +161,11 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   }
   const uint64_t t0 = now_ticks();
   uint64_t s = 0;
-  for (;;) {
+  for (uint64_t it = 0;; ++it) {
     s = sys_load64(&h->submitted);
     if (s > d->done) break;
     if (sys_load32(&h->stop)) return kCmdExit;
-    if (now_ticks() - t0 > a.idle_ticks) {
+    if (now_ticks() - t0 > a.idle_ticks || it > kMaxSpins) {
       // tell the host the loop is leaving, then look once more: a burst
       // submitted before the host saw EXITING is still taken
       sys_store32(&h->state, CKPP_SERVER_EXITING);
@@ -362,12 +365,14 @@ hipError_t launch_loop(ckpp_server *s) {
 // Makes sure a loop is running after a submit (see the exit protocol in
 // leader_next_round).
 int ensure_running(ckpp_server *s) {
+  const auto t0 = std::chrono::steady_clock::now();
   for (;;) {
     const uint32_t st = host_u32(&s->host->state)->load(std::memory_order_seq_cst);
     if (st == CKPP_SERVER_RUNNING) return CKPP_OK;
     if (st == CKPP_SERVER_ABORTED) return CKPP_EDEVICE;
-    if (st == CKPP_SERVER_EXITING) {
-      std::this_thread::yield();
+    if (st == CKPP_SERVER_EXITING &&
+        std::chrono::steady_clock::now() - t0 < std::chrono::seconds(5)) {
+      std::this_thread::yield();  // the loop decides within microseconds
       continue;
     }
     // stopped: the previous kernel has left (or is leaving) the loop
