@@ -53,6 +53,8 @@ def parse():
                     help="run only a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sweep", action="store_true",
                     help="lookup rate over loads x negative rates x modes (2^24 and 2^20 buckets)")
+    ap.add_argument("--serve", type=int, default=0, metavar="BURSTS",
+                    help="serving workload, BURSTS bursts per run: peak, then 25/50/75/100%% offered")
     ap.add_argument("--many-tables", type=int, default=0, metavar="N",
                     help="batching workload over N tables: per-table calls vs one plan launch")
     ap.add_argument("--insert-workload", action="store_true",
@@ -502,6 +504,99 @@ def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
     return out
 
 
+SERVE_UNIVERSE = 100_000_000
+SERVE_SCRAMBLE = 2654435761  # odd, prime to 10^8: rank -> flow is a permutation
+
+
+def serve_stream(nbursts, seed, keys, universe, vals, del_base):
+    """One serving run's bursts: sizes log-uniform in [1, 2048]; each burst
+    0.9 n lookups (rounded half up), 0.1 n inserts of new flows, 0.05 n
+    deletes of expired flows.  Lookups pick flows of the universe by Zipf
+    s = 1.1 popularity (rank r -> flow r * SERVE_SCRAMBLE mod universe);
+    inserts are fresh keys; deletes take stored keys outside the universe,
+    from del_base on."""
+    size = W.log_uniform_sizes(nbursts, 1, 2048, seed, 20)
+    nl = np.floor(0.9 * size + 0.5).astype(np.int64)
+    ni = np.floor(0.1 * size + 0.5).astype(np.int64)
+    nd = np.floor(0.05 * size + 0.5).astype(np.int64)
+    ranks = W.zipf_ranks(int(nl.sum()), universe, 1.1, seed, 21)
+    flows = (ranks.astype(np.uint64) * np.uint64(SERVE_SCRAMBLE)) % np.uint64(universe)
+    flows = flows.astype(np.int64)
+    ins = W.five_tuples(int(ni.sum()), seed, 22)
+    dels = np.arange(del_base, del_base + int(nd.sum()), dtype=np.int64)
+    if dels.size and dels[-1] >= len(keys):
+        raise RuntimeError("not enough expired flows for the deletes")
+    return {"nl": nl, "ni": ni, "nd": nd, "look": keys[flows], "look_val": vals[flows],
+            "ins": ins, "ins_val": np.arange(int(ni.sum()), dtype=np.uint64) + np.uint64(1 << 40),
+            "dels": keys[dels], "del_next": del_base + int(nd.sum())}
+
+
+def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0),
+                budget=1 << 20, capacity=1 << 25):
+    """Serving workload: a 2^24-bucket table at load 0.85 whose first 100M
+    keys are the flow universe; a closed-loop run measures the loop's peak,
+    then open-loop Poisson runs offer 25/50/75/100 % of it.  Every run's
+    lookups, inserts and deletes are checked against the ground truth."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Server
+    t, keys, vals, build_s = build_table(B, load, 11, dev)
+    universe = min(SERVE_UNIVERSE, len(keys))
+    srv = Server(t, capacity=capacity, budget=budget, blocks_per_cu=1, idle_ms=2000)
+    out = {"log2_buckets": B, "load": load, "stored_keys": len(keys), "universe": universe,
+           "budget_ops": budget, "ring_capacity": capacity, "bursts_per_run": nbursts,
+           "grid_blocks": srv.status()["grid"], "runs": []}
+    del_base = universe
+    peak_lps = None
+    for run, frac in enumerate((None,) + tuple(fracs)):
+        st = serve_stream(nbursts, 100 + run, keys, universe, vals, del_base)
+        del_base = st["del_next"]
+        # stage the run's operations in the rings
+        s0 = srv.status()
+        pos = [s0["lookup_tail"], s0["insert_tail"], s0["delete_tail"]]
+        srv.put("lookup", pos[0], to_dev(st["look"], dev))
+        if len(st["ins"]):
+            srv.put("insert", pos[1], to_dev(st["ins"], dev),
+                    to_dev(st["ins_val"].view(np.int64), dev))
+        if len(st["dels"]):
+            srv.put("delete", pos[2], to_dev(st["dels"], dev))
+        mean_l = float(st["nl"].mean())
+        if frac is None:
+            arrival = np.zeros(nbursts)
+        else:
+            arrival = W.poisson_arrivals(nbursts, frac * peak_lps / mean_l, 100 + run, 23)
+        r0 = srv.status()["rounds"]
+        adm, done = srv.replay(st["nl"], st["ni"], st["nd"], arrival, 120.0)
+        rounds = srv.status()["rounds"] - r0
+        # verify every result of the run
+        f, v = srv.get("lookup", pos[0], len(st["look"]))
+        ist = srv.get("insert", pos[1], len(st["ins"]))
+        dfo = srv.get("delete", pos[2], len(st["dels"]))
+        torch.cuda.current_stream(dev).synchronize()
+        ok = (bool((f.cpu().numpy() == 1).all())
+              and np.array_equal(v.cpu().numpy().view(np.uint64), st["look_val"])
+              and bool((ist.cpu().numpy() == 0).all()) and bool((dfo.cpu().numpy() == 1).all()))
+        if not ok:
+            raise RuntimeError(f"serving run {run}: wrong results")
+        span = float(done.max() - arrival.min())
+        lat = (done - arrival) * 1e6
+        nlook = int(st["nl"].sum())
+        ops = nlook + int(st["ni"].sum()) + int(st["nd"].sum())
+        rec = {"offered": "closed loop (peak)" if frac is None else frac,
+               "offered_glookups": None if frac is None else frac * peak_lps / 1e9,
+               "glookups": nlook / span / 1e9, "gops": ops / span / 1e9,
+               "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+               "mean_us": float(lat.mean()), "rounds": rounds,
+               "bursts_per_round": nbursts / max(rounds, 1), "lookups": nlook, "ops": ops,
+               "span_s": span}
+        if frac is None:
+            peak_lps = nlook / span
+        out["runs"].append(rec)
+        log(f"serve run {run}: {rec}")
+    srv.close()
+    t.close()
+    return out
+
+
 PROFILE_CMDS = {
     "trace": "rocprofv3 --kernel-trace --stats --output-format csv -d DIR/p4_trace -o core -- "
              "python3 bench.py --core-only --steps 5 --warmup 2",
@@ -618,6 +713,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.copy_calib:
         copy_calibration(dev)
+        return
+    if args.serve:
+        print(json.dumps({"serve": serve_bench(dev, args.serve)}), flush=True)
         return
     if args.many_tables:
         print(json.dumps({"many_tables": many_table_bench(dev, args.many_tables)}), flush=True)

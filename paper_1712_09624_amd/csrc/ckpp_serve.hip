@@ -557,10 +557,14 @@ int ckpp_server_status(ckpp_server *s, ckpp_server_status_t *out) {
   return CKPP_OK;
 }
 
-int ckpp_server_submit(ckpp_server *s, uint32_t n_lookup, uint32_t n_insert, uint32_t n_delete,
-                       uint64_t *burst) {
-  if (!s) return CKPP_EINVAL;
-  const uint64_t done = host_u64(&s->host->completed)->load(std::memory_order_acquire);
+}  // extern "C"
+
+namespace {
+
+// Records a burst's tails for the loop without publishing it; CKPP_EBUSY
+// when it does not fit the budget or the queue.  `done`: bursts completed.
+int stage_burst(ckpp_server *s, uint64_t done, uint32_t n_lookup, uint32_t n_insert,
+                uint32_t n_delete) {
   if (s->submitted - done >= ckpp::kQueue) return CKPP_EBUSY;
   // ops in flight of each kind after this burst
   const uint64_t *dt = done ? &s->burst_tails[3 * ((done - 1) % ckpp::kQueue)] : nullptr;
@@ -578,11 +582,30 @@ int ckpp_server_submit(ckpp_server *s, uint32_t n_lookup, uint32_t n_insert, uin
     s->tails[k] = nt[k];
   }
   s->submitted = b + 1;
-  host_u64(&s->host->submitted)->store(b + 1, std::memory_order_seq_cst);
-  if (burst) *burst = b;
+  return CKPP_OK;
+}
+
+// Hands every staged burst to the loop (one store), relaunching it if it
+// has left.
+int publish(ckpp_server *s) {
+  host_u64(&s->host->submitted)->store(s->submitted, std::memory_order_seq_cst);
   DeviceGuard g(s->device);
   if (!g.ok()) return CKPP_EDEVICE;
   return ensure_running(s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int ckpp_server_submit(ckpp_server *s, uint32_t n_lookup, uint32_t n_insert, uint32_t n_delete,
+                       uint64_t *burst) {
+  if (!s) return CKPP_EINVAL;
+  const uint64_t done = host_u64(&s->host->completed)->load(std::memory_order_acquire);
+  const int rc = stage_burst(s, done, n_lookup, n_insert, n_delete);
+  if (rc != CKPP_OK) return rc;
+  if (burst) *burst = s->submitted - 1;
+  return publish(s);
 }
 
 int ckpp_server_wait(ckpp_server *s, uint64_t burst, uint32_t timeout_ms) {
@@ -613,13 +636,20 @@ int ckpp_server_replay(ckpp_server *s, uint64_t nbursts, const uint32_t *h_nlook
   while (seen < nbursts) {
     const auto now = clk::now();
     const double ts = since(now);
+    // every burst that has arrived and fits is staged, then all are
+    // published with one store
+    const uint64_t done = host_u64(&s->host->completed)->load(std::memory_order_acquire);
+    const uint64_t staged = next;
     while (next < nbursts && h_arrival_s[next] <= ts) {
-      const int rc = ckpp_server_submit(s, h_nlookup[next], h_ninsert[next], h_ndelete[next],
-                                        nullptr);
-      if (rc == CKPP_EBUSY) break;
-      if (rc != CKPP_OK) return rc;
-      h_admit_s[next] = since(clk::now());
+      if (stage_burst(s, done, h_nlookup[next], h_ninsert[next], h_ndelete[next]) != CKPP_OK)
+        break;
       ++next;
+    }
+    if (next > staged) {
+      const int rc = publish(s);
+      if (rc != CKPP_OK) return rc;
+      const double ta = since(clk::now());
+      for (uint64_t i = staged; i < next; ++i) h_admit_s[i] = ta;
     }
     const uint64_t c = host_u64(&s->host->completed)->load(std::memory_order_acquire);
     if (c > first + seen) {

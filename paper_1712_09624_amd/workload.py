@@ -174,3 +174,22 @@ def many_tables(ntables: int, seed: int, log2_lo: int = 10, log2_hi: int = 18,
         "batch": (batch_lo + np.floor(u[2] * (batch_hi - batch_lo + 1))).astype(np.int64),
         "neg_rate": u[3],
     }
+
+
+def zipf_ranks(n: int, universe: int, s: float, seed: int, stream: int) -> np.ndarray:
+    """n popularity ranks in [0, universe), rank r drawn with probability
+    close to (r + 1)^-s / H(universe, s): the inverse of the continuous
+    approximation (density proportional to x^-s on [1, universe + 1)),
+    floored, for s != 1."""
+    u = uniform01(n, seed, stream)
+    a = 1.0 - s
+    lo, hi = 1.0, float(universe) + 1.0
+    x = (lo ** a + u * (hi ** a - lo ** a)) ** (1.0 / a)
+    return np.minimum(np.floor(x).astype(np.int64) - 1, universe - 1)
+
+
+def poisson_arrivals(n: int, rate: float, seed: int, stream: int) -> np.ndarray:
+    """Arrival times (seconds) of n events of a Poisson process of the given
+    rate, starting at the first inter-arrival gap."""
+    u = uniform01(n, seed, stream)
+    return np.cumsum(-np.log1p(-u) / rate)
