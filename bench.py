@@ -564,9 +564,12 @@ def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0
             arrival = np.zeros(nbursts)
         else:
             arrival = W.poisson_arrivals(nbursts, frac * peak_lps / mean_l, 100 + run, 23)
-        r0 = srv.status()["rounds"]
+        s_before = srv.status()
         adm, done = srv.replay(st["nl"], st["ni"], st["nd"], arrival, 120.0)
-        rounds = srv.status()["rounds"] - r0
+        s_after = srv.status()
+        rounds = s_after["rounds"] - s_before["rounds"]
+        phase_us = {k[:-3]: (s_after[k] - s_before[k]) / 1e3 / max(rounds, 1)
+                    for k in ("lookup_ns", "insert_ns", "delete_ns", "boundary_ns")}
         # verify every result of the run
         f, v = srv.get("lookup", pos[0], len(st["look"]))
         ist = srv.get("insert", pos[1], len(st["ins"]))
@@ -586,7 +589,8 @@ def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0
                "glookups": nlook / span / 1e9, "gops": ops / span / 1e9,
                "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
                "mean_us": float(lat.mean()), "rounds": rounds,
-               "bursts_per_round": nbursts / max(rounds, 1), "lookups": nlook, "ops": ops,
+               "bursts_per_round": nbursts / max(rounds, 1), "us_per_round": phase_us,
+               "lookups": nlook, "ops": ops,
                "span_s": span}
         if frac is None:
             peak_lps = nlook / span

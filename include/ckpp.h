@@ -356,6 +356,10 @@ typedef struct {
     uint64_t launches;    /* loop kernel launches (1 + restarts) */
     uint32_t state;       /* CKPP_SERVER_* */
     uint32_t grid;        /* blocks of the loop kernel */
+    /* the loop's own clock, summed over rounds, as of the last round
+       boundary: from the release of each phase until every block finished
+       it; at round boundaries apart from waiting; waiting for bursts */
+    uint64_t lookup_ns, insert_ns, delete_ns, boundary_ns, wait_ns;
 } ckpp_server_status_t;
 
 /* Creates a server on table t (the table must not be used by other calls

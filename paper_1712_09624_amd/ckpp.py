@@ -132,6 +132,11 @@ class _ServerStatus(ctypes.Structure):
         ("launches", ctypes.c_uint64),
         ("state", ctypes.c_uint32),
         ("grid", ctypes.c_uint32),
+        ("lookup_ns", ctypes.c_uint64),
+        ("insert_ns", ctypes.c_uint64),
+        ("delete_ns", ctypes.c_uint64),
+        ("boundary_ns", ctypes.c_uint64),
+        ("wait_ns", ctypes.c_uint64),
     ]
 
 

@@ -7,10 +7,10 @@
 // submitted bursts; the loop's leader (block 0, thread 0) polls that number
 // and publishes the number of completed bursts there.  A round:
 //
-//   boundary  every block arrives at the leader's barrier; once all have
-//             arrived the leader publishes the previous round's completion,
-//             waits for submitted bursts (or exits after idle_ms without
-//             any), writes the round's op ranges and releases the barrier
+//   boundary  every block arrives at a grid barrier; once all have arrived
+//             the leader publishes the previous round's completion, waits
+//             for submitted bursts (or exits after idle_ms without any),
+//             writes the round's op ranges and releases the barrier
 //   lookups   every wave runs 64-lookup passes over the round's lookup range
 //             (the lookup passes of the batch kernels, unchanged)
 //   inserts   after a barrier, one lane per key (the batch insert's state
@@ -19,10 +19,15 @@
 //   end       each block makes its results visible to the host (system-
 //             scope release) before it arrives at the next boundary
 //
-// Every wait is bounded by the real-time counter: a block that waits too
-// long for a barrier sets `abort`, every other wait sees it, and the whole
-// grid leaves the loop, so the kernel always ends.  The grid is launched
-// cooperatively, so all of its blocks are resident at once.
+// The barriers use no atomics (each block stores its arrival in a flag line
+// of its own; one wave polls them), and every polling load is relaxed, with
+// one acquire fence after the wait: on this GPU an acquire load invalidates
+// the cache, and a waiting wave must not keep invalidating the caches the
+// working waves read through.  Every wait is bounded by the real-time
+// counter and by an iteration count: a block that waits too long sets
+// `abort`, every other wait sees it, and the whole grid leaves the loop, so
+// the kernel always ends.  The grid is launched cooperatively, so all of
+// its blocks are resident at once.
 
 #include <algorithm>
 #include <atomic>
@@ -65,11 +70,20 @@ struct ServeHost {
 struct ServeDev {
   uint64_t done;              // bursts taken into rounds so far
   uint64_t lk0, lk1, in0, in1, de0, de1;  // the round's op ranges
+  uint64_t rounds;            // rounds completed
+  // leader's clock (real-time ticks): time from a phase's release until
+  // every block has finished it, per phase; time spent at round boundaries
+  // apart from waiting for work; time waiting for work
+  uint64_t t_lookup, t_insert, t_delete, t_boundary, t_wait;
+  uint64_t t_mark;            // when the leader last released a barrier
   uint32_t cmd;               // kCmdRun / kCmdExit for the blocks
   uint32_t abort;             // a wait ran out of time
-  uint32_t arrived;           // barrier: blocks arrived
-  uint32_t gen;               // barrier: generation, bumped by the leader
+  uint32_t gen;               // barrier: last epoch the leader released
 };
+
+// Barrier flags: block b stores the epoch it reached at arrive[b * kFlagStride]
+// (one 128-byte line per block, so arrivals never contend).
+constexpr uint32_t kFlagStride = 32;
 
 struct ServeArgs {
   TableRef T;
@@ -78,7 +92,8 @@ struct ServeArgs {
   uint32_t plain;
   ServeHost *host;
   ServeDev *dev;
-  uint64_t mask;  // capacity - 1
+  uint32_t *arrive;  // barrier flags, gridDim.x lines
+  uint64_t mask;     // capacity - 1
   const uint4 *lk_keys;
   uint8_t *lk_found;
   uint64_t *lk_vals;
@@ -98,56 +113,83 @@ __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memr
 __device__ __forceinline__ uint64_t sys_load64(const uint64_t *p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
-__device__ __forceinline__ uint32_t sys_load32(const uint32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
-}
 __device__ __forceinline__ void sys_store64(uint64_t *p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 __device__ __forceinline__ void sys_store32(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
-__device__ __forceinline__ uint32_t agent_load32(const uint32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// Polling loads: relaxed, so a spinning wave does not invalidate its caches
+// on every iteration (an acquire load does, which would slow every other
+// wave of the XCD while this one waits); the waiter issues one acquire
+// fence once the awaited value has arrived.
+__device__ __forceinline__ uint32_t poll32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t poll_sys64(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ uint32_t poll_sys32(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Non-leader side of a barrier (thread 0 of the block): arrive, then wait
-// until the leader bumps the generation.  Returns false when the wait ran
-// out of time or another block gave up.
-__device__ bool arrive_and_wait(ServeDev *d, uint64_t limit_ticks) {
-  const uint32_t g = agent_load32(&d->gen);
-  __hip_atomic_fetch_add(&d->arrived, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// A barrier over the grid without atomics.  Every block reaches the same
+// sequence of barriers and numbers them with the same epochs.  Thread 0 of
+// each block stores the epoch in its own flag line (release); the leader
+// wave (block 0, wave 0) polls all flags, 64 lanes at a time, until every
+// block has arrived, then the leader stores the epoch in `gen` (release);
+// the other blocks' thread 0 poll `gen`.  A wait that runs out of time or
+// iterations sets `abort`, which every other wait gives up on.
+__device__ __forceinline__ void block_arrive(const ServeArgs &a, uint32_t epoch) {
+  __hip_atomic_store(a.arrive + (uint64_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELEASE,
+                     __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void set_abort(ServeDev *d) {
+  __hip_atomic_store(&d->abort, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Non-leader blocks, thread 0: waits for the leader's release of `epoch`.
+__device__ bool wait_release(const ServeArgs &a, uint32_t epoch, uint64_t limit_ticks) {
+  ServeDev *d = a.dev;
   const uint64_t t0 = now_ticks();
-  for (uint64_t it = 0; agent_load32(&d->gen) == g; ++it) {
-    if (agent_load32(&d->abort)) return false;
+  for (uint64_t it = 0; (int32_t)(poll32(&d->gen) - epoch) < 0; ++it) {
+    if (poll32(&d->abort)) return false;
     if (now_ticks() - t0 > limit_ticks || it > kMaxSpins) {
-      __hip_atomic_store(&d->abort, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      set_abort(d);
       return false;
     }
     __builtin_amdgcn_s_sleep(2);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
 
-// Leader side: arrive and wait until every block has arrived.
-__device__ bool leader_gather(ServeDev *d, uint32_t nblocks, uint64_t limit_ticks) {
-  __hip_atomic_fetch_add(&d->arrived, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Leader wave (all 64 lanes of wave 0 of block 0): waits until every block
+// has stored `epoch`.  Uniform result.
+__device__ bool gather(const ServeArgs &a, uint32_t epoch, uint64_t limit_ticks) {
+  ServeDev *d = a.dev;
+  const uint32_t lane = threadIdx.x & 63u;
   const uint64_t t0 = now_ticks();
-  for (uint64_t it = 0; agent_load32(&d->arrived) != nblocks; ++it) {
-    if (agent_load32(&d->abort)) return false;
-    if (now_ticks() - t0 > limit_ticks || it > kMaxSpins) {
-      __hip_atomic_store(&d->abort, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  for (uint64_t it = 0;; ++it) {
+    bool mine = true;
+    for (uint32_t b = lane; b < gridDim.x; b += 64u)
+      mine = mine && (int32_t)(poll32(a.arrive + (uint64_t)b * kFlagStride) - epoch) >= 0;
+    if (__builtin_amdgcn_ballot_w64(!mine) == 0ull) break;
+    const bool stop = poll32(&d->abort) != 0u || now_ticks() - t0 > limit_ticks || it > kMaxSpins;
+    if (__builtin_amdgcn_readfirstlane((int)stop)) {
+      if (lane == 0u) set_abort(d);
       return false;
     }
     __builtin_amdgcn_s_sleep(2);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
 }
 
-// Leader: releases the blocks waiting at the barrier.
-__device__ void leader_release(ServeDev *d) {
-  __hip_atomic_store(&d->arrived, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_fetch_add(&d->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+// Leader: releases `epoch` to the waiting blocks.
+__device__ __forceinline__ void release_epoch(ServeDev *d, uint32_t epoch) {
+  __hip_atomic_store(&d->gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Leader at a round boundary (every block has arrived): publish the round
@@ -156,15 +198,16 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   ServeHost *h = a.host;
   ServeDev *d = a.dev;
   if (ran_round) {
+    d->rounds += 1u;
+    sys_store64(&h->rounds, d->rounds);
     sys_store64(&h->completed, d->done);
-    sys_store64(&h->rounds, sys_load64(&h->rounds) + 1u);
   }
   const uint64_t t0 = now_ticks();
   uint64_t s = 0;
   for (uint64_t it = 0;; ++it) {
-    s = sys_load64(&h->submitted);
+    s = poll_sys64(&h->submitted);
     if (s > d->done) break;
-    if (sys_load32(&h->stop)) return kCmdExit;
+    if (poll_sys32(&h->stop)) return kCmdExit;
     if (now_ticks() - t0 > a.idle_ticks || it > kMaxSpins) {
       // tell the host the loop is leaving, then look once more: a burst
       // submitted before the host saw EXITING is still taken
@@ -179,6 +222,9 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
     }
     __builtin_amdgcn_s_sleep(4);
   }
+  d->t_wait += now_ticks() - t0;
+  // the tails the host wrote before it published `s`
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
   const uint64_t *t = h->tails[(s - 1u) % kQueue];
   d->lk0 = d->lk1;
   d->in0 = d->in1;
@@ -232,17 +278,24 @@ __device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1) {
 }
 
 // Grid-wide barrier inside a round (every thread of every block calls it).
-__device__ bool phase_barrier(const ServeArgs &a, uint32_t *s_ok) {
+__device__ bool phase_barrier(const ServeArgs &a, uint32_t epoch, uint32_t phase,
+                              uint32_t *s_ok) {
   __syncthreads();
-  if (threadIdx.x == 0) {
-    bool ok;
-    if (blockIdx.x == 0) {
-      ok = leader_gather(a.dev, gridDim.x, kPhaseMs * kTicksPerMs);
-      leader_release(a.dev);
-    } else {
-      ok = arrive_and_wait(a.dev, kPhaseMs * kTicksPerMs);
+  if (threadIdx.x == 0) block_arrive(a, epoch);
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 64u) {
+      const bool ok = gather(a, epoch, kPhaseMs * kTicksPerMs);
+      if (threadIdx.x == 0) {
+        // the phase that just ended: lookups (first barrier) or inserts
+        const uint64_t t = now_ticks();
+        *(phase == 0 ? &a.dev->t_lookup : &a.dev->t_insert) += t - a.dev->t_mark;
+        a.dev->t_mark = t;
+        release_epoch(a.dev, epoch);
+        *s_ok = ok ? 1u : 0u;
+      }
     }
-    *s_ok = ok ? 1u : 0u;
+  } else if (threadIdx.x == 0) {
+    *s_ok = wait_release(a, epoch, kPhaseMs * kTicksPerMs) ? 1u : 0u;
   }
   __syncthreads();
   return *s_ok != 0u;
@@ -256,24 +309,47 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
   const Wave w = wave_lines<NB>(s_lines);
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   ServeDev *d = a.dev;
+  // epochs continue from the last launch's (nothing writes gen until every
+  // block of this launch has arrived at its first barrier)
+  uint32_t epoch = poll32(&d->gen);
   bool ran = false;
   for (;;) {
     // round boundary
-    if (threadIdx.x == 0) {
-      uint32_t cmd = kCmdExit;
-      if (blockIdx.x == 0) {
-        if (leader_gather(d, gridDim.x, kPhaseMs * kTicksPerMs)) cmd = leader_next_round(a, ran);
-        d->cmd = cmd;
-        leader_release(d);
-      } else if (arrive_and_wait(d, a.idle_ticks + kPhaseMs * kTicksPerMs)) {
-        cmd = __hip_atomic_load(&d->cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ++epoch;
+    __syncthreads();
+    if (threadIdx.x == 0) block_arrive(a, epoch);
+    if (blockIdx.x == 0) {
+      if (threadIdx.x < 64u) {
+        const bool ok = gather(a, epoch, kPhaseMs * kTicksPerMs);
+        if (threadIdx.x == 0) {
+          const uint64_t tg = now_ticks();
+          if (ran) {  // the round's last phase ends here
+            const uint64_t dt = tg - d->t_mark;
+            if (s_range[5] > s_range[4]) d->t_delete += dt;
+            else if (s_range[3] > s_range[2]) d->t_insert += dt;
+            else d->t_lookup += dt;
+          }
+          const uint64_t w0 = d->t_wait;
+          const uint32_t cmd = ok ? leader_next_round(a, ran) : kCmdExit;
+          d->cmd = cmd;
+          const uint64_t tr = now_ticks();
+          d->t_boundary += (tr - tg) - (d->t_wait - w0);
+          d->t_mark = tr;
+          release_epoch(d, epoch);
+          s_cmd = cmd;
+        }
       }
-      if (agent_load32(&d->abort)) cmd = kCmdExit;
+    } else if (threadIdx.x == 0) {
+      s_cmd = wait_release(a, epoch, a.idle_ticks + kPhaseMs * kTicksPerMs)
+                  ? __hip_atomic_load(&d->cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                  : kCmdExit;
+    }
+    if (threadIdx.x == 0) {
+      if (poll32(&d->abort)) s_cmd = kCmdExit;
       // the round's ring entries were written by the host or a copy engine
       // while the kernel ran: drop any cached copy of them
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-      s_cmd = cmd;
-      if (cmd == kCmdRun) {
+      if (s_cmd == kCmdRun) {
         s_range[0] = d->lk0;
         s_range[1] = d->lk1;
         s_range[2] = d->in0;
@@ -288,20 +364,19 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
     const uint64_t d0 = s_range[4], d1 = s_range[5];
     lookup_phase<MODE>(a, w, l0, l1);
     if (i1 > i0 || d1 > d0) {
-      if (!phase_barrier(a, &s_ok)) break;
+      if (!phase_barrier(a, ++epoch, 0u, &s_ok)) break;
       insert_phase(a, i0, i1);
       if (d1 > d0) {
-        if (!phase_barrier(a, &s_ok)) break;
+        if (!phase_barrier(a, ++epoch, 1u, &s_ok)) break;
         delete_phase(a, d0, d1);
       }
     }
     // every wave's results become visible to the host and the copy engines
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-    __syncthreads();
     ran = true;
   }
   if (leader) {
-    const uint32_t aborted = agent_load32(&d->abort);
+    const uint32_t aborted = poll32(&d->abort);
     sys_store32(&a.host->state, aborted ? CKPP_SERVER_ABORTED : CKPP_SERVER_STOPPED);
   }
 }
@@ -323,6 +398,7 @@ struct ckpp_server {
   ServeHost *host;
   ServeDev *dev;
   uint32_t *paths;
+  uint32_t *arrive;
   ckpp_server_rings_t rings;
   ServeArgs args;
   uint64_t submitted;
@@ -393,6 +469,7 @@ void free_server(ckpp_server *s) {
   (void)hipFree(s->rings.d_delete_keys);
   (void)hipFree(s->rings.d_delete_found);
   (void)hipFree(s->paths);
+  (void)hipFree(s->arrive);
   (void)hipFree(s->dev);
   if (s->host) (void)hipHostFree(s->host);
   if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -450,6 +527,9 @@ int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_confi
   if (e == hipSuccess) e = hipMalloc(&s->paths, path_words * 4);
   if (e == hipSuccess) e = hipMalloc(&s->dev, sizeof(ServeDev));
   if (e == hipSuccess) e = hipMemset(s->dev, 0, sizeof(ServeDev));
+  const uint64_t flag_bytes = (uint64_t)s->grid * ckpp::kFlagStride * 4u;
+  if (e == hipSuccess) e = hipMalloc(&s->arrive, flag_bytes);
+  if (e == hipSuccess) e = hipMemset(s->arrive, 0, flag_bytes);
   if (e == hipSuccess) e = hipHostMalloc(&s->host, sizeof(ServeHost), hipHostMallocCoherent);
   if (e == hipSuccess) memset(s->host, 0, sizeof(ServeHost));
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -464,6 +544,7 @@ int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_confi
   a.plain = (t->flags & CKPP_PLAIN) ? 1u : 0u;
   a.host = s->host;
   a.dev = s->dev;
+  a.arrive = s->arrive;
   a.mask = C - 1u;
   a.lk_keys = reinterpret_cast<const uint4 *>(r.d_lookup_keys);
   a.lk_found = r.d_lookup_found;
@@ -554,6 +635,18 @@ int ckpp_server_status(ckpp_server *s, ckpp_server_status_t *out) {
   out->launches = s->launches;
   out->state = host_u32(&s->host->state)->load(std::memory_order_acquire);
   out->grid = s->grid;
+  // the loop's phase clocks (device memory; a copy while it runs is a
+  // snapshot as of the last round boundary)
+  uint64_t t[5] = {0, 0, 0, 0, 0};
+  DeviceGuard g(s->device);
+  if (!g.ok() || hipMemcpy(t, &s->dev->t_lookup, sizeof(t), hipMemcpyDeviceToHost) != hipSuccess)
+    return CKPP_EDEVICE;
+  // real-time counter ticks are 10 ns
+  out->lookup_ns = t[0] * 10u;
+  out->insert_ns = t[1] * 10u;
+  out->delete_ns = t[2] * 10u;
+  out->boundary_ns = t[3] * 10u;
+  out->wait_ns = t[4] * 10u;
   return CKPP_OK;
 }
 

@@ -75,6 +75,10 @@ def test_argument_checks_need_no_device(lib):
     assert lib.ckpp_plan_lookup(None, None, None, None, None) == ckpp.EINVAL
     assert lib.ckpp_plan_set_launch(None, None) == ckpp.EINVAL
     assert lib.ckpp_plan_destroy(None) == ckpp.OK
+    assert lib.ckpp_server_create(None, None, None) == ckpp.EINVAL
+    assert lib.ckpp_server_submit(None, 1, 0, 0, None) == ckpp.EINVAL
+    assert lib.ckpp_server_put(None, 0, 0, None, None, 1, None) == ckpp.EINVAL
+    assert lib.ckpp_server_destroy(None) == ckpp.OK
 
 
 def test_missing_library_fails_loudly(tmp_path):
@@ -88,9 +92,11 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "ckpp.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(ckpp_stats_t), offsetof(ckpp_stats_t, moved_hist),
-         sizeof(ckpp_info_t), sizeof(ckpp_launch_t), sizeof(ckpp_plan_launch_t),
-         sizeof(ckpp_plan_info_t), offsetof(ckpp_plan_info_t, key_span));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(ckpp_stats_t),
+         offsetof(ckpp_stats_t, moved_hist), sizeof(ckpp_info_t), sizeof(ckpp_launch_t),
+         sizeof(ckpp_plan_launch_t), sizeof(ckpp_plan_info_t), offsetof(ckpp_plan_info_t, key_span),
+         sizeof(ckpp_server_config_t), sizeof(ckpp_server_rings_t), sizeof(ckpp_server_status_t),
+         offsetof(ckpp_server_status_t, lookup_ns));
   return 0;
 }
 """
@@ -101,7 +107,8 @@ int main(void) {
         subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), "-o", exe, c],
                        check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
-    sz_stats, off_hist, sz_info, sz_launch, sz_pl, sz_pi, off_span = map(int, out)
+    (sz_stats, off_hist, sz_info, sz_launch, sz_pl, sz_pi, off_span, sz_sc, sz_sr, sz_ss,
+     off_lns) = map(int, out)
     assert sz_stats == ctypes.sizeof(ckpp._Stats)
     assert off_hist == ckpp._Stats.moved_hist.offset
     assert sz_info == ctypes.sizeof(ckpp._Info)
@@ -109,3 +116,7 @@ int main(void) {
     assert sz_pl == ctypes.sizeof(ckpp._PlanLaunch)
     assert sz_pi == ctypes.sizeof(ckpp._PlanInfo)
     assert off_span == ckpp._PlanInfo.key_span.offset
+    assert sz_sc == ctypes.sizeof(ckpp._ServerConfig)
+    assert sz_sr == ctypes.sizeof(ckpp._ServerRings)
+    assert sz_ss == ctypes.sizeof(ckpp._ServerStatus)
+    assert off_lns == ckpp._ServerStatus.lookup_ns.offset
