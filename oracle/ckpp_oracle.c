@@ -56,6 +56,8 @@
  *                            keys (Sec. 4.3)
  * Key/value record (32 bytes) for slot s of bucket b at index b*8+s of the
  * key/value array (implicit index, Sec. 4.3): key[16] | value u64 | pad u64.
+ * On a table with timers (Sec. 4.2) the low 16 bits of the pad hold the
+ * entry's expiration time; the pad is zero otherwise.
  */
 #include <stddef.h>
 #include <stdint.h>
@@ -99,6 +101,7 @@ typedef struct {
     uint64_t seed;
     uint32_t max_kicks;
     int plain; /* 1: no bloom filter / moved counter maintenance */
+    int timed; /* 1: every entry carries a 16-bit expiration time (Sec. 4.2) */
     orc_bucket *buckets;
     orc_kv *kv;
     uint64_t live;
@@ -218,18 +221,37 @@ static orc_kv *orc_rec(const orc_table *t, uint64_t b, int s)
     return &t->kv[b * ORC_SLOTS + (uint64_t)s];
 }
 
+/* Sec. 4.2: an entry with expiration time e is alive at time `now` iff
+ * (e - now) mod 2^16 < 1024: expiration times are kept within 1024 units
+ * of the current time, so the 16-bit difference tells valid entries from
+ * expired ones (and from wrapped-around ones, until 64512 units after
+ * expiry, which the periodic scan prevents).  Tables without timers have
+ * no expired entries. */
+#define ORC_MAX_DELAY 1024u
+
+static int orc_expired(const orc_table *t, uint64_t b, int s, uint16_t now)
+{
+    if (!t->timed) return 0;
+    uint16_t e = (uint16_t)t->kv[b * ORC_SLOTS + (uint64_t)s].pad;
+    return (uint16_t)(e - now) >= ORC_MAX_DELAY;
+}
+
+enum { ORC_ANY = 0, ORC_ALIVE = 1, ORC_DEAD = 2 };
+
 /* Slot of `key` in bucket b, or -1.  Candidates are the busy slots whose
- * tag equals the key's tag; each candidate's full key is compared, in
+ * tag equals the key's tag (and, on a table with timers, that are alive
+ * or expired as `want` asks); each candidate's full key is compared, in
  * ascending slot order (Sec. 2, lookup procedure).  *kv_lines counts the
  * distinct 64-byte lines of the key/value array that were read. */
 static int orc_find_in(const orc_table *t, uint64_t b, uint32_t tag, const uint8_t *key,
-                       uint32_t *kv_lines)
+                       uint32_t *kv_lines, int want, uint16_t now)
 {
     const orc_bucket *bk = &t->buckets[b];
     int64_t last_line = -1;
     for (int s = 0; s < ORC_SLOTS; s++) {
         if (!(bk->busy & (1u << s))) continue;
         if (bk->tag[s] != tag) continue;
+        if (want != ORC_ANY && orc_expired(t, b, s, now) != (want == ORC_DEAD)) continue;
         int64_t line = (int64_t)((b * ORC_SLOTS + (uint64_t)s) >> 1);
         if (kv_lines && line != last_line) (*kv_lines)++;
         last_line = line;
@@ -245,18 +267,28 @@ static int orc_lowest_free(const orc_bucket *bk)
     return -1;
 }
 
+/* Lowest slot that is free or holds an expired entry (Sec. 4.2: an insert
+ * overwrites expired entries as if their slots were free). */
+static int orc_lowest_available(const orc_table *t, uint64_t b, uint16_t now)
+{
+    const orc_bucket *bk = &t->buckets[b];
+    for (int s = 0; s < ORC_SLOTS; s++)
+        if (!(bk->busy & (1u << s)) || orc_expired(t, b, s, now)) return s;
+    return -1;
+}
+
 static int orc_bloom_pass(const orc_table *t, uint64_t p, uint64_t m)
 {
     return (t->buckets[p].bloom & m) == m;
 }
 
 static void orc_place(orc_table *t, uint64_t b, int s, const uint8_t *key, uint64_t value,
-                      uint32_t tag, uint64_t other, int in_secondary)
+                      uint32_t tag, uint64_t other, int in_secondary, uint16_t expiry)
 {
     orc_kv *r = orc_rec(t, b, s);
     memcpy(r->key, key, 16);
     r->value = value;
-    r->pad = 0;
+    r->pad = t->timed ? (uint64_t)expiry : 0;
     orc_bucket *bk = &t->buckets[b];
     bk->tag[s] = (uint16_t)tag;
     bk->other[s] = (uint32_t)other;
@@ -302,19 +334,16 @@ static int orc_moved_full(const orc_table *t, uint64_t p)
  * secondary whenever the key is not in the primary.
  * The answer is the same for every mode; *bucket_lines and *kv_lines report
  * the 64-byte lines fetched from the bucket and key/value arrays. */
-int orc_lookup(const orc_table *t, const uint8_t *key, int mode, uint64_t *value,
-               uint32_t *bucket_lines, uint32_t *kv_lines)
+int orc_lookup_at(orc_table *t, const uint8_t *key, int mode, uint16_t now, int refresh,
+                  uint16_t expiry, uint64_t *value, uint32_t *bucket_lines, uint32_t *kv_lines)
 {
     orc_split_t sp;
     orc_split(orc_hash(key, t->seed), t->log2_buckets, &sp);
     uint32_t bl = (mode == ORC_MODE_BOTH) ? 2 : 1, kl = 0;
     int found = 0;
-    uint64_t v = 0;
-    int s = orc_find_in(t, sp.p, sp.tag, key, &kl);
-    if (s >= 0) {
-        found = 1;
-        v = orc_rec(t, sp.p, s)->value;
-    } else {
+    uint64_t v = 0, b = sp.p;
+    int s = orc_find_in(t, sp.p, sp.tag, key, &kl, ORC_ALIVE, now);
+    if (s < 0) {
         int probe_secondary;
         if (mode == ORC_MODE_CUCKOOPP && !t->plain)
             probe_secondary = orc_bloom_pass(t, sp.p, sp.bloom_mask);
@@ -322,17 +351,27 @@ int orc_lookup(const orc_table *t, const uint8_t *key, int mode, uint64_t *value
             probe_secondary = 1;
         if (probe_secondary) {
             if (mode != ORC_MODE_BOTH) bl += 1;
-            s = orc_find_in(t, sp.a, sp.tag, key, &kl);
-            if (s >= 0) {
-                found = 1;
-                v = orc_rec(t, sp.a, s)->value;
-            }
+            s = orc_find_in(t, sp.a, sp.tag, key, &kl, ORC_ALIVE, now);
+            b = sp.a;
         }
+    }
+    if (s >= 0) {
+        found = 1;
+        v = orc_rec(t, b, s)->value;
+        /* Sec. 4.2: a lookup may set a new expiration time of the entry */
+        if (refresh && t->timed) orc_rec(t, b, s)->pad = expiry;
     }
     if (value) *value = v;
     if (bucket_lines) *bucket_lines = bl;
     if (kv_lines) *kv_lines = kl;
     return found;
+}
+
+/* Lookup without timers (every entry alive, nothing written). */
+int orc_lookup(const orc_table *t, const uint8_t *key, int mode, uint64_t *value,
+               uint32_t *bucket_lines, uint32_t *kv_lines)
+{
+    return orc_lookup_at((orc_table *)t, key, mode, 0, 0, 0, value, bucket_lines, kv_lines);
 }
 
 /* ----------------------------------------------------------- cuckoo path */
@@ -362,7 +401,7 @@ static void orc_move(orc_table *t, uint64_t x, int s, int f)
     orc_split_t sp;
     orc_split(orc_hash(r->key, t->seed), t->log2_buckets, &sp);
     int was_secondary = (bx->sec >> s) & 1;
-    orc_place(t, y, f, r->key, r->value, bx->tag[s], x, !was_secondary);
+    orc_place(t, y, f, r->key, r->value, bx->tag[s], x, !was_secondary, (uint16_t)r->pad);
     if (was_secondary)
         orc_bloom_remove(t, sp.p); /* y is the primary */
     else
@@ -419,38 +458,67 @@ static int orc_find_path(const orc_table *t, uint64_t start, uint64_t h, orc_ste
 
 /* --------------------------------------------------------------- insert */
 
+/* Removes the entry of slot s of bucket b (its key is not looked at): if it
+ * sat in its secondary bucket, the moved counter of its primary (the slot's
+ * other bucket) is decremented and that bloom filter reset at zero (Sec.
+ * 4.1). */
+static void orc_remove_slot(orc_table *t, uint64_t b, int s)
+{
+    orc_bucket *bk = &t->buckets[b];
+    if ((bk->sec >> s) & 1) orc_bloom_remove(t, bk->other[s]);
+    bk->busy &= (uint8_t)~(1u << s);
+    bk->sec &= (uint8_t)~(1u << s);
+    t->live--;
+}
+
 /* Insert (Sec. 2 and Sec. 4.1): update in place if present; else the
  * lowest free slot of the primary bucket; else the lowest free slot of the
  * secondary bucket, adding the key to the primary's bloom filter; else a
- * cuckoo path is computed and applied, freeing a slot of the primary. */
-int orc_insert(orc_table *t, const uint8_t *key, uint64_t value)
+ * cuckoo path is computed and applied, freeing a slot of the primary.
+ * With timers (Sec. 4.2) a value of 2^48 or more fails (status FAILED,
+ * table unchanged), only alive entries are "present", the key's
+ * expiration time is set (also on an update), an expired copy of the key
+ * is overwritten where it stands, and a slot holding an expired entry
+ * counts as free: the expired entry is removed first (lazy deletion).
+ * The cuckoo path moves expired entries like any other and ends only at a
+ * bucket with a slot that is really free. */
+int orc_insert_at(orc_table *t, const uint8_t *key, uint64_t value, uint16_t expiry,
+                  uint16_t now)
 {
+    /* a table with timers holds values below 2^48 (the expiration time
+     * shares the value's 64-bit word in the GPU layout); a wider value is
+     * refused and nothing changes */
+    if (t->timed && (value >> 48) != 0) return ORC_FAILED;
     uint64_t h = orc_hash(key, t->seed);
     orc_split_t sp;
     orc_split(h, t->log2_buckets, &sp);
+    const int pass = t->plain || orc_bloom_pass(t, sp.p, sp.bloom_mask);
 
-    int s = orc_find_in(t, sp.p, sp.tag, key, NULL);
-    if (s >= 0) {
-        orc_rec(t, sp.p, s)->value = value;
-        return ORC_UPDATED;
-    }
-    if (t->plain || orc_bloom_pass(t, sp.p, sp.bloom_mask)) {
-        s = orc_find_in(t, sp.a, sp.tag, key, NULL);
-        if (s >= 0) {
-            orc_rec(t, sp.a, s)->value = value;
-            return ORC_UPDATED;
+    for (int want = ORC_ALIVE; want <= ORC_DEAD; want++) {
+        if (want == ORC_DEAD && !t->timed) break;
+        for (int k = 0; k < 2; k++) {
+            uint64_t b = k ? sp.a : sp.p;
+            if (k && !pass) break;
+            int s = orc_find_in(t, b, sp.tag, key, NULL, want, now);
+            if (s >= 0) {
+                orc_rec(t, b, s)->value = value;
+                if (t->timed) orc_rec(t, b, s)->pad = expiry;
+                return want == ORC_ALIVE ? ORC_UPDATED : ORC_INSERTED;
+            }
         }
     }
 
-    s = orc_lowest_free(&t->buckets[sp.p]);
+    int s = orc_lowest_available(t, sp.p, now);
     if (s >= 0) {
-        orc_place(t, sp.p, s, key, value, sp.tag, sp.a, 0);
+        if (t->buckets[sp.p].busy & (1u << s)) orc_remove_slot(t, sp.p, s);
+        orc_place(t, sp.p, s, key, value, sp.tag, sp.a, 0, expiry);
         t->live++;
         return ORC_INSERTED;
     }
-    s = orc_lowest_free(&t->buckets[sp.a]);
+    s = orc_lowest_available(t, sp.a, now);
     if (s >= 0 && !orc_moved_full(t, sp.p)) {
-        orc_place(t, sp.a, s, key, value, sp.tag, sp.p, 1);
+        if (t->buckets[sp.a].busy & (1u << s)) orc_remove_slot(t, sp.a, s);
+        orc_place(t, sp.a, s, key, value, sp.tag, sp.p, 1, expiry);
         orc_bloom_add(t, sp.p, sp.bloom_mask);
         t->live++;
         return ORC_INSERTED;
@@ -473,39 +541,68 @@ int orc_insert(orc_table *t, const uint8_t *key, uint64_t value)
         f = path[i].s;
     }
     /* the walk started at the primary, whose slot path[0].s is now free */
-    orc_place(t, sp.p, path[0].s, key, value, sp.tag, sp.a, 0);
+    orc_place(t, sp.p, path[0].s, key, value, sp.tag, sp.a, 0, expiry);
     t->live++;
     free(path);
     return ORC_INSERTED;
+}
+
+/* Insert without timers. */
+int orc_insert(orc_table *t, const uint8_t *key, uint64_t value)
+{
+    return orc_insert_at(t, key, value, 0, 0);
 }
 
 /* --------------------------------------------------------------- delete */
 
 /* Delete (Sec. 4.1): find the key as a lookup does and free its slot; if it
  * sat in its secondary bucket, decrement the moved counter of its primary
- * and reset the primary's bloom filter when the counter reaches zero. */
-int orc_delete(orc_table *t, const uint8_t *key)
+ * and reset the primary's bloom filter when the counter reaches zero.
+ * With timers an expired copy is removed too, but only an alive one counts
+ * as found (Sec. 4.2: expired entries are absent). */
+int orc_delete_at(orc_table *t, const uint8_t *key, uint16_t now)
 {
     orc_split_t sp;
     orc_split(orc_hash(key, t->seed), t->log2_buckets, &sp);
-    int s = orc_find_in(t, sp.p, sp.tag, key, NULL);
-    if (s >= 0) {
-        t->buckets[sp.p].busy &= (uint8_t)~(1u << s);
-        t->buckets[sp.p].sec &= (uint8_t)~(1u << s);
-        t->live--;
-        return 1;
+    int s = orc_find_in(t, sp.p, sp.tag, key, NULL, ORC_ANY, now);
+    uint64_t b = sp.p;
+    if (s < 0 && (t->plain || orc_bloom_pass(t, sp.p, sp.bloom_mask))) {
+        s = orc_find_in(t, sp.a, sp.tag, key, NULL, ORC_ANY, now);
+        b = sp.a;
     }
-    if (t->plain || orc_bloom_pass(t, sp.p, sp.bloom_mask)) {
-        s = orc_find_in(t, sp.a, sp.tag, key, NULL);
-        if (s >= 0) {
-            t->buckets[sp.a].busy &= (uint8_t)~(1u << s);
-            t->buckets[sp.a].sec &= (uint8_t)~(1u << s);
-            orc_bloom_remove(t, sp.p);
-            t->live--;
-            return 1;
-        }
-    }
-    return 0;
+    if (s < 0) return 0;
+    const int alive = !orc_expired(t, b, s, now);
+    orc_remove_slot(t, b, s);
+    return alive;
+}
+
+/* Delete without timers. */
+int orc_delete(orc_table *t, const uint8_t *key)
+{
+    return orc_delete_at(t, key, 0);
+}
+
+/* Anti-revival scan (Sec. 4.2): every expired entry is removed, so that it
+ * cannot become alive again when the 16-bit clock wraps around; the scan
+ * must run at least every 64512 time units.  Returns the entries removed. */
+uint64_t orc_expire_scan(orc_table *t, uint16_t now)
+{
+    uint64_t removed = 0;
+    for (uint64_t b = 0; b < t->nbuckets; b++)
+        for (int s = 0; s < ORC_SLOTS; s++)
+            if ((t->buckets[b].busy & (1u << s)) && orc_expired(t, b, s, now)) {
+                orc_remove_slot(t, b, s);
+                removed++;
+            }
+    return removed;
+}
+
+/* A table whose entries carry expiration times (Sec. 4.2). */
+orc_table *orc_create_timed(uint32_t log2_buckets, uint64_t seed, uint32_t max_kicks, int plain)
+{
+    orc_table *t = orc_create(log2_buckets, seed, max_kicks, plain);
+    if (t) t->timed = 1;
+    return t;
 }
 
 /* -------------------------------------------------------------- batches */
@@ -544,6 +641,37 @@ void orc_delete_batch(orc_table *t, const uint8_t *keys, uint64_t n, uint8_t *fo
 {
     for (uint64_t i = 0; i < n; i++) {
         int f = orc_delete(t, keys + 16 * i);
+        if (found) found[i] = (uint8_t)f;
+    }
+}
+
+/* Timed batch forms: expiry has one entry per key (inserts); a lookup with
+ * refresh sets the expiration time of every alive entry it finds. */
+void orc_insert_batch_at(orc_table *t, const uint8_t *keys, const uint64_t *values,
+                         const uint16_t *expiry, uint64_t n, uint16_t now, uint8_t *status)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        int st = orc_insert_at(t, keys + 16 * i, values[i], expiry[i], now);
+        if (status) status[i] = (uint8_t)st;
+    }
+}
+
+void orc_lookup_batch_at(orc_table *t, const uint8_t *keys, uint64_t n, int mode, uint16_t now,
+                         int refresh, uint16_t expiry, uint8_t *found, uint64_t *values)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t v;
+        int f = orc_lookup_at(t, keys + 16 * i, mode, now, refresh, expiry, &v, NULL, NULL);
+        if (found) found[i] = (uint8_t)f;
+        if (values) values[i] = v;
+    }
+}
+
+void orc_delete_batch_at(orc_table *t, const uint8_t *keys, uint64_t n, uint16_t now,
+                         uint8_t *found)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        int f = orc_delete_at(t, keys + 16 * i, now);
         if (found) found[i] = (uint8_t)f;
     }
 }
@@ -601,12 +729,16 @@ uint64_t orc_stats_size(void) { return sizeof(orc_stats_t); }
  *      secondary bucket (0 everywhere on a plain table)
  *   I4 for every such key both of its bits are set in bloom[b]
  *   I5 moved[b] == 0 implies bloom[b] == 0
+ *   I6 the pad word of every busy slot is zero on a table without timers;
+ *      with timers it holds only a 16-bit expiration time and the value
+ *      is below 2^48
  *   I9 lock words are zero and sec is a subset of busy
  * Statement of I3-I5 follows Sec. 4.1 (bloom filter, moved counter and its
- * reset at zero). */
+ * reset at zero).  flags: bit 0 plain table, bit 1 table with timers. */
 int orc_check_image(const uint8_t *buckets, const uint8_t *kvbytes, uint32_t log2_buckets,
-                    uint64_t seed, int plain, char *msg, uint64_t msglen)
+                    uint64_t seed, int flags, char *msg, uint64_t msglen)
 {
+    const int plain = flags & 1, timed = (flags >> 1) & 1;
     const orc_bucket *bk = (const orc_bucket *)buckets;
     const orc_kv *kv = (const orc_kv *)kvbytes;
     uint64_t nb = 1ULL << log2_buckets;
@@ -634,6 +766,14 @@ int orc_check_image(const uint8_t *buckets, const uint8_t *kvbytes, uint32_t log
         for (int s = 0; s < ORC_SLOTS && !rc; s++) {
             if (!(bk[b].busy & (1u << s))) continue;
             const uint8_t *key = kv[b * ORC_SLOTS + (uint64_t)s].key;
+            const orc_kv *rec = &kv[b * ORC_SLOTS + (uint64_t)s];
+            if (timed ? ((rec->pad >> 16) != 0 || (rec->value >> 48) != 0) : rec->pad != 0) {
+                snprintf(msg, msglen, "I6: bucket %llu slot %d value %016llx pad %016llx",
+                         (unsigned long long)b, s, (unsigned long long)rec->value,
+                         (unsigned long long)rec->pad);
+                rc = 6;
+                break;
+            }
             orc_split_t sp;
             orc_split(orc_hash(key, seed), log2_buckets, &sp);
             int in_p = (b == sp.p), in_a = (b == sp.a);

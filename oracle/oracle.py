@@ -23,6 +23,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 INSERTED, UPDATED, FAILED = 0, 1, 2
 MODE_CUCKOOPP, MODE_BOTH, MODE_OPTIMISTIC = 0, 1, 2
 MOVED_BINS = 66
+MAX_DELAY = 1024  # expiration times lie within this many time units of now
 
 
 def build(cc: str = "gcc") -> str:
@@ -95,6 +96,21 @@ def load(path: str | None = None) -> ctypes.CDLL:
                                      u64p, u64p, u64p]
     lib.orc_delete_batch.restype = None
     lib.orc_delete_batch.argtypes = [ctypes.c_void_p, u8p, ctypes.c_uint64, u8p]
+    u16p = ctypes.POINTER(ctypes.c_uint16)
+    lib.orc_create_timed.restype = ctypes.c_void_p
+    lib.orc_create_timed.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                     ctypes.c_int]
+    lib.orc_insert_batch_at.restype = None
+    lib.orc_insert_batch_at.argtypes = [ctypes.c_void_p, u8p, u64p, u16p, ctypes.c_uint64,
+                                        ctypes.c_uint16, u8p]
+    lib.orc_lookup_batch_at.restype = None
+    lib.orc_lookup_batch_at.argtypes = [ctypes.c_void_p, u8p, ctypes.c_uint64, ctypes.c_int,
+                                        ctypes.c_uint16, ctypes.c_int, ctypes.c_uint16, u8p, u64p]
+    lib.orc_delete_batch_at.restype = None
+    lib.orc_delete_batch_at.argtypes = [ctypes.c_void_p, u8p, ctypes.c_uint64, ctypes.c_uint16,
+                                        u8p]
+    lib.orc_expire_scan.restype = ctypes.c_uint64
+    lib.orc_expire_scan.argtypes = [ctypes.c_void_p, ctypes.c_uint16]
     lib.orc_stats.restype = None
     lib.orc_stats.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Stats)]
     lib.orc_image_stats.restype = None
@@ -166,7 +182,7 @@ def fmix64(z: int, lib=None) -> int:
 
 
 def check_image(buckets: np.ndarray, kv: np.ndarray, log2_buckets: int, seed: int,
-                plain: bool = False, lib=None):
+                plain: bool = False, lib=None, timed: bool = False):
     """Runs the image invariant checker; returns (code, message), code 0 = ok."""
     lib = lib or load()
     b = np.ascontiguousarray(buckets, dtype=np.uint8).reshape(-1)
@@ -175,8 +191,9 @@ def check_image(buckets: np.ndarray, kv: np.ndarray, log2_buckets: int, seed: in
     if b.size != nb * 64 or k.size != nb * 256:
         raise ValueError("image size does not match log2_buckets")
     msg = ctypes.create_string_buffer(512)
-    rc = lib.orc_check_image(_u8(b), _u8(k), log2_buckets, ctypes.c_uint64(seed),
-                             1 if plain else 0, msg, 512)
+    flags = (1 if plain else 0) | (2 if timed else 0)
+    rc = lib.orc_check_image(_u8(b), _u8(k), log2_buckets, ctypes.c_uint64(seed), flags, msg,
+                             512)
     return int(rc), msg.value.decode()
 
 
@@ -192,14 +209,16 @@ class OracleTable:
     """Single-threaded reference cuckoo table (see ``ckpp_oracle.c``)."""
 
     def __init__(self, log2_buckets: int, seed: int, max_kicks: int = 500,
-                 plain: bool = False, lib=None):
+                 plain: bool = False, lib=None, timed: bool = False):
         self.lib = lib or load()
         self.log2_buckets = int(log2_buckets)
         self.nbuckets = 1 << self.log2_buckets
         self.seed = int(seed)
         self.plain = bool(plain)
-        self._t = self.lib.orc_create(self.log2_buckets, ctypes.c_uint64(self.seed),
-                                      int(max_kicks), 1 if plain else 0)
+        self.timed = bool(timed)
+        create = self.lib.orc_create_timed if timed else self.lib.orc_create
+        self._t = create(self.log2_buckets, ctypes.c_uint64(self.seed), int(max_kicks),
+                         1 if plain else 0)
         if not self._t:
             raise MemoryError("orc_create failed")
 
@@ -244,6 +263,43 @@ class OracleTable:
         self.lib.orc_delete_batch(self._t, _u8(k), len(k), _u8(f))
         return f
 
+    # -- tables with timers (Sec. 4.2); `now` and expiration times are u16
+
+    def insert_at(self, keys: np.ndarray, values: np.ndarray, expiry: np.ndarray,
+                  now: int) -> np.ndarray:
+        k = _keys(keys)
+        v = np.ascontiguousarray(values, dtype=np.uint64)
+        e = np.ascontiguousarray(expiry, dtype=np.uint16)
+        if len(v) != len(k) or len(e) != len(k):
+            raise ValueError("keys, values and expiry differ in length")
+        st = np.empty(len(k), dtype=np.uint8)
+        self.lib.orc_insert_batch_at(self._t, _u8(k), _u64(v),
+                                     e.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)), len(k),
+                                     int(now) & 0xFFFF, _u8(st))
+        return st
+
+    def lookup_at(self, keys: np.ndarray, now: int, mode: int = MODE_CUCKOOPP,
+                  refresh: int | None = None):
+        """Returns (found u8, values u64); with `refresh` set, every alive
+        entry found gets that expiration time."""
+        k = _keys(keys)
+        f = np.empty(len(k), dtype=np.uint8)
+        v = np.empty(len(k), dtype=np.uint64)
+        self.lib.orc_lookup_batch_at(self._t, _u8(k), len(k), int(mode), int(now) & 0xFFFF,
+                                     0 if refresh is None else 1,
+                                     0 if refresh is None else int(refresh) & 0xFFFF,
+                                     _u8(f), _u64(v))
+        return f, v
+
+    def delete_at(self, keys: np.ndarray, now: int) -> np.ndarray:
+        k = _keys(keys)
+        f = np.empty(len(k), dtype=np.uint8)
+        self.lib.orc_delete_batch_at(self._t, _u8(k), len(k), int(now) & 0xFFFF, _u8(f))
+        return f
+
+    def expire_scan(self, now: int) -> int:
+        return int(self.lib.orc_expire_scan(self._t, int(now) & 0xFFFF))
+
     def stats(self) -> dict:
         st = _Stats()
         self.lib.orc_stats(self._t, ctypes.byref(st))
@@ -261,4 +317,5 @@ class OracleTable:
 
     def check(self):
         b, k = self.image()
-        return check_image(b, k, self.log2_buckets, self.seed, self.plain, lib=self.lib)
+        return check_image(b, k, self.log2_buckets, self.seed, self.plain, lib=self.lib,
+                           timed=self.timed)

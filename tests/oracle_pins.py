@@ -377,7 +377,180 @@ def pin_delete_cycle(lib, B: int = 6):
     t.close()
 
 
+# ------------------------------------------------------------- timer pins
+
+def alive(expiry: int, now: int) -> bool:
+    """Sec. 4.2: an entry is alive iff its 16-bit expiration time minus the
+    16-bit current time, modulo 2^16, is below the maximum delay 1024."""
+    return ((expiry - now) & 0xFFFF) < 1024
+
+
+def pin_timer_dict_differential(lib, B: int = 5, rounds: int = 60, seed: int = 21,
+                                plain: bool = False):
+    """Timed table against a Python dict of key -> (value, expiration time)
+    (the plain definition of Sec. 4.2): lookups see alive entries only, a
+    lookup may set a new expiration time, inserts and updates set the key's
+    expiration time, a delete finds only alive entries, values of 2^48 or
+    more are refused.  Time advances in small and large steps across the
+    16-bit wrap-around; expiration times are set within the allowed window
+    and the anti-revival scan runs well inside every 64512 units, so an
+    expired entry never returns and the dict may forget it at once."""
+    rng = np.random.default_rng(seed)
+    cap = 8 << B
+    universe = W.distinct_five_tuples(max(3 * cap, 64), seed + 2000, check=True)
+    t = O.OracleTable(B, W.HASH_SEED, 500, plain, lib=lib, timed=True)
+    ref: dict[bytes, tuple[int, int]] = {}
+    now = int(rng.integers(64000, 65536))
+    since_scan = 0
+    for r in range(rounds):
+        op = rng.choice(["ins", "ins", "ins", "del", "look", "tick", "tick"])
+        k = int(rng.integers(1, max(2, cap // 3)))
+        rows = rng.choice(len(universe), size=min(k, len(universe)), replace=False)
+        keys = universe[rows]
+        if op == "tick":
+            step = int(rng.choice([int(rng.integers(1, 64)), int(rng.integers(200, 3000))]))
+            if since_scan + step > 30000:
+                t.expire_scan(now)
+                since_scan = 0
+            now = (now + step) & 0xFFFF
+            since_scan += step
+            ref = {kb: ve for kb, ve in ref.items() if alive(ve[1], now)}
+        elif op == "ins":
+            vals = rng.integers(0, 1 << 48, size=len(rows), dtype=np.int64).astype(np.uint64)
+            wide = rng.random(len(rows)) < 0.05
+            vals[wide] |= np.uint64(1 << 60)
+            exp = (now + rng.integers(0, 1024, size=len(rows))) & 0xFFFF
+            st = t.insert_at(keys, vals, exp, now)
+            for i in range(len(rows)):
+                kb = keys[i].tobytes()
+                if wide[i]:
+                    assert st[i] == O.FAILED, "a value of 2^48 or more must be refused"
+                elif kb in ref:
+                    assert st[i] == O.UPDATED, "alive key must be UPDATED"
+                    ref[kb] = (int(vals[i]), int(exp[i]))
+                else:
+                    assert st[i] in (O.INSERTED, O.FAILED)
+                    if st[i] == O.INSERTED:
+                        ref[kb] = (int(vals[i]), int(exp[i]))
+        elif op == "del":
+            f = t.delete_at(keys, now)
+            for i in range(len(rows)):
+                kb = keys[i].tobytes()
+                assert bool(f[i]) == (kb in ref), "delete reports an alive key"
+                ref.pop(kb, None)
+        else:
+            new_exp = (now + int(rng.integers(0, 1024))) & 0xFFFF
+            f, v = t.lookup_at(keys, now, refresh=new_exp)
+            for i in range(len(rows)):
+                kb = keys[i].tobytes()
+                assert bool(f[i]) == (kb in ref), "refreshing lookup: found"
+                assert int(v[i]) == (ref[kb][0] if kb in ref else 0), "refreshing lookup: value"
+                if kb in ref:
+                    ref[kb] = (ref[kb][0], new_exp)
+        want_f = np.array([u.tobytes() in ref for u in universe], dtype=np.uint8)
+        want_v = np.array([ref[u.tobytes()][0] if u.tobytes() in ref else 0 for u in universe],
+                          dtype=np.uint64)
+        for mode in (O.MODE_CUCKOOPP, O.MODE_BOTH, O.MODE_OPTIMISTIC):
+            f, v = t.lookup_at(universe, now, mode)
+            assert np.array_equal(f, want_f), f"round {r} mode {mode}: found differs from dict"
+            assert np.array_equal(v, want_v), f"round {r} mode {mode}: value differs from dict"
+        rc, msg = t.check()
+        assert rc == 0, msg
+        if r % 10 == 9:
+            python_invariants(t, lib)
+            # after a scan the table holds exactly the alive entries
+            t.expire_scan(now)
+            since_scan = 0
+            assert t.live == len(ref), "scan leaves exactly the alive entries"
+            # and the stored expiration times are the dict's
+            b, kv = t.image()
+            recs = kv.reshape(-1, 32)
+            busy = b.reshape(-1, 64)[:, 26]
+            for bi in range(t.nbuckets):
+                for sl in range(8):
+                    if (int(busy[bi]) >> sl) & 1:
+                        rec = recs[bi * 8 + sl]
+                        ve = ref[rec[:16].tobytes()]
+                        assert int(rec[16:24].view(np.uint64)[0]) == ve[0]
+                        assert int(rec[24:32].view(np.uint64)[0]) == ve[1], "expiration time"
+    t.close()
+
+
+def pin_timer_revival(lib):
+    """Sec. 4.2: with 16-bit times and a 1024-unit window, an entry expiring
+    at e is alive up to e, expired from e + 1 through e + 64512, and would be
+    alive again at e + 64513 (the wrap-around the periodic scan exists to
+    prevent); after a scan while it is expired it stays absent."""
+    keys = W.distinct_five_tuples(2, 31, check=True)
+    for now0 in (0, 1000, 65530):
+        t = O.OracleTable(4, W.HASH_SEED, 500, lib=lib, timed=True)
+        e = (now0 + 5) & 0xFFFF
+        assert (t.insert_at(keys, np.array([7, 9], np.uint64), np.array([e, e]), now0)
+                == O.INSERTED).all()
+        for dt, want in ((0, 1), (5, 1), (6, 0), (5 + 64512, 0), (5 + 64513, 1), (5 + 65535, 1)):
+            f, v = t.lookup_at(keys, now0 + dt)
+            assert list(f) == [want, want], f"now0 {now0} + {dt}: found {list(f)}"
+            assert list(v) == ([7, 9] if want else [0, 0])
+        assert t.expire_scan(now0 + 6) == 2, "the scan removes both expired entries"
+        assert t.live == 0
+        f, _ = t.lookup_at(keys, now0 + 5 + 64513)
+        assert not f.any(), "a scanned entry never revives"
+        t.close()
+
+
+def pin_timer_lazy_reuse(lib):
+    """Sec. 4.2 lazy deletion: an insert takes a slot holding an expired
+    entry as if it were free.  Two buckets hold 16 entries; once all 16 have
+    expired, 16 fresh keys are inserted without a failure (each overwrites an
+    expired entry, so the table still holds 16), the 17th fails, the old
+    keys are absent, and the filter counters stay exact (entries that sat in
+    their secondary bucket were removed with their counter update)."""
+    keys = W.distinct_five_tuples(33, 41, check=True)
+    t = O.OracleTable(1, W.HASH_SEED, 500, lib=lib, timed=True)
+    exp = np.full(16, 110)
+    assert (t.insert_at(keys[:16], W.insertion_values(16), exp, 100) == O.INSERTED).all()
+    assert t.stats()["in_secondary"] > 0
+    assert t.insert_at(keys[16:17], W.insertion_values(1), np.array([110]), 100)[0] == O.FAILED
+    st = t.insert_at(keys[17:33], W.insertion_values(16, 100), np.full(16, 200), 111)
+    assert (st == O.INSERTED).all(), f"expired slots are reused: {st}"
+    assert t.live == 16
+    f, v = t.lookup_at(keys, 111)
+    assert not f[:17].any() and f[17:].all()
+    assert np.array_equal(v[17:], W.insertion_values(16, 100))
+    rc, msg = t.check()
+    assert rc == 0, msg
+    python_invariants(t, lib)
+    assert t.insert_at(keys[16:17], W.insertion_values(1), np.array([200]), 111)[0] == O.FAILED
+    t.close()
+
+
+def pin_timer_reduces_to_untimed(lib, B: int = 7):
+    """Special case: when no entry ever expires, a table with timers holds
+    exactly what the table without timers holds (same buckets, same keys and
+    values at the same implicit indices), apart from the expiration times."""
+    n = W.keys_at_load(B, 0.95)
+    keys = W.distinct_five_tuples(n, 51, check=True)
+    vals = W.insertion_values(n)
+    a = O.OracleTable(B, W.HASH_SEED, 500, lib=lib)
+    b = O.OracleTable(B, W.HASH_SEED, 500, lib=lib, timed=True)
+    sa = a.insert(keys, vals)
+    sb = b.insert_at(keys, vals, np.full(n, 1023), 0)
+    assert np.array_equal(sa, sb)
+    rows = W.choose_rows(n, n // 3, 52)
+    assert np.array_equal(a.delete(keys[rows]), b.delete_at(keys[rows], 0))
+    ba, ka = a.image()
+    bb, kb = b.image()
+    assert np.array_equal(ba, bb), "bucket arrays differ"
+    ka, kb = ka.reshape(-1, 32), kb.reshape(-1, 32)
+    assert np.array_equal(ka[:, :24], kb[:, :24]), "keys or values differ"
+    a.close()
+    b.close()
+
+
 QUICK_PINS = [
+    "pin_timer_revival",
+    "pin_timer_lazy_reuse",
+    "pin_timer_reduces_to_untimed",
     "pin_delete_cycle",
     "pin_splitmix_finalizer",
     "pin_hash_composition",
@@ -402,6 +575,10 @@ def run_quick(lib) -> list:
             pin_dict_differential(lib, B=B, rounds=12, seed=B, plain=plain, pycheck_every=4)
         except AssertionError:
             failed.append(f"pin_dict_differential_B{B}")
+    try:
+        pin_timer_dict_differential(lib, B=3, rounds=40, seed=5)
+    except AssertionError:
+        failed.append("pin_timer_dict_differential")
     try:
         pin_paper_statistics(paper_statistics(lib, B=17))
     except AssertionError:

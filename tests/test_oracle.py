@@ -127,3 +127,20 @@ def test_hash_vectors_regression(lib):
         s14, s24 = O.split(h, 14, lib=lib), O.split(h, 24, lib=lib)
         assert (s14["p"], s14["a"], s14["tag"]) == (int(p14), int(a14), int(tag))
         assert (s24["p"], s24["a"]) == (int(p24), int(a24))
+
+
+@pytest.mark.parametrize("B,plain", [(1, False), (3, False), (5, False), (4, True)])
+def test_timer_dict_differential(lib, B, plain):
+    P.pin_timer_dict_differential(lib, B=B, rounds=60, seed=20 + B, plain=plain)
+
+
+def test_timer_revival(lib):
+    P.pin_timer_revival(lib)
+
+
+def test_timer_lazy_reuse(lib):
+    P.pin_timer_lazy_reuse(lib)
+
+
+def test_timer_reduces_to_untimed(lib):
+    P.pin_timer_reduces_to_untimed(lib)

@@ -29,10 +29,10 @@ MUTANTS = [
     ("big_endian_words", "for (int i = 7; i >= 0; i--) lo = (lo << 8) | key[i];",
      "for (int i = 0; i < 8; i++) lo = (lo << 8) | key[i];"),
     ("tag_off_by_one", "out->tag = (uint32_t)(h >> 48);", "out->tag = (uint32_t)(h >> 47);"),
-    ("secondary_insert_not_marked", "orc_place(t, sp.a, s, key, value, sp.tag, sp.p, 1);",
-     "orc_place(t, sp.a, s, key, value, sp.tag, sp.p, 0);"),
-    ("delete_keeps_moved_count", "            orc_bloom_remove(t, sp.p);\n            t->live--;",
-     "            t->live--;"),
+    ("secondary_insert_not_marked", "orc_place(t, sp.a, s, key, value, sp.tag, sp.p, 1, expiry);",
+     "orc_place(t, sp.a, s, key, value, sp.tag, sp.p, 0, expiry);"),
+    ("delete_keeps_moved_count", "if ((bk->sec >> s) & 1) orc_bloom_remove(t, bk->other[s]);",
+     ";"),
     ("move_maintenance_swapped", "    if (was_secondary)\n        orc_bloom_remove",
      "    if (!was_secondary)\n        orc_bloom_remove"),
     ("key_compare_8_bytes", "if (memcmp(orc_rec(t, b, s)->key, key, 16) == 0) return s;",
@@ -41,6 +41,20 @@ MUTANTS = [
      "uint32_t bl = 1, kl = 0;"),
     ("seed_ignored", "return orc_fmix64(orc_fmix64(lo ^ seed) ^ hi);",
      "return orc_fmix64(orc_fmix64(lo) ^ hi);"),
+    # timers (Sec. 4.2)
+    ("timer_window_off_by_one", "return (uint16_t)(e - now) >= ORC_MAX_DELAY;",
+     "return (uint16_t)(e - now) > ORC_MAX_DELAY;"),
+    ("timer_difference_reversed", "return (uint16_t)(e - now) >= ORC_MAX_DELAY;",
+     "return (uint16_t)(now - e) >= ORC_MAX_DELAY;"),
+    ("lookup_sees_expired", "int s = orc_find_in(t, sp.p, sp.tag, key, &kl, ORC_ALIVE, now);",
+     "int s = orc_find_in(t, sp.p, sp.tag, key, &kl, ORC_ANY, now);"),
+    ("insert_ignores_expired_slots",
+     "if (!(bk->busy & (1u << s)) || orc_expired(t, b, s, now)) return s;",
+     "if (!(bk->busy & (1u << s))) return s;"),
+    ("refresh_not_written", "if (refresh && t->timed) orc_rec(t, b, s)->pad = expiry;", ";"),
+    ("scan_keeps_expired", "orc_remove_slot(t, b, s);\n                removed++;", "removed++;"),
+    ("timed_value_width_unchecked", "if (t->timed && (value >> 48) != 0) return ORC_FAILED;", ";"),
+    ("update_keeps_old_expiry", "if (t->timed) orc_rec(t, b, s)->pad = expiry;\n", "\n"),
 ]
 
 RUNNER = r"""
