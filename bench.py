@@ -117,21 +117,28 @@ def expected_lines(stats: dict) -> dict:
 STREAM_BYTES = 16 + 1 + 8  # key in, found + value out, per lookup
 
 
-def build_table(B, load, seed, dev, batch=1 << 22):
+def build_table(B, load, seed, dev, batch=1 << 22, expiry=None, now=0):
+    """A table of 2^B buckets filled to `load` with the keys of workload
+    `seed` (values = insertion index); with `expiry` (one u16 time per key)
+    a table with timers, built at time `now`."""
     import torch
     from paper_1712_09624_amd.ckpp import Table
     n = W.keys_at_load(B, load)
     log(f"generating {n} keys for 2^{B} buckets at load {load}")
     keys = W.distinct_five_tuples(n, seed)
     vals = W.insertion_values(n)
-    t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=dev.index)
+    t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=dev.index, timers=expiry is not None)
     nfail = torch.zeros(1, dtype=torch.int64, device=dev)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(0, n, batch):
         dk = to_dev(keys[s:s + batch], dev)
         dv = to_dev(vals[s:s + batch].view(np.int64), dev)
-        t.insert(dk, dv, nfailed=nfail)
+        if expiry is None:
+            t.insert(dk, dv, nfailed=nfail)
+        else:
+            de = to_dev(expiry[s:s + batch].view(np.int16), dev)
+            t.insert_at(dk, dv, de, now, nfailed=nfail)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     nf = int(nfail.item())
@@ -206,6 +213,67 @@ def cache_resident_table(dev, lookups):
         for name, d in (("pos", dp), ("neg", dn)):
             ms = timed(lambda: t.lookup(d, mode, found=f, values=v), 5, dev)
             out[f"{mode}_{name}_glookups"] = n / (ms * 1e-3) / 1e9
+    t.close()
+    return out
+
+
+def timers_leg(dev, B, load, n, dpos, dneg, pos_idx, untimed):
+    """Tables with timers (Sec. 4.2) on the same workload: the table is built
+    with expiration times uniform over the 1024 units after now0, and the
+    positive and negative lookup batches are timed at now0 (every entry
+    alive: the answers equal those of the table without timers, so the time
+    difference is the overhead of the timer check), at now0 + 512 (about
+    half the entries expired), and at now0 + 512 with a refresh of every
+    entry found.  Then the anti-revival scan over the whole table once every
+    entry has expired.  Answers are checked on a sample: found iff the key's
+    entry is alive, value = insertion index."""
+    import torch
+    now0 = 65000
+    nkeys = W.keys_at_load(B, load)
+    exp = W.times_after(nkeys, now0, 1024, 1)
+    t, keys, vals, build_s = build_table(B, load, 1, dev, expiry=exp, now=now0)
+    f = torch.empty(n, dtype=torch.uint8, device=dev)
+    v = torch.empty(n, dtype=torch.int64, device=dev)
+    out = {"log2_buckets": B, "load": load, "lookups": n, "build_s": build_s,
+           "expiry": "uniform over [now0, now0 + 1023], now0 = 65000 (the window wraps)"}
+    chk = np.arange(0, n, max(1, n // 65536))
+    half = (now0 + 512) & 0xFFFF
+    for label, now, refresh in (("", now0, None), ("half_expired_", half, None),
+                                ("refresh_", half, (half + 1023) & 0xFFFF)):
+        for name, d in (("pos", dpos), ("neg", dneg)):
+            ms = timed(lambda: t.lookup_at(d, now, found=f, values=v, refresh=refresh), 5, dev)
+            out[f"{label}{name}_glookups"] = n / (ms * 1e-3) / 1e9
+            fo = f.cpu().numpy()[chk]
+            if name == "neg":
+                ok = not fo.any()
+            else:
+                # a refresh keeps alive what it finds, so the answers stay
+                # those of the times before it
+                e = exp[pos_idx[chk]].astype(np.int64)
+                want = (((e - now) & 0xFFFF) < 1024).astype(np.uint8)
+                vo = v.cpu().numpy().view(np.uint64)[chk]
+                ok = np.array_equal(fo, want) and np.array_equal(
+                    vo[want == 1], vals[pos_idx[chk]][want == 1])
+                if refresh is not None:
+                    found_rows = np.unique(pos_idx[f.cpu().numpy() == 1])
+                    exp[found_rows] = refresh
+            if not ok:
+                raise RuntimeError(f"timed lookups ({label}{name}) returned a wrong answer")
+    for name in ("pos", "neg"):
+        out[f"overhead_{name}"] = untimed[f"cuckoopp_{name}_glookups"] / out[f"{name}_glookups"] - 1
+    removed = torch.zeros(1, dtype=torch.int64, device=dev)
+    later = (half + 2000) & 0xFFFF
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    t.expire_scan(later, removed=removed)
+    e1.record()
+    e1.synchronize()
+    out["scan_ms"] = e0.elapsed_time(e1)
+    out["scan_removed"] = int(removed.item())
+    out["scan_table_GBps"] = (256 << B) / (out["scan_ms"] * 1e-3) / 1e9
+    if t.stats()["live"] != 0 or out["scan_removed"] != nkeys:
+        raise RuntimeError("the scan did not remove every expired entry")
     t.close()
     return out
 
@@ -870,6 +938,8 @@ def main():
                                                  / lk[f"plain_{name}_glookups"])
         out["burst_latency"] = burst_latency(t, dpos, dneg, dev)
         t.close()
+        log("tables with timers")
+        out["timers"] = timers_leg(dev, B, load, n, dpos, dneg, pos_idx, lk)
         del dpos, dneg, f_pos, v_pos, f_neg, v_neg
         torch.cuda.empty_cache()
         peak = probe_rand_peak(dev)

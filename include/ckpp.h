@@ -38,7 +38,8 @@
  *     28..31 lock     u32  zero whenever no batch is running
  *     32..63 other[8] u32  the other bucket of each slot's entry (Sec. 4.3)
  *   key/value record of slot s of bucket b, 32 bytes at offset 32*(8*b+s)
- *   (implicit index, Sec. 4.3): key[16] | value u64 | reserved u64 (0).
+ *   (implicit index, Sec. 4.3): key[16] | value u64 | reserved u64 (0; on
+ *   a table with timers the entry's 16-bit expiration time).
  *
  * Hash (the paper uses CityHash64, Sec. 5): with the key read as
  * little-endian u64 halves lo and hi, h = f(f(lo ^ seed) ^ hi), where f is
@@ -82,6 +83,11 @@ enum {
 #define CKPP_PLAIN 1u /* plain (pessimistic) cuckoo table: no bloom filter or
                          moved counter is kept; lookups read both buckets
                          (the comparison baseline of Sec. 3) */
+#define CKPP_TIMERS 2u /* table with timers (Sec. 4.2): every entry carries a
+                          16-bit expiration time; values are below 2^48.  Such
+                          a table is used through the *_at calls below (and
+                          export/import, stats, clear, hash); the other batch
+                          calls, plans and servers refuse it (CKPP_EINVAL). */
 
 /* Lookup modes (Sec. 3 and Sec. 4.1).  All modes give the same answers. */
 enum {
@@ -97,7 +103,7 @@ enum {
 /* Creates an empty table of 2^log2_buckets buckets (1 <= log2_buckets <= 24)
  * on HIP device `device` and stores its handle in *out.  hash_seed seeds the
  * hash; max_kicks bounds the displacements of one cuckoo path (Sec. 2);
- * flags is 0 or CKPP_PLAIN.  Errors: CKPP_EINVAL (out null, B out of range,
+ * flags: 0, CKPP_PLAIN and/or CKPP_TIMERS.  Errors: CKPP_EINVAL (out null, B out of range,
  * unknown flag, bad device), CKPP_ENOMEM, CKPP_EDEVICE. */
 int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uint32_t max_kicks,
                 uint32_t flags, int device);
@@ -144,6 +150,58 @@ int ckpp_lookup_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mo
 int ckpp_delete_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_found,
                       void *stream);
 
+/* ---- Timers (Sec. 4.2) -------------------------------------------------
+ * On a table created with CKPP_TIMERS each entry has a 16-bit expiration
+ * time in caller-chosen units; `now` is the current time in the same units,
+ * modulo 2^16.  An entry with expiration time e is alive at `now` iff
+ * (e - now) mod 2^16 < 1024: expiration times are set at most 1023 units
+ * ahead, and an expired entry counts as absent.  Expired entries are deleted
+ * lazily: an insert takes a slot holding one as if it were free (the slot's
+ * entry is removed with the filter maintenance of a delete).  An expired
+ * entry would look alive again 64512 units after it expired (the 16-bit
+ * time wraps); ckpp_expire_scan removes every expired entry and must run at
+ * least once every 64512 units.  In device memory the time occupies the high
+ * 16 bits of the entry's value word, so it is read with the value (no extra
+ * memory access for lookups) and values are limited to 48 bits. */
+
+/* Batched insert on a table with timers: as ckpp_insert_batch, where only
+ * alive entries are present (an alive key is UPDATED; a key whose entry has
+ * expired is overwritten in place and reported INSERTED), and key i's entry
+ * gets expiration time d_expiry[i] (n u16, required; a time outside
+ * [now, now + 1023] gives an entry that is not alive at `now`).  A value of
+ * 2^48 or more is not stored: that key reports CKPP_FAILED.
+ * Errors: as ckpp_insert_batch, and CKPP_EINVAL on a table without timers. */
+int ckpp_insert_batch_at(ckpp_table *t, const void *d_keys, const uint64_t *d_values,
+                         const uint16_t *d_expiry, uint64_t n, uint16_t now, uint8_t *d_status,
+                         uint64_t *d_nfailed, void *stream);
+
+/* Batched lookup on a table with timers: as ckpp_lookup_batch, where only
+ * entries alive at `now` are found (values are the stored 48-bit values).
+ * refresh = 1: every entry found gets expiration time `expiry` (Sec. 4.2: a
+ * lookup may update it), which must lie in [now, now + 1023] mod 2^16 so
+ * that the answers do not depend on the order of the batch's lookups; the
+ * table is then written, so the batch must not run concurrently with other
+ * lookups of the same table.  refresh = 0: nothing is written.
+ * Errors: as ckpp_lookup_batch; CKPP_EINVAL on a table without timers,
+ * refresh > 1, or a refresh time outside the window. */
+int ckpp_lookup_batch_at(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
+                         uint16_t now, uint32_t refresh, uint16_t expiry, uint8_t *d_found,
+                         uint64_t *d_values, void *stream);
+
+/* Batched delete on a table with timers: as ckpp_delete_batch; an expired
+ * entry of the key is removed too but reports 0 (only alive keys are found).
+ * Errors: as ckpp_delete_batch, and CKPP_EINVAL on a table without timers. */
+int ckpp_delete_batch_at(ckpp_table *t, const void *d_keys, uint64_t n, uint16_t now,
+                         uint8_t *d_found, void *stream);
+
+/* Anti-revival scan (Sec. 4.2): removes every entry expired at `now`, with
+ * the filter maintenance of a delete (moved counters of the primaries of
+ * removed displaced entries decrease; filters whose counter reaches zero are
+ * emptied).  *d_removed (one u64, nullable) is incremented by the number of
+ * entries removed.  Reads the whole table (two kernels).
+ * Errors: CKPP_EINVAL (table without timers, misaligned d_removed). */
+int ckpp_expire_scan(ckpp_table *t, uint16_t now, uint64_t *d_removed, void *stream);
+
 /* Copies the table image to host memory (h_buckets: 64 * 2^B bytes, h_kv:
  * 256 * 2^B bytes; either may be null to skip it) after the stream's earlier
  * work; returns when the copy is complete. */
@@ -154,7 +212,9 @@ int ckpp_export(const ckpp_table *t, void *h_buckets, void *h_kv, void *stream);
  * The image must satisfy the table's invariants (each entry in one of its
  * two buckets with its tag and other bucket, exact moved counters, no
  * filter false negative, zero locks); lookups on any other image are
- * unspecified. */
+ * unspecified.  On a table with timers every record's value must be below
+ * 2^48 and its reserved word below 2^16, else CKPP_EINVAL (table
+ * unchanged). */
 int ckpp_import(ckpp_table *t, const void *h_buckets, const void *h_kv, void *stream);
 
 /* Table statistics (Sec. 3 entries in secondary; Sec. 4.1 moved counters;
@@ -166,7 +226,8 @@ int ckpp_import(ckpp_table *t, const void *h_buckets, const void *h_kv, void *st
 #define CKPP_MOVED_BINS 66 /* moved counter values 0..64, then "> 64" */
 typedef struct {
     uint64_t nbuckets;
-    uint64_t live;          /* occupied slots */
+    uint64_t live;          /* occupied slots (with timers: expired entries
+                               not yet reused or scanned count too) */
     uint64_t in_secondary;  /* entries stored in their secondary bucket */
     uint64_t bloom_pc_sum;  /* sum of popcount(bloom) over buckets */
     uint64_t bloom_pc2_sum; /* sum of popcount(bloom)^2 over buckets */

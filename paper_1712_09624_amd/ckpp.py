@@ -19,6 +19,8 @@ LIB_PATH = os.path.join(HERE, "libckpp.so")
 OK, EINVAL, ENOMEM, EDEVICE = 0, 1, 2, 3
 INSERTED, UPDATED, FAILED = 0, 1, 2
 PLAIN = 1
+TIMERS = 2  # entries carry 16-bit expiration times (Sec. 4.2); values < 2^48
+MAX_DELAY = 1024
 LOOKUP_DEFAULT, LOOKUP_BOTH, LOOKUP_OPTIMISTIC = 0, 1, 2
 MODES = {"cuckoopp": LOOKUP_DEFAULT, "default": LOOKUP_DEFAULT, "both": LOOKUP_BOTH,
          "plain": LOOKUP_BOTH, "pessimistic": LOOKUP_BOTH, "optimistic": LOOKUP_OPTIMISTIC}
@@ -159,6 +161,11 @@ SIGNATURES = [
     ("ckpp_insert_batch", _I, [_VP, _VP, _VP, _U64, _VP, _VP, _VP]),
     ("ckpp_lookup_batch", _I, [_VP, _VP, _U64, _U32, _VP, _VP, _VP]),
     ("ckpp_delete_batch", _I, [_VP, _VP, _U64, _VP, _VP]),
+    ("ckpp_insert_batch_at", _I, [_VP, _VP, _VP, _VP, _U64, ctypes.c_uint16, _VP, _VP, _VP]),
+    ("ckpp_lookup_batch_at", _I, [_VP, _VP, _U64, _U32, ctypes.c_uint16, _U32, ctypes.c_uint16,
+                                  _VP, _VP, _VP]),
+    ("ckpp_delete_batch_at", _I, [_VP, _VP, _U64, ctypes.c_uint16, _VP, _VP]),
+    ("ckpp_expire_scan", _I, [_VP, ctypes.c_uint16, _VP, _VP]),
     ("ckpp_export", _I, [_VP, _VP, _VP, _VP]),
     ("ckpp_import", _I, [_VP, _VP, _VP, _VP]),
     ("ckpp_stats", _I, [_VP, ctypes.POINTER(_Stats), _VP]),
@@ -245,7 +252,8 @@ class Table:
     """A Cuckoo++ hash table in device memory (see include/ckpp.h)."""
 
     def __init__(self, log2_buckets: int, hash_seed: int = DEFAULT_HASH_SEED,
-                 max_kicks: int = 500, plain: bool = False, device: int | None = None):
+                 max_kicks: int = 500, plain: bool = False, device: int | None = None,
+                 timers: bool = False):
         torch = _torch()
         self.lib = load()
         if device is None:
@@ -255,10 +263,12 @@ class Table:
         self.nbuckets = 1 << self.log2_buckets
         self.hash_seed = int(hash_seed)
         self.plain = bool(plain)
+        self.timers = bool(timers)
         h = ctypes.c_void_p()
         rc = self.lib.ckpp_create(ctypes.byref(h), self.log2_buckets,
                                   ctypes.c_uint64(self.hash_seed), int(max_kicks),
-                                  PLAIN if plain else 0, self.device)
+                                  (PLAIN if plain else 0) | (TIMERS if timers else 0),
+                                  self.device)
         _check(rc, "ckpp_create")
         self._h = h
 
@@ -326,6 +336,67 @@ class Table:
         rc = self.lib.ckpp_delete_batch(self._h, kp, n, found.data_ptr(), _stream_handle(stream))
         _check(rc, "ckpp_delete_batch")
         return found
+
+    # -- batches on a table with timers (Sec. 4.2); now and times are u16
+    def insert_at(self, keys, values, expiry, now, status=None, nfailed=None, stream=None):
+        """Enqueues an insert batch with one expiration time per key (u16
+        tensor); returns (status u8[n], nfailed i64[1])."""
+        torch = _torch()
+        kp, n = _keys_ptr(keys)
+        if values.numel() != n or values.element_size() != 8 or not values.is_contiguous():
+            raise CkppError("values must be n contiguous 64-bit integers")
+        if expiry.numel() != n or expiry.element_size() != 2 or not expiry.is_contiguous():
+            raise CkppError("expiry must be n contiguous 16-bit integers")
+        if status is None:
+            status = torch.empty(n, dtype=torch.uint8, device=self._dev())
+        if nfailed is None:
+            nfailed = torch.zeros(1, dtype=torch.int64, device=self._dev())
+        rc = self.lib.ckpp_insert_batch_at(self._h, kp, values.data_ptr(), expiry.data_ptr(), n,
+                                           int(now) & 0xFFFF, status.data_ptr(),
+                                           nfailed.data_ptr(), _stream_handle(stream))
+        _check(rc, "ckpp_insert_batch_at")
+        return status, nfailed
+
+    def lookup_at(self, keys, now, mode="cuckoopp", refresh=None, found=None, values=None,
+                  stream=None):
+        """Enqueues a lookup batch at time `now`; with `refresh` (a u16 time)
+        every entry found gets that expiration time.  Returns (found, values)."""
+        torch = _torch()
+        kp, n = _keys_ptr(keys)
+        m = MODES[mode] if isinstance(mode, str) else int(mode)
+        if found is None:
+            found = torch.empty(n, dtype=torch.uint8, device=self._dev())
+        if values is None:
+            values = torch.empty(n, dtype=torch.int64, device=self._dev())
+        rc = self.lib.ckpp_lookup_batch_at(self._h, kp, n, m, int(now) & 0xFFFF,
+                                           0 if refresh is None else 1,
+                                           0 if refresh is None else int(refresh) & 0xFFFF,
+                                           found.data_ptr(), values.data_ptr(),
+                                           _stream_handle(stream))
+        _check(rc, "ckpp_lookup_batch_at")
+        return found, values
+
+    def delete_at(self, keys, now, found=None, stream=None):
+        """Enqueues a delete batch at time `now`; returns found u8[n]."""
+        torch = _torch()
+        kp, n = _keys_ptr(keys)
+        if found is None:
+            found = torch.empty(n, dtype=torch.uint8, device=self._dev())
+        rc = self.lib.ckpp_delete_batch_at(self._h, kp, n, int(now) & 0xFFFF, found.data_ptr(),
+                                           _stream_handle(stream))
+        _check(rc, "ckpp_delete_batch_at")
+        return found
+
+    def expire_scan(self, now, removed=None, stream=None):
+        """Enqueues the anti-revival scan; returns the removed-entry counter
+        (i64[1], incremented)."""
+        torch = _torch()
+        if removed is None:
+            removed = torch.zeros(1, dtype=torch.int64, device=self._dev())
+        rc = self.lib.ckpp_expire_scan(self._h, int(now) & 0xFFFF, removed.data_ptr(),
+                                       _stream_handle(stream))
+        _check(rc, "ckpp_expire_scan")
+        return removed
 
     def hash(self, keys, stream=None):
         torch = _torch()

@@ -1,6 +1,7 @@
 // ckpp_api.hip -- the C ABI: argument checks, device memory, dispatch.
 
 #include <algorithm>
+#include <atomic>
 #include <new>
 #include <stdint.h>
 #include <string.h>
@@ -48,9 +49,16 @@ void parallel_range(uint64_t n, F f) {
   for (auto &x : th) x.join();
 }
 
-// image (64-byte buckets + 32-byte records) -> device layout
-void image_to_device(const uint8_t *hb, const uint8_t *hk, uint8_t *dev, uint64_t nb) {
-  parallel_range(nb, [=](uint64_t lo, uint64_t hi) {
+constexpr uint64_t kValueBits48 = (1ull << 48) - 1ull;
+
+// image (64-byte buckets + 32-byte records) -> device layout.  With timers
+// the device value word is value | expiration time << 48 (the image keeps
+// the time in the record's reserved word).  Returns false (the staging copy
+// then is not used) when a timed record's value or time is out of range.
+bool image_to_device(const uint8_t *hb, const uint8_t *hk, uint8_t *dev, uint64_t nb,
+                     bool timed) {
+  std::atomic<bool> ok{true};
+  parallel_range(nb, [=, &ok](uint64_t lo, uint64_t hi) {
     for (uint64_t b = lo; b < hi; ++b) {
       uint8_t *d = dev + 256 * b;
       const uint8_t *src = hb + 64 * b;
@@ -59,14 +67,23 @@ void image_to_device(const uint8_t *hb, const uint8_t *hk, uint8_t *dev, uint64_
       for (uint32_t s = 0; s < 8; ++s) {
         const uint8_t *r = hk + 32 * (8 * b + s);
         memcpy(d + dev_key_offset(s), r, 16);
-        memcpy(d + dev_value_offset(s), r + 16, 8);
+        uint64_t v, pad;
+        memcpy(&v, r + 16, 8);
+        memcpy(&pad, r + 24, 8);
+        if (timed) {
+          if ((v >> 48) != 0 || (pad >> 16) != 0) ok.store(false);
+          v = (v & kValueBits48) | ((pad & 0xffffull) << 48);
+        }
+        memcpy(d + dev_value_offset(s), &v, 8);
       }
     }
   });
+  return ok.load();
 }
 
-// device layout -> image (the records' reserved 8 bytes are written as 0)
-void device_to_image(const uint8_t *dev, uint8_t *hb, uint8_t *hk, uint64_t nb) {
+// device layout -> image (the records' reserved 8 bytes are written as 0,
+// or as the expiration time on a table with timers)
+void device_to_image(const uint8_t *dev, uint8_t *hb, uint8_t *hk, uint64_t nb, bool timed) {
   parallel_range(nb, [=](uint64_t lo, uint64_t hi) {
     for (uint64_t b = lo; b < hi; ++b) {
       const uint8_t *d = dev + 256 * b;
@@ -78,13 +95,23 @@ void device_to_image(const uint8_t *dev, uint8_t *hb, uint8_t *hk, uint64_t nb) 
         for (uint32_t s = 0; s < 8; ++s) {
           uint8_t *r = hk + 32 * (8 * b + s);
           memcpy(r, d + dev_key_offset(s), 16);
-          memcpy(r + 16, d + dev_value_offset(s), 8);
-          memset(r + 24, 0, 8);
+          uint64_t v;
+          memcpy(&v, d + dev_value_offset(s), 8);
+          const uint64_t pad = timed ? (v >> 48) : 0ull;
+          if (timed) v &= kValueBits48;
+          memcpy(r + 16, &v, 8);
+          memcpy(r + 24, &pad, 8);
         }
       }
     }
   });
 }
+
+bool timed(const ckpp_table *t) { return (t->flags & CKPP_TIMERS) != 0; }
+
+// A refresh time must keep the entry alive at `now` (Sec. 4.2: expiration
+// times lie within 1024 units after the current time).
+bool in_window(uint32_t expiry, uint32_t now) { return ((expiry - now) & 0xffffu) < 1024u; }
 
 }  // namespace
 
@@ -106,7 +133,7 @@ int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uin
   *out = nullptr;
   if (log2_buckets < 1 || log2_buckets > kMaxLog2Buckets) return CKPP_EINVAL;
   if (max_kicks > kMaxKicksLimit) return CKPP_EINVAL;
-  if (flags & ~CKPP_PLAIN) return CKPP_EINVAL;
+  if (flags & ~(CKPP_PLAIN | CKPP_TIMERS)) return CKPP_EINVAL;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess) return CKPP_EDEVICE;
   if (device < 0 || device >= ndev) return CKPP_EINVAL;
@@ -176,21 +203,23 @@ int ckpp_clear(ckpp_table *t, void *stream) {
   return dev_status(ckpp::launch_fill_zero(t->d_table, table_bytes(t), s));
 }
 
-int ckpp_insert_batch(ckpp_table *t, const void *d_keys, const uint64_t *d_values, uint64_t n,
-                      uint8_t *d_status, uint64_t *d_nfailed, void *stream) {
-  if (!t) return CKPP_EINVAL;
+namespace {
+
+int insert_common(ckpp_table *t, const void *d_keys, const uint64_t *d_values,
+                  const uint16_t *d_expiry, const ckpp::TimerArgs *tm, uint64_t n,
+                  uint8_t *d_status, uint64_t *d_nfailed, void *stream) {
   if (n == 0) return CKPP_OK;
   if (!d_keys || !d_values || !aligned(d_keys, 16) || !aligned(d_values, 8)) return CKPP_EINVAL;
+  if (tm && (!d_expiry || !aligned(d_expiry, 2))) return CKPP_EINVAL;
   if (d_nfailed && !aligned(d_nfailed, 8)) return CKPP_EINVAL;
   DeviceGuard g(t->device);
   if (!g.ok()) return CKPP_EDEVICE;
-  return dev_status(ckpp::launch_insert(t, d_keys, d_values, n, d_status, d_nfailed,
+  return dev_status(ckpp::launch_insert(t, d_keys, d_values, d_expiry, tm, n, d_status, d_nfailed,
                                         reinterpret_cast<hipStream_t>(stream)));
 }
 
-int ckpp_lookup_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
-                      uint8_t *d_found, uint64_t *d_values, void *stream) {
-  if (!t) return CKPP_EINVAL;
+int lookup_common(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
+                  const ckpp::TimerArgs *tm, uint8_t *d_found, uint64_t *d_values, void *stream) {
   if (mode > CKPP_LOOKUP_OPTIMISTIC) return CKPP_EINVAL;
   if (n == 0) return CKPP_OK;
   if (!d_keys || !d_found || !d_values) return CKPP_EINVAL;
@@ -199,19 +228,71 @@ int ckpp_lookup_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mo
   if (mode == CKPP_LOOKUP_DEFAULT && (t->flags & CKPP_PLAIN)) mode = CKPP_LOOKUP_BOTH;
   DeviceGuard g(t->device);
   if (!g.ok()) return CKPP_EDEVICE;
-  return dev_status(ckpp::launch_lookup(t, d_keys, n, mode, d_found, d_values,
+  return dev_status(ckpp::launch_lookup(t, d_keys, n, mode, tm, d_found, d_values,
                                         reinterpret_cast<hipStream_t>(stream)));
 }
 
-int ckpp_delete_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_found,
-                      void *stream) {
-  if (!t) return CKPP_EINVAL;
+int delete_common(ckpp_table *t, const void *d_keys, uint64_t n, const ckpp::TimerArgs *tm,
+                  uint8_t *d_found, void *stream) {
   if (n == 0) return CKPP_OK;
   if (!d_keys || !aligned(d_keys, 16)) return CKPP_EINVAL;
   DeviceGuard g(t->device);
   if (!g.ok()) return CKPP_EDEVICE;
   return dev_status(
-      ckpp::launch_delete(t, d_keys, n, d_found, reinterpret_cast<hipStream_t>(stream)));
+      ckpp::launch_delete(t, d_keys, n, tm, d_found, reinterpret_cast<hipStream_t>(stream)));
+}
+
+}  // namespace
+
+int ckpp_insert_batch(ckpp_table *t, const void *d_keys, const uint64_t *d_values, uint64_t n,
+                      uint8_t *d_status, uint64_t *d_nfailed, void *stream) {
+  if (!t || timed(t)) return CKPP_EINVAL;
+  return insert_common(t, d_keys, d_values, nullptr, nullptr, n, d_status, d_nfailed, stream);
+}
+
+int ckpp_lookup_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
+                      uint8_t *d_found, uint64_t *d_values, void *stream) {
+  if (!t || timed(t)) return CKPP_EINVAL;
+  return lookup_common(t, d_keys, n, mode, nullptr, d_found, d_values, stream);
+}
+
+int ckpp_delete_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_found,
+                      void *stream) {
+  if (!t || timed(t)) return CKPP_EINVAL;
+  return delete_common(t, d_keys, n, nullptr, d_found, stream);
+}
+
+int ckpp_insert_batch_at(ckpp_table *t, const void *d_keys, const uint64_t *d_values,
+                         const uint16_t *d_expiry, uint64_t n, uint16_t now, uint8_t *d_status,
+                         uint64_t *d_nfailed, void *stream) {
+  if (!t || !timed(t)) return CKPP_EINVAL;
+  const ckpp::TimerArgs tm{now, 0u, 0u};
+  return insert_common(t, d_keys, d_values, d_expiry, &tm, n, d_status, d_nfailed, stream);
+}
+
+int ckpp_lookup_batch_at(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
+                         uint16_t now, uint32_t refresh, uint16_t expiry, uint8_t *d_found,
+                         uint64_t *d_values, void *stream) {
+  if (!t || !timed(t) || refresh > 1u) return CKPP_EINVAL;
+  if (refresh && !in_window(expiry, now)) return CKPP_EINVAL;
+  const ckpp::TimerArgs tm{now, refresh, expiry};
+  return lookup_common(t, d_keys, n, mode, &tm, d_found, d_values, stream);
+}
+
+int ckpp_delete_batch_at(ckpp_table *t, const void *d_keys, uint64_t n, uint16_t now,
+                         uint8_t *d_found, void *stream) {
+  if (!t || !timed(t)) return CKPP_EINVAL;
+  const ckpp::TimerArgs tm{now, 0u, 0u};
+  return delete_common(t, d_keys, n, &tm, d_found, stream);
+}
+
+int ckpp_expire_scan(ckpp_table *t, uint16_t now, uint64_t *d_removed, void *stream) {
+  if (!t || !timed(t)) return CKPP_EINVAL;
+  if (d_removed && !aligned(d_removed, 8)) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  return dev_status(
+      ckpp::launch_expire_scan(t, now, d_removed, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int ckpp_export(const ckpp_table *t, void *h_buckets, void *h_kv, void *stream) {
@@ -226,7 +307,7 @@ int ckpp_export(const ckpp_table *t, void *h_buckets, void *h_kv, void *stream) 
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e == hipSuccess)
     device_to_image(stage, static_cast<uint8_t *>(h_buckets), static_cast<uint8_t *>(h_kv),
-                    nbuckets(t));
+                    nbuckets(t), timed(t));
   delete[] stage;
   return dev_status(e);
 }
@@ -237,8 +318,11 @@ int ckpp_import(ckpp_table *t, const void *h_buckets, const void *h_kv, void *st
   if (!g.ok()) return CKPP_EDEVICE;
   uint8_t *stage = new (std::nothrow) uint8_t[table_bytes(t)];
   if (!stage) return CKPP_ENOMEM;
-  image_to_device(static_cast<const uint8_t *>(h_buckets), static_cast<const uint8_t *>(h_kv),
-                  stage, nbuckets(t));
+  if (!image_to_device(static_cast<const uint8_t *>(h_buckets),
+                       static_cast<const uint8_t *>(h_kv), stage, nbuckets(t), timed(t))) {
+    delete[] stage;
+    return CKPP_EINVAL;
+  }
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(t->d_table, stage, table_bytes(t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);

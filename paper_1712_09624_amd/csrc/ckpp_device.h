@@ -17,6 +17,10 @@
 //                    path is searched without reading keys (Sec. 4.3)
 // Viewed as uint4 quarters: 16 per bucket; quarter r of line 0 is read by
 // lane r of an 8-lane lookup group.
+// On a table with timers (Sec. 4.2) the value word of a slot holds the value
+// in its low 48 bits and the entry's 16-bit expiration time in its high 16
+// bits: the time is read with the value, in the line that holds the key, so
+// checking it costs a lookup no extra memory request.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -113,6 +117,16 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ uint4 load_stream(const uint4 *p) {
   const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
   return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+// Timers (Sec. 4.2): 16-bit times; an entry whose expiration time is e is
+// alive at time `now` iff (e - now) mod 2^16 < 1024.
+constexpr uint32_t kTimerShift = 48;
+constexpr uint64_t kValueMask = (1ull << kTimerShift) - 1ull;
+constexpr uint32_t kMaxDelay = 1024;
+
+__device__ __forceinline__ bool word_alive(uint64_t word, uint32_t now) {
+  return (((uint32_t)(word >> kTimerShift) - now) & 0xffffu) < kMaxDelay;
 }
 
 __device__ __forceinline__ bool key_eq(uint4 a, uint4 b) {

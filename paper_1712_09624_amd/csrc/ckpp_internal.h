@@ -38,8 +38,18 @@ constexpr uint32_t kModeCuckoopp = 0;
 constexpr uint32_t kModeBoth = 1;
 constexpr uint32_t kModeOptimistic = 2;
 
+// Timers of a batch on a table with timers (Sec. 4.2): the current time;
+// for lookups, whether a hit sets the entry's expiration time to `expiry`.
+struct TimerArgs {
+  uint32_t now;
+  uint32_t refresh;
+  uint32_t expiry;
+};
+
+// timers: null on a table without timers.
 hipError_t launch_lookup(const ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
-                         uint8_t *d_found, uint64_t *d_values, hipStream_t s);
+                         const TimerArgs *timers, uint8_t *d_found, uint64_t *d_values,
+                         hipStream_t s);
 // One launch of the plan's persistent lookup kernel over its items.
 // d_ctr: two u32 counters (next item, finished waves), zero before the
 // launch and zero again after it.  two_buffers: some table uses the
@@ -47,10 +57,15 @@ hipError_t launch_lookup(const ckpp_table *t, const void *d_keys, uint64_t n, ui
 hipError_t launch_plan(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr, bool two_buffers,
                        const ckpp_plan_launch_t &L, int num_cus, const void *d_keys,
                        uint8_t *d_found, uint64_t *d_values, hipStream_t s);
+// d_expiry and timers: null on a table without timers.
 hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t *d_values,
-                         uint64_t n, uint8_t *d_status, uint64_t *d_nfailed, hipStream_t s);
-hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_found,
-                         hipStream_t s);
+                         const uint16_t *d_expiry, const TimerArgs *timers, uint64_t n,
+                         uint8_t *d_status, uint64_t *d_nfailed, hipStream_t s);
+hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n,
+                         const TimerArgs *timers, uint8_t *d_found, hipStream_t s);
+// Removes every entry expired at `now` (two kernels: slots, then filters).
+hipError_t launch_expire_scan(const ckpp_table *t, uint32_t now, uint64_t *d_removed,
+                              hipStream_t s);
 hipError_t launch_stats(const ckpp_table *t, uint64_t *d_acc, hipStream_t s);
 hipError_t launch_hash(const ckpp_table *t, const void *d_keys, uint64_t n, uint64_t *d_hash,
                        hipStream_t s);

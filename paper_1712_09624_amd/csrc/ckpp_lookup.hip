@@ -33,7 +33,7 @@ namespace {
 
 // One table's batch, one lookup per lane per pass; the grid strides over
 // the batch and each wave loads its next keys while its lines are in flight.
-template <uint32_t WAVES, uint32_t MODE>
+template <uint32_t WAVES, uint32_t MODE, bool TIMED>
 __global__ void __launch_bounds__(64 * WAVES)
     lookup_lds(TableRef T, const uint4 *__restrict__ keys, uint64_t n,
                uint8_t *__restrict__ found, uint64_t *__restrict__ vals) {
@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(64 * WAVES)
   // the wave stays together: its loop condition is the wave's first lookup
   for (; i - w.lane < n; i += stride) {
     uint4 knext;
-    lds_pass<MODE>(w, T, key, i < n, found + i, vals + i, [&] {
+    lds_pass<MODE, TIMED>(w, T, key, i < n, found + i, vals + i, [&] {
       const uint64_t inext = i + stride;
       knext = inext < n ? load_stream(keys + inext) : zero4();
     });
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(64 * WAVES)
 
 // One table's batch, two lookups per lane per pass (lookups w0 + lane and
 // w0 + 64 + lane of the wave's 128-lookup tile).
-template <uint32_t WAVES, uint32_t MODE>
+template <uint32_t WAVES, uint32_t MODE, bool TIMED>
 __global__ void __launch_bounds__(64 * WAVES)
     lookup_dual(TableRef T, const uint4 *__restrict__ keys, uint64_t n,
                 uint8_t *__restrict__ found, uint64_t *__restrict__ vals) {
@@ -70,7 +70,8 @@ __global__ void __launch_bounds__(64 * WAVES)
   for (uint64_t w0 = wave0; w0 < n; w0 += stride) {
     const uint64_t ia = w0 + lane, ib = w0 + 64u + lane;
     uint4 na, nb;
-    dual_pass<MODE>(w, T, ka, ia < n, kb, ib < n, found + ia, vals + ia, found + ib, vals + ib,
+    dual_pass<MODE, TIMED>(w, T, ka, ia < n, kb, ib < n, found + ia, vals + ia, found + ib,
+                           vals + ib,
                     [&] {
                       const uint64_t nx = w0 + stride;
                       na = nx + lane < n ? load_stream(keys + nx + lane) : zero4();
@@ -209,32 +210,40 @@ uint64_t capped_grid(uint64_t n, uint64_t per_block, uint32_t blocks_per_cu, int
   return grid > 0x7fffffffull ? 0x7fffffffull : grid;
 }
 
-template <uint32_t WAVES, uint32_t MODE>
-hipError_t launch_shape(const ckpp_table *t, const uint4 *keys, uint64_t n, uint8_t *found,
-                        uint64_t *vals, hipStream_t s) {
+template <uint32_t WAVES, uint32_t MODE, bool TIMED>
+hipError_t launch_shape(const ckpp_table *t, const TableRef &T, const uint4 *keys, uint64_t n,
+                        uint8_t *found, uint64_t *vals, hipStream_t s) {
   const ckpp_launch_t &L = t->lookup_launch;
-  const TableRef T{reinterpret_cast<const uint4 *>(t->d_table), t->seed, t->log2_buckets};
   if (MODE != kModeBoth && L.lookups_per_lane == 2) {
     constexpr uint32_t M = MODE == kModeBoth ? kModeCuckoopp : MODE;
     const uint64_t grid = capped_grid(n, 128ull * WAVES, L.blocks_per_cu, t->num_cus);
-    hipLaunchKernelGGL((lookup_dual<WAVES, M>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, s, T,
-                       keys, n, found, vals);
+    hipLaunchKernelGGL((lookup_dual<WAVES, M, TIMED>), dim3((uint32_t)grid), dim3(64 * WAVES), 0,
+                       s, T, keys, n, found, vals);
   } else {
     const uint64_t grid = capped_grid(n, 64ull * WAVES, L.blocks_per_cu, t->num_cus);
-    hipLaunchKernelGGL((lookup_lds<WAVES, MODE>), dim3((uint32_t)grid), dim3(64 * WAVES), 0, s, T,
-                       keys, n, found, vals);
+    hipLaunchKernelGGL((lookup_lds<WAVES, MODE, TIMED>), dim3((uint32_t)grid), dim3(64 * WAVES),
+                       0, s, T, keys, n, found, vals);
   }
   return hipGetLastError();
 }
 
-template <uint32_t MODE>
-hipError_t launch_mode(const ckpp_table *t, const uint4 *keys, uint64_t n, uint8_t *found,
-                       uint64_t *vals, hipStream_t s) {
+template <uint32_t MODE, bool TIMED>
+hipError_t launch_mode(const ckpp_table *t, const TableRef &T, const uint4 *keys, uint64_t n,
+                       uint8_t *found, uint64_t *vals, hipStream_t s) {
   switch (t->lookup_launch.block) {
-    case 64: return launch_shape<1, MODE>(t, keys, n, found, vals, s);
-    case 128: return launch_shape<2, MODE>(t, keys, n, found, vals, s);
-    default: return launch_shape<4, MODE>(t, keys, n, found, vals, s);
+    case 64: return launch_shape<1, MODE, TIMED>(t, T, keys, n, found, vals, s);
+    case 128: return launch_shape<2, MODE, TIMED>(t, T, keys, n, found, vals, s);
+    default: return launch_shape<4, MODE, TIMED>(t, T, keys, n, found, vals, s);
   }
+}
+
+template <bool TIMED>
+hipError_t launch_timing(const ckpp_table *t, const TableRef &T, const uint4 *keys, uint64_t n,
+                         uint32_t mode, uint8_t *found, uint64_t *vals, hipStream_t s) {
+  if (mode == kModeBoth) return launch_mode<kModeBoth, TIMED>(t, T, keys, n, found, vals, s);
+  if (mode == kModeOptimistic)
+    return launch_mode<kModeOptimistic, TIMED>(t, T, keys, n, found, vals, s);
+  return launch_mode<kModeCuckoopp, TIMED>(t, T, keys, n, found, vals, s);
 }
 
 template <uint32_t WAVES, uint32_t NB, uint32_t PER>
@@ -288,12 +297,15 @@ hipError_t launch_plan(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr
 }
 
 hipError_t launch_lookup(const ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
-                         uint8_t *d_found, uint64_t *d_values, hipStream_t s) {
+                         const TimerArgs *timers, uint8_t *d_found, uint64_t *d_values,
+                         hipStream_t s) {
   const uint4 *keys = reinterpret_cast<const uint4 *>(d_keys);
-  if (mode == kModeBoth) return launch_mode<kModeBoth>(t, keys, n, d_found, d_values, s);
-  if (mode == kModeOptimistic)
-    return launch_mode<kModeOptimistic>(t, keys, n, d_found, d_values, s);
-  return launch_mode<kModeCuckoopp>(t, keys, n, d_found, d_values, s);
+  TableRef T{reinterpret_cast<const uint4 *>(t->d_table), t->seed, t->log2_buckets};
+  if (!timers) return launch_timing<false>(t, T, keys, n, mode, d_found, d_values, s);
+  T.now = timers->now;
+  T.refresh = timers->refresh;
+  T.expiry = timers->expiry;
+  return launch_timing<true>(t, T, keys, n, mode, d_found, d_values, s);
 }
 
 }  // namespace ckpp

@@ -45,30 +45,44 @@ __device__ __forceinline__ uint64_t quarter_value(uint4 q, uint32_t s) {
                   : ((uint64_t)q.x | ((uint64_t)q.y << 32));
 }
 
+// A slot answers the lookup iff its full key equals the searched key and,
+// with timers, its entry is alive at `now` (Sec. 4.2: expired entries are
+// not considered); on a hit sets hit, val (the value without the time) and
+// slot.
+template <bool TIMED>
+__device__ __forceinline__ void take_word(uint64_t w, uint32_t s, uint32_t now, bool &hit,
+                                          uint64_t &val, uint32_t &slot) {
+  if (!TIMED || word_alive(w, now)) {
+    hit = true;
+    val = TIMED ? (w & kValueMask) : w;
+    slot = s;
+  }
+}
+
 // Compares the key with the candidate slots `cand` (ascending) of a first
-// line (mine[0..7]); on a hit sets hit/val.
-__device__ __forceinline__ void match_line0(const uint4 *mine, uint32_t cand, uint4 key, bool &hit,
-                                            uint64_t &val) {
+// line (mine[0..7]).
+template <bool TIMED>
+__device__ __forceinline__ void match_line0(const uint4 *mine, uint32_t cand, uint4 key,
+                                            uint32_t now, bool &hit, uint64_t &val,
+                                            uint32_t &slot) {
   while (cand != 0u && !hit) {
     const uint32_t s = (uint32_t)__builtin_ctz(cand);
     cand &= cand - 1u;
-    if (key_eq(mine[2u + s], key)) {
-      hit = true;
-      val = quarter_value(mine[6u + (s >> 1)], s);
-    }
+    if (key_eq(mine[2u + s], key))
+      take_word<TIMED>(quarter_value(mine[6u + (s >> 1)], s), s, now, hit, val, slot);
   }
 }
 
 // Same for slots 4..7 on a second line (mine[0..7]).
-__device__ __forceinline__ void match_line1(const uint4 *mine, uint32_t cand, uint4 key, bool &hit,
-                                            uint64_t &val) {
+template <bool TIMED>
+__device__ __forceinline__ void match_line1(const uint4 *mine, uint32_t cand, uint4 key,
+                                            uint32_t now, bool &hit, uint64_t &val,
+                                            uint32_t &slot) {
   while (cand != 0u && !hit) {
     const uint32_t s = (uint32_t)__builtin_ctz(cand);
     cand &= cand - 1u;
-    if (key_eq(mine[s - 4u], key)) {
-      hit = true;
-      val = quarter_value(mine[4u + ((s - 4u) >> 1)], s);
-    }
+    if (key_eq(mine[s - 4u], key))
+      take_word<TIMED>(quarter_value(mine[4u + ((s - 4u) >> 1)], s), s, now, hit, val, slot);
   }
 }
 
@@ -95,12 +109,28 @@ __device__ __forceinline__ Wave wave_lines(uint4 *s_lines) {
   return w;
 }
 
-// What a lookup needs of its table.
+// What a lookup needs of its table.  Timers (tables with timers only): the
+// current time, and whether a hit sets the entry's expiration time to
+// `expiry` (Sec. 4.2: a lookup may update it).
 struct TableRef {
   const uint4 *tab;
   uint64_t seed;
   uint32_t log2b;
+  uint32_t now = 0u;
+  uint32_t refresh = 0u;
+  uint32_t expiry = 0u;
 };
+
+// Writes the new expiration time of the entry in slot s of bucket b: the
+// high 16 bits of its value word, nothing else.  Lookups of the same batch
+// may read the word meanwhile; they see the old or the new time, and both
+// are alive at `now`, so their answers do not depend on the order.
+__device__ __forceinline__ void refresh_entry(const TableRef &T, uint32_t b, uint32_t s) {
+  const uint32_t off = s < 4u ? 96u + 8u * s : 192u + 8u * (s - 4u);
+  uint8_t *base = reinterpret_cast<uint8_t *>(const_cast<uint4 *>(T.tab)) +
+                  (uint64_t)b * kBucketBytes + off + kTimerShift / 8u;
+  *reinterpret_cast<uint16_t *>(base) = (uint16_t)T.expiry;
+}
 
 __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
 
@@ -109,7 +139,7 @@ __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }
 // `pre` runs once the first lines are requested and before they are waited
 // for: the caller loads its next keys there.  The pessimistic mode needs a
 // wave with two line buffers; the other modes use the first one only.
-template <uint32_t MODE, class Pre>
+template <uint32_t MODE, bool TIMED = false, class Pre>
 __device__ __forceinline__ void lds_pass(const Wave &w, const TableRef &T, uint4 key, bool ok,
                                          uint8_t *found, uint64_t *val_out, Pre &&pre) {
   // the secondary's lines: the second buffer in the pessimistic mode (fetched
@@ -124,17 +154,19 @@ __device__ __forceinline__ void lds_pass(const Wave &w, const TableRef &T, uint4
   lines_landed();
   bool hit = false;
   uint64_t val = 0;
+  uint32_t slot = 0u;
   const uint4 t0 = w.mine[0], t1 = w.mine[1];
   const uint32_t cand = ok ? (tag_eq_mask(t0, f.tag) & meta_busy(t1.z)) : 0u;
   const bool pass = MODE != kModeCuckoopp || bloom_pass(t1, f.bloom_bits);
-  match_line0(w.mine, cand & 0xfu, key, hit, val);
+  match_line0<TIMED>(w.mine, cand & 0xfu, key, T.now, hit, val, slot);
   // second line of the primary, for keys whose tag sits in slots 4..7
   bool need = !hit && (cand & 0xf0u);
   if (__builtin_amdgcn_ballot_w64(need)) {
     fetch_lines(w.lines, T.tab, need ? f.p : kNoFetch, 1u, w.g, w.r);
     lines_landed();
-    if (need) match_line1(w.mine, cand & 0xf0u, key, hit, val);
+    if (need) match_line1<TIMED>(w.mine, cand & 0xf0u, key, T.now, hit, val, slot);
   }
+  const bool hit_primary = hit;
   // secondary bucket
   need = ok && !hit && pass;
   if (__builtin_amdgcn_ballot_w64(need)) {
@@ -146,15 +178,16 @@ __device__ __forceinline__ void lds_pass(const Wave &w, const TableRef &T, uint4
     if (need) {
       const uint4 u0 = mine_a[0], u1 = mine_a[1];
       cand2 = tag_eq_mask(u0, f.tag) & meta_busy(u1.z);
-      match_line0(mine_a, cand2 & 0xfu, key, hit, val);
+      match_line0<TIMED>(mine_a, cand2 & 0xfu, key, T.now, hit, val, slot);
     }
     need = need && !hit && (cand2 & 0xf0u);
     if (__builtin_amdgcn_ballot_w64(need)) {
       fetch_lines(lines_a, T.tab, need ? f.a : kNoFetch, 1u, w.g, w.r);
       lines_landed();
-      if (need) match_line1(mine_a, cand2 & 0xf0u, key, hit, val);
+      if (need) match_line1<TIMED>(mine_a, cand2 & 0xf0u, key, T.now, hit, val, slot);
     }
   }
+  if (TIMED && T.refresh && ok && hit) refresh_entry(T, hit_primary ? f.p : f.a, slot);
   if (ok) {
     __builtin_nontemporal_store((uint8_t)(hit ? 1 : 0), found);
     __builtin_nontemporal_store(hit ? val : 0ull, val_out);
@@ -184,16 +217,18 @@ __device__ __forceinline__ void park_lines(uint4 *lines, const uint4 (&q)[8], ui
 struct Look {
   uint4 key;
   KeyFields f;
-  bool ok, hit, pass;
-  uint32_t cand;
+  bool ok, hit, pass, hit_primary;
+  uint32_t cand, slot;
   uint64_t val;
 };
 
-__device__ __forceinline__ void first_line(const uint4 *mine, Look &L, uint32_t mode) {
+template <bool TIMED>
+__device__ __forceinline__ void first_line(const uint4 *mine, Look &L, uint32_t mode,
+                                           uint32_t now) {
   const uint4 t0 = mine[0], t1 = mine[1];
   L.cand = L.ok ? (tag_eq_mask(t0, L.f.tag) & meta_busy(t1.z)) : 0u;
   L.pass = mode != kModeCuckoopp || bloom_pass(t1, L.f.bloom_bits);
-  match_line0(mine, L.cand & 0xfu, L.key, L.hit, L.val);
+  match_line0<TIMED>(mine, L.cand & 0xfu, L.key, now, L.hit, L.val, L.slot);
 }
 
 // One pass of a wave over 128 lookups, two per lane (A and B): for each
@@ -201,7 +236,7 @@ __device__ __forceinline__ void first_line(const uint4 *mine, Look &L, uint32_t 
 // lookups in registers, which are parked in LDS once the A lookups have been
 // analysed -- twice the line requests in flight for the same LDS.  `pre` as
 // in lds_pass.  Not for the pessimistic mode.
-template <uint32_t MODE, class Pre>
+template <uint32_t MODE, bool TIMED = false, class Pre>
 __device__ __forceinline__ void dual_pass(const Wave &w, const TableRef &T, uint4 ka, bool oka,
                                           uint4 kb, bool okb, uint8_t *fa, uint64_t *va,
                                           uint8_t *fb, uint64_t *vb, Pre &&pre) {
@@ -218,25 +253,29 @@ __device__ __forceinline__ void dual_pass(const Wave &w, const TableRef &T, uint
   Bq.f = key_fields(key_hash(Bq.key, T.seed), T.log2b);
   A.hit = Bq.hit = false;
   A.val = Bq.val = 0ull;
+  A.slot = Bq.slot = 0u;
+  const uint32_t now = T.now;
   uint4 q[8];
   // phase 1: primary first lines
   fetch_lines(lines, T.tab, A.ok ? A.f.p : kNoFetch, 0u, g, r);
   fetch_lines_reg(q, T.tab, Bq.ok ? Bq.f.p : kNoFetch, 0u, g, r);
   pre();
   lines_landed();
-  first_line(mine, A, MODE);
+  first_line<TIMED>(mine, A, MODE, now);
   park_lines(lines, q, lane);
-  first_line(mine, Bq, MODE);
+  first_line<TIMED>(mine, Bq, MODE, now);
   // phase 2: primary second lines
   bool na = !A.hit && (A.cand & 0xf0u), nb = !Bq.hit && (Bq.cand & 0xf0u);
   if (__builtin_amdgcn_ballot_w64(na || nb)) {
     fetch_lines(lines, T.tab, na ? A.f.p : kNoFetch, 1u, g, r);
     fetch_lines_reg(q, T.tab, nb ? Bq.f.p : kNoFetch, 1u, g, r);
     lines_landed();
-    if (na) match_line1(mine, A.cand & 0xf0u, A.key, A.hit, A.val);
+    if (na) match_line1<TIMED>(mine, A.cand & 0xf0u, A.key, now, A.hit, A.val, A.slot);
     park_lines(lines, q, lane);
-    if (nb) match_line1(mine, Bq.cand & 0xf0u, Bq.key, Bq.hit, Bq.val);
+    if (nb) match_line1<TIMED>(mine, Bq.cand & 0xf0u, Bq.key, now, Bq.hit, Bq.val, Bq.slot);
   }
+  A.hit_primary = A.hit;
+  Bq.hit_primary = Bq.hit;
   // phase 3: secondary first lines
   na = A.ok && !A.hit && A.pass;
   nb = Bq.ok && !Bq.hit && Bq.pass;
@@ -247,12 +286,12 @@ __device__ __forceinline__ void dual_pass(const Wave &w, const TableRef &T, uint
     uint32_t ca = 0u, cb = 0u;
     if (na) {
       ca = tag_eq_mask(mine[0], A.f.tag) & meta_busy(mine[1].z);
-      match_line0(mine, ca & 0xfu, A.key, A.hit, A.val);
+      match_line0<TIMED>(mine, ca & 0xfu, A.key, now, A.hit, A.val, A.slot);
     }
     park_lines(lines, q, lane);
     if (nb) {
       cb = tag_eq_mask(mine[0], Bq.f.tag) & meta_busy(mine[1].z);
-      match_line0(mine, cb & 0xfu, Bq.key, Bq.hit, Bq.val);
+      match_line0<TIMED>(mine, cb & 0xfu, Bq.key, now, Bq.hit, Bq.val, Bq.slot);
     }
     // phase 4: secondary second lines
     na = na && !A.hit && (ca & 0xf0u);
@@ -261,10 +300,14 @@ __device__ __forceinline__ void dual_pass(const Wave &w, const TableRef &T, uint
       fetch_lines(lines, T.tab, na ? A.f.a : kNoFetch, 1u, g, r);
       fetch_lines_reg(q, T.tab, nb ? Bq.f.a : kNoFetch, 1u, g, r);
       lines_landed();
-      if (na) match_line1(mine, ca & 0xf0u, A.key, A.hit, A.val);
+      if (na) match_line1<TIMED>(mine, ca & 0xf0u, A.key, now, A.hit, A.val, A.slot);
       park_lines(lines, q, lane);
-      if (nb) match_line1(mine, cb & 0xf0u, Bq.key, Bq.hit, Bq.val);
+      if (nb) match_line1<TIMED>(mine, cb & 0xf0u, Bq.key, now, Bq.hit, Bq.val, Bq.slot);
     }
+  }
+  if (TIMED && T.refresh) {
+    if (A.ok && A.hit) refresh_entry(T, A.hit_primary ? A.f.p : A.f.a, A.slot);
+    if (Bq.ok && Bq.hit) refresh_entry(T, Bq.hit_primary ? Bq.f.p : Bq.f.a, Bq.slot);
   }
   if (A.ok) {
     __builtin_nontemporal_store((uint8_t)(A.hit ? 1 : 0), fa);

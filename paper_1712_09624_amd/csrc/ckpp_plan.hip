@@ -94,7 +94,7 @@ int ckpp_plan_create(ckpp_plan **out, ckpp_table *const *tables, uint32_t ntable
   uint64_t lookups = 0, span = 0;
   for (uint32_t i = 0; i < ntables; ++i) {
     const ckpp_table *t = tables[i];
-    if (!t || t->device != tables[0]->device) return CKPP_EINVAL;
+    if (!t || t->device != tables[0]->device || (t->flags & CKPP_TIMERS)) return CKPP_EINVAL;
     uint32_t mode = h_modes ? h_modes[i] : (uint32_t)CKPP_LOOKUP_DEFAULT;
     if (mode > CKPP_LOOKUP_OPTIMISTIC) return CKPP_EINVAL;
     // a plain table keeps no filter: its default lookup reads both buckets

@@ -485,7 +485,7 @@ extern "C" {
 int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_config_t *cfg) {
   if (!out) return CKPP_EINVAL;
   *out = nullptr;
-  if (!t || !cfg) return CKPP_EINVAL;
+  if (!t || !cfg || (t->flags & CKPP_TIMERS)) return CKPP_EINVAL;
   const ckpp_server_config_t &c = *cfg;
   if (!pow2(c.capacity) || c.capacity < 64 || c.capacity > (1ull << 30)) return CKPP_EINVAL;
   if (c.budget == 0 || c.budget > c.capacity) return CKPP_EINVAL;

@@ -7,9 +7,13 @@
 namespace ckpp {
 namespace {
 
+// TIMED: the table has timers; expiry[i] is key i's expiration time and
+// `now` the current time (Sec. 4.2).
+template <bool TIMED>
 __global__ void __launch_bounds__(256)
     insert_kernel(uint8_t *bk, const uint4 *__restrict__ keys,
-                  const uint64_t *__restrict__ vals, uint64_t n, uint32_t log2b, uint64_t seed,
+                  const uint64_t *__restrict__ vals, const uint16_t *__restrict__ expiry,
+                  uint32_t now, uint64_t n, uint32_t log2b, uint64_t seed,
                   uint32_t max_kicks, uint32_t plain_flag, uint32_t *paths,
                   uint8_t *__restrict__ status, unsigned long long *nfailed,
                   unsigned long long *nspin) {
@@ -18,15 +22,17 @@ __global__ void __launch_bounds__(256)
   const uint64_t nlanes = (uint64_t)gridDim.x * blockDim.x;
   uint32_t *path = paths + lane * (uint64_t)(max_kicks ? max_kicks : 1u);
   for (uint64_t i = lane; i < n; i += nlanes) {
-    const InsertOutcome o = insert_one(bk, keys[i], vals[i], log2b, seed, max_kicks, plain, path);
+    const InsertOutcome o = insert_one<TIMED>(bk, keys[i], vals[i], log2b, seed, max_kicks, plain,
+                                              path, TIMED ? expiry[i] : 0u, now);
     if (status) status[i] = (uint8_t)o.status;
     if (o.status == CKPP_FAILED && nfailed) atomicAdd(nfailed, 1ull);
     if (o.spun && nspin) atomicAdd(nspin, 1ull);
   }
 }
 
+template <bool TIMED>
 __global__ void __launch_bounds__(256)
-    delete_kernel(uint8_t *bk, const uint4 *__restrict__ keys, uint64_t n,
+    delete_kernel(uint8_t *bk, const uint4 *__restrict__ keys, uint64_t n, uint32_t now,
                   uint32_t log2b, uint64_t seed, uint32_t plain_flag,
                   uint8_t *__restrict__ found, unsigned long long *nspin) {
   const bool plain = plain_flag != 0u;
@@ -34,16 +40,61 @@ __global__ void __launch_bounds__(256)
   const uint64_t nlanes = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = lane; i < n; i += nlanes) {
     bool spun = false;
-    const int r = delete_one(bk, keys[i], log2b, seed, plain, &spun);
+    const int r = delete_one<TIMED>(bk, keys[i], log2b, seed, plain, &spun, now);
     if (spun && nspin) atomicAdd(nspin, 1ull);
     if (found) found[i] = (uint8_t)r;
+  }
+}
+
+// Anti-revival scan (Sec. 4.2), first kernel: every bucket removes its
+// expired entries.  Only a bucket's own lane changes its busy and sec bits;
+// the moved counter of the primary bucket of a removed entry that sat in its
+// secondary drops by one through an atomic subtraction on that bucket's
+// meta word (the counter is its low 16 bits and is at least 1 while the
+// entry is counted there), so no lock is needed.  The filters of counters
+// that reach zero are emptied by the second kernel.
+__global__ void __launch_bounds__(256)
+    expire_slots_kernel(uint8_t *bk, uint64_t nb, uint32_t now, uint32_t plain_flag,
+                        unsigned long long *removed) {
+  const bool plain = plain_flag != 0u;
+  uint64_t count = 0;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+       b += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t meta = __hip_atomic_load(meta_ptr(bk, (uint32_t)b), __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t busy = meta_busy(meta);
+    if (!busy) continue;
+    const uint32_t exp = expired_mask(bk, (uint32_t)b, busy, now);
+    if (!exp) continue;
+    __hip_atomic_fetch_and(meta_ptr(bk, (uint32_t)b), ~((exp << 16) | (exp << 24)),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!plain) {
+      for (uint32_t e = exp & meta_sec(meta); e; e &= e - 1u) {
+        const uint32_t y = other_ptr(bk, (uint32_t)b)[__builtin_ctz(e)];
+        if (y < nb)  // always, on a table that keeps its invariants
+          __hip_atomic_fetch_sub(meta_ptr(bk, y), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    count += (uint64_t)__builtin_popcount(exp);
+  }
+  if (count && removed) atomicAdd(removed, (unsigned long long)count);
+}
+
+// Second kernel: a bucket whose moved counter is zero has an empty filter
+// (Sec. 4.1: the filter is reset when its counter returns to zero).
+__global__ void __launch_bounds__(256) expire_filters_kernel(uint8_t *bk, uint64_t nb) {
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+       b += (uint64_t)gridDim.x * blockDim.x) {
+    if (meta_moved(*meta_ptr(bk, (uint32_t)b)) == 0u && *bloom_ptr(bk, (uint32_t)b) != 0ull)
+      *bloom_ptr(bk, (uint32_t)b) = 0ull;
   }
 }
 
 }  // namespace
 
 hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t *d_values,
-                         uint64_t n, uint8_t *d_status, uint64_t *d_nfailed, hipStream_t s) {
+                         const uint16_t *d_expiry, const TimerArgs *timers, uint64_t n,
+                         uint8_t *d_status, uint64_t *d_nfailed, hipStream_t s) {
   const uint64_t lanes = n < t->path_lanes ? n : t->path_lanes;
   const uint32_t block = 256;
   const uint32_t grid = (uint32_t)((lanes + block - 1) / block);
@@ -54,24 +105,53 @@ hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t
   hipError_t e = hipMallocAsync(reinterpret_cast<void **>(&paths), words * sizeof(uint32_t), s);
   if (e != hipSuccess) return e;
   unsigned long long *nspin = reinterpret_cast<unsigned long long *>(t->d_stats) + 127;
-  hipLaunchKernelGGL(insert_kernel, dim3(grid), dim3(block), 0, s, t->d_table,
-                     reinterpret_cast<const uint4 *>(d_keys), d_values, n, t->log2_buckets,
-                     t->seed, t->max_kicks, (t->flags & CKPP_PLAIN) ? 1u : 0u, paths,
-                     d_status, reinterpret_cast<unsigned long long *>(d_nfailed), nspin);
+  const uint32_t plain = (t->flags & CKPP_PLAIN) ? 1u : 0u;
+  unsigned long long *nfailed = reinterpret_cast<unsigned long long *>(d_nfailed);
+  const uint4 *keys = reinterpret_cast<const uint4 *>(d_keys);
+  if (timers)
+    hipLaunchKernelGGL(insert_kernel<true>, dim3(grid), dim3(block), 0, s, t->d_table, keys,
+                       d_values, d_expiry, timers->now, n, t->log2_buckets, t->seed, t->max_kicks,
+                       plain, paths, d_status, nfailed, nspin);
+  else
+    hipLaunchKernelGGL(insert_kernel<false>, dim3(grid), dim3(block), 0, s, t->d_table, keys,
+                       d_values, nullptr, 0u, n, t->log2_buckets, t->seed, t->max_kicks, plain,
+                       paths, d_status, nfailed, nspin);
   e = hipGetLastError();
   const hipError_t f = hipFreeAsync(paths, s);
   return e != hipSuccess ? e : f;
 }
 
-hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_found,
-                         hipStream_t s) {
+hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n,
+                         const TimerArgs *timers, uint8_t *d_found, hipStream_t s) {
   const uint64_t lanes = n < t->path_lanes ? n : t->path_lanes;
   const uint32_t block = 256;
   const uint32_t grid = (uint32_t)((lanes + block - 1) / block);
   unsigned long long *nspin = reinterpret_cast<unsigned long long *>(t->d_stats) + 127;
-  hipLaunchKernelGGL(delete_kernel, dim3(grid), dim3(block), 0, s, t->d_table,
-                     reinterpret_cast<const uint4 *>(d_keys), n, t->log2_buckets, t->seed,
-                     (t->flags & CKPP_PLAIN) ? 1u : 0u, d_found, nspin);
+  const uint32_t plain = (t->flags & CKPP_PLAIN) ? 1u : 0u;
+  const uint4 *keys = reinterpret_cast<const uint4 *>(d_keys);
+  if (timers)
+    hipLaunchKernelGGL(delete_kernel<true>, dim3(grid), dim3(block), 0, s, t->d_table, keys, n,
+                       timers->now, t->log2_buckets, t->seed, plain, d_found, nspin);
+  else
+    hipLaunchKernelGGL(delete_kernel<false>, dim3(grid), dim3(block), 0, s, t->d_table, keys, n,
+                       0u, t->log2_buckets, t->seed, plain, d_found, nspin);
+  return hipGetLastError();
+}
+
+hipError_t launch_expire_scan(const ckpp_table *t, uint32_t now, uint64_t *d_removed,
+                              hipStream_t s) {
+  const uint64_t nb = 1ull << t->log2_buckets;
+  const uint32_t block = 256;
+  uint64_t grid = (nb + block - 1) / block;
+  const uint64_t cap = 16ull * (uint64_t)t->num_cus;
+  if (grid > cap) grid = cap;
+  hipLaunchKernelGGL(expire_slots_kernel, dim3((uint32_t)grid), dim3(block), 0, s, t->d_table, nb,
+                     now, (t->flags & CKPP_PLAIN) ? 1u : 0u,
+                     reinterpret_cast<unsigned long long *>(d_removed));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(expire_filters_kernel, dim3((uint32_t)grid), dim3(block), 0, s, t->d_table,
+                     nb);
   return hipGetLastError();
 }
 

@@ -32,6 +32,17 @@
 //           applied, p has a free slot and the key returns to DIRECT.
 // Every loop is bounded: walks by max_kicks, retries by a fixed limit whose
 // exhaustion reports FAILED and is counted separately.
+//
+// Timers (Sec. 4.2, tables with timers only): an entry's expiration time
+// sits in the high 16 bits of its value word, so every move carries it
+// along.  Only alive entries are present: an insert of a key whose entry has
+// expired overwrites that entry where it stands (INSERTED), and a delete of
+// it reports 0.  DIRECT takes a slot holding an expired entry as if it were
+// free (lazy deletion), after a free one: the expired entry is removed first,
+// with the counter update of its primary bucket when it sat in its secondary
+// -- under the pair's locks when that primary is p or a, else under the
+// primary's own lock, taken like the others (never waited on).  A cuckoo
+// path still ends only at a bucket with a free slot.
 
 #pragma once
 
@@ -141,6 +152,123 @@ __device__ __forceinline__ void write_entry(uint8_t *bk, uint32_t b, uint32_t s,
 
 constexpr int kBusy = -2;    // a lock was taken by another lane: retry
 constexpr int kNeedPath = -1;
+
+// Busy slots of bucket b whose entries have expired at `now`.
+__device__ __forceinline__ uint32_t expired_mask(uint8_t *bk, uint32_t b, uint32_t busy,
+                                                 uint32_t now) {
+  uint32_t m = 0u;
+#pragma unroll
+  for (uint32_t s = 0; s < kSlots; ++s)
+    if (((busy >> s) & 1u) && !word_alive(*value_ptr(bk, b, s), now)) m |= 1u << s;
+  return m;
+}
+
+// Working copy of the metadata of the two buckets a key may live in (both
+// locked), written back once the insert is decided.
+struct Pair {
+  uint32_t b[2];
+  uint32_t meta[2];
+};
+
+// moved - 1, and the filter of bucket y emptied when it reaches zero
+// (Sec. 4.1); y's lock is held.
+__device__ __forceinline__ uint32_t moved_down(uint8_t *bk, uint32_t y, uint32_t meta) {
+  uint32_t mv = meta_moved(meta);
+  if (mv > 0u) {
+    mv -= 1u;
+    if (mv == 0u) *bloom_ptr(bk, y) = 0ull;
+  }
+  return make_meta(mv, meta_busy(meta), meta_sec(meta));
+}
+
+// Removes the expired entry of slot s of the pair's bucket xi (lazy
+// deletion, Sec. 4.2): its busy and sec bits are cleared in the working
+// copy; if it sat in its secondary bucket, the moved counter of its primary
+// y drops by one -- in the working copy when y is the pair's other bucket,
+// else under y's lock, taken here.  Returns false, having changed nothing,
+// when y's lock is held by another lane.
+__device__ bool remove_expired(uint8_t *bk, Pair &P, int xi, uint32_t s, bool plain) {
+  const uint32_t bit = 1u << s;
+  if (!plain && (meta_sec(P.meta[xi]) & bit)) {
+    const uint32_t y = other_ptr(bk, P.b[xi])[s];
+    const int yi = y == P.b[0] ? 0 : (y == P.b[1] ? 1 : -1);
+    if (yi >= 0) {
+      P.meta[yi] = moved_down(bk, y, P.meta[yi]);
+    } else {
+      if (!try_lock(bk, y)) return false;
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      *meta_ptr(bk, y) = moved_down(bk, y, *meta_ptr(bk, y));
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      unlock(bk, y);
+    }
+  }
+  P.meta[xi] = make_meta(meta_moved(P.meta[xi]), meta_busy(P.meta[xi]) & ~bit,
+                         meta_sec(P.meta[xi]) & ~bit);
+  return true;
+}
+
+// DIRECT step of a table with timers; word = value | expiry << 48.
+__device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const KeyFields &f,
+                                   bool plain, uint32_t now) {
+  if (!lock_two(bk, f.p, f.a)) return kBusy;
+  const Head hp = read_head(bk, f.p);
+  const Head ha = read_head(bk, f.a);
+  int r = kNeedPath;
+  int s = find_slot(bk, f.p, hp, key, f.tag);
+  uint32_t b = f.p;
+  if (s < 0 && (plain || bloom_pass(hp.q1, f.bloom_bits))) {
+    s = find_slot(bk, f.a, ha, key, f.tag);
+    b = f.a;
+  }
+  if (s >= 0) {
+    // the key's entry, alive (an update) or expired (overwritten in place)
+    uint64_t *vp = value_ptr(bk, b, (uint32_t)s);
+    r = word_alive(*vp, now) ? CKPP_UPDATED : CKPP_INSERTED;
+    *vp = word;
+  } else {
+    Pair P{{f.p, f.a}, {hp.q1.z, ha.q1.z}};
+    for (int xi = 0; xi < 2 && r == kNeedPath; ++xi) {
+      if (xi == 1 && !plain && meta_moved(P.meta[0]) >= 0xffffu) break;
+      const uint32_t x = P.b[xi];
+      const uint32_t busy = meta_busy(P.meta[xi]);
+      uint32_t fs;
+      if (busy != 0xffu) {
+        fs = (uint32_t)__builtin_ctz(~busy & 0xffu);
+      } else {
+        const uint32_t exp = expired_mask(bk, x, busy, now);
+        if (!exp) continue;
+        // prefer an entry whose removal needs no lock beyond the pair's
+        uint32_t cheap = exp & ~meta_sec(P.meta[xi]);
+        for (uint32_t e = exp & meta_sec(P.meta[xi]); e; e &= e - 1u) {
+          const uint32_t v = (uint32_t)__builtin_ctz(e);
+          const uint32_t y = other_ptr(bk, x)[v];
+          if (y == f.p || y == f.a) cheap |= 1u << v;
+        }
+        fs = (uint32_t)__builtin_ctz(cheap ? cheap : exp);
+        if (!remove_expired(bk, P, xi, fs, plain)) {
+          r = kBusy;
+          break;
+        }
+      }
+      write_entry(bk, x, fs, key, word, f.tag, xi ? f.p : f.a);
+      const uint32_t m = P.meta[xi], bit = 1u << fs;
+      P.meta[xi] = make_meta(meta_moved(m), meta_busy(m) | bit,
+                             xi ? (meta_sec(m) | bit) : (meta_sec(m) & ~bit));
+      if (xi == 1 && !plain) {
+        *bloom_ptr(bk, f.p) |= f.bloom_bits;
+        P.meta[0] = make_meta(meta_moved(P.meta[0]) + 1u, meta_busy(P.meta[0]),
+                              meta_sec(P.meta[0]));
+      }
+      r = CKPP_INSERTED;
+    }
+    if (r == CKPP_INSERTED) {
+      *meta_ptr(bk, f.p) = P.meta[0];
+      *meta_ptr(bk, f.a) = P.meta[1];
+    }
+  }
+  unlock_two(bk, f.p, f.a);
+  return r;
+}
 
 __device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value,
                              const KeyFields &f, bool plain) {
@@ -287,10 +415,14 @@ struct InsertOutcome {
 
 // Runs one key through the DIRECT / WALK / MOVE state machine until it is
 // placed, updated or fails.  path: this lane's scratch, max(1, max_kicks)
-// words.
+// words.  TIMED: the table has timers; the entry gets expiration time
+// `expiry`, and a value of 2^48 or more fails at once.
+template <bool TIMED = false>
 __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint32_t log2b,
                                     uint64_t seed, uint32_t max_kicks, bool plain,
-                                    uint32_t *path) {
+                                    uint32_t *path, uint32_t expiry = 0u, uint32_t now = 0u) {
+  if (TIMED && (value >> kTimerShift) != 0ull) return InsertOutcome{CKPP_FAILED, false};
+  const uint64_t word = TIMED ? (value | ((uint64_t)(expiry & 0xffffu) << kTimerShift)) : value;
   const uint64_t h = key_hash(key, seed);
   const KeyFields f = key_fields(h, log2b);
   enum { DIRECT, WALK, MOVE };
@@ -304,7 +436,8 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
       break;
     }
     if (state == DIRECT) {
-      const int r = insert_direct(bk, key, value, f, plain);
+      const int r = TIMED ? insert_direct_timed(bk, key, word, f, plain, now)
+                          : insert_direct(bk, key, value, f, plain);
       if (r >= 0)
         result = r;
       else if (r == kNeedPath)
@@ -339,8 +472,11 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
   return InsertOutcome{result, spun};
 }
 
-// Returns 1 if the key was removed, 0 if absent, kBusy to retry.
-__device__ int delete_direct(uint8_t *bk, uint4 key, const KeyFields &f, bool plain) {
+// Returns 1 if the key was removed, 0 if absent, kBusy to retry.  TIMED:
+// an expired entry of the key is removed too, but reports 0 (Sec. 4.2).
+template <bool TIMED>
+__device__ int delete_direct(uint8_t *bk, uint4 key, const KeyFields &f, bool plain,
+                             uint32_t now) {
   if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   int r = 0;
@@ -348,20 +484,20 @@ __device__ int delete_direct(uint8_t *bk, uint4 key, const KeyFields &f, bool pl
   const uint32_t mp = hp.q1.z;
   if (s >= 0) {
     const uint32_t bit = 1u << s;
+    r = (!TIMED || word_alive(*value_ptr(bk, f.p, (uint32_t)s), now)) ? 1 : 0;
     *meta_ptr(bk, f.p) = make_meta(meta_moved(mp), meta_busy(mp) & ~bit, meta_sec(mp) & ~bit);
-    r = 1;
   } else if (plain || bloom_pass(hp.q1, f.bloom_bits)) {
     const Head ha = read_head(bk, f.a);
     s = find_slot(bk, f.a, ha, key, f.tag);
     if (s >= 0) {
       const uint32_t bit = 1u << s, ma = ha.q1.z;
+      r = (!TIMED || word_alive(*value_ptr(bk, f.a, (uint32_t)s), now)) ? 1 : 0;
       *meta_ptr(bk, f.a) = make_meta(meta_moved(ma), meta_busy(ma) & ~bit, meta_sec(ma) & ~bit);
       if (!plain && meta_moved(mp) > 0u) {
         const uint32_t moved = meta_moved(mp) - 1u;
         if (moved == 0u) *bloom_ptr(bk, f.p) = 0ull;
         *meta_ptr(bk, f.p) = make_meta(moved, meta_busy(mp), meta_sec(mp));
       }
-      r = 1;
     }
   }
   unlock_two(bk, f.p, f.a);
@@ -371,14 +507,15 @@ __device__ int delete_direct(uint8_t *bk, uint4 key, const KeyFields &f, bool pl
 
 // Deletes one key: 1 if it was removed, 0 if absent; *spun is set when the
 // retry bound ran out (then 0 is returned).
+template <bool TIMED = false>
 __device__ int delete_one(uint8_t *bk, uint4 key, uint32_t log2b, uint64_t seed, bool plain,
-                          bool *spun) {
+                          bool *spun, uint32_t now = 0u) {
   const KeyFields f = key_fields(key_hash(key, seed), log2b);
   int r = kBusy;
   uint32_t iters = 0;
   while (r == kBusy && iters < kSpinLimit) {
     ++iters;
-    r = delete_direct(bk, key, f, plain);
+    r = delete_direct<TIMED>(bk, key, f, plain, now);
   }
   *spun = r == kBusy;
   return r == kBusy ? 0 : r;

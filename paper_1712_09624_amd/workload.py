@@ -36,6 +36,7 @@ STREAM_DELETE = 2
 STREAM_FRESH = 3
 STREAM_NEGATIVE = 4
 STREAM_TABLES = 5
+STREAM_TIMES = 6
 
 
 def raw_u64(seed: int, stream: int, n: int) -> np.ndarray:
@@ -193,3 +194,10 @@ def poisson_arrivals(n: int, rate: float, seed: int, stream: int) -> np.ndarray:
     rate, starting at the first inter-arrival gap."""
     u = uniform01(n, seed, stream)
     return np.cumsum(-np.log1p(-u) / rate)
+
+
+def times_after(n: int, now: int, width: int, seed: int, stream: int = STREAM_TIMES) -> np.ndarray:
+    """n 16-bit times uniform in [now, now + width) modulo 2^16 (expiration
+    times set some units ahead of a 16-bit clock)."""
+    r = raw_u64(seed, stream, n) % np.uint64(int(width))
+    return ((r + np.uint64(int(now))) & np.uint64(0xFFFF)).astype(np.uint16)
