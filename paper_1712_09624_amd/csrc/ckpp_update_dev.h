@@ -18,10 +18,12 @@
 //           the key's two bits in p's filter, moved[p] += 1) (INSERTED);
 //           else go to WALK.
 //   WALK    random walk over full buckets starting at p, reading without
-//           locks: at each bucket pick a victim -- preferably an entry that
-//           sits in its secondary bucket (it would move back home), then one
-//           whose other bucket is not the bucket just left -- and continue
-//           at the victim's other bucket, until one with a free slot, at most
+//           locks, with one step of lookahead: at each bucket, if the other
+//           bucket of some entry has a free slot, that entry (preferably one
+//           going home to its primary) ends the path; else pick a victim --
+//           preferably an entry that sits in its secondary bucket (it would
+//           move back home), then one whose other bucket is not the bucket
+//           just left -- and continue at the victim's other bucket, at most
 //           max_kicks steps; no (bucket, slot) twice.  No path: FAILED.
 //   MOVE    apply the path backwards, one displacement per iteration, each
 //           under the locks of its two buckets and re-validated there; a
@@ -321,9 +323,19 @@ __device__ __forceinline__ uint64_t load_relaxed(const uint8_t *p) {
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Random walk from bucket `start` (read without locks).  path[i] holds
-// bucket | slot << 24 of the i-th victim; *last receives the bucket with a
-// free slot that ends the path.  Returns the path length, or -1.
+// Random walk with one step of lookahead from bucket `start` (read without
+// locks).  At each full bucket the other buckets of all its candidate
+// entries are looked at together (their metadata words, loaded in
+// parallel): if one of them has a free slot, moving that entry there ends
+// the path (an entry sitting in its secondary bucket, i.e. going home,
+// preferred); otherwise a victim is drawn as in a plain random walk (an
+// entry going home, then one whose other bucket is not the bucket just
+// left, then any) and the walk continues at its other bucket.  The same
+// two memory round trips per step as a plain walk, but far fewer steps: at
+// load 0.9 the longest paths shrink from tens of displacements to a few.
+// path[i] holds bucket | slot << 24 of the i-th victim; *last receives the
+// bucket with a free slot that ends the path.  Returns the path length, or
+// -1.
 __device__ int walk(const uint8_t *bk, uint32_t start, uint64_t rbase, uint32_t max_kicks,
                     bool plain, uint32_t *path, uint32_t *last) {
   uint32_t cur = start, prev = kNoBucket;
@@ -345,24 +357,34 @@ __device__ int walk(const uint8_t *bk, uint32_t start, uint64_t rbase, uint32_t 
     const uint32_t sec = meta_sec(meta);
     uint32_t cand = meta_busy(meta) & ~used;
     if (!plain && meta_moved(meta) >= 0xffffu) cand &= sec;  // no owner may leave
+    if (!cand) return -1;
+    // lookahead: which candidates' other buckets have a free slot
+    uint32_t room = 0;
+#pragma unroll
+    for (uint32_t s = 0; s < kSlots; ++s) {
+      if ((cand >> s) & 1u) {
+        const uint32_t om = (uint32_t)load_relaxed(bucket_ptr(bk, other[s]) + kMetaOffset);
+        if (meta_busy(om) != 0xffu) room |= 1u << s;
+      }
+    }
+    const uint64_t r = mix64(rbase + (uint64_t)(step + 1) * 0x9e3779b97f4a7c15ull);
+    if (room) {
+      const uint32_t pick = (room & sec) ? (room & sec) : room;
+      const uint32_t v = nth_bit(pick, (uint32_t)(r % (uint64_t)__builtin_popcount(pick)));
+      path[step] = cur | (v << 24);
+      *last = other[v];
+      return (int)step + 1;
+    }
     uint32_t pref = 0;
 #pragma unroll
     for (uint32_t s = 0; s < kSlots; ++s)
       if (((cand >> s) & 1u) && other[s] != prev) pref |= 1u << s;
     const uint32_t home = pref & sec;
     const uint32_t pick = home ? home : (pref ? pref : cand);
-    if (!pick) return -1;
-    const uint64_t r = mix64(rbase + (uint64_t)(step + 1) * 0x9e3779b97f4a7c15ull);
     const uint32_t v = nth_bit(pick, (uint32_t)(r % (uint64_t)__builtin_popcount(pick)));
     path[step] = cur | (v << 24);
-    const uint32_t nxt = other[v];
-    const uint32_t nmeta = (uint32_t)load_relaxed(bucket_ptr(bk, nxt) + kMetaOffset);
-    if (meta_busy(nmeta) != 0xffu) {
-      *last = nxt;
-      return (int)step + 1;
-    }
     prev = cur;
-    cur = nxt;
+    cur = other[v];
   }
   return -1;
 }
