@@ -544,9 +544,9 @@ def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
     out["plan_tuned_shape"] = ranked[0][1]
     out["plan_tune_top"] = [{"us": r[0] * 1e3, **r[1]} for r in ranked[:8]]
     best_of = {}
-    for ms_, sh in ranked:  # fastest shape per (lookups per lane, schedule)
-        best_of.setdefault(f"per{sh['lookups_per_lane']}_sched{sh['schedule']}",
-                           {"us": ms_ * 1e3, **sh})
+    for ms_, sh in ranked:  # fastest shape per (lanes per lookup, lookups per lane, schedule)
+        best_of.setdefault(f"lanes{sh['lanes_per_lookup']}_per{sh['lookups_per_lane']}"
+                           f"_sched{sh['schedule']}", {"us": ms_ * 1e3, **sh})
     out["plan_tune_best_of"] = best_of
     plan.lookup(keys_d, found, vals_d)
     check("plan (tuned shape)")

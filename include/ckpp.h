@@ -262,18 +262,22 @@ typedef struct {
 
 int ckpp_info(const ckpp_table *t, ckpp_info_t *out);
 
-/* Launch shape of the lookup kernel.  Each lane owns one lookup; the line
- * of a bucket is read by a group of lanes_per_lookup = 8 neighbouring lanes
- * (16 bytes each, one 128-byte request) straight into LDS, and each lane
- * then analyses its own line there.  lookups_per_lane: 1, or 2 (each lane
- * owns two lookups; the lines of the second half land in registers and are
- * parked in LDS after the first half is analysed: twice the requests in
- * flight; the pessimistic mode always uses 1); block: 64, 128 or 256 (1, 2
- * or 4 wavefronts, 8 KiB of LDS each, 16 KiB for the pessimistic mode);
- * blocks_per_cu: grid size in blocks per compute unit (0: enough blocks to
- * cover the batch in one pass).  Applies to every later lookup on t.  A new
- * table starts with {8, 2, 128, 0}, the fastest shape on 2^20..2^24-bucket
- * tables at load 0.9. */
+/* Launch shape of the lookup kernel.  lanes_per_lookup 8: each lane owns
+ * one lookup; the line of a bucket is read by a group of 8 neighbouring
+ * lanes (16 bytes each, one 128-byte request) straight into LDS, and each
+ * lane then analyses its own line there; lookups_per_lane 1, or 2 (each
+ * lane owns two lookups; the lines of the second half land in registers
+ * and are parked in LDS after the first half is analysed: twice the
+ * requests in flight; the pessimistic mode always uses 1).
+ * lanes_per_lookup 1: each lane reads the 32-byte head of its own bucket
+ * (tags, filter, masks) into registers, and a candidate's key and value
+ * only on a tag match; lookups_per_lane 1, 2 or 4; no LDS.
+ * block: 64, 128 or 256 (1, 2 or 4 wavefronts; with 8 lanes, 8 KiB of LDS
+ * each, 16 KiB for the pessimistic mode); blocks_per_cu: grid size in
+ * blocks per compute unit (0: enough blocks to cover the batch in one
+ * pass).  Applies to every later lookup on t.  A new table starts with
+ * {8, 2, 128, 0}, the fastest shape on 2^20..2^24-bucket tables at load
+ * 0.9.  Errors: CKPP_EINVAL (a shape outside these sets). */
 typedef struct {
     uint32_t lanes_per_lookup;
     uint32_t lookups_per_lane;
@@ -294,13 +298,15 @@ int ckpp_get_lookup_launch(const ckpp_table *t, ckpp_launch_t *cfg);
  * results are those of one ckpp_lookup_batch call per table. */
 typedef struct ckpp_plan ckpp_plan;
 
-/* Launch shape of a plan's kernel.  lookups_per_lane: 1 or 2 (as in
+/* Launch shape of a plan's kernel.  lookups_per_lane: 1 or 2 with
+ * lanes_per_lookup 8, 1, 2 or 4 with lanes_per_lookup 1 (as in
  * ckpp_launch_t); block: 64, 128 or 256; blocks_per_cu: 1..64, the
  * persistent grid is blocks_per_cu blocks per compute unit (at most one
  * wavefront per work item); passes_per_item: 1..64; schedule:
  * CKPP_PLAN_STATIC (wavefront w runs items w, w + W, ... for W wavefronts)
  * or CKPP_PLAN_DYNAMIC (each wavefront takes the next item from a device
- * counter). */
+ * counter); lanes_per_lookup: 8 (a bucket line read by 8 lanes into LDS)
+ * or 1 (each lane reads its bucket's head into registers). */
 enum { CKPP_PLAN_STATIC = 0, CKPP_PLAN_DYNAMIC = 1 };
 
 typedef struct {
@@ -309,6 +315,7 @@ typedef struct {
     uint32_t blocks_per_cu;
     uint32_t passes_per_item;
     uint32_t schedule;
+    uint32_t lanes_per_lookup;
 } ckpp_plan_launch_t;
 
 typedef struct {
@@ -327,7 +334,7 @@ typedef struct {
  * The plan keeps the tables' device addresses, not the tables: it must be
  * destroyed before any of them, and inserts and deletes between plan
  * lookups are seen by the next one.  Host arrays are read during the call
- * only.  Starts with the launch shape {1, 128, 8, 1, CKPP_PLAN_STATIC}.
+ * only.  Starts with the launch shape {1, 128, 8, 1, CKPP_PLAN_STATIC, 8}.
  * Errors: CKPP_EINVAL (null arguments, ntables 0, overlapping ranges, bad
  * mode, tables on different devices), CKPP_ENOMEM, CKPP_EDEVICE. */
 int ckpp_plan_create(ckpp_plan **out, ckpp_table *const *tables, uint32_t ntables,

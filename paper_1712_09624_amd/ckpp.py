@@ -32,6 +32,8 @@ DEFAULT_LAUNCH = {"lanes_per_lookup": 8, "lookups_per_lane": 2, "block": 128, "b
 
 def lookup_kernel_name(launch: dict, mode: str = "cuckoopp") -> str:
     """Name of the lookup kernel a launch shape selects for a lookup mode."""
+    if launch["lanes_per_lookup"] == 1:
+        return "lookup_reg"
     if launch["lookups_per_lane"] == 2 and mode != "both":
         return "lookup_dual"
     return "lookup_lds"
@@ -86,6 +88,7 @@ class _PlanLaunch(ctypes.Structure):
         ("blocks_per_cu", ctypes.c_uint32),
         ("passes_per_item", ctypes.c_uint32),
         ("schedule", ctypes.c_uint32),
+        ("lanes_per_lookup", ctypes.c_uint32),
     ]
 
 
@@ -148,7 +151,7 @@ SERVER_STOPPED, SERVER_RUNNING, SERVER_EXITING, SERVER_ABORTED = 0, 1, 2, 3
 # launch shape a new plan starts with (ckpp_plan_create sets the same)
 PLAN_STATIC, PLAN_DYNAMIC = 0, 1
 DEFAULT_PLAN_LAUNCH = {"lookups_per_lane": 1, "block": 128, "blocks_per_cu": 8,
-                       "passes_per_item": 1, "schedule": PLAN_STATIC}
+                       "passes_per_item": 1, "schedule": PLAN_STATIC, "lanes_per_lookup": 8}
 
 _lib = None
 
@@ -537,8 +540,10 @@ class Plan:
                    block=DEFAULT_PLAN_LAUNCH["block"],
                    blocks_per_cu=DEFAULT_PLAN_LAUNCH["blocks_per_cu"],
                    passes_per_item=DEFAULT_PLAN_LAUNCH["passes_per_item"],
-                   schedule=DEFAULT_PLAN_LAUNCH["schedule"]):
-        cfg = _PlanLaunch(lookups_per_lane, block, blocks_per_cu, passes_per_item, schedule)
+                   schedule=DEFAULT_PLAN_LAUNCH["schedule"],
+                   lanes_per_lookup=DEFAULT_PLAN_LAUNCH["lanes_per_lookup"]):
+        cfg = _PlanLaunch(lookups_per_lane, block, blocks_per_cu, passes_per_item, schedule,
+                          lanes_per_lookup)
         _check(self.lib.ckpp_plan_set_launch(self._h, ctypes.byref(cfg)), "ckpp_plan_set_launch")
 
     def get_launch(self) -> dict:

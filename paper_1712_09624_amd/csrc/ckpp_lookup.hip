@@ -82,6 +82,38 @@ __global__ void __launch_bounds__(64 * WAVES)
   }
 }
 
+// One table's batch, one lane per lookup with lines in registers, PER
+// lookups per lane per pass (lookups w0 + 64 j + lane of the wave's tile).
+template <uint32_t WAVES, uint32_t MODE, bool TIMED, uint32_t PER>
+__global__ void __launch_bounds__(64 * WAVES)
+    lookup_reg(TableRef T, const uint4 *__restrict__ keys, uint64_t n,
+               uint8_t *__restrict__ found, uint64_t *__restrict__ vals) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wave0 = ((uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 64u * PER;
+  const uint64_t stride = (uint64_t)gridDim.x * WAVES * 64u * PER;
+  uint4 k[PER];
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    const uint64_t i = wave0 + 64u * j + lane;
+    k[j] = i < n ? load_stream(keys + i) : zero4();
+  }
+  for (uint64_t w0 = wave0; w0 < n; w0 += stride) {
+    bool ok[PER];
+    uint4 kn[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) ok[j] = w0 + 64u * j + lane < n;
+    reg_pass<MODE, TIMED, PER>(T, k, ok, found + w0 + lane, vals + w0 + lane, [&] {
+#pragma unroll
+      for (uint32_t j = 0; j < PER; ++j) {
+        const uint64_t i = w0 + stride + 64u * j + lane;
+        kn[j] = i < n ? load_stream(keys + i) : zero4();
+      }
+    });
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) k[j] = kn[j];
+  }
+}
+
 // The wave's next work item: lane 0 takes a ticket from the plan's counter
 // and the wave shares it.
 __device__ __forceinline__ uint32_t take_item(uint32_t *ctr, uint32_t lane) {
@@ -100,13 +132,15 @@ __device__ __forceinline__ uint32_t next_item(uint32_t prev, uint32_t stride, ui
   return DYN ? take_item(ctr, lane) : prev + stride;
 }
 
-// Keys of one pass of an item: lookups off + lane (and off + 64 + lane).
+// Keys of one pass of an item: lookups off + 64 j + lane.
 template <uint32_t PER>
 __device__ __forceinline__ void item_keys(const uint4 *keys, const PlanItem &I, uint32_t off,
-                                          uint32_t lane, uint4 &ka, uint4 &kb) {
-  const uint32_t o = off + lane;
-  ka = o < I.count ? load_stream(keys + I.start + o) : zero4();
-  if (PER == 2) kb = o + 64u < I.count ? load_stream(keys + I.start + o + 64u) : zero4();
+                                          uint32_t lane, uint4 (&k)[PER]) {
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    const uint32_t o = off + 64u * j + lane;
+    k[j] = o < I.count ? load_stream(keys + I.start + o) : zero4();
+  }
 }
 
 // A plan's batches in one persistent launch.  Each wave runs work items (a
@@ -118,17 +152,22 @@ __device__ __forceinline__ void item_keys(const uint4 *keys, const PlanItem &I, 
 // are in flight.  DYN: items are handed out by a device counter (the wave
 // that finishes last rewinds it, so the next launch or graph replay starts
 // from zero without a memory set); else wave w runs items w, w + W, ...
-// NB = 2 gives each wave the second line buffer of the pessimistic mode;
-// with NB = 1 the host passes no pessimistic item.
-template <uint32_t WAVES, uint32_t NB, uint32_t PER, bool DYN>
+// LANES = 8: lines land in LDS (the passes of lookup_lds / lookup_dual,
+// PER 1 or 2); NB = 2 gives each wave the second line buffer of the
+// pessimistic mode, and with NB = 1 the host passes no pessimistic item.
+// LANES = 1: bucket heads in registers (the passes of lookup_reg, PER 1, 2
+// or 4, every mode, no LDS).
+template <uint32_t WAVES, uint32_t NB, uint32_t PER, bool DYN, uint32_t LANES>
 __global__ void __launch_bounds__(64 * WAVES)
     lookup_plan(const PlanItem *__restrict__ items, uint32_t nitems,
                 const uint4 *__restrict__ keys, uint8_t *__restrict__ found,
                 uint64_t *__restrict__ vals, uint32_t *__restrict__ ctr) {
+  static_assert(LANES == 1 || PER <= 2, "lines in LDS: one or two lookups per lane");
   constexpr uint32_t P = 64u * PER;  // lookups per pass
-  __shared__ uint4 s_lines[WAVES * NB * kWaveQuarters];
-  const Wave w = wave_lines<NB>(s_lines);
-  const uint32_t lane = w.lane;
+  __shared__ uint4 s_lines[LANES == 8 ? WAVES * NB * kWaveQuarters : 1];
+  Wave w;
+  if constexpr (LANES == 8) w = wave_lines<NB>(s_lines);
+  const uint32_t lane = threadIdx.x & 63u;
   const uint32_t stride = gridDim.x * WAVES;
   const uint32_t wave_id =
       (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * WAVES + (threadIdx.x >> 6)));
@@ -138,50 +177,62 @@ __global__ void __launch_bounds__(64 * WAVES)
   const PlanItem none{nullptr, 0ull, 0ull, 0u, 0u, 0u, 0u};
   PlanItem I = cur < nitems ? items[cur] : none;
   PlanItem I1 = n1 < nitems ? items[n1] : none;
-  uint4 ka = zero4(), kb = zero4();
-  if (cur < nitems) item_keys<PER>(keys, I, 0u, lane, ka, kb);
+  uint4 k[PER];
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) k[j] = zero4();
+  if (cur < nitems) item_keys<PER>(keys, I, 0u, lane, k);
   while (cur < nitems) {
     const TableRef T{I.tab, I.seed, I.log2b};
     PlanItem I2 = none;
     uint32_t n3 = n2;
     for (uint32_t off = 0u; off < I.count; off += P) {
       const bool last = off + P >= I.count;
-      uint4 na = zero4(), nb = zero4();
+      uint4 kn[PER];
+#pragma unroll
+      for (uint32_t j = 0; j < PER; ++j) kn[j] = zero4();
       auto pre = [&] {
         if (!last) {
-          item_keys<PER>(keys, I, off + P, lane, na, nb);
+          item_keys<PER>(keys, I, off + P, lane, kn);
         } else {
-          if (n1 < nitems) item_keys<PER>(keys, I1, 0u, lane, na, nb);
+          if (n1 < nitems) item_keys<PER>(keys, I1, 0u, lane, kn);
           if (n2 < nitems) I2 = items[n2];
           n3 = next_item<DYN>(n2, stride, nitems, ctr, lane);
         }
       };
       const uint64_t ia = I.start + off + lane;
-      const bool oka = off + lane < I.count;
-      if (PER == 1) {
+      bool ok[PER];
+#pragma unroll
+      for (uint32_t j = 0; j < PER; ++j) ok[j] = off + 64u * j + lane < I.count;
+      if constexpr (LANES == 1) {
+        if (I.mode == kModeCuckoopp)
+          reg_pass<kModeCuckoopp, false, PER>(T, k, ok, found + ia, vals + ia, pre);
+        else if (I.mode == kModeOptimistic)
+          reg_pass<kModeOptimistic, false, PER>(T, k, ok, found + ia, vals + ia, pre);
+        else
+          reg_pass<kModeBoth, false, PER>(T, k, ok, found + ia, vals + ia, pre);
+      } else if constexpr (PER == 1) {
         if (I.mode == kModeCuckoopp) {
-          lds_pass<kModeCuckoopp>(w, T, ka, oka, found + ia, vals + ia, pre);
+          lds_pass<kModeCuckoopp>(w, T, k[0], ok[0], found + ia, vals + ia, pre);
         } else if (I.mode == kModeOptimistic) {
-          lds_pass<kModeOptimistic>(w, T, ka, oka, found + ia, vals + ia, pre);
+          lds_pass<kModeOptimistic>(w, T, k[0], ok[0], found + ia, vals + ia, pre);
         } else if (NB == 2) {
-          lds_pass<kModeBoth>(w, T, ka, oka, found + ia, vals + ia, pre);
+          lds_pass<kModeBoth>(w, T, k[0], ok[0], found + ia, vals + ia, pre);
         }
       } else {
         const uint64_t ib = ia + 64u;
-        const bool okb = off + 64u + lane < I.count;
         if (I.mode == kModeCuckoopp) {
-          dual_pass<kModeCuckoopp>(w, T, ka, oka, kb, okb, found + ia, vals + ia, found + ib,
-                                   vals + ib, pre);
+          dual_pass<kModeCuckoopp>(w, T, k[0], ok[0], k[1], ok[1], found + ia, vals + ia,
+                                   found + ib, vals + ib, pre);
         } else if (I.mode == kModeOptimistic) {
-          dual_pass<kModeOptimistic>(w, T, ka, oka, kb, okb, found + ia, vals + ia, found + ib,
-                                     vals + ib, pre);
+          dual_pass<kModeOptimistic>(w, T, k[0], ok[0], k[1], ok[1], found + ia, vals + ia,
+                                     found + ib, vals + ib, pre);
         } else if (NB == 2) {
-          lds_pass<kModeBoth>(w, T, ka, oka, found + ia, vals + ia, [] {});
-          lds_pass<kModeBoth>(w, T, kb, okb, found + ib, vals + ib, pre);
+          lds_pass<kModeBoth>(w, T, k[0], ok[0], found + ia, vals + ia, [] {});
+          lds_pass<kModeBoth>(w, T, k[1], ok[1], found + ib, vals + ib, pre);
         }
       }
-      ka = na;
-      kb = nb;
+#pragma unroll
+      for (uint32_t j = 0; j < PER; ++j) k[j] = kn[j];
     }
     cur = n1;
     I = I1;
@@ -210,10 +261,27 @@ uint64_t capped_grid(uint64_t n, uint64_t per_block, uint32_t blocks_per_cu, int
   return grid > 0x7fffffffull ? 0x7fffffffull : grid;
 }
 
+template <uint32_t WAVES, uint32_t MODE, bool TIMED, uint32_t PER>
+hipError_t launch_reg(const ckpp_table *t, const TableRef &T, const uint4 *keys, uint64_t n,
+                      uint8_t *found, uint64_t *vals, hipStream_t s) {
+  const uint64_t grid =
+      capped_grid(n, 64ull * PER * WAVES, t->lookup_launch.blocks_per_cu, t->num_cus);
+  hipLaunchKernelGGL((lookup_reg<WAVES, MODE, TIMED, PER>), dim3((uint32_t)grid),
+                     dim3(64 * WAVES), 0, s, T, keys, n, found, vals);
+  return hipGetLastError();
+}
+
 template <uint32_t WAVES, uint32_t MODE, bool TIMED>
 hipError_t launch_shape(const ckpp_table *t, const TableRef &T, const uint4 *keys, uint64_t n,
                         uint8_t *found, uint64_t *vals, hipStream_t s) {
   const ckpp_launch_t &L = t->lookup_launch;
+  if (L.lanes_per_lookup == 1) {
+    if (L.lookups_per_lane == 4)
+      return launch_reg<WAVES, MODE, TIMED, 4>(t, T, keys, n, found, vals, s);
+    if (L.lookups_per_lane == 2)
+      return launch_reg<WAVES, MODE, TIMED, 2>(t, T, keys, n, found, vals, s);
+    return launch_reg<WAVES, MODE, TIMED, 1>(t, T, keys, n, found, vals, s);
+  }
   if (MODE != kModeBoth && L.lookups_per_lane == 2) {
     constexpr uint32_t M = MODE == kModeBoth ? kModeCuckoopp : MODE;
     const uint64_t grid = capped_grid(n, 128ull * WAVES, L.blocks_per_cu, t->num_cus);
@@ -246,17 +314,17 @@ hipError_t launch_timing(const ckpp_table *t, const TableRef &T, const uint4 *ke
   return launch_mode<kModeCuckoopp, TIMED>(t, T, keys, n, found, vals, s);
 }
 
-template <uint32_t WAVES, uint32_t NB, uint32_t PER>
+template <uint32_t WAVES, uint32_t NB, uint32_t PER, uint32_t LANES>
 hipError_t launch_plan_shape(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr,
                              const ckpp_plan_launch_t &L, int num_cus, const uint4 *keys,
                              uint8_t *found, uint64_t *vals, hipStream_t s) {
   // persistent grid: blocks_per_cu per CU, but no more waves than items
   const uint64_t grid = capped_grid(nitems, WAVES, L.blocks_per_cu, num_cus);
   if (L.schedule == CKPP_PLAN_DYNAMIC)
-    hipLaunchKernelGGL((lookup_plan<WAVES, NB, PER, true>), dim3((uint32_t)grid), dim3(64 * WAVES),
-                       0, s, d_items, nitems, keys, found, vals, d_ctr);
+    hipLaunchKernelGGL((lookup_plan<WAVES, NB, PER, true, LANES>), dim3((uint32_t)grid),
+                       dim3(64 * WAVES), 0, s, d_items, nitems, keys, found, vals, d_ctr);
   else
-    hipLaunchKernelGGL((lookup_plan<WAVES, NB, PER, false>), dim3((uint32_t)grid),
+    hipLaunchKernelGGL((lookup_plan<WAVES, NB, PER, false, LANES>), dim3((uint32_t)grid),
                        dim3(64 * WAVES), 0, s, d_items, nitems, keys, found, vals, d_ctr);
   return hipGetLastError();
 }
@@ -265,15 +333,28 @@ template <uint32_t WAVES>
 hipError_t launch_plan_waves(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr,
                              bool two_buffers, const ckpp_plan_launch_t &L, int num_cus,
                              const uint4 *keys, uint8_t *found, uint64_t *vals, hipStream_t s) {
+  if (L.lanes_per_lookup == 1) {
+    if (L.lookups_per_lane == 4)
+      return launch_plan_shape<WAVES, 1, 4, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found,
+                                               vals, s);
+    if (L.lookups_per_lane == 2)
+      return launch_plan_shape<WAVES, 1, 2, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found,
+                                               vals, s);
+    return launch_plan_shape<WAVES, 1, 1, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found,
+                                             vals, s);
+  }
   if (two_buffers) {
     if (L.lookups_per_lane == 2)
-      return launch_plan_shape<WAVES, 2, 2>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals,
-                                            s);
-    return launch_plan_shape<WAVES, 2, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals, s);
+      return launch_plan_shape<WAVES, 2, 2, 8>(d_items, nitems, d_ctr, L, num_cus, keys, found,
+                                               vals, s);
+    return launch_plan_shape<WAVES, 2, 1, 8>(d_items, nitems, d_ctr, L, num_cus, keys, found,
+                                             vals, s);
   }
   if (L.lookups_per_lane == 2)
-    return launch_plan_shape<WAVES, 1, 2>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals, s);
-  return launch_plan_shape<WAVES, 1, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals, s);
+    return launch_plan_shape<WAVES, 1, 2, 8>(d_items, nitems, d_ctr, L, num_cus, keys, found,
+                                             vals, s);
+  return launch_plan_shape<WAVES, 1, 1, 8>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals,
+                                           s);
 }
 
 }  // namespace

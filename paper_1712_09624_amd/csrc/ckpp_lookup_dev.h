@@ -319,5 +319,133 @@ __device__ __forceinline__ void dual_pass(const Wave &w, const TableRef &T, uint
   }
 }
 
+// ---- One lane per lookup, lines in registers -----------------------------
+// Each lane fetches the 32-byte head of its own bucket (tags, filter, masks:
+// two 16-byte loads of the first line, one memory request) into registers,
+// and only for tag matches the candidate's key and value word (the same
+// line for slots 0..3, the second for 4..7).  A negative lookup keeps 8
+// registers per lookup in flight and no LDS, so a lane can own PER lookups
+// and a compute unit keeps far more lines in flight than with lines landing
+// in LDS; a positive lookup reads its line twice (head, then key), which
+// costs a second request when the line has left the L2 in between.
+
+template <uint32_t PER>
+struct RegLooks {
+  uint4 key[PER];
+  KeyFields f[PER];
+  uint4 h0[PER], h1[PER];  // head of the bucket being probed
+  uint32_t cand[PER], slot[PER];
+  bool ok[PER], hit[PER], pass[PER], hit_primary[PER];
+  uint64_t val[PER];
+};
+
+__device__ __forceinline__ const uint8_t *bucket_bytes(const uint4 *tab, uint32_t b) {
+  return reinterpret_cast<const uint8_t *>(tab) + (uint64_t)b * kBucketBytes;
+}
+
+// Probes the candidates of every lookup (ascending slot order), one
+// candidate per lookup per round trip, until each has a hit or none left.
+template <bool TIMED, uint32_t PER>
+__device__ __forceinline__ void reg_match(const uint4 *tab, RegLooks<PER> &L, const uint32_t *b,
+                                          uint32_t now) {
+  for (;;) {
+    uint4 k[PER];
+    uint64_t w[PER];
+    uint32_t s[PER];
+    bool any = false;
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+      s[j] = kSlots;
+      if (L.cand[j] != 0u && !L.hit[j]) {
+        s[j] = (uint32_t)__builtin_ctz(L.cand[j]);
+        L.cand[j] &= L.cand[j] - 1u;
+        const uint8_t *base = bucket_bytes(tab, b[j]);
+        const uint32_t ko = s[j] < 4u ? 32u + 16u * s[j] : 128u + 16u * (s[j] - 4u);
+        const uint32_t vo = s[j] < 4u ? 96u + 8u * s[j] : 192u + 8u * (s[j] - 4u);
+        k[j] = *reinterpret_cast<const uint4 *>(base + ko);
+        w[j] = *reinterpret_cast<const uint64_t *>(base + vo);
+        any = true;
+      }
+    }
+    if (!any) break;
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j)
+      if (s[j] < kSlots && key_eq(k[j], L.key[j]))
+        take_word<TIMED>(w[j], s[j], now, L.hit[j], L.val[j], L.slot[j]);
+  }
+}
+
+// One pass of a wave over 64 * PER lookups: lookup j of lane l is lookup
+// 64 j + l of the tile, its results at found[64 j] / vals[64 j] (the
+// caller offsets both by the lane).  `pre` runs once the first heads are
+// requested.
+template <uint32_t MODE, bool TIMED, uint32_t PER, class Pre>
+__device__ __forceinline__ void reg_pass(const TableRef &T, const uint4 (&key)[PER],
+                                         const bool (&ok)[PER], uint8_t *found, uint64_t *vals,
+                                         Pre &&pre) {
+  RegLooks<PER> L;
+  uint32_t b[PER];
+  uint4 g0[PER], g1[PER];  // pessimistic mode: head of the secondary, fetched with the primary
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    L.key[j] = key[j];
+    L.ok[j] = ok[j];
+    L.hit[j] = false;
+    L.val[j] = 0ull;
+    L.slot[j] = 0u;
+    L.f[j] = key_fields(key_hash(key[j], T.seed), T.log2b);
+    L.h0[j] = L.h1[j] = g0[j] = g1[j] = zero4();
+    if (ok[j]) {
+      const uint4 *q = T.tab + (uint64_t)L.f[j].p * kQuartersPerBucket;
+      L.h0[j] = q[0];
+      L.h1[j] = q[1];
+      if (MODE == kModeBoth) {
+        const uint4 *r = T.tab + (uint64_t)L.f[j].a * kQuartersPerBucket;
+        g0[j] = r[0];
+        g1[j] = r[1];
+      }
+    }
+  }
+  pre();
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    L.cand[j] = L.ok[j] ? (tag_eq_mask(L.h0[j], L.f[j].tag) & meta_busy(L.h1[j].z)) : 0u;
+    L.pass[j] = MODE != kModeCuckoopp || bloom_pass(L.h1[j], L.f[j].bloom_bits);
+    b[j] = L.f[j].p;
+  }
+  reg_match<TIMED, PER>(T.tab, L, b, T.now);
+  bool need_any = false;
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    L.hit_primary[j] = L.hit[j];
+    const bool need = L.ok[j] && !L.hit[j] && L.pass[j];
+    L.cand[j] = 0u;
+    b[j] = L.f[j].a;
+    if (need) {
+      if (MODE != kModeBoth) {
+        const uint4 *q = T.tab + (uint64_t)L.f[j].a * kQuartersPerBucket;
+        g0[j] = q[0];
+        g1[j] = q[1];
+      }
+      need_any = true;
+    }
+    L.pass[j] = need;
+  }
+  if (need_any) {
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j)
+      if (L.pass[j]) L.cand[j] = tag_eq_mask(g0[j], L.f[j].tag) & meta_busy(g1[j].z);
+    reg_match<TIMED, PER>(T.tab, L, b, T.now);
+  }
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    if (!L.ok[j]) continue;
+    if (TIMED && T.refresh && L.hit[j])
+      refresh_entry(T, L.hit_primary[j] ? L.f[j].p : L.f[j].a, L.slot[j]);
+    __builtin_nontemporal_store((uint8_t)(L.hit[j] ? 1 : 0), found + 64u * j);
+    __builtin_nontemporal_store(L.hit[j] ? L.val[j] : 0ull, vals + 64u * j);
+  }
+}
+
 }  // namespace
 }  // namespace ckpp

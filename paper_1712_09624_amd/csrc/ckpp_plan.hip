@@ -32,7 +32,10 @@ namespace {
 bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 bool valid_launch(const ckpp_plan_launch_t &L) {
-  return (L.lookups_per_lane == 1 || L.lookups_per_lane == 2) &&
+  const bool lanes_ok = L.lanes_per_lookup == 1 || L.lanes_per_lookup == 8;
+  const bool per_ok = L.lookups_per_lane == 1 || L.lookups_per_lane == 2 ||
+                      (L.lookups_per_lane == 4 && L.lanes_per_lookup == 1);
+  return lanes_ok && per_ok &&
          (L.block == 64 || L.block == 128 || L.block == 256) && L.blocks_per_cu >= 1 &&
          L.blocks_per_cu <= 64 && L.passes_per_item >= 1 && L.passes_per_item <= 64 &&
          (L.schedule == CKPP_PLAN_STATIC || L.schedule == CKPP_PLAN_DYNAMIC);
@@ -140,7 +143,7 @@ int ckpp_plan_create(ckpp_plan **out, ckpp_table *const *tables, uint32_t ntable
     free_plan(p);
     return dev_status(e);
   }
-  const ckpp_plan_launch_t L{1u, 128u, 8u, 1u, CKPP_PLAN_STATIC};
+  const ckpp_plan_launch_t L{1u, 128u, 8u, 1u, CKPP_PLAN_STATIC, 8u};
   const int rc = build_items(p, L);
   if (rc != CKPP_OK) {
     free_plan(p);

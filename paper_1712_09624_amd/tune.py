@@ -1,7 +1,8 @@
 """Launch-shape autotuner of the lookup kernels and of plans.
 
-Times every lookup launch shape (lanes per lookup, lookups in flight per
-lane, block size, grid cap) on a caller's table and key batches, and returns
+Times every lookup launch shape (lanes per lookup: 8, lines landing in LDS,
+or 1, bucket heads in registers; lookups in flight per lane, block size,
+grid cap) on a caller's table and key batches, and returns
 the shapes ranked by lookups per second.  Timing uses device events on the
 current stream; the answers do not depend on the shape (the parity tests
 check every shape), only the speed does.
@@ -14,6 +15,9 @@ import itertools
 SHAPES = [
     {"lanes_per_lookup": lanes, "lookups_per_lane": per, "block": block, "blocks_per_cu": bpc}
     for lanes, per, block, bpc in itertools.product((8,), (1, 2), (64, 128, 256), (0, 5, 10))
+] + [
+    {"lanes_per_lookup": 1, "lookups_per_lane": per, "block": block, "blocks_per_cu": bpc}
+    for per, block, bpc in itertools.product((1, 2, 4), (64, 128, 256), (0, 8, 16))
 ]
 
 
@@ -56,14 +60,15 @@ def tune(table, batches, mode="cuckoopp", shapes=None, reps=3, apply=True):
     return results
 
 
-# Launch shapes of a plan's persistent kernel: lookups per lane, block size,
+# Launch shapes of a plan's persistent kernel: lanes per lookup (8: lines in
+# LDS, 1: bucket heads in registers) with lookups per lane, block size,
 # blocks per compute unit (persistent grid), lookup passes per work item and
 # schedule (0 static, 1 dynamic).
 PLAN_SHAPES = [
     {"lookups_per_lane": per, "block": block, "blocks_per_cu": bpc, "passes_per_item": passes,
-     "schedule": sched}
-    for per, block, bpc, passes, sched in itertools.product((1, 2), (64, 128, 256), (2, 4, 8, 16),
-                                                            (1, 2, 4), (0, 1))
+     "schedule": sched, "lanes_per_lookup": lanes}
+    for (lanes, per), block, bpc, passes, sched in itertools.product(
+        ((8, 1), (8, 2), (1, 1), (1, 2), (1, 4)), (64, 128, 256), (2, 4, 8, 16), (1, 2, 4), (0, 1))
 ]
 
 
@@ -90,10 +95,10 @@ def tune_plan(plan, keys, found, values, shapes=None, reps=5, apply=True):
     results = []
     for sh in shapes:
         plan.set_launch(sh["lookups_per_lane"], sh["block"], sh["blocks_per_cu"],
-                        sh["passes_per_item"], sh["schedule"])
+                        sh["passes_per_item"], sh["schedule"], sh["lanes_per_lookup"])
         results.append((time_plan(plan, keys, found, values, reps), dict(sh)))
     results.sort(key=lambda r: r[0])
     best = results[0][1] if apply else before
     plan.set_launch(best["lookups_per_lane"], best["block"], best["blocks_per_cu"],
-                    best["passes_per_item"], best["schedule"])
+                    best["passes_per_item"], best["schedule"], best["lanes_per_lookup"])
     return results

@@ -63,6 +63,11 @@ def test_argument_checks_need_no_device(lib):
     assert lib.ckpp_insert_batch(None, None, None, 5, None, None, None) == ckpp.EINVAL
     assert lib.ckpp_lookup_batch(None, None, 5, 0, None, None, None) == ckpp.EINVAL
     assert lib.ckpp_delete_batch(None, None, 5, None, None) == ckpp.EINVAL
+    assert lib.ckpp_insert_batch_at(None, None, None, None, 5, 0, None, None, None) == ckpp.EINVAL
+    assert lib.ckpp_lookup_batch_at(None, None, 5, 0, 0, 0, 0, None, None, None) == ckpp.EINVAL
+    assert lib.ckpp_delete_batch_at(None, None, 5, 0, None, None) == ckpp.EINVAL
+    assert lib.ckpp_expire_scan(None, 0, None, None) == ckpp.EINVAL
+    assert lib.ckpp_set_lookup_launch(None, None) == ckpp.EINVAL
     assert lib.ckpp_destroy(None) == ckpp.OK
     assert lib.ckpp_probe_random_reads(None, 64, 64, 1, 1, 0, 256, 1, 0, None, None) == ckpp.EINVAL
     offs = (ctypes.c_uint64 * 1)(0)

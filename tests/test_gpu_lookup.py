@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 
 MODES = [("cuckoopp", O.MODE_CUCKOOPP), ("both", O.MODE_BOTH), ("optimistic", O.MODE_OPTIMISTIC)]
 SHAPES = [(8, per, block, bpc) for per in (1, 2) for block in (64, 128, 256) for bpc in (0, 1, 3)]
+SHAPES += [(1, per, block, bpc) for per in (1, 2, 4) for block in (64, 256) for bpc in (0, 3)]
 
 
 @pytest.fixture(scope="module")

@@ -15,8 +15,10 @@ from paper_1712_09624_amd import workload as W
 pytestmark = pytest.mark.gpu
 
 OMODE = {"cuckoopp": O.MODE_CUCKOOPP, "both": O.MODE_BOTH, "optimistic": O.MODE_OPTIMISTIC}
-PLAN_SHAPES = [(per, block, bpc, passes, sched) for per in (1, 2) for block in (64, 128, 256)
+PLAN_SHAPES = [(per, block, bpc, passes, sched, 8) for per in (1, 2) for block in (64, 128, 256)
                for bpc, passes in ((1, 1), (8, 1), (2, 3)) for sched in (0, 1)]
+PLAN_SHAPES += [(per, block, bpc, passes, sched, 1) for per in (1, 2, 4) for block in (64, 256)
+                for bpc, passes in ((8, 1), (2, 3)) for sched in (0, 1)]
 SENTINEL_F, SENTINEL_V = 0xAB, 0x5A5A5A5A5A5A5A5A
 
 
@@ -108,15 +110,16 @@ def fleet():
     f.close()
 
 
-@pytest.mark.parametrize("shape", PLAN_SHAPES, ids=[f"per{a}_b{b}_bpc{c}_p{d}_s{e}"
-                                                    for a, b, c, d, e in PLAN_SHAPES])
+@pytest.mark.parametrize("shape", PLAN_SHAPES, ids=[f"per{a}_b{b}_bpc{c}_p{d}_s{e}_l{g}"
+                                                    for a, b, c, d, e, g in PLAN_SHAPES])
 def test_plan_matches_oracle(fleet, shape):
     from paper_1712_09624_amd.ckpp import Plan
     want_f, want_v = fleet.expected()
     plan = Plan(fleet.tables, fleet.offsets, fleet.counts, fleet.modes)
     plan.set_launch(*shape)
     assert plan.get_launch() == dict(zip(("lookups_per_lane", "block", "blocks_per_cu",
-                                          "passes_per_item", "schedule"), shape))
+                                          "passes_per_item", "schedule", "lanes_per_lookup"),
+                                         shape))
     say(f"plan lookup shape={shape} tables={len(fleet.tables)} span={fleet.span}")
     for rep in range(2):  # a second launch starts from the rewound counters
         f, v = run_plan(plan, fleet)
@@ -148,8 +151,8 @@ def test_plan_info_and_items():
     assert inf["ntables"] == 5 and inf["lookups"] == int(f.counts.sum())
     assert inf["key_span"] == f.span
     assert plan.get_launch() == ckpp_default_plan_launch()
-    for per, passes in ((1, 1), (2, 1), (2, 4)):
-        plan.set_launch(per, 128, 4, passes)
+    for per, passes, lanes in ((1, 1, 8), (2, 1, 8), (2, 4, 8), (4, 2, 1)):
+        plan.set_launch(per, 128, 4, passes, 0, lanes)
         tile = 64 * per * passes
         assert plan.info()["nitems"] == int(sum((int(c) + tile - 1) // tile for c in f.counts))
     plan.close()
@@ -173,6 +176,10 @@ def test_plan_rejects_bad_arguments():
         plan.set_launch(2, 128, 0, 1)
     with pytest.raises(CkppError):
         plan.set_launch(2, 128, 4, 1, 2)
+    with pytest.raises(CkppError):  # four lookups per lane need one lane per lookup
+        plan.set_launch(4, 128, 4, 1, 0, 8)
+    with pytest.raises(CkppError):
+        plan.set_launch(1, 128, 4, 1, 0, 4)
     with pytest.raises(CkppError):  # fewer keys than the plan's span
         plan.lookup(torch.zeros((30, 16), dtype=torch.uint8, device="cuda:0"))
     plan.close()

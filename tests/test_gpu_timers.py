@@ -79,7 +79,8 @@ def test_timed_lookup_bit_exact(timed_cfg1, mode, omode):
     t.close()
 
 
-@pytest.mark.parametrize("shape", [(8, 1, 64, 0), (8, 1, 256, 3), (8, 2, 64, 1), (8, 2, 256, 0)])
+@pytest.mark.parametrize("shape", [(8, 1, 64, 0), (8, 1, 256, 3), (8, 2, 64, 1), (8, 2, 256, 0),
+                                   (1, 1, 64, 0), (1, 2, 128, 3), (1, 4, 256, 0)])
 def test_timed_lookup_launch_shapes(timed_cfg1, shape):
     B, now0, ref, keys, exp, look = timed_cfg1
     now = (now0 + 400) & 0xFFFF
@@ -115,6 +116,28 @@ def test_refreshing_lookup_image_bit_exact(timed_cfg1, mode, omode):
     f2, _ = t.lookup_at(to_dev(keys), (now + 999) & 0xFFFF)
     wf2, _ = ref.lookup_at(keys, (now + 999) & 0xFFFF)
     assert np.array_equal(u8(f2), wf2) and int(wf2.sum()) > 0
+    t.close()
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 64, 0), (1, 4, 256, 0), (8, 1, 256, 0)])
+def test_refreshing_lookup_shapes(timed_cfg1, shape):
+    """Refreshing lookups of the other kernels (one lane per lookup with
+    bucket heads in registers, one lookup per lane with lines in LDS) leave
+    the same image as the oracle."""
+    B, now0, _, keys, exp, look = timed_cfg1
+    ref = O.OracleTable(B, W.HASH_SEED, W.MAX_KICKS, timed=True)
+    assert (ref.insert_at(keys, W.insertion_values(len(keys)), exp, now0) == O.INSERTED).all()
+    t = gpu_from(ref)
+    t.set_lookup_launch(*shape)
+    now = (now0 + 300) & 0xFFFF
+    new_exp = (now + 700) & 0xFFFF
+    want_f, want_v = ref.lookup_at(look, now, O.MODE_CUCKOOPP, refresh=new_exp)
+    say(f"refreshing lookup shape={shape}")
+    f, v = t.lookup_at(to_dev(look), now, "cuckoopp", refresh=new_exp)
+    assert np.array_equal(u8(f), want_f) and np.array_equal(u64(v), want_v)
+    gb, gk = t.export()
+    rb, rk = ref.image()
+    assert np.array_equal(gb, rb) and np.array_equal(gk, rk), "images differ after refresh"
     t.close()
 
 
