@@ -301,9 +301,16 @@ def burst_latency(t, pos_keys_dev, neg_keys_dev, dev, nbursts=2000):
             "bursts": int(len(lat)), "sizes": "log-uniform [1, 2048]"}
 
 
-def cpu_baseline(B=22, load=0.9, n=1 << 22):
-    """The oracle (single-threaded C, as it stands) timed on the host."""
+def cpu_baseline(B=22, load=0.9, n=1 << 22, threads=None):
+    """The oracle (single-threaded C, as it stands) timed on the host: once
+    on one thread, then with the same lookups split over `threads` host
+    threads (each a plain oracle lookup call on its own slice; the calls
+    release the interpreter lock and only read the table).  The
+    multi-threaded rate is the reported value."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
+    if threads is None:
+        threads = max(1, min(16, os.cpu_count() or 1))
     nk = W.keys_at_load(B, load)
     keys = W.distinct_five_tuples(nk, 1, check=False)
     t = O.OracleTable(B, W.HASH_SEED, W.MAX_KICKS)
@@ -314,15 +321,23 @@ def cpu_baseline(B=22, load=0.9, n=1 << 22):
     pos, _, _ = W.lookup_mix(keys, n, 0.0, 2)
     neg = W.five_tuples(n, 3, stream=W.STREAM_NEGATIVE)
     t0 = time.perf_counter()
-    t.lookup(pos)
-    t.lookup(neg)
-    dt = time.perf_counter() - t0
+    fp, _, _, _ = t.lookup(pos)
+    fn, _, _, _ = t.lookup(neg)
+    dt1 = time.perf_counter() - t0
+    assert fp.all() and not fn.any()
+    chunks = [a for q in (pos, neg) for a in np.array_split(q, threads)]
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        t0 = time.perf_counter()
+        res = list(ex.map(lambda q: t.lookup(q)[0], chunks))
+        dtn = time.perf_counter() - t0
+    assert int(sum(int(r.sum()) for r in res)) == n
     t.close()
-    return {"value": 2 * n / dt / 1e9, "unit": "Glookups/s", "cores": 1, "kind": "oracle",
+    return {"value": 2 * n / dtn / 1e9, "unit": "Glookups/s", "cores": threads, "kind": "oracle",
             "sample": f"oracle table of 2^{B} buckets x 8 slots at load {load} "
                       f"({nk} keys, the paper's 32M-entry size; built in {t_ins:.1f}s), "
-                      f"{n} positive + {n} negative Cuckoo++ lookups, single thread",
-            "insert_per_s": nk / t_ins}
+                      f"{n} positive + {n} negative Cuckoo++ lookups, split over {threads} host "
+                      f"threads",
+            "single_thread_value": 2 * n / dt1 / 1e9, "insert_per_s": nk / t_ins}
 
 
 def copy_calibration(dev):
