@@ -191,6 +191,7 @@ int ckpp_destroy(ckpp_table *t) {
   (void)hipDeviceSynchronize();
   (void)hipFree(t->d_table);
   (void)hipFree(t->d_stats);
+  if (t->d_small_paths) (void)hipFree(t->d_small_paths);
   delete t;
   return CKPP_OK;
 }

@@ -14,12 +14,19 @@ struct ckpp_table {
   uint64_t seed;
   uint8_t *d_table;     // 256 * 2^B bytes: bucket b at 256 * b (ckpp_device.h)
   uint32_t path_lanes;  // lanes of the persistent insert grid
+  uint32_t *d_small_paths;  // cuckoo-path scratch of small insert batches
+                            // (kSmallPathLanes lanes), allocated on first use
   uint64_t *d_stats;    // device accumulator of ckpp_stats_t
   ckpp_launch_t lookup_launch;
   int num_cus;
 };
 
 namespace ckpp {
+
+// Insert batches launching at most this many lanes take their cuckoo-path
+// scratch from the table's own buffer instead of the stream-ordered pool
+// (whose allocate/free pair costs tens of microseconds on the host).
+constexpr uint32_t kSmallPathLanes = 4096;
 
 // One work item of a plan: lookups [start, start + count) of the
 // concatenated key batch, all of one table, with that table's parameters

@@ -152,6 +152,17 @@ __device__ __forceinline__ void write_entry(uint8_t *bk, uint32_t b, uint32_t s,
   other_ptr(bk, b)[s] = other;
 }
 
+// Index of the k-th set bit of m (k < popcount(m)).
+__device__ __forceinline__ uint32_t nth_bit(uint32_t m, uint32_t k) {
+  for (uint32_t i = 0; i < k; ++i) m &= m - 1u;
+  return (uint32_t)__builtin_ctz(m);
+}
+
+__device__ __forceinline__ uint64_t load_relaxed(const uint8_t *p) {
+  return __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 constexpr int kBusy = -2;    // a lock was taken by another lane: retry
 constexpr int kNeedPath = -1;
 
@@ -209,9 +220,82 @@ __device__ bool remove_expired(uint8_t *bk, Pair &P, int xi, uint32_t s, bool pl
   return true;
 }
 
+// One displacement done inside DIRECT, under the locks of the key's two
+// buckets, when both are full: the other buckets of p's entries are looked
+// at together (the walk's lookahead step); an entry whose other bucket y
+// has a free slot -- preferably one going home -- moves there under y's
+// lock (taken here, never waited on), with the filter maintenance of a
+// cuckoo move (Sec. 4.1), and the key takes its slot in p.  Most keys that
+// need a cuckoo path at all need exactly this one displacement, which then
+// costs one critical section instead of a walk, a move and a second DIRECT
+// step.  mp: p's meta word read under the lock (p full).  Returns true
+// when the key was placed; false, with nothing changed, when no entry of p
+// can move in one step or y's lock is held by another lane (the caller
+// falls back to the walk).
+__device__ bool displace_and_place(uint8_t *bk, uint32_t log2b, uint64_t seed, bool plain,
+                                   const KeyFields &f, uint64_t h, uint4 key, uint64_t word,
+                                   uint32_t mp) {
+  const uint32_t busy = meta_busy(mp), sec = meta_sec(mp);
+  uint32_t cand = busy;
+  if (!plain && meta_moved(mp) >= 0xffffu) cand &= sec;  // an owner leaving would overflow
+  uint32_t other[kSlots];
+  const uint32_t *op = other_ptr(bk, f.p);
+#pragma unroll
+  for (uint32_t s = 0; s < kSlots; ++s) other[s] = op[s];
+  uint32_t room = 0;
+#pragma unroll
+  for (uint32_t s = 0; s < kSlots; ++s) {
+    if ((cand >> s) & 1u) {
+      const uint32_t om = (uint32_t)load_relaxed(bucket_ptr(bk, other[s]) + kMetaOffset);
+      if (meta_busy(om) != 0xffu) room |= 1u << s;
+    }
+  }
+  if (!room) return false;
+  const uint32_t pick = (room & sec) ? (room & sec) : room;
+  const uint32_t v = nth_bit(pick, (uint32_t)(mix64(h ^ 0x5851f42d4c957f2dull) %
+                                              (uint64_t)__builtin_popcount(pick)));
+  const uint32_t y = other[v];
+  if (!try_lock(bk, y)) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  const uint32_t my = *meta_ptr(bk, y);
+  const uint32_t busy_y = meta_busy(my);
+  bool done = false;
+  if (busy_y != 0xffu) {
+    const uint32_t fs = (uint32_t)__builtin_ctz(~busy_y & 0xffu);
+    const uint4 vk = *key_ptr(bk, f.p, v);
+    const uint64_t vw = *value_ptr(bk, f.p, v);
+    const uint32_t vtag = tag_ptr(bk, f.p)[v];
+    const bool guest = (sec >> v) & 1u;  // v sits in its secondary p: y is its home
+    write_entry(bk, y, fs, vk, vw, vtag, f.p);
+    uint32_t moved_y = meta_moved(my), moved_p = meta_moved(mp);
+    if (!plain) {
+      if (guest) {
+        if (moved_y > 0u) {
+          moved_y -= 1u;
+          if (moved_y == 0u) *bloom_ptr(bk, y) = 0ull;
+        }
+      } else {
+        *bloom_ptr(bk, f.p) |= key_fields(key_hash(vk, seed), log2b).bloom_bits;
+        moved_p += 1u;
+      }
+    }
+    const uint32_t fbit = 1u << fs;
+    *meta_ptr(bk, y) = make_meta(moved_y, busy_y | fbit,
+                                 guest ? (meta_sec(my) & ~fbit) : (meta_sec(my) | fbit));
+    // the key takes slot v of p, its primary
+    write_entry(bk, f.p, v, key, word, f.tag, f.a);
+    *meta_ptr(bk, f.p) = make_meta(moved_p, busy, sec & ~(1u << v));
+    done = true;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  unlock(bk, y);
+  return done;
+}
+
 // DIRECT step of a table with timers; word = value | expiry << 48.
 __device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const KeyFields &f,
-                                   bool plain, uint32_t now) {
+                                   uint64_t h, uint32_t log2b, uint64_t seed, bool plain,
+                                   uint32_t now) {
   if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   const Head ha = read_head(bk, f.a);
@@ -266,14 +350,17 @@ __device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const 
     if (r == CKPP_INSERTED) {
       *meta_ptr(bk, f.p) = P.meta[0];
       *meta_ptr(bk, f.a) = P.meta[1];
+    } else if (r == kNeedPath &&
+               displace_and_place(bk, log2b, seed, plain, f, h, key, word, hp.q1.z)) {
+      r = CKPP_INSERTED;
     }
   }
   unlock_two(bk, f.p, f.a);
   return r;
 }
 
-__device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value,
-                             const KeyFields &f, bool plain) {
+__device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value, const KeyFields &f,
+                             uint64_t h, uint32_t log2b, uint64_t seed, bool plain) {
   if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   const Head ha = read_head(bk, f.a);
@@ -304,6 +391,8 @@ __device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value,
         *meta_ptr(bk, f.p) = make_meta(meta_moved(mp) + 1u, busy_p, meta_sec(mp));
       }
       r = CKPP_INSERTED;
+    } else if (displace_and_place(bk, log2b, seed, plain, f, h, key, value, mp)) {
+      r = CKPP_INSERTED;
     } else {
       r = kNeedPath;
     }
@@ -312,16 +401,6 @@ __device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value,
   return r;
 }
 
-// Index of the k-th set bit of m (k < popcount(m)).
-__device__ __forceinline__ uint32_t nth_bit(uint32_t m, uint32_t k) {
-  for (uint32_t i = 0; i < k; ++i) m &= m - 1u;
-  return (uint32_t)__builtin_ctz(m);
-}
-
-__device__ __forceinline__ uint64_t load_relaxed(const uint8_t *p) {
-  return __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Random walk with one step of lookahead from bucket `start` (read without
 // locks).  At each full bucket the other buckets of all its candidate
@@ -458,8 +537,8 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
       break;
     }
     if (state == DIRECT) {
-      const int r = TIMED ? insert_direct_timed(bk, key, word, f, plain, now)
-                          : insert_direct(bk, key, value, f, plain);
+      const int r = TIMED ? insert_direct_timed(bk, key, word, f, h, log2b, seed, plain, now)
+                          : insert_direct(bk, key, value, f, h, log2b, seed, plain);
       if (r >= 0)
         result = r;
       else if (r == kNeedPath)
