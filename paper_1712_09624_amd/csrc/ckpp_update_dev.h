@@ -220,28 +220,57 @@ __device__ bool remove_expired(uint8_t *bk, Pair &P, int xi, uint32_t s, bool pl
   return true;
 }
 
-// One displacement done inside DIRECT, under the locks of the key's two
-// buckets, when both are full: the other buckets of p's entries are looked
-// at together (the walk's lookahead step); an entry whose other bucket y
-// has a free slot -- preferably one going home -- moves there under y's
-// lock (taken here, never waited on), with the filter maintenance of a
-// cuckoo move (Sec. 4.1), and the key takes its slot in p.  Most keys that
-// need a cuckoo path at all need exactly this one displacement, which then
-// costs one critical section instead of a walk, a move and a second DIRECT
-// step.  mp: p's meta word read under the lock (p full).  Returns true
-// when the key was placed; false, with nothing changed, when no entry of p
-// can move in one step or y's lock is held by another lane (the caller
-// falls back to the walk).
-__device__ bool displace_and_place(uint8_t *bk, uint32_t log2b, uint64_t seed, bool plain,
-                                   const KeyFields &f, uint64_t h, uint4 key, uint64_t word,
-                                   uint32_t mp) {
-  const uint32_t busy = meta_busy(mp), sec = meta_sec(mp);
-  uint32_t cand = busy;
-  if (!plain && meta_moved(mp) >= 0xffffu) cand &= sec;  // an owner leaving would overflow
-  uint32_t other[kSlots];
-  const uint32_t *op = other_ptr(bk, f.p);
+// Moves the entry of slot s of bucket x into the free slot fs of its other
+// bucket y (both locked), with the filter maintenance of a cuckoo move
+// (Sec. 4.1): an entry leaving its primary x adds its two bits to x's
+// filter and 1 to x's moved counter; an entry going home to y takes 1 off
+// y's counter and empties y's filter when it reaches zero.  The metadata
+// words are read and written in memory.
+__device__ void move_locked(uint8_t *bk, uint32_t x, uint32_t s, uint32_t y, uint32_t fs,
+                            uint32_t log2b, uint64_t seed, bool plain) {
+  const uint32_t mx = *meta_ptr(bk, x), my = *meta_ptr(bk, y);
+  const uint4 k = *key_ptr(bk, x, s);
+  const uint64_t w = *value_ptr(bk, x, s);
+  const uint32_t tag = tag_ptr(bk, x)[s];
+  const bool guest = (meta_sec(mx) >> s) & 1u;  // in its secondary x: y is its home
+  write_entry(bk, y, fs, k, w, tag, x);
+  uint32_t moved_x = meta_moved(mx), moved_y = meta_moved(my);
+  if (!plain) {
+    if (guest) {
+      if (moved_y > 0u) {
+        moved_y -= 1u;
+        if (moved_y == 0u) *bloom_ptr(bk, y) = 0ull;
+      }
+    } else {
+      *bloom_ptr(bk, x) |= key_fields(key_hash(k, seed), log2b).bloom_bits;
+      moved_x += 1u;
+    }
+  }
+  const uint32_t fb = 1u << fs, sb = 1u << s;
+  *meta_ptr(bk, y) = make_meta(moved_y, meta_busy(my) | fb,
+                               guest ? (meta_sec(my) & ~fb) : (meta_sec(my) | fb));
+  *meta_ptr(bk, x) = make_meta(moved_x, meta_busy(mx) & ~sb, meta_sec(mx) & ~sb);
+}
+
+// Entries of a full bucket that may move (an entry leaving its primary
+// must not overflow that primary's moved counter).
+__device__ __forceinline__ uint32_t movable(uint32_t meta, bool plain) {
+  uint32_t c = meta_busy(meta);
+  if (!plain && meta_moved(meta) >= 0xffffu) c &= meta_sec(meta);
+  return c;
+}
+
+// The other buckets of bucket b's entries and, for the entries in `cand`,
+// which of those buckets have a free slot (their metadata words loaded
+// together, without locks).
+__device__ __forceinline__ uint32_t room_of(const uint8_t *bk, uint32_t b, uint32_t cand,
+                                            uint32_t (&other)[kSlots]) {
 #pragma unroll
-  for (uint32_t s = 0; s < kSlots; ++s) other[s] = op[s];
+  for (uint32_t w = 0; w < 4; ++w) {
+    const uint64_t o = load_relaxed(bucket_ptr(bk, b) + kOtherOffset + 8 * w);
+    other[2 * w] = (uint32_t)o;
+    other[2 * w + 1] = (uint32_t)(o >> 32);
+  }
   uint32_t room = 0;
 #pragma unroll
   for (uint32_t s = 0; s < kSlots; ++s) {
@@ -250,45 +279,99 @@ __device__ bool displace_and_place(uint8_t *bk, uint32_t log2b, uint64_t seed, b
       if (meta_busy(om) != 0xffu) room |= 1u << s;
     }
   }
-  if (!room) return false;
-  const uint32_t pick = (room & sec) ? (room & sec) : room;
-  const uint32_t v = nth_bit(pick, (uint32_t)(mix64(h ^ 0x5851f42d4c957f2dull) %
-                                              (uint64_t)__builtin_popcount(pick)));
-  const uint32_t y = other[v];
-  if (!try_lock(bk, y)) return false;
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  const uint32_t my = *meta_ptr(bk, y);
-  const uint32_t busy_y = meta_busy(my);
-  bool done = false;
-  if (busy_y != 0xffu) {
-    const uint32_t fs = (uint32_t)__builtin_ctz(~busy_y & 0xffu);
-    const uint4 vk = *key_ptr(bk, f.p, v);
-    const uint64_t vw = *value_ptr(bk, f.p, v);
-    const uint32_t vtag = tag_ptr(bk, f.p)[v];
-    const bool guest = (sec >> v) & 1u;  // v sits in its secondary p: y is its home
-    write_entry(bk, y, fs, vk, vw, vtag, f.p);
-    uint32_t moved_y = meta_moved(my), moved_p = meta_moved(mp);
-    if (!plain) {
-      if (guest) {
-        if (moved_y > 0u) {
-          moved_y -= 1u;
-          if (moved_y == 0u) *bloom_ptr(bk, y) = 0ull;
+  return room;
+}
+
+// Takes the lock of bucket b unless the caller holds it already.
+__device__ __forceinline__ bool lock_extra(uint8_t *bk, uint32_t b, const KeyFields &f) {
+  return b == f.p || b == f.a || try_lock(bk, b);
+}
+__device__ __forceinline__ void unlock_extra(uint8_t *bk, uint32_t b, const KeyFields &f) {
+  if (b != f.p && b != f.a) unlock(bk, b);
+}
+
+// Cuckoo displacements done inside DIRECT, under the locks of the key's two
+// buckets, when the primary p is full: the walk's lookahead from p, one
+// level and, if no entry of p can move at once, two.  One step: an entry v
+// of p whose other bucket y has a free slot (preferably one going home)
+// moves there.  Two steps: an entry of some y1 = other(v) moves on to its
+// own other bucket y2, which has a free slot, and v takes its place.  The
+// buckets beyond p and a are locked here (never waited on), the path is
+// re-checked under the locks, the moves are applied last to first with the
+// filter maintenance of Sec. 4.1, and the key takes v's slot in p.  Almost
+// every key that needs a cuckoo path needs at most two displacements, which
+// then cost one critical section instead of a walk, one locked move per
+// displacement and a second DIRECT step.  mp: p's meta word read under the
+// lock.  Returns true when the key was placed; false, with nothing changed,
+// when no such path exists or a lock is held by another lane (the caller
+// falls back to the walk).
+__device__ bool displace_and_place(uint8_t *bk, uint32_t log2b, uint64_t seed, bool plain,
+                                   const KeyFields &f, uint64_t h, uint4 key, uint64_t word,
+                                   uint32_t mp) {
+  const uint32_t cand = movable(mp, plain), sec = meta_sec(mp);
+  uint32_t other[kSlots];
+  const uint32_t room = room_of(bk, f.p, cand, other);
+  uint32_t v = kSlots, y1 = kNoBucket, t = kSlots, y2 = kNoBucket;
+  if (room) {
+    const uint32_t pick = (room & sec) ? (room & sec) : room;
+    v = nth_bit(pick, (uint32_t)(mix64(h ^ 0x5851f42d4c957f2dull) %
+                                 (uint64_t)__builtin_popcount(pick)));
+    y1 = other[v];
+  } else {
+    // second level: entries of p going home first
+    for (uint32_t order = 0; order < 2 && t == kSlots; ++order) {
+      for (uint32_t c = cand & (order ? ~sec : sec); c && t == kSlots; c &= c - 1u) {
+        const uint32_t s = (uint32_t)__builtin_ctz(c);
+        const uint32_t b1 = other[s];
+        const uint32_t m1 = (uint32_t)load_relaxed(bucket_ptr(bk, b1) + kMetaOffset);
+        uint32_t other1[kSlots];
+        const uint32_t r1 = room_of(bk, b1, movable(m1, plain), other1);
+        if (r1) {
+          const uint32_t pick = (r1 & meta_sec(m1)) ? (r1 & meta_sec(m1)) : r1;
+          v = s;
+          y1 = b1;
+          t = (uint32_t)__builtin_ctz(pick);
+          y2 = other1[t];
         }
-      } else {
-        *bloom_ptr(bk, f.p) |= key_fields(key_hash(vk, seed), log2b).bloom_bits;
-        moved_p += 1u;
       }
     }
-    const uint32_t fbit = 1u << fs;
-    *meta_ptr(bk, y) = make_meta(moved_y, busy_y | fbit,
-                                 guest ? (meta_sec(my) & ~fbit) : (meta_sec(my) | fbit));
+    if (t == kSlots) return false;
+  }
+  // lock the buckets beyond p and a, then re-check the path under the locks
+  if (!lock_extra(bk, y1, f)) return false;
+  if (y2 != kNoBucket && !lock_extra(bk, y2, f)) {
+    unlock_extra(bk, y1, f);
+    return false;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  bool done = false;
+  const uint32_t my1 = *meta_ptr(bk, y1);
+  if (y2 == kNoBucket) {
+    if (meta_busy(my1) != 0xffu) {
+      move_locked(bk, f.p, v, y1, (uint32_t)__builtin_ctz(~meta_busy(my1) & 0xffu), log2b, seed,
+                  plain);
+      done = true;
+    }
+  } else {
+    const uint32_t my2 = *meta_ptr(bk, y2);
+    const bool still = ((meta_busy(my1) >> t) & 1u) && other_ptr(bk, y1)[t] == y2 &&
+                       ((movable(my1, plain) >> t) & 1u) && meta_busy(my2) != 0xffu;
+    if (still) {
+      move_locked(bk, y1, t, y2, (uint32_t)__builtin_ctz(~meta_busy(my2) & 0xffu), log2b, seed,
+                  plain);
+      move_locked(bk, f.p, v, y1, t, log2b, seed, plain);
+      done = true;
+    }
+  }
+  if (done) {
     // the key takes slot v of p, its primary
     write_entry(bk, f.p, v, key, word, f.tag, f.a);
-    *meta_ptr(bk, f.p) = make_meta(moved_p, busy, sec & ~(1u << v));
-    done = true;
+    const uint32_t m = *meta_ptr(bk, f.p), vb = 1u << v;
+    *meta_ptr(bk, f.p) = make_meta(meta_moved(m), meta_busy(m) | vb, meta_sec(m) & ~vb);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  unlock(bk, y);
+  if (y2 != kNoBucket) unlock_extra(bk, y2, f);
+  unlock_extra(bk, y1, f);
   return done;
 }
 
