@@ -680,8 +680,56 @@ def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0
         out["runs"].append(rec)
         log(f"serve run {run}: {rec}")
     srv.close()
+    # the same kind of stream through the plain batch calls, burst by burst
+    # (lookup, insert and delete batch of each burst, then a synchronization)
+    nplain = min(5000, nbursts)
+    st = serve_stream(nplain, 100 + len(out["runs"]), keys, universe, vals, del_base)
+    out["plain_calls"] = plain_call_run(t, st, dev)
+    log(f"plain calls: {out['plain_calls']}")
     t.close()
     return out
+
+
+def plain_call_run(t, st, dev):
+    """Bursts served one at a time by the plain batch calls, back to back
+    (closed loop): per burst a lookup, an insert and a delete batch on the
+    caller's stream and a synchronization.  Every result is checked."""
+    import torch
+    look, ins, dels = to_dev(st["look"], dev), to_dev(st["ins"], dev), to_dev(st["dels"], dev)
+    ins_v = to_dev(st["ins_val"].view(np.int64), dev)
+    nl, ni, nd = st["nl"], st["ni"], st["nd"]
+    f = torch.empty(len(st["look"]), dtype=torch.uint8, device=dev)
+    v = torch.empty(len(st["look"]), dtype=torch.int64, device=dev)
+    ist = torch.empty(max(1, len(st["ins"])), dtype=torch.uint8, device=dev)
+    dfo = torch.empty(max(1, len(st["dels"])), dtype=torch.uint8, device=dev)
+    nf = torch.zeros(1, dtype=torch.int64, device=dev)
+    lat = np.empty(len(nl))
+    ol = oi = od = 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for b in range(len(nl)):
+        t0 = time.perf_counter()
+        a, c, e = int(nl[b]), int(ni[b]), int(nd[b])
+        if a:
+            t.lookup(look[ol:ol + a], found=f[ol:ol + a], values=v[ol:ol + a])
+        if c:
+            t.insert(ins[oi:oi + c], ins_v[oi:oi + c], status=ist[oi:oi + c], nfailed=nf)
+        if e:
+            t.delete(dels[od:od + e], found=dfo[od:od + e])
+        torch.cuda.synchronize()
+        lat[b] = time.perf_counter() - t0
+        ol, oi, od = ol + a, oi + c, od + e
+    span = time.perf_counter() - t_start
+    ok = (bool((f.cpu().numpy() == 1).all())
+          and np.array_equal(v.cpu().numpy().view(np.uint64), st["look_val"])
+          and bool((ist[:oi].cpu().numpy() == 0).all()) and bool((dfo[:od].cpu().numpy() == 1).all())
+          and int(nf.item()) == 0)
+    if not ok:
+        raise RuntimeError("plain-call serving run: wrong results")
+    lat *= 1e6
+    return {"bursts": int(len(nl)), "glookups": ol / span / 1e9, "gops": (ol + oi + od) / span / 1e9,
+            "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+            "mean_us": float(lat.mean()), "span_s": span}
 
 
 PROFILE_CMDS = {
