@@ -7,16 +7,18 @@
 // taken with a single compare-and-swap and never waited on: a lane that
 // misses a lock drops every lock it holds and retries in its next loop
 // iteration, so no lane ever spins on a lock that a lane of its own
-// wavefront holds.  A lane holds the locks of at most two buckets, taken in
-// ascending bucket order, always the two buckets an entry may live in, so
-// every bloom-filter and moved-counter update -- which concerns the primary
-// bucket of the entry that moves -- happens under the lock of that bucket.
+// wavefront holds.  Every entry that moves is moved under the locks of both buckets it may
+// live in, so every bloom-filter and moved-counter update -- which concerns
+// the primary bucket of the entry that moves -- happens under the lock of
+// that bucket.
 //
 // A key's state machine:
 //   DIRECT  lock p and a; if the key is present, replace its value
 //           (UPDATED); else take the lowest free slot of p, else of a (set
 //           the key's two bits in p's filter, moved[p] += 1) (INSERTED);
-//           else go to WALK.
+//           else, still under those locks, try a cuckoo path of one or two
+//           displacements out of p (the buckets it touches are locked too),
+//           and the key takes the freed slot of p (INSERTED); else WALK.
 //   WALK    random walk over full buckets starting at p, reading without
 //           locks, with one step of lookahead: at each bucket, if the other
 //           bucket of some entry has a free slot, that entry (preferably one
@@ -79,9 +81,12 @@ __device__ __forceinline__ void unlock(uint8_t *bk, uint32_t b) {
   __hip_atomic_store(lock_word(bk, b), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Takes the locks of buckets x != y in ascending order, or none.  On
-// success the caller's later reads see every write made under these locks
-// by earlier holders.
+// Takes the locks of buckets x != y in ascending order, or none.  The
+// order makes retries live: of two lanes that need the same pair, the one
+// that takes the lower lock first can always try the higher one, whereas
+// two lanes taking the two locks at once could each get one, give both
+// back, and repeat in lockstep forever.  On success the caller's later
+// reads see every write made under these locks by earlier holders.
 __device__ __forceinline__ bool lock_two(uint8_t *bk, uint32_t x, uint32_t y) {
   const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
   if (!try_lock(bk, lo)) return false;
@@ -337,10 +342,14 @@ __device__ bool displace_and_place(uint8_t *bk, uint32_t log2b, uint64_t seed, b
     }
     if (t == kSlots) return false;
   }
-  // lock the buckets beyond p and a, then re-check the path under the locks
-  if (!lock_extra(bk, y1, f)) return false;
-  if (y2 != kNoBucket && !lock_extra(bk, y2, f)) {
-    unlock_extra(bk, y1, f);
+  // lock the buckets beyond p and a (both compare-and-swaps issued
+  // together: a failure here is not retried but falls back to the walk, so
+  // it cannot repeat in lockstep), then re-check the path under the locks
+  const bool ok1 = lock_extra(bk, y1, f);
+  const bool ok2 = y2 == kNoBucket || lock_extra(bk, y2, f);
+  if (!(ok1 && ok2)) {
+    if (ok1) unlock_extra(bk, y1, f);
+    if (ok2 && y2 != kNoBucket) unlock_extra(bk, y2, f);
     return false;
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
