@@ -215,3 +215,75 @@ def test_clear():
     f, _ = t.lookup(to_dev(keys))
     assert not u8(f).any()
     t.close()
+
+
+@pytest.mark.parametrize("B,timed", [(6, False), (9, False), (7, True), (9, True)])
+def test_churn_near_capacity(B, timed):
+    """Forty batches alternate fresh inserts that bring the table to load
+    0.97 (many keys need cuckoo paths, many lanes contend for the same
+    buckets) with deletes of a random third of the stored keys and of some
+    absent keys.  After every batch the table holds exactly what the
+    statuses say (INSERTED kept, FAILED absent) with its values, every
+    delete reports presence, the invariants hold and no lane gave up on a
+    lock.  With timers the clock advances 60 units a batch and expiration
+    times are up to 1023 units ahead, so entries expire, are reused lazily
+    and are removed by a scan every ten batches."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Table
+    rng = np.random.default_rng(B + (100 if timed else 0))
+    cap = 8 << B
+    universe = W.distinct_five_tuples(24 * cap, 300 + B)
+    t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=0, timers=timed)
+    live = {}  # row -> (value, expiry)
+    nxt, now = 0, 65000
+
+    def alive(row):
+        return row in live and (not timed or ((live[row][1] - now) & 0xFFFF) < 1024)
+
+    for r in range(40):
+        if timed:
+            now = (now + 60) & 0xFFFF
+            for row in [x for x in live if not alive(x)]:
+                del live[row]
+            if r % 10 == 9:
+                t.expire_scan(now)
+        want = int(0.97 * cap) - len(live)
+        if want > 0:
+            rows = np.arange(nxt, nxt + want)
+            nxt += want
+            vals = rng.integers(0, 1 << 40, size=want).astype(np.uint64)
+            exp = ((now + rng.integers(0, 1024, size=want)) & 0xFFFF).astype(np.uint16)
+            say(f"churn B={B} timed={timed} round={r} insert {want}")
+            if timed:
+                st, nf = t.insert_at(to_dev(universe[rows]), vals_dev(vals),
+                                     to_dev(exp.view(np.int16)), now)
+            else:
+                st, nf = t.insert(to_dev(universe[rows]), vals_dev(vals))
+            torch.cuda.synchronize()
+            st = u8(st)
+            assert set(np.unique(st)) <= {O.INSERTED, O.FAILED}
+            assert int(nf.item()) == int((st == O.FAILED).sum())
+            for i in np.flatnonzero(st == O.INSERTED):
+                live[int(rows[i])] = (int(vals[i]), int(exp[i]))
+        stored = np.array(sorted(live), dtype=np.int64)
+        drop = rng.choice(stored, size=len(stored) // 3, replace=False) if len(stored) else stored
+        absent = rng.integers(nxt, len(universe), size=50)
+        drows = np.concatenate([drop, absent])
+        say(f"churn B={B} timed={timed} round={r} delete {len(drows)}")
+        d = u8(t.delete_at(to_dev(universe[drows]), now) if timed
+               else t.delete(to_dev(universe[drows])))
+        assert np.array_equal(d, np.array([alive(int(x)) for x in drows], np.uint8))
+        for x in drop:
+            live.pop(int(x), None)
+        probe = universe[:nxt]
+        f, v = t.lookup_at(to_dev(probe), now) if timed else t.lookup(to_dev(probe))
+        wf = np.array([alive(i) for i in range(nxt)], np.uint8)
+        wv = np.array([live[i][0] if alive(i) else 0 for i in range(nxt)], np.uint64)
+        assert np.array_equal(u8(f), wf), f"round {r}: found flags"
+        assert np.array_equal(u64(v), wv), f"round {r}: values"
+        b, k = t.export()
+        rc, msg = O.check_image(b, k, B, W.HASH_SEED, timed=timed)
+        assert rc == 0, f"round {r}: invariant {rc}: {msg}"
+    s = t.stats()
+    assert s["locked"] == 0 and s["retry_exhausted"] == 0
+    t.close()
