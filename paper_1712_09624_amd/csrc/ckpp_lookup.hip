@@ -25,6 +25,13 @@
 // that need them, and skipped when none does.  Keys for the next tile are
 // loaded while the current tile is processed; keys stream in and results
 // stream out with non-temporal accesses.
+//
+// Other forms of the same lookup: two lookups per lane (lookup_dual: the
+// second half's lines land in registers and are parked in LDS), one lane
+// per lookup with bucket heads in registers (lookup_reg), and a plan's
+// persistent kernel over many tables' batches (lookup_plan).  On a table
+// with timers (Sec. 4.2) a key match counts only if the entry is alive,
+// and a refreshing lookup writes the new time into the entry's value word.
 
 #include "ckpp_lookup_dev.h"
 
