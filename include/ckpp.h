@@ -370,12 +370,17 @@ int ckpp_plan_info(const ckpp_plan *p, ckpp_plan_info_t *out);
  * the positions following the previous burst's, then submit the burst's
  * three counts.  The loop gathers every burst submitted before it starts a
  * round (continuous batching: bursts that arrive while a round runs join
- * the next one) and runs the round's lookups, then its inserts, then its
+ * the next one) and runs the round's lookups, then its inserts and
  * deletes, each phase over all of the round's bursts at once, with grid-wide
- * barriers between the phases; rounds run in submission order.  So a lookup
- * sees every insert and delete of the bursts of earlier rounds and none of
- * its own round's, and a burst's results do not depend on which other
- * bursts share its round as long as their writes concern other keys.  Each
+ * barriers between the phases; rounds run in submission order.  Inserts and
+ * deletes of different keys run side by side; the deletes of keys that the
+ * round also inserts run after all of its inserts (so a burst that inserts
+ * and deletes a key ends without it).  So a lookup sees every insert and
+ * delete of the bursts of earlier rounds and none of its own round's, and a
+ * burst's results do not depend on which other bursts share its round as
+ * long as their writes concern other keys (an insert may take a slot that a
+ * delete of the same round frees, which only matters when the table is
+ * full).  Each
  * operation is the Sec. 2 / Sec. 4.1 operation of ckpp_lookup_batch,
  * ckpp_insert_batch or ckpp_delete_batch; results land in the rings at the
  * operation's position.  Admission: a burst is accepted only while the
@@ -428,7 +433,9 @@ typedef struct {
     uint32_t grid;        /* blocks of the loop kernel */
     /* the loop's own clock, summed over rounds, as of the last round
        boundary: from the release of each phase until every block finished
-       it; at round boundaries apart from waiting; waiting for bursts */
+       it (insert_ns: the inserts, or inserts and deletes side by side;
+       delete_ns: deletes after the inserts); at round boundaries apart from
+       waiting; waiting for bursts */
     uint64_t lookup_ns, insert_ns, delete_ns, boundary_ns, wait_ns;
 } ckpp_server_status_t;
 

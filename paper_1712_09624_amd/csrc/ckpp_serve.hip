@@ -12,10 +12,17 @@
 //             for submitted bursts (or exits after idle_ms without any),
 //             writes the round's op ranges and releases the barrier
 //   lookups   every wave runs 64-lookup passes over the round's lookup range
-//             (the lookup passes of the batch kernels, unchanged)
-//   inserts   after a barrier, one lane per key (the batch insert's state
-//             machine, unchanged), at most `path_lanes` lanes
-//   deletes   after a barrier, one lane per key
+//             (the lookup passes of the batch kernels, unchanged); then the
+//             round's insert keys go into a set
+//   updates   after a barrier, the inserts (one lane per key, the batch
+//             insert's state machine, unchanged, at most `path_lanes` lanes)
+//             and the deletes (one lane per key, from the other end of the
+//             grid) run side by side; a delete of a key the round also
+//             inserts is deferred
+//   deferred  only if some delete was deferred: after the next barrier
+//             (every insert is done), the deferred deletes.  A round with
+//             more updates than lanes, or more inserts than the set holds,
+//             runs inserts, a barrier, deletes
 //   end       each block makes its results visible to the host (system-
 //             scope release) before it arrives at the next boundary
 //
@@ -54,7 +61,12 @@ constexpr uint32_t kMaxPathLanes = 65536;
 // memory, so this is tens of seconds)
 constexpr uint64_t kMaxSpins = 1ull << 26;
 
-constexpr uint32_t kCmdRun = 1, kCmdExit = 2;
+constexpr uint32_t kCmdRun = 1, kCmdExit = 2, kCmdDeferred = 3;
+// The round's insert-key set holds at most this many entries (twice the
+// inserts it takes); a round with more inserts runs inserts, then deletes.
+constexpr uint64_t kMaxSetEntries = 1ull << 22;
+// Result byte of a delete waiting for the round's inserts.
+constexpr uint8_t kDeferred = 0xffu;
 
 // Pinned host memory shared by the host and the loop.
 struct ServeHost {
@@ -76,9 +88,10 @@ struct ServeDev {
   // apart from waiting for work; time waiting for work
   uint64_t t_lookup, t_insert, t_delete, t_boundary, t_wait;
   uint64_t t_mark;            // when the leader last released a barrier
-  uint32_t cmd;               // kCmdRun / kCmdExit for the blocks
+  uint32_t cmd;               // kCmdRun / kCmdExit / kCmdDeferred for the blocks
   uint32_t abort;             // a wait ran out of time
   uint32_t gen;               // barrier: last epoch the leader released
+  uint32_t deferred;          // some delete of the round waits for its inserts
 };
 
 // Barrier flags: block b stores the epoch it reached at arrive[b * kFlagStride]
@@ -106,6 +119,9 @@ struct ServeArgs {
   uint32_t path_lanes;
   uint64_t idle_ticks;
   unsigned long long *nspin;
+  uint4 *set_keys;    // the round's insert keys, open addressing
+  uint32_t *set_tag;  // entry in use by the round whose tag it holds
+  uint64_t set_mask;  // entries - 1
 };
 
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
@@ -253,6 +269,43 @@ __device__ void lookup_phase(const ServeArgs &a, const Wave &w, uint64_t l0, uin
   }
 }
 
+// The round's insert keys in a set (open addressing, linear probing): an
+// entry belongs to the round whose tag it carries, so the set is never
+// cleared.  Built before a barrier, read after it.
+__device__ __forceinline__ uint64_t set_slot(const ServeArgs &a, uint4 k) {
+  return key_hash(k, 0x9e3779b97f4a7c15ull) & a.set_mask;
+}
+
+__device__ void set_build(const ServeArgs &a, uint64_t i0, uint64_t i1, uint32_t tag) {
+  const uint64_t nlanes = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t j = i0 + (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < i1; j += nlanes) {
+    const uint4 k = a.in_keys[j & a.mask];
+    uint64_t pos = set_slot(a, k);
+    for (uint64_t probe = 0; probe <= a.set_mask; ++probe, pos = (pos + 1u) & a.set_mask) {
+      uint32_t t = __hip_atomic_load(a.set_tag + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t == tag) continue;  // taken by another key of this round
+      if (__hip_atomic_compare_exchange_strong(a.set_tag + pos, &t, tag, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        uint32_t *dst = reinterpret_cast<uint32_t *>(a.set_keys + pos);
+        __hip_atomic_store(dst + 0, k.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(dst + 1, k.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(dst + 2, k.z, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(dst + 3, k.w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+}
+
+__device__ bool set_has(const ServeArgs &a, uint4 k, uint32_t tag) {
+  uint64_t pos = set_slot(a, k);
+  for (uint64_t probe = 0; probe <= a.set_mask; ++probe, pos = (pos + 1u) & a.set_mask) {
+    if (a.set_tag[pos] != tag) return false;
+    if (key_eq(a.set_keys[pos], k)) return true;
+  }
+  return false;
+}
+
 __device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1) {
   const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= a.path_lanes) return;
@@ -266,15 +319,32 @@ __device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1) {
   }
 }
 
-__device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1) {
+// The round's deletes.  Lane g takes the deletes at offsets nlanes - 1 - g,
+// 2 nlanes - 1 - g, ... (the far end of the grid from the insert lanes, so
+// that inserts and deletes run side by side).  filter: a delete of a key
+// the round also inserts is deferred (its result byte set to kDeferred)
+// until every insert of the round is done.  deferred_only: runs just the
+// deferred deletes (the same lane took them).
+__device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1, bool filter,
+                             uint32_t tag, bool deferred_only) {
   const uint64_t nlanes = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t j = d0 + (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < d1; j += nlanes) {
-    const uint64_t slot = j & a.mask;
+  const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool deferred = false;
+  for (uint64_t o = nlanes - 1u - g; d0 + o < d1; o += nlanes) {
+    const uint64_t slot = (d0 + o) & a.mask;
+    if (deferred_only && a.de_found[slot] != kDeferred) continue;
+    const uint4 k = a.de_keys[slot];
+    if (filter && set_has(a, k, tag)) {
+      a.de_found[slot] = kDeferred;
+      deferred = true;
+      continue;
+    }
     bool spun = false;
-    a.de_found[slot] = (uint8_t)delete_one(a.bk, a.de_keys[slot], a.T.log2b, a.T.seed,
-                                           a.plain != 0u, &spun);
+    a.de_found[slot] = (uint8_t)delete_one(a.bk, k, a.T.log2b, a.T.seed, a.plain != 0u, &spun);
     if (spun) atomicAdd(a.nspin, 1ull);
   }
+  if (deferred)
+    __hip_atomic_store(&a.dev->deferred, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Grid-wide barrier inside a round (every thread of every block calls it).
@@ -313,6 +383,9 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
   // block of this launch has arrived at its first barrier)
   uint32_t epoch = poll32(&d->gen);
   bool ran = false;
+  // the leader's note of the phase that ends at the next boundary:
+  // 0 lookups, 1 inserts (or inserts and deletes together), 2 deletes
+  uint32_t last_phase = 0u;
   for (;;) {
     // round boundary
     ++epoch;
@@ -325,12 +398,21 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
           const uint64_t tg = now_ticks();
           if (ran) {  // the round's last phase ends here
             const uint64_t dt = tg - d->t_mark;
-            if (s_range[5] > s_range[4]) d->t_delete += dt;
-            else if (s_range[3] > s_range[2]) d->t_insert += dt;
+            if (last_phase == 2u) d->t_delete += dt;
+            else if (last_phase == 1u) d->t_insert += dt;
             else d->t_lookup += dt;
           }
           const uint64_t w0 = d->t_wait;
-          const uint32_t cmd = ok ? leader_next_round(a, ran) : kCmdExit;
+          uint32_t cmd;
+          if (ok && ran && __hip_atomic_load(&d->deferred, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)) {
+            // some deletes of the round wait for its inserts, which are all
+            // done now: run them before the round is published complete
+            d->deferred = 0u;
+            cmd = kCmdDeferred;
+          } else {
+            cmd = ok ? leader_next_round(a, ran) : kCmdExit;
+          }
           d->cmd = cmd;
           const uint64_t tr = now_ticks();
           d->t_boundary += (tr - tg) - (d->t_wait - w0);
@@ -349,7 +431,7 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
       // the round's ring entries were written by the host or a copy engine
       // while the kernel ran: drop any cached copy of them
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-      if (s_cmd == kCmdRun) {
+      if (s_cmd == kCmdRun || s_cmd == kCmdDeferred) {
         s_range[0] = d->lk0;
         s_range[1] = d->lk1;
         s_range[2] = d->in0;
@@ -359,16 +441,40 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
       }
     }
     __syncthreads();
-    if (s_cmd != kCmdRun) break;
+    if (s_cmd != kCmdRun && s_cmd != kCmdDeferred) break;
     const uint64_t l0 = s_range[0], l1 = s_range[1], i0 = s_range[2], i1 = s_range[3];
     const uint64_t d0 = s_range[4], d1 = s_range[5];
-    lookup_phase<MODE>(a, w, l0, l1);
-    if (i1 > i0 || d1 > d0) {
-      if (!phase_barrier(a, ++epoch, 0u, &s_ok)) break;
-      insert_phase(a, i0, i1);
-      if (d1 > d0) {
-        if (!phase_barrier(a, ++epoch, 1u, &s_ok)) break;
-        delete_phase(a, d0, d1);
+    if (s_cmd == kCmdDeferred) {
+      delete_phase(a, d0, d1, false, 0u, true);
+      last_phase = 2u;
+    } else {
+      // a round with inserts and deletes runs them side by side, deferring
+      // the deletes of keys it also inserts, when the updates are few enough
+      // for each to get a lane of its own with half the lanes to spare
+      // (building and probing the insert-key set costs about as much as the
+      // barrier it saves once most lanes are busy) and the set has room;
+      // else it runs the inserts, then the deletes
+      const bool ins = i1 > i0, del = d1 > d0;
+      const uint64_t nlanes = (uint64_t)gridDim.x * kBlock;
+      const uint64_t lanes = nlanes < a.path_lanes ? nlanes : a.path_lanes;
+      const bool merge = ins && del && 2u * (i1 - i0) <= a.set_mask + 1u &&
+                         2u * ((i1 - i0) + (d1 - d0)) <= lanes;
+      const uint32_t tag = epoch;  // unique to this round
+      lookup_phase<MODE>(a, w, l0, l1);
+      if (merge) set_build(a, i0, i1, tag);
+      last_phase = 0u;
+      if (ins || del) {
+        if (!phase_barrier(a, ++epoch, 0u, &s_ok)) break;
+        if (!ins || !del || merge) {
+          insert_phase(a, i0, i1);
+          delete_phase(a, d0, d1, merge, tag, false);
+          last_phase = ins ? 1u : 2u;
+        } else {
+          insert_phase(a, i0, i1);
+          if (!phase_barrier(a, ++epoch, 1u, &s_ok)) break;
+          delete_phase(a, d0, d1, false, 0u, false);
+          last_phase = 2u;
+        }
       }
     }
     // every wave's results become visible to the host and the copy engines
@@ -399,6 +505,8 @@ struct ckpp_server {
   ServeDev *dev;
   uint32_t *paths;
   uint32_t *arrive;
+  uint4 *set_keys;
+  uint32_t *set_tag;
   ckpp_server_rings_t rings;
   ServeArgs args;
   uint64_t submitted;
@@ -470,6 +578,8 @@ void free_server(ckpp_server *s) {
   (void)hipFree(s->rings.d_delete_found);
   (void)hipFree(s->paths);
   (void)hipFree(s->arrive);
+  (void)hipFree(s->set_keys);
+  (void)hipFree(s->set_tag);
   (void)hipFree(s->dev);
   if (s->host) (void)hipHostFree(s->host);
   if (s->stream) (void)hipStreamDestroy(s->stream);
@@ -530,6 +640,12 @@ int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_confi
   const uint64_t flag_bytes = (uint64_t)s->grid * ckpp::kFlagStride * 4u;
   if (e == hipSuccess) e = hipMalloc(&s->arrive, flag_bytes);
   if (e == hipSuccess) e = hipMemset(s->arrive, 0, flag_bytes);
+  // the round's insert-key set: twice the inserts one round may take
+  uint64_t set_entries = 64;
+  while (set_entries < 2u * c.budget && set_entries < ckpp::kMaxSetEntries) set_entries <<= 1;
+  if (e == hipSuccess) e = hipMalloc(&s->set_keys, set_entries * 16);
+  if (e == hipSuccess) e = hipMalloc(&s->set_tag, set_entries * 4);
+  if (e == hipSuccess) e = hipMemset(s->set_tag, 0, set_entries * 4);
   if (e == hipSuccess) e = hipHostMalloc(&s->host, sizeof(ServeHost), hipHostMallocCoherent);
   if (e == hipSuccess) memset(s->host, 0, sizeof(ServeHost));
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -558,6 +674,9 @@ int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_confi
   a.path_lanes = path_lanes;
   a.idle_ticks = (uint64_t)c.idle_ms * ckpp::kTicksPerMs;
   a.nspin = reinterpret_cast<unsigned long long *>(t->d_stats) + 127;
+  a.set_keys = s->set_keys;
+  a.set_tag = s->set_tag;
+  a.set_mask = set_entries - 1u;
   e = launch_loop(s);
   if (e != hipSuccess) {
     free_server(s);

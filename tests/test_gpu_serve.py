@@ -213,3 +213,43 @@ def test_server_replay_open_loop():
         for i, (c, f) in enumerate(placed):
             check(fetch(srv, c, f), want[i], f"replayed burst {i}")
     t.close()
+
+
+def test_server_insert_and_delete_of_one_key_in_a_round():
+    """A burst that inserts keys and deletes some of them: the deletes wait
+    for the round's inserts (they are deferred past them), report found, and
+    the keys end absent; bursts that write other keys run alongside.  The
+    final table equals the oracle's after the same bursts one by one."""
+    from paper_1712_09624_amd.ckpp import Server
+    ref, t, keys = oracle_and_table(10, 0.5, 31)
+    fresh = W.distinct_five_tuples(2000, 32, stream=W.STREAM_FRESH)
+    bursts = []
+    for b in range(8):
+        ins = fresh[250 * b: 250 * b + 60]
+        dels = np.concatenate([ins[:20], keys[40 * b: 40 * b + 10]])  # own inserts + stored keys
+        look = np.concatenate([keys[1000 + 30 * b: 1000 + 30 * b + 30], fresh[250 * b + 200:
+                                                                             250 * b + 230]])
+        ivals = np.arange(60, dtype=np.uint64) + np.uint64(10**9 * (b + 1))
+        bursts.append((np.ascontiguousarray(look), np.ascontiguousarray(ins), ivals,
+                       np.ascontiguousarray(dels)))
+    want = oracle_run(ref, bursts)
+    with Server(t, capacity=1 << 12, idle_ms=500) as srv:
+        say("server: one burst inserting and deleting the same keys")
+        counts, first = put(srv, bursts[0])
+        srv.wait(srv.submit(*counts), 10000)
+        check(fetch(srv, counts, first), want[0], "burst 0")
+        assert srv.status()["delete_ns"] > 0, "the deletes of the burst's own keys were deferred"
+        say("server: seven such bursts back to back")
+        placed = [put(srv, b) for b in bursts[1:]]
+        ids = [srv.submit(*c) for c, _ in placed]
+        srv.wait(ids[-1], 10000)
+        for i, (c, f) in enumerate(placed):
+            check(fetch(srv, c, f), want[i + 1], f"burst {i + 1}")
+    bk, kv = t.export()
+    rc, msg = O.check_image(bk, kv, 10, W.HASH_SEED, False)
+    assert rc == 0, msg
+    probe = np.concatenate([keys, fresh])
+    wf, wv, _, _ = ref.lookup(probe, O.MODE_CUCKOOPP)
+    gf, gv = t.lookup(to_dev(probe))
+    assert np.array_equal(u8(gf), wf) and np.array_equal(u64(gv), wv)
+    t.close()
