@@ -121,3 +121,54 @@ def test_batched_build_delete_reinsert():
     say("insert workload: image invariants")
     check_image(t)
     t.close()
+
+
+def test_benchmark_table_with_timers():
+    """The benchmark's table with timers (expiration times uniform over the
+    1024 units after 65000, so the window wraps) in the default launch
+    configuration: at 65000 every key is found with its value; at 65512
+    exactly the keys whose time has not passed; a refreshing lookup keeps
+    every key it finds alive until its new time; the scan then removes the
+    rest, and the invariants hold throughout."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Table
+    n = W.keys_at_load(B, 0.9)
+    keys = W.distinct_five_tuples(n, 1)
+    vals = W.insertion_values(n)
+    now0 = 65000
+    exp = W.times_after(n, now0, 1024, 1)
+    say("full size timers: build 2^24 buckets at load 0.9")
+    t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=0, timers=True)
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    for s in range(0, n, 1 << 22):
+        t.insert_at(to_dev(keys[s:s + (1 << 22)]), vals_dev(vals[s:s + (1 << 22)]),
+                    to_dev(exp[s:s + (1 << 22)].view(np.int16)), now0, nfailed=nf)
+    torch.cuda.synchronize()
+    assert int(nf.item()) == 0
+    pos, _, idx = W.lookup_mix(keys, 1 << 26, 0.0, 2)
+    dpos = to_dev(pos)
+    say("full size timers: lookups at the build time")
+    f, v = t.lookup_at(dpos, now0)
+    assert u8(f).all() and np.array_equal(u64(v), vals[idx])
+    half = (now0 + 512) & 0xFFFF
+    alive = (((exp.astype(np.int64) - half) & 0xFFFF) < 1024)
+    say("full size timers: lookups half way, with refresh")
+    new_exp = (half + 1000) & 0xFFFF
+    f, v = t.lookup_at(dpos, half, refresh=new_exp)
+    f, v = u8(f), u64(v)
+    assert np.array_equal(f, alive[idx].astype(np.uint8))
+    assert np.array_equal(v, np.where(alive[idx], vals[idx], 0).astype(np.uint64))
+    refreshed = np.zeros(n, bool)
+    refreshed[idx[f == 1]] = True
+    later = (half + 700) & 0xFFFF
+    say("full size timers: scan")
+    removed = t.expire_scan(later)
+    want_alive = refreshed  # every other entry has expired by then
+    assert int(removed.item()) == n - int(want_alive.sum())
+    assert t.stats()["live"] == int(want_alive.sum())
+    f, v = t.lookup_at(to_dev(keys), later)
+    assert np.array_equal(u8(f), want_alive.astype(np.uint8))
+    b, k = t.export()
+    rc, msg = O.check_image(b, k, B, W.HASH_SEED, timed=True)
+    assert rc == 0, msg
+    t.close()
