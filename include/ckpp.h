@@ -126,10 +126,13 @@ int ckpp_clear(ckpp_table *t, void *stream);
  * d_status (n bytes, nullable) receives CKPP_INSERTED / UPDATED / FAILED;
  * d_nfailed (one u64, nullable) is incremented by the number of FAILED keys.
  * The cuckoo-path scratch of the call (4 * max_kicks bytes per launched
- * lane, at most 2^16 lanes) comes from the device's stream-ordered memory
- * pool and is returned to it on `stream`; a batch launching at most 4096
- * lanes uses instead a buffer of the table's own (4096 * 4 * max_kicks
- * bytes), allocated on the first such batch and freed with the table.
+ * lane, at most 2^16 lanes) is a buffer of the table's own, allocated on
+ * the first batch that uses it and freed with the table; it holds as many
+ * lanes as a launch uses, as long as that stays within 1/32 of the table's
+ * device memory (at least 4096 lanes).  A batch needing more takes its
+ * scratch from the device's stream-ordered memory pool and returns it on
+ * `stream`.  Two insert batches of one table must therefore not overlap in
+ * time (order them on one stream).
  * Errors: CKPP_EINVAL (null table/keys/values with n > 0, misaligned keys),
  * CKPP_ENOMEM (scratch allocation failed). */
 int ckpp_insert_batch(ckpp_table *t, const void *d_keys, const uint64_t *d_values, uint64_t n,

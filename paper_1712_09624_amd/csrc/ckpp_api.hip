@@ -164,6 +164,15 @@ int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uin
   if (lanes < 256) lanes = 256;
   if (lanes > kMaxPathLanes) lanes = kMaxPathLanes;
   t->path_lanes = (uint32_t)lanes;
+  // the table's own path scratch: as many lanes as a launch may use while
+  // it stays within a small share of the table's memory, at least 4096
+  {
+    const uint64_t lane_bytes = 4ull * (max_kicks ? max_kicks : 1u);
+    uint64_t own = table_bytes(t) / ckpp::kOwnPathShare / lane_bytes;
+    if (own > lanes) own = lanes;
+    if (own < ckpp::kOwnPathLanesMin) own = ckpp::kOwnPathLanesMin;
+    t->own_path_lanes = (uint32_t)own;
+  }
 
   int rc = CKPP_OK;
   if (hipMalloc(&t->d_table, table_bytes(t)) != hipSuccess ||
@@ -191,7 +200,7 @@ int ckpp_destroy(ckpp_table *t) {
   (void)hipDeviceSynchronize();
   (void)hipFree(t->d_table);
   (void)hipFree(t->d_stats);
-  if (t->d_small_paths) (void)hipFree(t->d_small_paths);
+  if (t->d_own_paths) (void)hipFree(t->d_own_paths);
   delete t;
   return CKPP_OK;
 }

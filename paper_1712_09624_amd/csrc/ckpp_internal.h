@@ -14,8 +14,9 @@ struct ckpp_table {
   uint64_t seed;
   uint8_t *d_table;     // 256 * 2^B bytes: bucket b at 256 * b (ckpp_device.h)
   uint32_t path_lanes;  // lanes of the persistent insert grid
-  uint32_t *d_small_paths;  // cuckoo-path scratch of small insert batches
-                            // (kSmallPathLanes lanes), allocated on first use
+  uint32_t *d_own_paths;    // the table's own cuckoo-path scratch (own_path_lanes
+                            // lanes), allocated on the first batch that fits it
+  uint32_t own_path_lanes;
   uint64_t *d_stats;    // device accumulator of ckpp_stats_t
   ckpp_launch_t lookup_launch;
   int num_cus;
@@ -23,10 +24,15 @@ struct ckpp_table {
 
 namespace ckpp {
 
-// Insert batches launching at most this many lanes take their cuckoo-path
-// scratch from the table's own buffer instead of the stream-ordered pool
-// (whose allocate/free pair costs tens of microseconds on the host).
-constexpr uint32_t kSmallPathLanes = 4096;
+// Insert batches take their cuckoo-path scratch (max_kicks words per
+// launched lane) from a buffer of the table's own, kept for its lifetime,
+// when it fits: the stream-ordered pool's allocate/free pair costs tens of
+// microseconds of host time per batch, during which the device idles.  The
+// buffer holds at least kOwnPathLanesMin lanes, and more up to the launch's
+// maximum while it stays within 1/kOwnPathShare of the table's own memory;
+// larger batches use the pool.
+constexpr uint32_t kOwnPathLanesMin = 4096;
+constexpr uint64_t kOwnPathShare = 32;
 
 // One work item of a plan: lookups [start, start + count) of the
 // concatenated key batch, all of one table, with that table's parameters

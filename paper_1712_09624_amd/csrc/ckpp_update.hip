@@ -130,19 +130,19 @@ hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t
   const uint32_t block = 256;
   const uint32_t grid = (uint32_t)((lanes + block - 1) / block);
   // cuckoo-path scratch of this batch, one path of max_kicks entries per
-  // launched lane: the table's small buffer when it is enough, else
+  // launched lane: the table's own buffer when it is large enough, else
   // stream-ordered from the device's pool
   const uint64_t per_lane = (uint64_t)(t->max_kicks ? t->max_kicks : 1u);
   const uint64_t words = (uint64_t)grid * block * per_lane;
   uint32_t *paths = nullptr;
-  const bool small = (uint64_t)grid * block <= kSmallPathLanes;
+  const bool own = (uint64_t)grid * block <= t->own_path_lanes;
   hipError_t e = hipSuccess;
-  if (small) {
+  if (own) {
     ckpp_table *tm = const_cast<ckpp_table *>(t);
-    if (!tm->d_small_paths)
-      e = hipMalloc(reinterpret_cast<void **>(&tm->d_small_paths),
-                    (uint64_t)kSmallPathLanes * per_lane * sizeof(uint32_t));
-    paths = tm->d_small_paths;
+    if (!tm->d_own_paths)
+      e = hipMalloc(reinterpret_cast<void **>(&tm->d_own_paths),
+                    (uint64_t)t->own_path_lanes * per_lane * sizeof(uint32_t));
+    paths = tm->d_own_paths;
   } else {
     e = hipMallocAsync(reinterpret_cast<void **>(&paths), words * sizeof(uint32_t), s);
   }
@@ -160,7 +160,7 @@ hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t
                        d_values, nullptr, 0u, n, t->log2_buckets, t->seed, t->max_kicks, plain,
                        paths, d_status, nfailed, nspin);
   e = hipGetLastError();
-  if (small) return e;
+  if (own) return e;
   const hipError_t f = hipFreeAsync(paths, s);
   return e != hipSuccess ? e : f;
 }
