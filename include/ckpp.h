@@ -274,6 +274,11 @@ int ckpp_info(const ckpp_table *t, ckpp_info_t *out);
  * lane owns two lookups; the lines of the second half land in registers
  * and are parked in LDS after the first half is analysed: twice the
  * requests in flight; the pessimistic mode always uses 1).
+ * lanes_per_lookup 4: each lane owns one lookup; a quad of 4 neighbouring
+ * lanes reads each of its four lookups' lines into registers (32 bytes per
+ * lane, one request per line) and analyses the line there, the lanes
+ * exchanging keys and answers through DPP; lookups_per_lane 1 or 2 (a
+ * quad then holds the lines of eight lookups); no LDS.
  * lanes_per_lookup 1: each lane reads the 32-byte head of its own bucket
  * (tags, filter, masks) into registers, and a candidate's key and value
  * only on a tag match; lookups_per_lane 1, 2 or 4; no LDS.
@@ -304,14 +309,15 @@ int ckpp_get_lookup_launch(const ckpp_table *t, ckpp_launch_t *cfg);
 typedef struct ckpp_plan ckpp_plan;
 
 /* Launch shape of a plan's kernel.  lookups_per_lane: 1 or 2 with
- * lanes_per_lookup 8, 1, 2 or 4 with lanes_per_lookup 1 (as in
+ * lanes_per_lookup 8 or 4, 1, 2 or 4 with lanes_per_lookup 1 (as in
  * ckpp_launch_t); block: 64, 128 or 256; blocks_per_cu: 1..64, the
  * persistent grid is blocks_per_cu blocks per compute unit (at most one
  * wavefront per work item); passes_per_item: 1..64; schedule:
  * CKPP_PLAN_STATIC (wavefront w runs items w, w + W, ... for W wavefronts)
  * or CKPP_PLAN_DYNAMIC (each wavefront takes the next item from a device
- * counter); lanes_per_lookup: 8 (a bucket line read by 8 lanes into LDS)
- * or 1 (each lane reads its bucket's head into registers). */
+ * counter); lanes_per_lookup: 8 (a bucket line read by 8 lanes into LDS),
+ * 4 (a line read into a quad's registers) or 1 (each lane reads its
+ * bucket's head into registers). */
 enum { CKPP_PLAN_STATIC = 0, CKPP_PLAN_DYNAMIC = 1 };
 
 typedef struct {

@@ -34,6 +34,8 @@ def lookup_kernel_name(launch: dict, mode: str = "cuckoopp") -> str:
     """Name of the lookup kernel a launch shape selects for a lookup mode."""
     if launch["lanes_per_lookup"] == 1:
         return "lookup_reg"
+    if launch["lanes_per_lookup"] == 4:
+        return "lookup_quad"
     if launch["lookups_per_lane"] == 2 and mode != "both":
         return "lookup_dual"
     return "lookup_lds"

@@ -392,9 +392,9 @@ int ckpp_info(const ckpp_table *t, ckpp_info_t *out) {
 
 int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg) {
   if (!t || !cfg) return CKPP_EINVAL;
-  if (cfg->lanes_per_lookup != 1 && cfg->lanes_per_lookup != 8) return CKPP_EINVAL;
-  const uint32_t per = cfg->lookups_per_lane;
-  if (per != 1 && per != 2 && !(per == 4 && cfg->lanes_per_lookup == 1)) return CKPP_EINVAL;
+  const uint32_t lanes = cfg->lanes_per_lookup, per = cfg->lookups_per_lane;
+  if (lanes != 1 && lanes != 4 && lanes != 8) return CKPP_EINVAL;
+  if (per != 1 && per != 2 && !(per == 4 && lanes == 1)) return CKPP_EINVAL;
   if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return CKPP_EINVAL;
   if (cfg->blocks_per_cu > 4096) return CKPP_EINVAL;
   t->lookup_launch = *cfg;

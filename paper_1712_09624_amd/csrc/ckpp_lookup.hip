@@ -27,9 +27,11 @@
 // stream out with non-temporal accesses.
 //
 // Other forms of the same lookup: two lookups per lane (lookup_dual: the
-// second half's lines land in registers and are parked in LDS), one lane
-// per lookup with bucket heads in registers (lookup_reg), and a plan's
-// persistent kernel over many tables' batches (lookup_plan).  On a table
+// second half's lines land in registers and are parked in LDS), four lanes
+// per lookup with each line spread over a quad's registers and analysed
+// there (lookup_quad), one lane per lookup with bucket heads in registers
+// (lookup_reg), and a plan's persistent kernel over many tables' batches
+// (lookup_plan).  On a table
 // with timers (Sec. 4.2) a key match counts only if the entry is alive,
 // and a refreshing lookup writes the new time into the entry's value word.
 
@@ -86,6 +88,40 @@ __global__ void __launch_bounds__(64 * WAVES)
                     });
     ka = na;
     kb = nb;
+  }
+}
+
+// One table's batch, four lanes per line with the lines in registers, PER
+// lookups per lane per pass (lookups w0 + 64 j + lane of the wave's tile).
+template <uint32_t WAVES, uint32_t MODE, bool TIMED, uint32_t PER>
+__global__ void __launch_bounds__(64 * WAVES)
+    lookup_quad(TableRef T, const uint4 *__restrict__ keys, uint64_t n,
+                uint8_t *__restrict__ found, uint64_t *__restrict__ vals) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wave0 = ((uint64_t)blockIdx.x * WAVES + (threadIdx.x >> 6)) * 64u * PER;
+  const uint64_t stride = (uint64_t)gridDim.x * WAVES * 64u * PER;
+  uint4 k[PER];
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    const uint64_t i = wave0 + 64u * j + lane;
+    k[j] = i < n ? load_stream(keys + i) : zero4();
+  }
+  // the wave stays together (the quads exchange registers): the loop runs
+  // over the wave's tiles
+  for (uint64_t w0 = wave0; w0 < n; w0 += stride) {
+    bool ok[PER];
+    uint4 kn[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) ok[j] = w0 + 64u * j + lane < n;
+    quad_pass<MODE, TIMED, PER>(T, k, ok, found + w0 + lane, vals + w0 + lane, [&] {
+#pragma unroll
+      for (uint32_t j = 0; j < PER; ++j) {
+        const uint64_t i = w0 + stride + 64u * j + lane;
+        kn[j] = i < n ? load_stream(keys + i) : zero4();
+      }
+    });
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) k[j] = kn[j];
   }
 }
 
@@ -162,14 +198,17 @@ __device__ __forceinline__ void item_keys(const uint4 *keys, const PlanItem &I, 
 // LANES = 8: lines land in LDS (the passes of lookup_lds / lookup_dual,
 // PER 1 or 2); NB = 2 gives each wave the second line buffer of the
 // pessimistic mode, and with NB = 1 the host passes no pessimistic item.
-// LANES = 1: bucket heads in registers (the passes of lookup_reg, PER 1, 2
-// or 4, every mode, no LDS).
+// LANES = 4: lines spread over a quad's registers (the passes of
+// lookup_quad, PER 1 or 2, no LDS); NB = 2 compiles in the pessimistic
+// mode, whose secondary lines take registers of their own.  LANES = 1: bucket heads in
+// registers (the passes of lookup_reg, PER 1, 2 or 4, every mode, no LDS).
 template <uint32_t WAVES, uint32_t NB, uint32_t PER, bool DYN, uint32_t LANES>
 __global__ void __launch_bounds__(64 * WAVES)
     lookup_plan(const PlanItem *__restrict__ items, uint32_t nitems,
                 const uint4 *__restrict__ keys, uint8_t *__restrict__ found,
                 uint64_t *__restrict__ vals, uint32_t *__restrict__ ctr) {
   static_assert(LANES == 1 || PER <= 2, "lines in LDS: one or two lookups per lane");
+  static_assert(LANES != 4 || PER <= 2, "lines in a quad: one or two lookups per lane");
   constexpr uint32_t P = 64u * PER;  // lookups per pass
   __shared__ uint4 s_lines[LANES == 8 ? WAVES * NB * kWaveQuarters : 1];
   Wave w;
@@ -217,6 +256,13 @@ __global__ void __launch_bounds__(64 * WAVES)
           reg_pass<kModeOptimistic, false, PER>(T, k, ok, found + ia, vals + ia, pre);
         else
           reg_pass<kModeBoth, false, PER>(T, k, ok, found + ia, vals + ia, pre);
+      } else if constexpr (LANES == 4) {
+        if (I.mode == kModeCuckoopp)
+          quad_pass<kModeCuckoopp, false, PER>(T, k, ok, found + ia, vals + ia, pre);
+        else if (I.mode == kModeOptimistic)
+          quad_pass<kModeOptimistic, false, PER>(T, k, ok, found + ia, vals + ia, pre);
+        else if (NB == 2)
+          quad_pass<kModeBoth, false, PER>(T, k, ok, found + ia, vals + ia, pre);
       } else if constexpr (PER == 1) {
         if (I.mode == kModeCuckoopp) {
           lds_pass<kModeCuckoopp>(w, T, k[0], ok[0], found + ia, vals + ia, pre);
@@ -278,10 +324,25 @@ hipError_t launch_reg(const ckpp_table *t, const TableRef &T, const uint4 *keys,
   return hipGetLastError();
 }
 
+template <uint32_t WAVES, uint32_t MODE, bool TIMED, uint32_t PER>
+hipError_t launch_quad(const ckpp_table *t, const TableRef &T, const uint4 *keys, uint64_t n,
+                       uint8_t *found, uint64_t *vals, hipStream_t s) {
+  const uint64_t grid =
+      capped_grid(n, 64ull * PER * WAVES, t->lookup_launch.blocks_per_cu, t->num_cus);
+  hipLaunchKernelGGL((lookup_quad<WAVES, MODE, TIMED, PER>), dim3((uint32_t)grid),
+                     dim3(64 * WAVES), 0, s, T, keys, n, found, vals);
+  return hipGetLastError();
+}
+
 template <uint32_t WAVES, uint32_t MODE, bool TIMED>
 hipError_t launch_shape(const ckpp_table *t, const TableRef &T, const uint4 *keys, uint64_t n,
                         uint8_t *found, uint64_t *vals, hipStream_t s) {
   const ckpp_launch_t &L = t->lookup_launch;
+  if (L.lanes_per_lookup == 4) {
+    if (L.lookups_per_lane == 2)
+      return launch_quad<WAVES, MODE, TIMED, 2>(t, T, keys, n, found, vals, s);
+    return launch_quad<WAVES, MODE, TIMED, 1>(t, T, keys, n, found, vals, s);
+  }
   if (L.lanes_per_lookup == 1) {
     if (L.lookups_per_lane == 4)
       return launch_reg<WAVES, MODE, TIMED, 4>(t, T, keys, n, found, vals, s);
@@ -349,6 +410,17 @@ hipError_t launch_plan_waves(const PlanItem *d_items, uint32_t nitems, uint32_t 
                                                vals, s);
     return launch_plan_shape<WAVES, 1, 1, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found,
                                              vals, s);
+  }
+  if (L.lanes_per_lookup == 4) {
+    if (L.lookups_per_lane == 2)
+      return two_buffers ? launch_plan_shape<WAVES, 2, 2, 4>(d_items, nitems, d_ctr, L, num_cus,
+                                                             keys, found, vals, s)
+                         : launch_plan_shape<WAVES, 1, 2, 4>(d_items, nitems, d_ctr, L, num_cus,
+                                                             keys, found, vals, s);
+    return two_buffers ? launch_plan_shape<WAVES, 2, 1, 4>(d_items, nitems, d_ctr, L, num_cus,
+                                                           keys, found, vals, s)
+                       : launch_plan_shape<WAVES, 1, 1, 4>(d_items, nitems, d_ctr, L, num_cus,
+                                                           keys, found, vals, s);
   }
   if (two_buffers) {
     if (L.lookups_per_lane == 2)

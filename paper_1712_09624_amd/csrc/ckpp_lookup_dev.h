@@ -447,5 +447,274 @@ __device__ __forceinline__ void reg_pass(const TableRef &T, const uint4 (&key)[P
   }
 }
 
+// ---- Four lanes per lookup, lines in registers ----------------------------
+// A quad of lanes (4q .. 4q+3) owns four lookups, one per lane, and reads
+// each of their lines together: lane j of the quad loads the line's j-th
+// 32-byte chunk (two 16-byte loads; the quad's loads of one line make one
+// memory request).  The chunks of a first line are the header (tags, filter,
+// masks) | keys of slots 0,1 | keys of slots 2,3 | value words of slots
+// 0..3; of a second line keys 4,5 | keys 6,7 | value words 4..7 | other[]
+// (not read).  A line is analysed where it lies: the header lane finds the
+// tag candidates and the filter test, the key lanes compare full keys, the
+// value lane picks the value; quad_perm DPP moves carry the lookup's key
+// and fields to the quad and the answer back to the lookup's lane.  No LDS;
+// 8 registers per line in flight per lane.
+
+template <uint32_t R>
+struct QuadR {
+  static constexpr uint32_t value = R;
+};
+
+// Runs f(QuadR<R>{}) for R = 0..3 (R a constant inside f, as DPP needs).
+template <class F>
+__device__ __forceinline__ void each_of_quad(F &&f) {
+  f(QuadR<0>{});
+  f(QuadR<1>{});
+  f(QuadR<2>{});
+  f(QuadR<3>{});
+}
+
+// Value of v in lane R of the caller's quad.  Every lane of the wave must be
+// active (DPP reads the other lane's register).
+template <uint32_t R>
+__device__ __forceinline__ uint32_t quad_get(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, (int)(R * 0x55u), 0xf, 0xf, false);
+}
+
+template <uint32_t R>
+__device__ __forceinline__ uint4 quad_get4(uint4 v) {
+  return make_uint4(quad_get<R>(v.x), quad_get<R>(v.y), quad_get<R>(v.z), quad_get<R>(v.w));
+}
+
+// OR of v over the caller's quad.
+__device__ __forceinline__ uint32_t quad_or(uint32_t v) {
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false);  // lanes 1,0,3,2
+  v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false);  // lanes 2,3,0,1
+  return v;
+}
+
+// Line `H` of the bucket of each of the quad's lookups whose lane passes a
+// bucket other than kNoFetch: c[R] receives this lane's chunk of lookup R's
+// line (zero when not fetched).
+template <uint32_t H>
+__device__ __forceinline__ void quad_fetch(uint4 (&c)[4][2], const uint4 *tab, uint32_t bucket,
+                                           uint32_t j) {
+  each_of_quad([&](auto rc) {
+    constexpr uint32_t R = decltype(rc)::value;
+    const uint32_t b = quad_get<R>(bucket);
+    c[R][0] = c[R][1] = zero4();
+    if (b != kNoFetch && (H == 0u || j < 3u)) {
+      const uint4 *src = tab + (uint64_t)b * kQuartersPerBucket + 8u * H + 2u * j;
+      c[R][0] = src[0];
+      c[R][1] = src[1];
+    }
+  });
+}
+
+// Answer of one line for one lookup, the same in every lane of the quad.
+struct QuadAnswer {
+  uint32_t cand;  // first line: tag candidates (tag match and busy)
+  bool pass;      // first line: the filter holds both of the key's bits
+  bool hit;
+  uint32_t slot;
+  uint64_t val;
+};
+
+// The value lane's part: the first slot of m (ascending) whose entry is
+// alive picks its value word from the lane's two quarters (four words of
+// consecutive slots from `first`); the answer is broadcast from lane VL.
+template <bool TIMED, uint32_t VL>
+__device__ __forceinline__ void quad_pick(const uint4 (&c)[2], uint32_t j, uint32_t m,
+                                          uint32_t first, uint32_t now, QuadAnswer &A) {
+  uint32_t res = 0u, lo = 0u, hi = 0u;
+  if (j == VL) {
+    uint64_t w[4];
+    w[0] = (uint64_t)c[0].x | ((uint64_t)c[0].y << 32);
+    w[1] = (uint64_t)c[0].z | ((uint64_t)c[0].w << 32);
+    w[2] = (uint64_t)c[1].x | ((uint64_t)c[1].y << 32);
+    w[3] = (uint64_t)c[1].z | ((uint64_t)c[1].w << 32);
+    uint32_t live = m;
+    if (TIMED) {
+#pragma unroll
+      for (uint32_t s = 0; s < 4u; ++s)
+        if (!word_alive(w[s], now)) live &= ~(1u << (first + s));
+    }
+    if (live != 0u) {
+      const uint32_t s = (uint32_t)__builtin_ctz(live), i = s - first;
+      const uint64_t wi = (i & 2u) ? ((i & 1u) ? w[3] : w[2]) : ((i & 1u) ? w[1] : w[0]);
+      const uint64_t v = TIMED ? (wi & kValueMask) : wi;
+      res = 1u | (s << 1);
+      lo = (uint32_t)v;
+      hi = (uint32_t)(v >> 32);
+    }
+  }
+  res = quad_get<VL>(res);
+  lo = quad_get<VL>(lo);
+  hi = quad_get<VL>(hi);
+  A.hit = (res & 1u) != 0u;
+  A.slot = res >> 1;
+  A.val = (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// First line of a bucket for the quad's lookup whose key is k and whose tag
+// and filter bits are packed in pk (tag | bit index 1 << 16 | bit index 2
+// << 22): slots 0..3.
+template <bool TIMED>
+__device__ __forceinline__ QuadAnswer quad_first(const uint4 (&c)[2], uint32_t j, uint4 k,
+                                                 uint32_t pk, uint32_t now) {
+  uint32_t x = 0u;
+  if (j == 0u) {
+    const uint32_t cand = tag_eq_mask(c[0], pk & 0xffffu) & meta_busy(c[1].z);
+    const uint64_t bits = (1ull << ((pk >> 16) & 63u)) | (1ull << ((pk >> 22) & 63u));
+    x = (cand << 8) | (bloom_pass(c[1], bits) ? 0x10000u : 0u);
+  } else if (j < 3u) {
+    x = ((key_eq(c[0], k) ? 1u : 0u) | (key_eq(c[1], k) ? 2u : 0u)) << (2u * (j - 1u));
+  }
+  x = quad_or(x);
+  QuadAnswer A;
+  A.cand = (x >> 8) & 0xffu;
+  A.pass = (x & 0x10000u) != 0u;
+  quad_pick<TIMED, 3>(c, j, x & (x >> 8) & 0xfu, 0u, now, A);
+  return A;
+}
+
+// Second line of a bucket: slots 4..7 among the candidates cm.
+template <bool TIMED>
+__device__ __forceinline__ QuadAnswer quad_second(const uint4 (&c)[2], uint32_t j, uint4 k,
+                                                  uint32_t cm, uint32_t now) {
+  uint32_t x = 0u;
+  if (j < 2u) x = ((key_eq(c[0], k) ? 1u : 0u) | (key_eq(c[1], k) ? 2u : 0u)) << (4u + 2u * j);
+  x = quad_or(x);
+  QuadAnswer A;
+  A.cand = 0u;
+  A.pass = false;
+  quad_pick<TIMED, 2>(c, j, x & cm & 0xf0u, 4u, now, A);
+  return A;
+}
+
+// One pass of a wave over 64 * PER lookups (PER 1 or 2), four lanes per
+// line: lookup j of lane l is lookup 64 j + l of the tile, its results at
+// found[64 j] / vals[64 j] (the caller offsets both by the lane); the
+// phases and answers are those of lds_pass.  `pre` runs once the first
+// lines are requested.
+template <uint32_t MODE, bool TIMED, uint32_t PER, class Pre>
+__device__ __forceinline__ void quad_pass(const TableRef &T, const uint4 (&key)[PER],
+                                          const bool (&ok)[PER], uint8_t *found, uint64_t *vals,
+                                          Pre &&pre) {
+  const uint32_t j = threadIdx.x & 3u;
+  KeyFields f[PER];
+  uint32_t pk[PER];  // tag | filter bit index 1 << 16 | index 2 << 22
+  uint4 c[PER][4][2], d[PER][4][2];  // chunks of the primary's and the secondary's lines
+#pragma unroll
+  for (uint32_t p = 0; p < PER; ++p) {
+    const uint64_t h = key_hash(key[p], T.seed);
+    f[p] = key_fields(h, T.log2b);
+    pk[p] = f[p].tag | (((uint32_t)(h >> 24) & 0xfffu) << 16);
+    quad_fetch<0>(c[p], T.tab, ok[p] ? f[p].p : kNoFetch, j);
+    if (MODE == kModeBoth) quad_fetch<0>(d[p], T.tab, ok[p] ? f[p].a : kNoFetch, j);
+  }
+  pre();
+  // the quad's keys and packed fields are fetched from their lanes where
+  // used (a DPP move each) rather than held: registers are line slots
+  bool hit[PER], pass[PER], hit_primary[PER], need[PER];
+  uint64_t val[PER];
+  uint32_t slot[PER], cand[PER];
+  auto take = [&](uint32_t p, const QuadAnswer &A) {
+    hit[p] = true;
+    val[p] = A.val;
+    slot[p] = A.slot;
+  };
+  bool any = false;
+#pragma unroll
+  for (uint32_t p = 0; p < PER; ++p) {
+    hit[p] = pass[p] = false;
+    val[p] = 0ull;
+    slot[p] = cand[p] = 0u;
+    each_of_quad([&](auto rc) {
+      constexpr uint32_t R = decltype(rc)::value;
+      const QuadAnswer A =
+          quad_first<TIMED>(c[p][R], j, quad_get4<R>(key[p]), quad_get<R>(pk[p]), T.now);
+      if (j == R && ok[p]) {
+        cand[p] = A.cand;
+        pass[p] = MODE != kModeCuckoopp || A.pass;
+        if (A.hit) take(p, A);
+      }
+    });
+    // second line of the primary, for keys whose tag sits in slots 4..7
+    need[p] = !hit[p] && (cand[p] & 0xf0u);
+    any = any || need[p];
+  }
+  if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+    for (uint32_t p = 0; p < PER; ++p)
+      quad_fetch<1>(c[p], T.tab, need[p] ? f[p].p : kNoFetch, j);
+#pragma unroll
+    for (uint32_t p = 0; p < PER; ++p) {
+      const uint32_t cm = need[p] ? cand[p] : 0u;
+      each_of_quad([&](auto rc) {
+        constexpr uint32_t R = decltype(rc)::value;
+        const QuadAnswer A =
+            quad_second<TIMED>(c[p][R], j, quad_get4<R>(key[p]), quad_get<R>(cm), T.now);
+        if (j == R && need[p] && A.hit) take(p, A);
+      });
+    }
+  }
+  // secondary bucket
+  any = false;
+#pragma unroll
+  for (uint32_t p = 0; p < PER; ++p) {
+    hit_primary[p] = hit[p];
+    need[p] = ok[p] && !hit[p] && pass[p];
+    any = any || need[p];
+  }
+  if (__builtin_amdgcn_ballot_w64(any)) {
+    if (MODE != kModeBoth) {
+#pragma unroll
+      for (uint32_t p = 0; p < PER; ++p)
+        quad_fetch<0>(d[p], T.tab, need[p] ? f[p].a : kNoFetch, j);
+    }
+    any = false;
+#pragma unroll
+    for (uint32_t p = 0; p < PER; ++p) {
+      uint32_t cand2 = 0u;
+      each_of_quad([&](auto rc) {
+        constexpr uint32_t R = decltype(rc)::value;
+        const QuadAnswer A =
+            quad_first<TIMED>(d[p][R], j, quad_get4<R>(key[p]), quad_get<R>(pk[p]), T.now);
+        if (j == R && need[p]) {
+          cand2 = A.cand;
+          if (A.hit) take(p, A);
+        }
+      });
+      cand[p] = cand2;
+      need[p] = need[p] && !hit[p] && (cand2 & 0xf0u);
+      any = any || need[p];
+    }
+    if (__builtin_amdgcn_ballot_w64(any)) {
+#pragma unroll
+      for (uint32_t p = 0; p < PER; ++p)
+        quad_fetch<1>(d[p], T.tab, need[p] ? f[p].a : kNoFetch, j);
+#pragma unroll
+      for (uint32_t p = 0; p < PER; ++p) {
+        const uint32_t cm = need[p] ? cand[p] : 0u;
+        each_of_quad([&](auto rc) {
+          constexpr uint32_t R = decltype(rc)::value;
+          const QuadAnswer A =
+              quad_second<TIMED>(d[p][R], j, quad_get4<R>(key[p]), quad_get<R>(cm), T.now);
+          if (j == R && need[p] && A.hit) take(p, A);
+        });
+      }
+    }
+  }
+#pragma unroll
+  for (uint32_t p = 0; p < PER; ++p) {
+    if (!ok[p]) continue;
+    if (TIMED && T.refresh && hit[p])
+      refresh_entry(T, hit_primary[p] ? f[p].p : f[p].a, slot[p]);
+    __builtin_nontemporal_store((uint8_t)(hit[p] ? 1 : 0), found + 64u * p);
+    __builtin_nontemporal_store(hit[p] ? val[p] : 0ull, vals + 64u * p);
+  }
+}
+
 }  // namespace
 }  // namespace ckpp

@@ -32,7 +32,8 @@ namespace {
 bool aligned(const void *p, uintptr_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 bool valid_launch(const ckpp_plan_launch_t &L) {
-  const bool lanes_ok = L.lanes_per_lookup == 1 || L.lanes_per_lookup == 8;
+  const bool lanes_ok =
+      L.lanes_per_lookup == 1 || L.lanes_per_lookup == 4 || L.lanes_per_lookup == 8;
   const bool per_ok = L.lookups_per_lane == 1 || L.lookups_per_lane == 2 ||
                       (L.lookups_per_lane == 4 && L.lanes_per_lookup == 1);
   return lanes_ok && per_ok &&

@@ -1,8 +1,8 @@
 """Launch-shape autotuner of the lookup kernels and of plans.
 
 Times every lookup launch shape (lanes per lookup: 8, lines landing in LDS,
-or 1, bucket heads in registers; lookups in flight per lane, block size,
-grid cap) on a caller's table and key batches, and returns
+4, lines spread over a quad's registers, or 1, bucket heads in registers;
+lookups in flight per lane, block size, grid cap) on a caller's table and key batches, and returns
 the shapes ranked by lookups per second.  Timing uses device events on the
 current stream; the answers do not depend on the shape (the parity tests
 check every shape), only the speed does.
@@ -15,6 +15,9 @@ import itertools
 SHAPES = [
     {"lanes_per_lookup": lanes, "lookups_per_lane": per, "block": block, "blocks_per_cu": bpc}
     for lanes, per, block, bpc in itertools.product((8,), (1, 2), (64, 128, 256), (0, 5, 10))
+] + [
+    {"lanes_per_lookup": 4, "lookups_per_lane": per, "block": block, "blocks_per_cu": bpc}
+    for per, block, bpc in itertools.product((1, 2), (64, 128, 256), (0, 8, 16))
 ] + [
     {"lanes_per_lookup": 1, "lookups_per_lane": per, "block": block, "blocks_per_cu": bpc}
     for per, block, bpc in itertools.product((1, 2, 4), (64, 128, 256), (0, 8, 16))
@@ -61,14 +64,15 @@ def tune(table, batches, mode="cuckoopp", shapes=None, reps=3, apply=True):
 
 
 # Launch shapes of a plan's persistent kernel: lanes per lookup (8: lines in
-# LDS, 1: bucket heads in registers) with lookups per lane, block size,
+# LDS, 4: lines in a quad's registers, 1: bucket heads in registers) with
+# lookups per lane, block size,
 # blocks per compute unit (persistent grid), lookup passes per work item and
 # schedule (0 static, 1 dynamic).
 PLAN_SHAPES = [
     {"lookups_per_lane": per, "block": block, "blocks_per_cu": bpc, "passes_per_item": passes,
      "schedule": sched, "lanes_per_lookup": lanes}
     for (lanes, per), block, bpc, passes, sched in itertools.product(
-        ((8, 1), (8, 2), (1, 1), (1, 2), (1, 4)), (64, 128, 256), (2, 4, 8, 16), (1, 2, 4), (0, 1))
+        ((8, 1), (8, 2), (4, 1), (4, 2), (1, 1), (1, 2), (1, 4)), (64, 128, 256), (2, 4, 8, 16), (1, 2, 4), (0, 1))
 ]
 
 

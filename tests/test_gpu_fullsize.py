@@ -73,6 +73,12 @@ def test_benchmark_table_lookups():
     check_lookups(t, pos, np.ones(len(pos), np.uint8), vals[idx])
     say("full size: 2^26 negative lookups, three modes")
     check_lookups(t, neg, np.zeros(len(neg), np.uint8), np.zeros(len(neg), np.uint64))
+    # the other lookup forms the tuners choose from: 4 lanes and 1 lane per lookup
+    for shape in ((4, 1, 256, 0), (1, 2, 128, 0)):
+        t.set_lookup_launch(*shape)
+        say(f"full size: positive and negative lookups, three modes, shape {shape}")
+        check_lookups(t, pos, np.ones(len(pos), np.uint8), vals[idx])
+        check_lookups(t, neg, np.zeros(len(neg), np.uint8), np.zeros(len(neg), np.uint64))
     say("full size: image invariants")
     check_image(t)
     t.close()

@@ -15,7 +15,10 @@ pytestmark = pytest.mark.gpu
 
 MODES = [("cuckoopp", O.MODE_CUCKOOPP), ("both", O.MODE_BOTH), ("optimistic", O.MODE_OPTIMISTIC)]
 SHAPES = [(8, per, block, bpc) for per in (1, 2) for block in (64, 128, 256) for bpc in (0, 1, 3)]
+SHAPES += [(4, per, block, bpc) for per in (1, 2) for block in (64, 128, 256) for bpc in (0, 3)]
 SHAPES += [(1, per, block, bpc) for per in (1, 2, 4) for block in (64, 256) for bpc in (0, 3)]
+# the default shape and one of each other form, for the degenerate tables
+FORMS = [None, (8, 1, 64, 0), (4, 1, 128, 0), (4, 2, 64, 0), (1, 2, 64, 0)]
 
 
 @pytest.fixture(scope="module")
@@ -121,6 +124,17 @@ def test_default_launch_shape():
     t.close()
 
 
+def test_lookup_launch_rejects_bad_shapes():
+    from paper_1712_09624_amd import ckpp
+    t = ckpp.Table(8, W.HASH_SEED, device=0)
+    for shape in ((2, 1, 128, 0), (4, 3, 128, 0), (4, 4, 128, 0), (8, 4, 128, 0), (1, 3, 128, 0),
+                  (8, 1, 96, 0), (4, 1, 512, 0)):
+        with pytest.raises(ckpp.CkppError):
+            t.set_lookup_launch(*shape)
+    assert t.get_lookup_launch() == ckpp.DEFAULT_LAUNCH
+    t.close()
+
+
 def test_empty_table_misses_everything():
     from paper_1712_09624_amd.ckpp import Table
     q = W.five_tuples(5000, 3)
@@ -132,8 +146,9 @@ def test_empty_table_misses_everything():
     t.close()
 
 
+@pytest.mark.parametrize("form", FORMS, ids=lambda s: "default" if s is None else f"l{s[0]}k{s[1]}")
 @pytest.mark.parametrize("B,load", [(1, 1.0), (2, 0.95), (3, 0.9), (6, 0.95), (10, 0.95)])
-def test_tiny_and_full_tables(B, load):
+def test_tiny_and_full_tables(B, load, form):
     """Degenerate sizes: 2 buckets (every key shares the pair), and tables
     filled to high load, where many keys sit in their secondary bucket."""
     n = W.keys_at_load(B, load)
@@ -142,16 +157,19 @@ def test_tiny_and_full_tables(B, load):
     st = ref.insert(keys, W.insertion_values(n))
     look = np.concatenate([keys, W.five_tuples(4 * n + 10, 50 + B)])
     t = gpu_table_from(ref)
+    if form:
+        t.set_lookup_launch(*form)
     for mode, omode in MODES:
         want_f, want_v, _, _ = ref.lookup(look, omode)
         assert int(want_f[:n].sum()) == int((st == O.INSERTED).sum())
-        say(f"tiny B={B} load={load} mode={mode}")
+        say(f"tiny B={B} load={load} mode={mode} shape={form}")
         f, v = t.lookup(to_dev(look), mode)
         assert np.array_equal(u8(f), want_f) and np.array_equal(u64(v), want_v)
     t.close()
 
 
-def test_colliding_keys():
+@pytest.mark.parametrize("form", FORMS, ids=lambda s: "default" if s is None else f"l{s[0]}k{s[1]}")
+def test_colliding_keys(form):
     """Keys sharing bucket, tag and the first 8 bytes keep their own values."""
     import oracle_pins as P
     k1, k2 = P.colliding_pair(O.load())
@@ -159,8 +177,10 @@ def test_colliding_keys():
     ref = O.OracleTable(1, W.HASH_SEED, W.MAX_KICKS)
     ref.insert(keys, np.array([11, 22], np.uint64))
     t = gpu_table_from(ref)
+    if form:
+        t.set_lookup_launch(*form)
     for mode, _ in MODES:
-        say(f"colliding keys mode={mode}")
+        say(f"colliding keys mode={mode} shape={form}")
         f, v = t.lookup(to_dev(keys), mode)
         assert list(u8(f)) == [1, 1] and list(u64(v)) == [11, 22]
     t.close()

@@ -17,6 +17,8 @@ pytestmark = pytest.mark.gpu
 OMODE = {"cuckoopp": O.MODE_CUCKOOPP, "both": O.MODE_BOTH, "optimistic": O.MODE_OPTIMISTIC}
 PLAN_SHAPES = [(per, block, bpc, passes, sched, 8) for per in (1, 2) for block in (64, 128, 256)
                for bpc, passes in ((1, 1), (8, 1), (2, 3)) for sched in (0, 1)]
+PLAN_SHAPES += [(per, block, bpc, passes, sched, 4) for per in (1, 2) for block in (64, 256)
+                for bpc, passes in ((8, 1), (2, 3)) for sched in (0, 1)]
 PLAN_SHAPES += [(per, block, bpc, passes, sched, 1) for per in (1, 2, 4) for block in (64, 256)
                 for bpc, passes in ((8, 1), (2, 3)) for sched in (0, 1)]
 SENTINEL_F, SENTINEL_V = 0xAB, 0x5A5A5A5A5A5A5A5A
@@ -128,6 +130,29 @@ def test_plan_matches_oracle(fleet, shape):
     plan.close()
 
 
+NO_PESSIMISTIC_SHAPES = [(1, 128, 8, 1, 0, 8), (2, 256, 4, 1, 1, 8), (1, 128, 8, 1, 0, 4),
+                         (1, 64, 4, 2, 1, 4), (2, 256, 16, 3, 0, 4), (2, 64, 8, 1, 1, 4),
+                         (2, 128, 8, 1, 0, 1)]
+
+
+@pytest.mark.parametrize("shape", NO_PESSIMISTIC_SHAPES,
+                         ids=[f"per{a}_b{b}_bpc{c}_p{d}_s{e}_l{g}"
+                              for a, b, c, d, e, g in NO_PESSIMISTIC_SHAPES])
+def test_plan_without_pessimistic_tables(shape):
+    """A plan with no pessimistic table runs the kernel built without that
+    mode (one line buffer with 8 lanes, fewer registers with 4)."""
+    from paper_1712_09624_amd.ckpp import Plan
+    f = Fleet(40, 13, 1, 12, 1, 900, modes=["cuckoopp", "optimistic"], zero_every=9)
+    want_f, want_v = f.expected()
+    plan = Plan(f.tables, f.offsets, f.counts, f.modes)
+    plan.set_launch(*shape)
+    say(f"plan without pessimistic tables, shape={shape} span={f.span}")
+    got_f, got_v = run_plan(plan, f)
+    assert np.array_equal(got_f, want_f) and np.array_equal(got_v, want_v)
+    plan.close()
+    f.close()
+
+
 def test_plan_equals_per_table_calls(fleet):
     """The plan's answers are those of one ckpp_lookup_batch per table."""
     from paper_1712_09624_amd.ckpp import Plan
@@ -151,7 +176,7 @@ def test_plan_info_and_items():
     assert inf["ntables"] == 5 and inf["lookups"] == int(f.counts.sum())
     assert inf["key_span"] == f.span
     assert plan.get_launch() == ckpp_default_plan_launch()
-    for per, passes, lanes in ((1, 1, 8), (2, 1, 8), (2, 4, 8), (4, 2, 1)):
+    for per, passes, lanes in ((1, 1, 8), (2, 1, 8), (2, 4, 8), (1, 3, 4), (2, 2, 4), (4, 2, 1)):
         plan.set_launch(per, 128, 4, passes, 0, lanes)
         tile = 64 * per * passes
         assert plan.info()["nitems"] == int(sum((int(c) + tile - 1) // tile for c in f.counts))
@@ -178,8 +203,10 @@ def test_plan_rejects_bad_arguments():
         plan.set_launch(2, 128, 4, 1, 2)
     with pytest.raises(CkppError):  # four lookups per lane need one lane per lookup
         plan.set_launch(4, 128, 4, 1, 0, 8)
-    with pytest.raises(CkppError):
-        plan.set_launch(1, 128, 4, 1, 0, 4)
+    with pytest.raises(CkppError):  # two lanes per lookup: no such form
+        plan.set_launch(1, 128, 4, 1, 0, 2)
+    with pytest.raises(CkppError):  # four lookups per lane need one lane per lookup
+        plan.set_launch(4, 128, 4, 1, 0, 4)
     with pytest.raises(CkppError):  # fewer keys than the plan's span
         plan.lookup(torch.zeros((30, 16), dtype=torch.uint8, device="cuda:0"))
     plan.close()

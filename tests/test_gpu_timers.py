@@ -80,6 +80,7 @@ def test_timed_lookup_bit_exact(timed_cfg1, mode, omode):
 
 
 @pytest.mark.parametrize("shape", [(8, 1, 64, 0), (8, 1, 256, 3), (8, 2, 64, 1), (8, 2, 256, 0),
+                                   (4, 1, 64, 0), (4, 1, 256, 3), (4, 2, 128, 0),
                                    (1, 1, 64, 0), (1, 2, 128, 3), (1, 4, 256, 0)])
 def test_timed_lookup_launch_shapes(timed_cfg1, shape):
     B, now0, ref, keys, exp, look = timed_cfg1
@@ -119,7 +120,7 @@ def test_refreshing_lookup_image_bit_exact(timed_cfg1, mode, omode):
     t.close()
 
 
-@pytest.mark.parametrize("shape", [(1, 1, 64, 0), (1, 4, 256, 0), (8, 1, 256, 0)])
+@pytest.mark.parametrize("shape", [(1, 1, 64, 0), (1, 4, 256, 0), (4, 1, 128, 0), (4, 2, 64, 0), (8, 1, 256, 0)])
 def test_refreshing_lookup_shapes(timed_cfg1, shape):
     """Refreshing lookups of the other kernels (one lane per lookup with
     bucket heads in registers, one lookup per lane with lines in LDS) leave
