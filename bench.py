@@ -581,6 +581,44 @@ def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
     out["plan_achieved_GBps"] = alg_bytes / (out["plan_eager_us"] * 1e-6) / 1e9
     out["plan_frac_hbm_peak"] = out["plan_achieved_GBps"] / HBM_PEAK_GBS
     del g_plan, g_tab
+    tuned = plan.get_launch()
+    plan.close()
+    for t in tables:
+        t.close()
+    # (c) the same tables with timers (Sec. 4.2): every entry's expiration
+    # time uniform over the 1024 units after now0, so all are alive at now0
+    # and the answers are those above; one plan launch at the tuned shape,
+    # plain and refreshing
+    now0 = 65000
+    t0 = time.perf_counter()
+    tables = []
+    for i in range(ntables):
+        B, load = int(cfg["log2_buckets"][i]), float(cfg["load"][i])
+        n = W.keys_at_load(B, load)
+        keys = W.distinct_five_tuples(n, seed * 10000 + i, check=False)
+        vals = W.insertion_values(n, i << 32)
+        exp = W.times_after(n, now0, 1024, seed * 10000 + i)
+        t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=dev.index, timers=True)
+        t.insert_at(to_dev(keys, dev), to_dev(vals.view(np.int64), dev),
+                    to_dev(exp.view(np.int16), dev), now0, nfailed=nfail)
+        tables.append(t)
+    torch.cuda.synchronize()
+    out["timed_build_s"] = time.perf_counter() - t0
+    if int(nfail.item()):
+        raise RuntimeError(f"{int(nfail.item())} inserts failed while building the timed tables")
+    plan = Plan(tables, offsets, counts)
+    plan.set_launch(tuned["lookups_per_lane"], tuned["block"], tuned["blocks_per_cu"],
+                    tuned["passes_per_item"], tuned["schedule"], tuned["lanes_per_lookup"])
+    plan.lookup(keys_d, found, vals_d, now=now0)
+    check("plan with timers")
+    out["plan_timed_us"] = timed(lambda: plan.lookup(keys_d, found, vals_d, now=now0), reps,
+                                 dev) * 1e3
+    refresh = (now0 + 1000) & 0xFFFF
+    plan.lookup(keys_d, found, vals_d, now=now0, refresh=refresh)
+    check("refreshing plan with timers")
+    out["plan_timed_refresh_us"] = timed(
+        lambda: plan.lookup(keys_d, found, vals_d, now=now0, refresh=refresh), reps, dev) * 1e3
+    out["plan_timed_overhead"] = out["plan_timed_us"] / out["plan_eager_us"] - 1.0
     plan.close()
     for t in tables:
         t.close()

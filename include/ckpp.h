@@ -342,6 +342,8 @@ typedef struct {
  * positions of the output arrays; the ranges must not overlap (a count may
  * be 0).  h_modes (nullable: all CKPP_LOOKUP_DEFAULT) gives each table's
  * lookup mode; CKPP_LOOKUP_DEFAULT on a plain table is CKPP_LOOKUP_BOTH.
+ * Tables with timers may take part: such a plan is run with
+ * ckpp_plan_lookup_at.
  * The plan keeps the tables' device addresses, not the tables: it must be
  * destroyed before any of them, and inserts and deletes between plan
  * lookups are seen by the next one.  Host arrays are read during the call
@@ -362,9 +364,21 @@ int ckpp_plan_destroy(ckpp_plan *p);
  * be captured in a HIP graph.  The dynamic schedule's work counter lives in
  * the plan's device memory, so two launches of one plan must not overlap in
  * time (order them on one stream).  Must not run concurrently with inserts or deletes on its
- * tables.  Errors: CKPP_EINVAL (null or misaligned pointers). */
+ * tables.  Errors: CKPP_EINVAL (null or misaligned pointers, a plan with a
+ * table with timers). */
 int ckpp_plan_lookup(ckpp_plan *p, const void *d_keys, uint8_t *d_found, uint64_t *d_values,
                      void *stream);
+
+/* As ckpp_plan_lookup for a plan with tables with timers (Sec. 4.2): each
+ * such table's batch is that of ckpp_lookup_batch_at(table, ..., now,
+ * refresh, expiry); the other tables' batches are as in ckpp_plan_lookup.
+ * With refresh = 1 the tables with timers are written (the launch must not
+ * run concurrently with other lookups of them), and expiry must lie in
+ * [now, now + 1023] mod 2^16.  Errors: as ckpp_plan_lookup; CKPP_EINVAL on
+ * a plan without a table with timers, refresh > 1, or a refresh time outside
+ * the window. */
+int ckpp_plan_lookup_at(ckpp_plan *p, const void *d_keys, uint8_t *d_found, uint64_t *d_values,
+                        uint16_t now, uint32_t refresh, uint16_t expiry, void *stream);
 
 /* Sets the launch shape (rebuilds the work items: synchronizes the device,
  * not for use under graph capture).  Errors: CKPP_EINVAL (out of range). */
@@ -450,7 +464,8 @@ typedef struct {
 
 /* Creates a server on table t (the table must not be used by other calls
  * while the server exists) and launches its loop.
- * Errors: CKPP_EINVAL (bad config), CKPP_ENOMEM, CKPP_EDEVICE. */
+ * Errors: CKPP_EINVAL (bad config, a table with timers), CKPP_ENOMEM,
+ * CKPP_EDEVICE. */
 int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_config_t *cfg);
 
 int ckpp_server_rings(const ckpp_server *s, ckpp_server_rings_t *out);

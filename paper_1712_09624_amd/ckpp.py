@@ -181,6 +181,8 @@ SIGNATURES = [
     ("ckpp_plan_create", _I, [ctypes.POINTER(_VP), ctypes.POINTER(_VP), _U32, _VP, _VP, _VP]),
     ("ckpp_plan_destroy", _I, [_VP]),
     ("ckpp_plan_lookup", _I, [_VP, _VP, _VP, _VP, _VP]),
+    ("ckpp_plan_lookup_at", _I, [_VP, _VP, _VP, _VP, ctypes.c_uint16, _U32, ctypes.c_uint16,
+                                 _VP]),
     ("ckpp_plan_set_launch", _I, [_VP, ctypes.POINTER(_PlanLaunch)]),
     ("ckpp_plan_get_launch", _I, [_VP, ctypes.POINTER(_PlanLaunch)]),
     ("ckpp_plan_info", _I, [_VP, ctypes.POINTER(_PlanInfo)]),
@@ -520,8 +522,11 @@ class Plan:
     def __exit__(self, *exc):
         self.close()
 
-    def lookup(self, keys, found=None, values=None, stream=None):
-        """Enqueues the plan's lookups; returns (found u8[span], values i64[span])."""
+    def lookup(self, keys, found=None, values=None, stream=None, now=None, refresh=None):
+        """Enqueues the plan's lookups; returns (found u8[span], values i64[span]).
+        A plan with tables with timers runs at time `now` (required), and with
+        `refresh` (a u16 time) every entry found on them gets that expiration
+        time."""
         torch = _torch()
         kp, n = _keys_ptr(keys)
         if n < self.key_span:
@@ -533,9 +538,16 @@ class Plan:
             values = torch.zeros(self.key_span, dtype=torch.int64, device=dev)
         if found.numel() < self.key_span or values.numel() < self.key_span:
             raise CkppError("output arrays shorter than the plan's key span")
-        rc = self.lib.ckpp_plan_lookup(self._h, kp, found.data_ptr(), values.data_ptr(),
-                                       _stream_handle(stream))
-        _check(rc, "ckpp_plan_lookup")
+        if now is None:
+            rc = self.lib.ckpp_plan_lookup(self._h, kp, found.data_ptr(), values.data_ptr(),
+                                           _stream_handle(stream))
+            _check(rc, "ckpp_plan_lookup")
+        else:
+            rc = self.lib.ckpp_plan_lookup_at(self._h, kp, found.data_ptr(), values.data_ptr(),
+                                              int(now) & 0xFFFF, 0 if refresh is None else 1,
+                                              0 if refresh is None else int(refresh) & 0xFFFF,
+                                              _stream_handle(stream))
+            _check(rc, "ckpp_plan_lookup_at")
         return found, values
 
     def set_launch(self, lookups_per_lane=DEFAULT_PLAN_LAUNCH["lookups_per_lane"],

@@ -111,7 +111,6 @@ bool timed(const ckpp_table *t) { return (t->flags & CKPP_TIMERS) != 0; }
 
 // A refresh time must keep the entry alive at `now` (Sec. 4.2: expiration
 // times lie within 1024 units after the current time).
-bool in_window(uint32_t expiry, uint32_t now) { return ((expiry - now) & 0xffffu) < 1024u; }
 
 }  // namespace
 
@@ -284,7 +283,7 @@ int ckpp_lookup_batch_at(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t
                          uint16_t now, uint32_t refresh, uint16_t expiry, uint8_t *d_found,
                          uint64_t *d_values, void *stream) {
   if (!t || !timed(t) || refresh > 1u) return CKPP_EINVAL;
-  if (refresh && !in_window(expiry, now)) return CKPP_EINVAL;
+  if (refresh && !ckpp::in_window(expiry, now)) return CKPP_EINVAL;
   const ckpp::TimerArgs tm{now, refresh, expiry};
   return lookup_common(t, d_keys, n, mode, &tm, d_found, d_values, stream);
 }

@@ -50,6 +50,25 @@ struct PlanItem {
 constexpr uint32_t kModeCuckoopp = 0;
 constexpr uint32_t kModeBoth = 1;
 constexpr uint32_t kModeOptimistic = 2;
+// PlanItem::mode: the lookup mode in the low byte, and this flag on a table
+// with timers.
+constexpr uint32_t kPlanModeMask = 0xffu;
+constexpr uint32_t kPlanItemTimed = 0x100u;
+
+// Blocks of a launch over n items, per_block items per block: at most
+// blocks_per_cu per compute unit (0: no cap) and at most 2^31 - 1.
+inline uint64_t capped_grid(uint64_t n, uint64_t per_block, uint32_t blocks_per_cu, int num_cus) {
+  uint64_t grid = (n + per_block - 1) / per_block;
+  if (blocks_per_cu) {
+    const uint64_t cap = (uint64_t)blocks_per_cu * (uint64_t)num_cus;
+    if (grid > cap) grid = cap;
+  }
+  return grid > 0x7fffffffull ? 0x7fffffffull : grid;
+}
+
+// A refreshing lookup's new expiration time lies in [now, now + 1023] mod
+// 2^16, so the entry it writes is alive at `now` (Sec. 4.2).
+inline bool in_window(uint32_t expiry, uint32_t now) { return ((expiry - now) & 0xffffu) < 1024u; }
 
 // Timers of a batch on a table with timers (Sec. 4.2): the current time;
 // for lookups, whether a hit sets the entry's expiration time to `expiry`.
@@ -66,10 +85,11 @@ hipError_t launch_lookup(const ckpp_table *t, const void *d_keys, uint64_t n, ui
 // One launch of the plan's persistent lookup kernel over its items.
 // d_ctr: two u32 counters (next item, finished waves), zero before the
 // launch and zero again after it.  two_buffers: some table uses the
-// pessimistic mode.
+// pessimistic mode.  timers: the launch's time, for the items flagged
+// kPlanItemTimed (null: no item is).
 hipError_t launch_plan(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr, bool two_buffers,
-                       const ckpp_plan_launch_t &L, int num_cus, const void *d_keys,
-                       uint8_t *d_found, uint64_t *d_values, hipStream_t s);
+                       const TimerArgs *timers, const ckpp_plan_launch_t &L, int num_cus,
+                       const void *d_keys, uint8_t *d_found, uint64_t *d_values, hipStream_t s);
 // d_expiry and timers: null on a table without timers.
 hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t *d_values,
                          const uint16_t *d_expiry, const TimerArgs *timers, uint64_t n,

@@ -30,8 +30,8 @@
 // second half's lines land in registers and are parked in LDS), four lanes
 // per lookup with each line spread over a quad's registers and analysed
 // there (lookup_quad), one lane per lookup with bucket heads in registers
-// (lookup_reg), and a plan's persistent kernel over many tables' batches
-// (lookup_plan).  On a table
+// (lookup_reg).  A plan's persistent kernel over many tables' batches
+// (lookup_plan, in ckpp_plan.hip) runs the same passes.  On a table
 // with timers (Sec. 4.2) a key match counts only if the entry is alive,
 // and a refreshing lookup writes the new time into the entry's value word.
 
@@ -157,162 +157,6 @@ __global__ void __launch_bounds__(64 * WAVES)
   }
 }
 
-// The wave's next work item: lane 0 takes a ticket from the plan's counter
-// and the wave shares it.
-__device__ __forceinline__ uint32_t take_item(uint32_t *ctr, uint32_t lane) {
-  uint32_t v = 0u;
-  if (lane == 0u) v = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-
-// The item after `prev` for this wave: the wave's own stride through the
-// list (static schedule) or the next ticket (dynamic schedule); once past
-// the end, it stays there.
-template <bool DYN>
-__device__ __forceinline__ uint32_t next_item(uint32_t prev, uint32_t stride, uint32_t nitems,
-                                              uint32_t *ctr, uint32_t lane) {
-  if (prev >= nitems) return prev;
-  return DYN ? take_item(ctr, lane) : prev + stride;
-}
-
-// Keys of one pass of an item: lookups off + 64 j + lane.
-template <uint32_t PER>
-__device__ __forceinline__ void item_keys(const uint4 *keys, const PlanItem &I, uint32_t off,
-                                          uint32_t lane, uint4 (&k)[PER]) {
-#pragma unroll
-  for (uint32_t j = 0; j < PER; ++j) {
-    const uint32_t o = off + 64u * j + lane;
-    k[j] = o < I.count ? load_stream(keys + I.start + o) : zero4();
-  }
-}
-
-// A plan's batches in one persistent launch.  Each wave runs work items (a
-// range of one table's batch, in passes of PER * 64 lookups) in a
-// three-deep pipeline: while item `cur` runs, the descriptor of the next
-// item is already loaded and the index of the one after is known; the last
-// pass of `cur` loads the next item's first keys, the descriptor after it
-// and the next index, all independent loads issued while that pass's lines
-// are in flight.  DYN: items are handed out by a device counter (the wave
-// that finishes last rewinds it, so the next launch or graph replay starts
-// from zero without a memory set); else wave w runs items w, w + W, ...
-// LANES = 8: lines land in LDS (the passes of lookup_lds / lookup_dual,
-// PER 1 or 2); NB = 2 gives each wave the second line buffer of the
-// pessimistic mode, and with NB = 1 the host passes no pessimistic item.
-// LANES = 4: lines spread over a quad's registers (the passes of
-// lookup_quad, PER 1 or 2, no LDS); NB = 2 compiles in the pessimistic
-// mode, whose secondary lines take registers of their own.  LANES = 1: bucket heads in
-// registers (the passes of lookup_reg, PER 1, 2 or 4, every mode, no LDS).
-template <uint32_t WAVES, uint32_t NB, uint32_t PER, bool DYN, uint32_t LANES>
-__global__ void __launch_bounds__(64 * WAVES)
-    lookup_plan(const PlanItem *__restrict__ items, uint32_t nitems,
-                const uint4 *__restrict__ keys, uint8_t *__restrict__ found,
-                uint64_t *__restrict__ vals, uint32_t *__restrict__ ctr) {
-  static_assert(LANES == 1 || PER <= 2, "lines in LDS: one or two lookups per lane");
-  static_assert(LANES != 4 || PER <= 2, "lines in a quad: one or two lookups per lane");
-  constexpr uint32_t P = 64u * PER;  // lookups per pass
-  __shared__ uint4 s_lines[LANES == 8 ? WAVES * NB * kWaveQuarters : 1];
-  Wave w;
-  if constexpr (LANES == 8) w = wave_lines<NB>(s_lines);
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t stride = gridDim.x * WAVES;
-  const uint32_t wave_id =
-      (uint32_t)__builtin_amdgcn_readfirstlane((int)(blockIdx.x * WAVES + (threadIdx.x >> 6)));
-  uint32_t cur = DYN ? take_item(ctr, lane) : wave_id;
-  uint32_t n1 = next_item<DYN>(cur, stride, nitems, ctr, lane);
-  uint32_t n2 = next_item<DYN>(n1, stride, nitems, ctr, lane);
-  const PlanItem none{nullptr, 0ull, 0ull, 0u, 0u, 0u, 0u};
-  PlanItem I = cur < nitems ? items[cur] : none;
-  PlanItem I1 = n1 < nitems ? items[n1] : none;
-  uint4 k[PER];
-#pragma unroll
-  for (uint32_t j = 0; j < PER; ++j) k[j] = zero4();
-  if (cur < nitems) item_keys<PER>(keys, I, 0u, lane, k);
-  while (cur < nitems) {
-    const TableRef T{I.tab, I.seed, I.log2b};
-    PlanItem I2 = none;
-    uint32_t n3 = n2;
-    for (uint32_t off = 0u; off < I.count; off += P) {
-      const bool last = off + P >= I.count;
-      uint4 kn[PER];
-#pragma unroll
-      for (uint32_t j = 0; j < PER; ++j) kn[j] = zero4();
-      auto pre = [&] {
-        if (!last) {
-          item_keys<PER>(keys, I, off + P, lane, kn);
-        } else {
-          if (n1 < nitems) item_keys<PER>(keys, I1, 0u, lane, kn);
-          if (n2 < nitems) I2 = items[n2];
-          n3 = next_item<DYN>(n2, stride, nitems, ctr, lane);
-        }
-      };
-      const uint64_t ia = I.start + off + lane;
-      bool ok[PER];
-#pragma unroll
-      for (uint32_t j = 0; j < PER; ++j) ok[j] = off + 64u * j + lane < I.count;
-      if constexpr (LANES == 1) {
-        if (I.mode == kModeCuckoopp)
-          reg_pass<kModeCuckoopp, false, PER>(T, k, ok, found + ia, vals + ia, pre);
-        else if (I.mode == kModeOptimistic)
-          reg_pass<kModeOptimistic, false, PER>(T, k, ok, found + ia, vals + ia, pre);
-        else
-          reg_pass<kModeBoth, false, PER>(T, k, ok, found + ia, vals + ia, pre);
-      } else if constexpr (LANES == 4) {
-        if (I.mode == kModeCuckoopp)
-          quad_pass<kModeCuckoopp, false, PER>(T, k, ok, found + ia, vals + ia, pre);
-        else if (I.mode == kModeOptimistic)
-          quad_pass<kModeOptimistic, false, PER>(T, k, ok, found + ia, vals + ia, pre);
-        else if (NB == 2)
-          quad_pass<kModeBoth, false, PER>(T, k, ok, found + ia, vals + ia, pre);
-      } else if constexpr (PER == 1) {
-        if (I.mode == kModeCuckoopp) {
-          lds_pass<kModeCuckoopp>(w, T, k[0], ok[0], found + ia, vals + ia, pre);
-        } else if (I.mode == kModeOptimistic) {
-          lds_pass<kModeOptimistic>(w, T, k[0], ok[0], found + ia, vals + ia, pre);
-        } else if (NB == 2) {
-          lds_pass<kModeBoth>(w, T, k[0], ok[0], found + ia, vals + ia, pre);
-        }
-      } else {
-        const uint64_t ib = ia + 64u;
-        if (I.mode == kModeCuckoopp) {
-          dual_pass<kModeCuckoopp>(w, T, k[0], ok[0], k[1], ok[1], found + ia, vals + ia,
-                                   found + ib, vals + ib, pre);
-        } else if (I.mode == kModeOptimistic) {
-          dual_pass<kModeOptimistic>(w, T, k[0], ok[0], k[1], ok[1], found + ia, vals + ia,
-                                     found + ib, vals + ib, pre);
-        } else if (NB == 2) {
-          lds_pass<kModeBoth>(w, T, k[0], ok[0], found + ia, vals + ia, [] {});
-          lds_pass<kModeBoth>(w, T, k[1], ok[1], found + ib, vals + ib, pre);
-        }
-      }
-#pragma unroll
-      for (uint32_t j = 0; j < PER; ++j) k[j] = kn[j];
-    }
-    cur = n1;
-    I = I1;
-    n1 = n2;
-    I1 = I2;
-    n2 = n3;
-  }
-  if (DYN && lane == 0u) {
-    // every ticket this wave will ever take is taken: count the wave out;
-    // the last one (which sees every other wave's tickets) rewinds both
-    const uint32_t out = __hip_atomic_fetch_add(ctr + 1, 1u, __ATOMIC_ACQ_REL,
-                                                __HIP_MEMORY_SCOPE_AGENT);
-    if (out == gridDim.x * WAVES - 1u) {
-      __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(ctr + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-}
-
-uint64_t capped_grid(uint64_t n, uint64_t per_block, uint32_t blocks_per_cu, int num_cus) {
-  uint64_t grid = (n + per_block - 1) / per_block;
-  if (blocks_per_cu) {
-    const uint64_t cap = (uint64_t)blocks_per_cu * (uint64_t)num_cus;
-    if (grid > cap) grid = cap;
-  }
-  return grid > 0x7fffffffull ? 0x7fffffffull : grid;
-}
 
 template <uint32_t WAVES, uint32_t MODE, bool TIMED, uint32_t PER>
 hipError_t launch_reg(const ckpp_table *t, const TableRef &T, const uint4 *keys, uint64_t n,
@@ -382,79 +226,7 @@ hipError_t launch_timing(const ckpp_table *t, const TableRef &T, const uint4 *ke
   return launch_mode<kModeCuckoopp, TIMED>(t, T, keys, n, found, vals, s);
 }
 
-template <uint32_t WAVES, uint32_t NB, uint32_t PER, uint32_t LANES>
-hipError_t launch_plan_shape(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr,
-                             const ckpp_plan_launch_t &L, int num_cus, const uint4 *keys,
-                             uint8_t *found, uint64_t *vals, hipStream_t s) {
-  // persistent grid: blocks_per_cu per CU, but no more waves than items
-  const uint64_t grid = capped_grid(nitems, WAVES, L.blocks_per_cu, num_cus);
-  if (L.schedule == CKPP_PLAN_DYNAMIC)
-    hipLaunchKernelGGL((lookup_plan<WAVES, NB, PER, true, LANES>), dim3((uint32_t)grid),
-                       dim3(64 * WAVES), 0, s, d_items, nitems, keys, found, vals, d_ctr);
-  else
-    hipLaunchKernelGGL((lookup_plan<WAVES, NB, PER, false, LANES>), dim3((uint32_t)grid),
-                       dim3(64 * WAVES), 0, s, d_items, nitems, keys, found, vals, d_ctr);
-  return hipGetLastError();
-}
-
-template <uint32_t WAVES>
-hipError_t launch_plan_waves(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr,
-                             bool two_buffers, const ckpp_plan_launch_t &L, int num_cus,
-                             const uint4 *keys, uint8_t *found, uint64_t *vals, hipStream_t s) {
-  if (L.lanes_per_lookup == 1) {
-    if (L.lookups_per_lane == 4)
-      return launch_plan_shape<WAVES, 1, 4, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found,
-                                               vals, s);
-    if (L.lookups_per_lane == 2)
-      return launch_plan_shape<WAVES, 1, 2, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found,
-                                               vals, s);
-    return launch_plan_shape<WAVES, 1, 1, 1>(d_items, nitems, d_ctr, L, num_cus, keys, found,
-                                             vals, s);
-  }
-  if (L.lanes_per_lookup == 4) {
-    if (L.lookups_per_lane == 2)
-      return two_buffers ? launch_plan_shape<WAVES, 2, 2, 4>(d_items, nitems, d_ctr, L, num_cus,
-                                                             keys, found, vals, s)
-                         : launch_plan_shape<WAVES, 1, 2, 4>(d_items, nitems, d_ctr, L, num_cus,
-                                                             keys, found, vals, s);
-    return two_buffers ? launch_plan_shape<WAVES, 2, 1, 4>(d_items, nitems, d_ctr, L, num_cus,
-                                                           keys, found, vals, s)
-                       : launch_plan_shape<WAVES, 1, 1, 4>(d_items, nitems, d_ctr, L, num_cus,
-                                                           keys, found, vals, s);
-  }
-  if (two_buffers) {
-    if (L.lookups_per_lane == 2)
-      return launch_plan_shape<WAVES, 2, 2, 8>(d_items, nitems, d_ctr, L, num_cus, keys, found,
-                                               vals, s);
-    return launch_plan_shape<WAVES, 2, 1, 8>(d_items, nitems, d_ctr, L, num_cus, keys, found,
-                                             vals, s);
-  }
-  if (L.lookups_per_lane == 2)
-    return launch_plan_shape<WAVES, 1, 2, 8>(d_items, nitems, d_ctr, L, num_cus, keys, found,
-                                             vals, s);
-  return launch_plan_shape<WAVES, 1, 1, 8>(d_items, nitems, d_ctr, L, num_cus, keys, found, vals,
-                                           s);
-}
-
 }  // namespace
-
-hipError_t launch_plan(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr, bool two_buffers,
-                       const ckpp_plan_launch_t &L, int num_cus, const void *d_keys,
-                       uint8_t *d_found, uint64_t *d_values, hipStream_t s) {
-  if (nitems == 0) return hipSuccess;
-  const uint4 *keys = reinterpret_cast<const uint4 *>(d_keys);
-  switch (L.block) {
-    case 64:
-      return launch_plan_waves<1>(d_items, nitems, d_ctr, two_buffers, L, num_cus, keys, d_found,
-                                  d_values, s);
-    case 128:
-      return launch_plan_waves<2>(d_items, nitems, d_ctr, two_buffers, L, num_cus, keys, d_found,
-                                  d_values, s);
-    default:
-      return launch_plan_waves<4>(d_items, nitems, d_ctr, two_buffers, L, num_cus, keys, d_found,
-                                  d_values, s);
-  }
-}
 
 hipError_t launch_lookup(const ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
                          const TimerArgs *timers, uint8_t *d_found, uint64_t *d_values,

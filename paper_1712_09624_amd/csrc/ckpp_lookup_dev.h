@@ -45,6 +45,11 @@ __device__ __forceinline__ uint64_t quarter_value(uint4 q, uint32_t s) {
                   : ((uint64_t)q.x | ((uint64_t)q.y << 32));
 }
 
+// `now` of a table without timers in a timed pass (a plan's kernel serves
+// tables of both kinds with the timed passes): every entry counts and the
+// whole word is the value.
+constexpr uint32_t kNoTime = 0x10000u;
+
 // A slot answers the lookup iff its full key equals the searched key and,
 // with timers, its entry is alive at `now` (Sec. 4.2: expired entries are
 // not considered); on a hit sets hit, val (the value without the time) and
@@ -52,9 +57,10 @@ __device__ __forceinline__ uint64_t quarter_value(uint4 q, uint32_t s) {
 template <bool TIMED>
 __device__ __forceinline__ void take_word(uint64_t w, uint32_t s, uint32_t now, bool &hit,
                                           uint64_t &val, uint32_t &slot) {
-  if (!TIMED || word_alive(w, now)) {
+  const bool timed = TIMED && now < kNoTime;
+  if (!timed || word_alive(w, now)) {
     hit = true;
-    val = TIMED ? (w & kValueMask) : w;
+    val = timed ? (w & kValueMask) : w;
     slot = s;
   }
 }
@@ -533,8 +539,9 @@ __device__ __forceinline__ void quad_pick(const uint4 (&c)[2], uint32_t j, uint3
     w[1] = (uint64_t)c[0].z | ((uint64_t)c[0].w << 32);
     w[2] = (uint64_t)c[1].x | ((uint64_t)c[1].y << 32);
     w[3] = (uint64_t)c[1].z | ((uint64_t)c[1].w << 32);
+    const bool timed = TIMED && now < kNoTime;
     uint32_t live = m;
-    if (TIMED) {
+    if (timed) {
 #pragma unroll
       for (uint32_t s = 0; s < 4u; ++s)
         if (!word_alive(w[s], now)) live &= ~(1u << (first + s));
@@ -542,7 +549,7 @@ __device__ __forceinline__ void quad_pick(const uint4 (&c)[2], uint32_t j, uint3
     if (live != 0u) {
       const uint32_t s = (uint32_t)__builtin_ctz(live), i = s - first;
       const uint64_t wi = (i & 2u) ? ((i & 1u) ? w[3] : w[2]) : ((i & 1u) ? w[1] : w[0]);
-      const uint64_t v = TIMED ? (wi & kValueMask) : wi;
+      const uint64_t v = timed ? (wi & kValueMask) : wi;
       res = 1u | (s << 1);
       lo = (uint32_t)v;
       hi = (uint32_t)(v >> 32);

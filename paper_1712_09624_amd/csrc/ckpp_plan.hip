@@ -1,12 +1,30 @@
-// ckpp_plan.hip -- the C ABI of plans: many tables' lookup batches served by
-// one persistent launch (the kernel is in ckpp_lookup.hip).
+// ckpp_plan.hip -- plans: many tables' lookup batches served by one
+// persistent launch.  The kernel (lookup_plan, ckpp_plan_dev.h) runs the
+// lookup passes of the one-table kernels over work items; the C ABI below
+// cuts the batches into items and launches it.  This unit instantiates the
+// kernel without timers, ckpp_plan_timed.hip the one with.
 
 #include <algorithm>
 #include <new>
 #include <stdint.h>
 #include <vector>
 
-#include "ckpp_internal.h"
+#include "ckpp_plan_dev.h"
+
+namespace ckpp {
+
+hipError_t launch_plan(const PlanItem *d_items, uint32_t nitems, uint32_t *d_ctr, bool two_buffers,
+                       const TimerArgs *timers, const ckpp_plan_launch_t &L, int num_cus,
+                       const void *d_keys, uint8_t *d_found, uint64_t *d_values, hipStream_t s) {
+  if (nitems == 0) return hipSuccess;
+  PlanArgs A{d_items, nitems, reinterpret_cast<const uint4 *>(d_keys), d_found, d_values, d_ctr,
+             TimerArgs{0u, 0u, 0u}};
+  if (!timers) return launch_plan_block<false>(A, two_buffers, L, num_cus, s);
+  A.tm = *timers;
+  return launch_plan_timed(A, two_buffers, L, num_cus, s);
+}
+
+}  // namespace ckpp
 
 using ckpp::DeviceGuard;
 using ckpp::dev_status;
@@ -17,6 +35,7 @@ struct ckpp_plan {
   int num_cus;
   uint32_t ntables;
   bool two_buffers;  // some table uses the pessimistic mode
+  bool timed;        // some table has timers
   uint64_t lookups;
   uint64_t key_span;
   std::vector<uint64_t> offsets, counts;
@@ -82,6 +101,19 @@ void free_plan(ckpp_plan *p) {
   delete p;
 }
 
+int plan_lookup(ckpp_plan *p, const void *d_keys, uint8_t *d_found, uint64_t *d_values,
+                const ckpp::TimerArgs *tm, void *stream) {
+  if (p->nitems == 0) return CKPP_OK;
+  if (!d_keys || !d_found || !d_values) return CKPP_EINVAL;
+  if (!aligned(d_keys, 16) || !aligned(d_values, 8)) return CKPP_EINVAL;
+  DeviceGuard g(p->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  return dev_status(ckpp::launch_plan(p->d_items, p->nitems, p->d_ctr, p->two_buffers, tm,
+                                      p->launch, p->num_cus, d_keys, d_found, d_values,
+                                      reinterpret_cast<hipStream_t>(stream)));
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -94,19 +126,21 @@ int ckpp_plan_create(ckpp_plan **out, ckpp_table *const *tables, uint32_t ntable
   if (!tables || ntables == 0 || !h_offsets || !h_counts) return CKPP_EINVAL;
   std::vector<PlanItem> desc(ntables);
   std::vector<uint32_t> order(ntables);
-  bool two = false;
+  bool two = false, any_timed = false;
   uint64_t lookups = 0, span = 0;
   for (uint32_t i = 0; i < ntables; ++i) {
     const ckpp_table *t = tables[i];
-    if (!t || t->device != tables[0]->device || (t->flags & CKPP_TIMERS)) return CKPP_EINVAL;
+    if (!t || t->device != tables[0]->device) return CKPP_EINVAL;
     uint32_t mode = h_modes ? h_modes[i] : (uint32_t)CKPP_LOOKUP_DEFAULT;
     if (mode > CKPP_LOOKUP_OPTIMISTIC) return CKPP_EINVAL;
     // a plain table keeps no filter: its default lookup reads both buckets
     if (mode == CKPP_LOOKUP_DEFAULT && (t->flags & CKPP_PLAIN)) mode = CKPP_LOOKUP_BOTH;
     two = two || mode == CKPP_LOOKUP_BOTH;
     if (h_counts[i] > (1ull << 40) || h_offsets[i] > (1ull << 40)) return CKPP_EINVAL;
+    const bool tm = (t->flags & CKPP_TIMERS) != 0u;
+    any_timed = any_timed || tm;
     desc[i] = PlanItem{reinterpret_cast<const uint4 *>(t->d_table), t->seed, 0ull, 0u,
-                       t->log2_buckets, mode, i};
+                       t->log2_buckets, mode | (tm ? ckpp::kPlanItemTimed : 0u), i};
     lookups += h_counts[i];
     span = std::max(span, h_offsets[i] + h_counts[i]);
     order[i] = i;
@@ -129,6 +163,7 @@ int ckpp_plan_create(ckpp_plan **out, ckpp_table *const *tables, uint32_t ntable
   p->num_cus = tables[0]->num_cus;
   p->ntables = ntables;
   p->two_buffers = two;
+  p->timed = any_timed;
   p->lookups = lookups;
   p->key_span = span;
   p->offsets.assign(h_offsets, h_offsets + ntables);
@@ -162,17 +197,19 @@ int ckpp_plan_destroy(ckpp_plan *p) {
   return CKPP_OK;
 }
 
+
 int ckpp_plan_lookup(ckpp_plan *p, const void *d_keys, uint8_t *d_found, uint64_t *d_values,
                      void *stream) {
-  if (!p) return CKPP_EINVAL;
-  if (p->nitems == 0) return CKPP_OK;
-  if (!d_keys || !d_found || !d_values) return CKPP_EINVAL;
-  if (!aligned(d_keys, 16) || !aligned(d_values, 8)) return CKPP_EINVAL;
-  DeviceGuard g(p->device);
-  if (!g.ok()) return CKPP_EDEVICE;
-  return dev_status(ckpp::launch_plan(p->d_items, p->nitems, p->d_ctr, p->two_buffers, p->launch,
-                                      p->num_cus, d_keys, d_found, d_values,
-                                      reinterpret_cast<hipStream_t>(stream)));
+  if (!p || p->timed) return CKPP_EINVAL;
+  return plan_lookup(p, d_keys, d_found, d_values, nullptr, stream);
+}
+
+int ckpp_plan_lookup_at(ckpp_plan *p, const void *d_keys, uint8_t *d_found, uint64_t *d_values,
+                        uint16_t now, uint32_t refresh, uint16_t expiry, void *stream) {
+  if (!p || !p->timed || refresh > 1u) return CKPP_EINVAL;
+  if (refresh && !ckpp::in_window(expiry, now)) return CKPP_EINVAL;
+  const ckpp::TimerArgs tm{now, refresh, expiry};
+  return plan_lookup(p, d_keys, d_found, d_values, &tm, stream);
 }
 
 int ckpp_plan_set_launch(ckpp_plan *p, const ckpp_plan_launch_t *cfg) {

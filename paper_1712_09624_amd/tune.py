@@ -76,31 +76,32 @@ PLAN_SHAPES = [
 ]
 
 
-def time_plan(plan, keys, found, values, reps=5):
+def time_plan(plan, keys, found, values, reps=5, **lookup_args):
     import torch
     s = torch.cuda.current_stream()
-    plan.lookup(keys, found, values)
+    plan.lookup(keys, found, values, **lookup_args)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(reps):
-        plan.lookup(keys, found, values)
+        plan.lookup(keys, found, values, **lookup_args)
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps
 
 
-def tune_plan(plan, keys, found, values, shapes=None, reps=5, apply=True):
-    """Times every plan launch shape on the plan's own batches.  Returns
-    [(ms, shape)] sorted fastest first, and keeps the fastest shape on the
-    plan when apply is true (else restores the shape it had)."""
+def tune_plan(plan, keys, found, values, shapes=None, reps=5, apply=True, **lookup_args):
+    """Times every plan launch shape on the plan's own batches (lookup_args,
+    e.g. now= for a plan with tables with timers, go to each lookup).
+    Returns [(ms, shape)] sorted fastest first, and keeps the fastest shape
+    on the plan when apply is true (else restores the shape it had)."""
     shapes = shapes or PLAN_SHAPES
     before = plan.get_launch()
     results = []
     for sh in shapes:
         plan.set_launch(sh["lookups_per_lane"], sh["block"], sh["blocks_per_cu"],
                         sh["passes_per_item"], sh["schedule"], sh["lanes_per_lookup"])
-        results.append((time_plan(plan, keys, found, values, reps), dict(sh)))
+        results.append((time_plan(plan, keys, found, values, reps, **lookup_args), dict(sh)))
     results.sort(key=lambda r: r[0])
     best = results[0][1] if apply else before
     plan.set_launch(best["lookups_per_lane"], best["block"], best["blocks_per_cu"],

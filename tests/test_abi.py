@@ -78,6 +78,7 @@ def test_argument_checks_need_no_device(lib):
     assert lib.ckpp_plan_create(ctypes.byref(h), tabs, 0, offs, cnts, None) == ckpp.EINVAL
     assert lib.ckpp_plan_create(ctypes.byref(h), tabs, 1, offs, cnts, None) == ckpp.EINVAL
     assert lib.ckpp_plan_lookup(None, None, None, None, None) == ckpp.EINVAL
+    assert lib.ckpp_plan_lookup_at(None, None, None, None, 0, 0, 0, None) == ckpp.EINVAL
     assert lib.ckpp_plan_set_launch(None, None) == ckpp.EINVAL
     assert lib.ckpp_plan_destroy(None) == ckpp.OK
     assert lib.ckpp_server_create(None, None, None) == ckpp.EINVAL

@@ -29,7 +29,10 @@ class Fleet:
     oracle; batches concatenated with gaps between the ranges."""
 
     def __init__(self, ntables, seed, log2_lo, log2_hi, batch_lo, batch_hi, plain_every=0,
-                 modes=None, zero_every=0):
+                 modes=None, zero_every=0, timed_every=0, now0=0):
+        """timed_every: every timed_every-th table (from the second) has
+        timers, its entries' expiration times uniform over the 1024 units
+        after now0."""
         from paper_1712_09624_amd.ckpp import Table
         cfg = W.many_tables(ntables, seed, log2_lo, log2_hi, 0.6, 0.95, batch_lo, batch_hi)
         self.refs, self.tables, self.keys, self.live = [], [], [], []
@@ -39,11 +42,16 @@ class Fleet:
         for i in range(ntables):
             B = int(cfg["log2_buckets"][i])
             plain = bool(plain_every) and i % plain_every == plain_every - 1
+            timed = bool(timed_every) and i % timed_every == 1
             n = W.keys_at_load(B, float(cfg["load"][i]))
             keys = W.distinct_five_tuples(n, seed * 1000 + i)
-            ref = O.OracleTable(B, W.HASH_SEED, W.MAX_KICKS, plain)
-            ref.insert(keys, W.insertion_values(n, 1000 * i))
-            t = Table(B, W.HASH_SEED, W.MAX_KICKS, plain=plain, device=0)
+            ref = O.OracleTable(B, W.HASH_SEED, W.MAX_KICKS, plain, timed=timed)
+            if timed:
+                exp = W.times_after(n, now0, 1024, seed * 1000 + i)
+                ref.insert_at(keys, W.insertion_values(n, 1000 * i), exp, now0)
+            else:
+                ref.insert(keys, W.insertion_values(n, 1000 * i))
+            t = Table(B, W.HASH_SEED, W.MAX_KICKS, plain=plain, device=0, timers=timed)
             b, k = ref.image()
             t.import_image(b, k)
             cnt = int(cfg["batch"][i])
@@ -67,8 +75,10 @@ class Fleet:
         self.all_keys = np.concatenate(chunks) if chunks else np.zeros((0, 16), np.uint8)
         self.span = pos
 
-    def expected(self):
-        """Oracle answers at every position; sentinels outside the ranges."""
+    def expected(self, now=None, refresh=None):
+        """Oracle answers at every position; sentinels outside the ranges.
+        Tables with timers answer at `now`, refreshing found entries to
+        `refresh` when it is given."""
         f = np.full(self.span, SENTINEL_F, np.uint8)
         v = np.full(self.span, SENTINEL_V, np.uint64)
         for i, ref in enumerate(self.refs):
@@ -78,7 +88,10 @@ class Fleet:
             mode = self.modes[i]
             if mode == "cuckoopp" and ref.plain:
                 mode = "both"
-            wf, wv, _, _ = ref.lookup(self.keys[i], OMODE[mode])
+            if ref.timed:
+                wf, wv = ref.lookup_at(self.keys[i], now, OMODE[mode], refresh=refresh)
+            else:
+                wf, wv, _, _ = ref.lookup(self.keys[i], OMODE[mode])
             f[o:o + c] = wf
             v[o:o + c] = wv
         return f, v
@@ -93,12 +106,12 @@ def ckpp_default_plan_launch():
     return ckpp.DEFAULT_PLAN_LAUNCH
 
 
-def run_plan(plan, fleet):
+def run_plan(plan, fleet, **lookup_args):
     import torch
     keys = to_dev(fleet.all_keys)
     found = torch.full((fleet.span,), SENTINEL_F, dtype=torch.uint8, device="cuda:0")
     vals = torch.full((fleet.span,), SENTINEL_V, dtype=torch.int64, device="cuda:0")
-    plan.lookup(keys, found, vals)
+    plan.lookup(keys, found, vals, **lookup_args)
     return u8(found), u64(vals)
 
 
@@ -149,6 +162,57 @@ def test_plan_without_pessimistic_tables(shape):
     say(f"plan without pessimistic tables, shape={shape} span={f.span}")
     got_f, got_v = run_plan(plan, f)
     assert np.array_equal(got_f, want_f) and np.array_equal(got_v, want_v)
+    plan.close()
+    f.close()
+
+
+TIMED_SHAPES = [(1, 128, 8, 1, 0, 8), (2, 64, 4, 2, 1, 8), (1, 128, 8, 1, 0, 4),
+                (2, 256, 2, 3, 1, 4), (1, 64, 8, 1, 0, 1), (4, 128, 4, 2, 1, 1)]
+
+
+@pytest.mark.parametrize("shape", TIMED_SHAPES, ids=[f"per{a}_b{b}_bpc{c}_p{d}_s{e}_l{g}"
+                                                     for a, b, c, d, e, g in TIMED_SHAPES])
+def test_plan_with_tables_with_timers(shape):
+    """Tables with and without timers in one plan: a table with timers
+    answers as the oracle's lookups at the launch's time (the clock wraps),
+    the others as without timers."""
+    from paper_1712_09624_amd.ckpp import CkppError, Plan
+    now0 = 65000
+    f = Fleet(30, 17, 1, 11, 1, 900, plain_every=4, modes=["cuckoopp", "optimistic", "both"],
+              zero_every=8, timed_every=2, now0=now0)
+    plan = Plan(f.tables, f.offsets, f.counts, f.modes)
+    plan.set_launch(*shape)
+    for dt in (0, 500, 1023, 1024):
+        now = (now0 + dt) & 0xFFFF
+        want_f, want_v = f.expected(now=now)
+        say(f"timed plan shape={shape} now={now}")
+        got_f, got_v = run_plan(plan, f, now=now)
+        assert np.array_equal(got_f, want_f), f"found differs at now={now}"
+        assert np.array_equal(got_v, want_v), f"values differ at now={now}"
+    with pytest.raises(CkppError):  # a plan with timed tables runs with a time
+        run_plan(plan, f)
+    plan.close()
+    f.close()
+
+
+def test_plan_refreshing_lookup_with_tables_with_timers():
+    """A refreshing plan lookup leaves every table's image as the oracle's
+    refreshing lookups do (the tables without timers untouched)."""
+    from paper_1712_09624_amd.ckpp import CkppError, Plan
+    now0 = 200
+    f = Fleet(20, 19, 2, 10, 1, 900, modes=["cuckoopp", "optimistic"], timed_every=2, now0=now0)
+    plan = Plan(f.tables, f.offsets, f.counts, f.modes)
+    now, new_exp = now0 + 300, now0 + 1000
+    with pytest.raises(CkppError):  # a refresh time outside [now, now + 1023]
+        run_plan(plan, f, now=now, refresh=now + 1024)
+    want_f, want_v = f.expected(now=now, refresh=new_exp)
+    say("refreshing timed plan lookup")
+    got_f, got_v = run_plan(plan, f, now=now, refresh=new_exp)
+    assert np.array_equal(got_f, want_f) and np.array_equal(got_v, want_v)
+    for ref, t in zip(f.refs, f.tables):
+        gb, gk = t.export()
+        rb, rk = ref.image()
+        assert np.array_equal(gb, rb) and np.array_equal(gk, rk), "images differ after refresh"
     plan.close()
     f.close()
 
