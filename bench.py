@@ -195,24 +195,54 @@ def probe_rand_peak(dev, gib=8, nreads=1 << 26):
     return best
 
 
-def cache_resident_table(dev, lookups):
-    """2^20 buckets (64 MiB bucket array, which fits the 256 MiB last-level
-    cache; the 256 MiB record array only partly) at load 0.9."""
+def probe_line_peak(dev, nbytes, nreads=1 << 26):
+    """Measured rate of random 128-byte line reads (cooperative, the lookups'
+    request shape) at uniformly random positions of a buffer of nbytes;
+    best launch shape.  On a buffer the size of a table it is that table's
+    random-line ceiling: HBM for 4 GiB, the last-level cache (256 MiB) for
+    tables that fit it."""
     import torch
-    t, keys, _, _ = build_table(20, 0.9, 77, dev)
+    from paper_1712_09624_amd import ckpp
+    buf = torch.empty(nbytes // 8, dtype=torch.int64, device=dev)
+    buf.zero_()
+    ncu = torch.cuda.get_device_properties(dev).multi_processor_count
+    best = 0.0
+    for per_lane in (4, 8):
+        for bpc in (8, 16):
+            grid = ncu * bpc
+            sink = torch.empty(grid * 256, dtype=torch.int64, device=dev)
+            ms = timed(lambda: ckpp.probe_random_reads(buf, 128, nreads, per_lane, 256, grid,
+                                                       12345, sink, True), 3, dev)
+            best = max(best, nreads / (ms * 1e-3))
+    del buf
+    torch.cuda.empty_cache()
+    return best
+
+
+def cache_resident_table(dev, lookups, B=20):
+    """A table of 2^B buckets at load 0.9 whose buckets fit the 256 MiB
+    last-level cache (B = 20: 256 MiB, the cache's size, so only partly
+    resident; B = 19: 128 MiB), with its own random-line ceiling measured on
+    a buffer of the table's size."""
+    import torch
+    t, keys, _, _ = build_table(B, 0.9, 77, dev)
     n = min(lookups, 1 << 24)
     pos, _, _ = W.lookup_mix(keys, n, 0.0, 78)
     neg = W.five_tuples(n, 79, stream=W.STREAM_NEGATIVE)
     dp, dn = to_dev(pos, dev), to_dev(neg, dev)
     f = torch.empty(n, dtype=torch.uint8, device=dev)
     v = torch.empty(n, dtype=torch.int64, device=dev)
-    out = {"log2_buckets": 20, "load": 0.9, "lookups": n}
+    out = {"log2_buckets": B, "load": 0.9, "lookups": n, "table_bytes": 256 << B}
     st = t.stats()
     out["f_sec"] = st["f_sec"]
-    for mode in ("cuckoopp", "both"):
+    lines = expected_lines(st)
+    out["random_line_peak_same_size_per_s"] = peak = probe_line_peak(dev, 256 << B)
+    for mode, lk in (("cuckoopp", "cuckoopp"), ("both", "plain")):
         for name, d in (("pos", dp), ("neg", dn)):
             ms = timed(lambda: t.lookup(d, mode, found=f, values=v), 5, dev)
-            out[f"{mode}_{name}_glookups"] = n / (ms * 1e-3) / 1e9
+            rate = n / (ms * 1e-3)
+            out[f"{mode}_{name}_glookups"] = rate / 1e9
+            out[f"{mode}_{name}_frac_same_size_peak"] = rate * lines[f"{lk}_{name}"] / peak
     t.close()
     return out
 
@@ -353,14 +383,20 @@ def copy_calibration(dev):
 
 def sweep(dev, lookups, probe_peak):
     """Lookup rate of Cuckoo++ and plain lookups over loads {0.6 .. 0.95} and
-    negative rates {0 .. 1}, on a 2^24-bucket (HBM-resident) and a
-    2^20-bucket (256 MiB, cache-sized) table built incrementally."""
+    negative rates {0 .. 1}, on a 2^24-bucket (4 GiB, HBM-resident), a
+    2^20-bucket (256 MiB, the size of the last-level cache) and a
+    2^19-bucket (128 MiB, cache-resident) table built incrementally.  Each
+    point's frac is given against the HBM random-line peak and against the
+    random-line peak measured on a buffer of the table's size."""
     import torch
     from paper_1712_09624_amd.ckpp import Table
     loads = (0.6, 0.7, 0.8, 0.9, 0.95)
     rates = (0.0, 0.25, 0.5, 0.75, 1.0)
     rows = []
-    for B, nlook in ((24, lookups), (20, min(lookups, 1 << 24))):
+    for B, nlook in ((24, lookups), (20, min(lookups, 1 << 24)), (19, min(lookups, 1 << 24))):
+        size_peak = probe_line_peak(dev, 256 << B)
+        log(f"sweep B={B}: random-line peak on a {256 << B >> 20} MiB buffer "
+            f"{size_peak / 1e9:.2f} G/s")
         nmax = W.keys_at_load(B, max(loads))
         keys = W.distinct_five_tuples(nmax, 21 + B, check=False)
         t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=dev.index)
@@ -391,6 +427,8 @@ def sweep(dev, lookups, probe_peak):
                     rows.append({"log2_buckets": B, "load": ld, "neg_rate": r, "mode": lk,
                                  "glookups": rate / 1e9, "lines_per_lookup": req,
                                  "frac_random_line_peak": rate * req / probe_peak,
+                                 "same_size_peak_per_s": size_peak,
+                                 "frac_same_size_peak": rate * req / size_peak,
                                  "failed_inserts": int(nf.item())})
             del pos_pool
             log(f"sweep B={B} load={ld}: " + " ".join(
@@ -1050,7 +1088,8 @@ def main():
         for k in ("cuckoopp_pos", "cuckoopp_neg", "plain_pos", "plain_neg", "optimistic_pos",
                   "optimistic_neg"):
             lk[f"{k}_frac_random_line_peak"] = lk[f"{k}_glookups"] * 1e9 * lines[k] / p128
-        out["cache_resident_table"] = cache_resident_table(dev, n)
+        out["cache_resident_table"] = cache_resident_table(dev, n, 20)
+        out["mall_resident_table"] = cache_resident_table(dev, n, 19)
         if not args.no_cpu_baseline:
             log("timing the oracle on the host")
             out["cpu_baseline"] = cpu_baseline()
