@@ -47,13 +47,6 @@ __global__ void __launch_bounds__(256)
 }
 
 // Anti-revival scan (Sec. 4.2), first kernel: every bucket removes its
-// expired entries.  Only a bucket's own lane changes its busy and sec bits;
-// the moved counter of the primary bucket of a removed entry that sat in its
-// secondary drops by one through an atomic subtraction on that bucket's
-// meta word (the counter is its low 16 bits and is at least 1 while the
-// entry is counted there), so no lock is needed.  The filters of counters
-// that reach zero are emptied by the second kernel.
-// Anti-revival scan (Sec. 4.2), first kernel: every bucket removes its
 // expired entries.  The table is read as a stream: 16 neighbouring lanes
 // read one bucket's 256 bytes, one 16-byte quarter each (a wavefront reads
 // four consecutive buckets per instruction, 1 KiB, fully coalesced).  Lane
@@ -92,7 +85,7 @@ __global__ void __launch_bounds__(256)
                           (uint32_t)__shfl((int)mine, (int)(g0 + 13u)));
     if (!exp) continue;
     if (r == 0u) {
-      __hip_atomic_fetch_and(meta_ptr(bk, (uint32_t)b), ~((exp << 16) | (exp << 24)),
+      __hip_atomic_fetch_and(meta_ptr(bk, (uint32_t)b).p, ~((exp << 16) | (exp << 24)),
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       count += (uint64_t)__builtin_popcount(exp);
     }
@@ -104,7 +97,7 @@ __global__ void __launch_bounds__(256)
         const uint32_t y = oth[k];
         if (((exp & meta_sec(meta)) >> (base + k)) & 1u && y < nb)  // y < nb: always, on a
                                                                    // table that keeps its invariants
-          __hip_atomic_fetch_sub(meta_ptr(bk, y), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_fetch_sub(meta_ptr(bk, y).p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
     }
   }

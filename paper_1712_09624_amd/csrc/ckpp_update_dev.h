@@ -81,6 +81,22 @@ __device__ __forceinline__ void unlock(uint8_t *bk, uint32_t b) {
   __hip_atomic_store(lock_word(bk, b), 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Ordering of a critical section.  Every table word a lane reads or writes
+// under a lock goes through a device-coherent access (Coh below: relaxed
+// agent-scope atomics, performed where every XCD's accesses meet), so
+// taking and dropping a lock needs no flush of the per-XCD L2 caches.
+// Acquire: the section's accesses are issued after the lock's CAS has
+// returned (a compiler barrier keeps them there; the GPU issues a wave's
+// memory accesses in order).  Release: the unlocking store waits until
+// every access of the section has completed.
+__device__ __forceinline__ void section_begin() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+__device__ __forceinline__ void section_end() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Takes the locks of buckets x != y in ascending order, or none.  The
 // order makes retries live: of two lanes that need the same pair, the one
 // that takes the lower lock first can always try the higher one, whereas
@@ -94,47 +110,91 @@ __device__ __forceinline__ bool lock_two(uint8_t *bk, uint32_t x, uint32_t y) {
     unlock(bk, lo);
     return false;
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  section_begin();
   return true;
 }
 
 // Publishes the writes made under the locks, then drops both locks.
 __device__ __forceinline__ void unlock_two(uint8_t *bk, uint32_t x, uint32_t y) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  section_end();
   unlock(bk, x);
   unlock(bk, y);
 }
+
+// A table word read and written with device-coherent accesses (relaxed
+// agent-scope atomics): converts to its value, assigns with a store.
+template <class T>
+struct Coh {
+  T *p;
+  __device__ __forceinline__ operator T() const {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ __forceinline__ const Coh &operator=(T v) const {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return *this;
+  }
+  __device__ __forceinline__ const Coh &operator|=(T v) const { return *this = (T)(T(*this) | v); }
+};
+
+// A 16-byte key: two 8-byte halves (a lock guards it, so halves suffice).
+template <>
+struct Coh<uint4> {
+  uint4 *p;
+  __device__ __forceinline__ operator uint4() const {
+    const uint64_t *q = reinterpret_cast<const uint64_t *>(p);
+    const uint64_t lo = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t hi = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return make_uint4((uint32_t)lo, (uint32_t)(lo >> 32), (uint32_t)hi, (uint32_t)(hi >> 32));
+  }
+  __device__ __forceinline__ const Coh &operator=(uint4 v) const {
+    uint64_t *q = reinterpret_cast<uint64_t *>(p);
+    __hip_atomic_store(q, (uint64_t)v.x | ((uint64_t)v.y << 32), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, (uint64_t)v.z | ((uint64_t)v.w << 32), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    return *this;
+  }
+};
+
+// Address of table words of type T: `*` and `[]` give coherent words; p is
+// the raw address (for read-modify-write atomics).
+template <class T>
+struct CohPtr {
+  T *p;
+  __device__ __forceinline__ Coh<T> operator*() const { return Coh<T>{p}; }
+  __device__ __forceinline__ Coh<T> operator[](uint32_t i) const { return Coh<T>{p + i}; }
+};
 
 struct Head {
   uint4 q0;  // tags
   uint4 q1;  // bloom lo, bloom hi, meta, lock
 };
 
-__device__ __forceinline__ Head read_head(const uint8_t *bk, uint32_t b) {
-  const uint4 *q = reinterpret_cast<const uint4 *>(bucket_ptr(bk, b));
+__device__ __forceinline__ Head read_head(uint8_t *bk, uint32_t b) {
+  uint4 *q = reinterpret_cast<uint4 *>(bucket_ptr(bk, b));
   Head h;
-  h.q0 = q[0];
-  h.q1 = q[1];
+  h.q0 = Coh<uint4>{q};
+  h.q1 = Coh<uint4>{q + 1};
   return h;
 }
 
-__device__ __forceinline__ uint32_t *meta_ptr(uint8_t *bk, uint32_t b) {
-  return reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kMetaOffset);
+__device__ __forceinline__ CohPtr<uint32_t> meta_ptr(uint8_t *bk, uint32_t b) {
+  return {reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kMetaOffset)};
 }
-__device__ __forceinline__ uint64_t *bloom_ptr(uint8_t *bk, uint32_t b) {
-  return reinterpret_cast<uint64_t *>(bucket_ptr(bk, b) + 16);
+__device__ __forceinline__ CohPtr<uint64_t> bloom_ptr(uint8_t *bk, uint32_t b) {
+  return {reinterpret_cast<uint64_t *>(bucket_ptr(bk, b) + 16)};
 }
-__device__ __forceinline__ uint16_t *tag_ptr(uint8_t *bk, uint32_t b) {
-  return reinterpret_cast<uint16_t *>(bucket_ptr(bk, b));
+__device__ __forceinline__ CohPtr<uint16_t> tag_ptr(uint8_t *bk, uint32_t b) {
+  return {reinterpret_cast<uint16_t *>(bucket_ptr(bk, b))};
 }
-__device__ __forceinline__ uint32_t *other_ptr(uint8_t *bk, uint32_t b) {
-  return reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kOtherOffset);
+__device__ __forceinline__ CohPtr<uint32_t> other_ptr(uint8_t *bk, uint32_t b) {
+  return {reinterpret_cast<uint32_t *>(bucket_ptr(bk, b) + kOtherOffset)};
 }
-__device__ __forceinline__ uint4 *key_ptr(uint8_t *bk, uint32_t b, uint32_t s) {
-  return reinterpret_cast<uint4 *>(bucket_ptr(bk, b) + key_offset(s));
+__device__ __forceinline__ CohPtr<uint4> key_ptr(uint8_t *bk, uint32_t b, uint32_t s) {
+  return {reinterpret_cast<uint4 *>(bucket_ptr(bk, b) + key_offset(s))};
 }
-__device__ __forceinline__ uint64_t *value_ptr(uint8_t *bk, uint32_t b, uint32_t s) {
-  return reinterpret_cast<uint64_t *>(bucket_ptr(bk, b) + value_offset(s));
+__device__ __forceinline__ CohPtr<uint64_t> value_ptr(uint8_t *bk, uint32_t b, uint32_t s) {
+  return {reinterpret_cast<uint64_t *>(bucket_ptr(bk, b) + value_offset(s))};
 }
 
 // Slot of `key` in a bucket whose head is h (bucket locked), or -1.
@@ -218,9 +278,9 @@ __device__ __attribute__((noinline)) bool remove_expired(uint8_t *bk, Pair &P, i
       P.meta[yi] = moved_down(bk, y, P.meta[yi]);
     } else {
       if (!try_lock(bk, y)) return false;
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      section_begin();
       *meta_ptr(bk, y) = moved_down(bk, y, *meta_ptr(bk, y));
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      section_end();
       unlock(bk, y);
     }
   }
@@ -356,7 +416,7 @@ __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32
     if (ok2 && y2 != kNoBucket) unlock_extra(bk, y2, f);
     return false;
   }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  section_begin();
   bool done = false;
   const uint32_t my1 = *meta_ptr(bk, y1);
   if (y2 == kNoBucket) {
@@ -382,7 +442,7 @@ __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32
     const uint32_t m = *meta_ptr(bk, f.p), vb = 1u << v;
     *meta_ptr(bk, f.p) = make_meta(meta_moved(m), meta_busy(m) | vb, meta_sec(m) & ~vb);
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  section_end();
   if (y2 != kNoBucket) unlock_extra(bk, y2, f);
   unlock_extra(bk, y1, f);
   return done;
@@ -404,9 +464,9 @@ __device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const 
   }
   if (s >= 0) {
     // the key's entry, alive (an update) or expired (overwritten in place)
-    uint64_t *vp = value_ptr(bk, b, (uint32_t)s);
-    r = word_alive(*vp, now) ? CKPP_UPDATED : CKPP_INSERTED;
-    *vp = word;
+    const Coh<uint64_t> vw = *value_ptr(bk, b, (uint32_t)s);
+    r = word_alive(vw, now) ? CKPP_UPDATED : CKPP_INSERTED;
+    vw = word;
   } else {
     Pair P{{f.p, f.a}, {hp.q1.z, ha.q1.z}};
     for (int xi = 0; xi < 2 && r == kNeedPath; ++xi) {
