@@ -7,10 +7,12 @@
 // taken with a single compare-and-swap and never waited on: a lane that
 // misses a lock drops every lock it holds and retries in its next loop
 // iteration, so no lane ever spins on a lock that a lane of its own
-// wavefront holds.  Every entry that moves is moved under the locks of both buckets it may
-// live in, so every bloom-filter and moved-counter update -- which concerns
-// the primary bucket of the entry that moves -- happens under the lock of
-// that bucket.
+// wavefront holds.  Every entry that moves is moved under the locks of both
+// buckets it may live in, so every bloom-filter and moved-counter update --
+// which concerns the primary bucket of the entry that moves -- happens under
+// the lock of that bucket.  Inside a critical section every table word is
+// read and written with device-coherent accesses, so a lock cycle flushes
+// no cache (section_begin / section_end).
 //
 // A key's state machine:
 //   DIRECT  lock p and a; if the key is present, replace its value
