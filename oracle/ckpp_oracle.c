@@ -22,12 +22,18 @@
  *   - hash: a seeded 64-bit mixer of the four little-endian key words built
  *     from the SplitMix64 output finalizer (Steele, Lea, Flood, OOPSLA 2014);
  *     the paper uses CityHash64 (Sec. 5, common parameters).
- *   - split of the 64-bit hash h for 2^B buckets (B <= 24):
+ *   - split of the 64-bit hash h for 2^B buckets (B <= 29):
  *       primary   p = h mod 2^B
- *       alternate a = (h >> 24) mod 2^B, and a = a xor 1 when a == p
  *       tag       t = h >> 48                        (16-bit tags, Sec. 4.3)
- *       bloom bit indices (h >> 24) mod 64 and (h >> 30) mod 64, i.e. two
- *       values taken from the secondary-hash field (Sec. 4.1).
+ *       for B <= 24, the secondary-hash field is h >> 24:
+ *         alternate a = (h >> 24) mod 2^B
+ *         bloom bit indices (h >> 24) mod 64 and (h >> 30) mod 64
+ *       for B > 24 that field would overlap p, so a second word
+ *       g = fmix(h xor 0xc2b2ae3d27d4eb4f) takes its place:
+ *         alternate a = g mod 2^B
+ *         bloom bit indices (g >> 32) mod 64 and (g >> 38) mod 64
+ *       and a = a xor 1 when a == p.  The two bloom bits come from the key's
+ *       secondary hash (Sec. 4.1) in both cases.
  *   - placement: primary before secondary, lowest free slot first.
  *   - insert of a present key overwrites its value (status UPDATED).
  *   - cuckoo path: random walk from the primary bucket, at most max_kicks
@@ -162,11 +168,19 @@ void orc_split(uint64_t h, uint32_t log2_buckets, orc_split_t *out)
 {
     uint64_t mask = (log2_buckets >= 64) ? ~0ULL : ((1ULL << log2_buckets) - 1);
     out->p = h & mask;
-    out->a = (h >> 24) & mask;
-    if (out->a == out->p) out->a ^= 1;
     out->tag = (uint32_t)(h >> 48);
-    out->b1 = (uint32_t)((h >> 24) & 63);
-    out->b2 = (uint32_t)((h >> 30) & 63);
+    if (log2_buckets <= 24) {
+        out->a = (h >> 24) & mask;
+        out->b1 = (uint32_t)((h >> 24) & 63);
+        out->b2 = (uint32_t)((h >> 30) & 63);
+    } else {
+        /* the field above bit 24 overlaps p: a second word of the hash */
+        uint64_t g = orc_fmix64(h ^ 0xc2b2ae3d27d4eb4fULL);
+        out->a = g & mask;
+        out->b1 = (uint32_t)((g >> 32) & 63);
+        out->b2 = (uint32_t)((g >> 38) & 63);
+    }
+    if (out->a == out->p) out->a ^= 1;
     out->bloom_mask = (1ULL << out->b1) | (1ULL << out->b2);
 }
 
@@ -181,7 +195,7 @@ static uint64_t orc_stream(uint64_t base, uint64_t i)
 
 orc_table *orc_create(uint32_t log2_buckets, uint64_t seed, uint32_t max_kicks, int plain)
 {
-    if (log2_buckets < 1 || log2_buckets > 24) return NULL;
+    if (log2_buckets < 1 || log2_buckets > 29) return NULL;
     orc_table *t = (orc_table *)calloc(1, sizeof(orc_table));
     if (!t) return NULL;
     t->log2_buckets = log2_buckets;

@@ -62,7 +62,8 @@ def pin_split_properties(lib):
     """Split of a hash (reading of Sec. 4.1 and 4.3): primary and alternate
     lie in range and differ; with two buckets they are {0, 1}; the tag has
     16 bits; the two bloom bits come from the secondary-hash field, which is
-    disjoint from the primary's bits for B <= 24."""
+    disjoint from the primary's bits for B <= 24, and from a second word of
+    the hash above that."""
     rng = np.random.default_rng(7)
     hs = rng.integers(0, 2**63, size=2000, dtype=np.int64).astype(np.uint64) * np.uint64(2) + \
         rng.integers(0, 2, size=2000).astype(np.uint64)
@@ -76,6 +77,24 @@ def pin_split_properties(lib):
             assert m != 0 and bin(m).count("1") in (1, 2)
             if B == 1:
                 assert {s["p"], s["a"]} == {0, 1}
+    # above 2^24 buckets the alternate and the filter bits come from a second
+    # word of the hash: in range, a != p, and neither repeats the primary's
+    # bits above bit 24 (each match only at the rate of chance, within 5 sd)
+    for B in (25, 27, 29):
+        k = B - 24
+        kb = min(k, 6)
+        same_a = same_b = 0
+        for h in hs:
+            s = O.split(int(h), B, lib=lib)
+            assert 0 <= s["p"] < (1 << B) and 0 <= s["a"] < (1 << B) and s["p"] != s["a"]
+            assert 0 <= s["tag"] < (1 << 16) and bin(s["bloom_mask"]).count("1") in (1, 2)
+            hi = s["p"] >> 24
+            same_a += (s["a"] & ((1 << k) - 1)) == hi
+            same_b += (s["b1"] & ((1 << kb) - 1)) == (hi & ((1 << kb) - 1))
+        for same, bits in ((same_a, k), (same_b, kb)):
+            q = 2.0 ** -bits
+            sd = (len(hs) * q * (1 - q)) ** 0.5
+            assert abs(same - len(hs) * q) < 5 * sd + 1, f"B={B}: split fields repeat p's bits"
     # independence: flipping a bit of the primary field never changes the
     # tag or the bloom bits; flipping a tag bit never changes p or a
     for h in hs[:200]:
@@ -554,6 +573,7 @@ QUICK_PINS = [
     "pin_delete_cycle",
     "pin_splitmix_finalizer",
     "pin_hash_composition",
+    "pin_split_properties",
     "pin_two_bucket_capacity",
     "pin_full_key_compare",
     "pin_lookup_costs",

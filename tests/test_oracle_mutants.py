@@ -23,6 +23,7 @@ MUTANTS = [
     ("second_bloom_bit_equals_first", "out->b2 = (uint32_t)((h >> 30) & 63);",
      "out->b2 = (uint32_t)((h >> 24) & 63);"),
     ("alternate_may_equal_primary", "if (out->a == out->p) out->a ^= 1;", ";"),
+    ("large_tables_keep_small_split", "if (log2_buckets <= 24) {", "if (1) {"),
     ("bloom_prune_inverted", "probe_secondary = orc_bloom_pass(t, sp.p, sp.bloom_mask);",
      "probe_secondary = !orc_bloom_pass(t, sp.p, sp.bloom_mask);"),
     ("no_home_preference", "if (nhome > 0)", "if (0)"),
