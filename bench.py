@@ -383,7 +383,8 @@ def copy_calibration(dev):
 
 def sweep(dev, lookups, probe_peak):
     """Lookup rate of Cuckoo++ and plain lookups over loads {0.6 .. 0.95} and
-    negative rates {0 .. 1}, on a 2^24-bucket (4 GiB, HBM-resident), a
+    negative rates {0 .. 1}, on a 2^25-bucket (8 GiB, above the 2^24 buckets
+    where the hash split changes), a 2^24-bucket (4 GiB, HBM-resident), a
     2^20-bucket (256 MiB, the size of the last-level cache) and a
     2^19-bucket (128 MiB, cache-resident) table built incrementally.  Each
     point's frac is given against the HBM random-line peak and against the
@@ -393,7 +394,8 @@ def sweep(dev, lookups, probe_peak):
     loads = (0.6, 0.7, 0.8, 0.9, 0.95)
     rates = (0.0, 0.25, 0.5, 0.75, 1.0)
     rows = []
-    for B, nlook in ((24, lookups), (20, min(lookups, 1 << 24)), (19, min(lookups, 1 << 24))):
+    for B, nlook in ((25, lookups), (24, lookups), (20, min(lookups, 1 << 24)),
+                     (19, min(lookups, 1 << 24))):
         size_peak = probe_line_peak(dev, 256 << B)
         log(f"sweep B={B}: random-line peak on a {256 << B >> 20} MiB buffer "
             f"{size_peak / 1e9:.2f} G/s")

@@ -100,7 +100,8 @@ enum {
                                    key is not in the primary (no filter) */
 };
 
-/* Creates an empty table of 2^log2_buckets buckets (1 <= log2_buckets <= 24)
+/* Creates an empty table of 2^log2_buckets buckets (1 <= log2_buckets <= 29;
+ * 256 bytes of device memory per bucket: 4 GiB at 2^24, 128 GiB at 2^29)
  * on HIP device `device` and stores its handle in *out.  hash_seed seeds the
  * hash; max_kicks bounds the displacements of one cuckoo path (Sec. 2);
  * flags: 0, CKPP_PLAIN and/or CKPP_TIMERS.  Errors: CKPP_EINVAL (out null, B out of range,

@@ -15,7 +15,7 @@ namespace {
 using ckpp::DeviceGuard;
 using ckpp::dev_status;
 
-constexpr uint32_t kMaxLog2Buckets = 24;
+using ckpp::kMaxLog2Buckets;
 constexpr uint32_t kMaxKicksLimit = 4096;
 constexpr uint32_t kMaxPathLanes = 65536;
 constexpr uint32_t kAccWords = 128;   // device accumulator words

@@ -58,13 +58,18 @@ __device__ __forceinline__ uint64_t key_hash(uint4 k, uint64_t seed) {
   return mix64(mix64(lo ^ seed) ^ hi);
 }
 
-// Fields of a key derived from its hash for 2^log2b buckets (log2b <= 24):
-// primary p, alternate a (never equal to p), 16-bit tag, and the two bloom
-// bits taken from the alternate-bucket field (Sec. 4.1).
+// Fields of a key derived from its hash for 2^log2b buckets: primary p,
+// alternate a (never equal to p), 16-bit tag, and the two bloom bits, taken
+// from the alternate-bucket field (Sec. 4.1).  That field is h >> 24 up to
+// 2^24 buckets; above, where it would overlap p, a second word
+// g = mix(h ^ 0xc2b2ae3d27d4eb4f) gives a = g mod 2^B and the bloom bit
+// indices (g >> 32) mod 64 and (g >> 38) mod 64.  bidx packs the two
+// indices (first | second << 6).
 struct KeyFields {
   uint32_t p;
   uint32_t a;
   uint32_t tag;
+  uint32_t bidx;
   uint64_t bloom_bits;
 };
 
@@ -72,11 +77,19 @@ __device__ __forceinline__ KeyFields key_fields(uint64_t h, uint32_t log2b) {
   const uint32_t mask = (1u << log2b) - 1u;
   KeyFields f;
   f.p = (uint32_t)h & mask;
-  uint32_t a = (uint32_t)(h >> 24) & mask;
-  f.a = (a == f.p) ? (a ^ 1u) : a;
   f.tag = (uint32_t)(h >> 48);
-  const uint32_t sh = (uint32_t)(h >> 24);
-  f.bloom_bits = (1ull << (sh & 63u)) | (1ull << ((sh >> 6) & 63u));
+  uint64_t field = h >> 24;
+  uint32_t a = (uint32_t)field & mask;
+  uint32_t b1 = (uint32_t)field & 63u, b2 = (uint32_t)(field >> 6) & 63u;
+  if (log2b > 24u) {
+    const uint64_t g = mix64(h ^ 0xc2b2ae3d27d4eb4full);
+    a = (uint32_t)g & mask;
+    b1 = (uint32_t)(g >> 32) & 63u;
+    b2 = (uint32_t)(g >> 38) & 63u;
+  }
+  f.a = (a == f.p) ? (a ^ 1u) : a;
+  f.bidx = b1 | (b2 << 6);
+  f.bloom_bits = (1ull << b1) | (1ull << b2);
   return f;
 }
 

@@ -47,6 +47,10 @@ struct PlanItem {
   uint32_t table;    // index of the table in the plan
 };
 
+// Largest table: 2^29 buckets (128 GiB, 2^32 slots); bucket indices fit in
+// 29 bits.
+constexpr uint32_t kMaxLog2Buckets = 29;
+
 constexpr uint32_t kModeCuckoopp = 0;
 constexpr uint32_t kModeBoth = 1;
 constexpr uint32_t kModeOptimistic = 2;

@@ -9,7 +9,7 @@
 namespace ckpp {
 namespace {
 
-constexpr uint32_t kNoFetch = 0xffffffffu;  // bucket indices are < 2^24
+constexpr uint32_t kNoFetch = 0xffffffffu;  // bucket indices are < 2^29
 
 // Lines of one wave: 64 lines x 8 quarters; lookup j's line at [8j, 8j+8).
 constexpr uint32_t kWaveQuarters = 64 * 8;
@@ -614,9 +614,8 @@ __device__ __forceinline__ void quad_pass(const TableRef &T, const uint4 (&key)[
   uint4 c[PER][4][2], d[PER][4][2];  // chunks of the primary's and the secondary's lines
 #pragma unroll
   for (uint32_t p = 0; p < PER; ++p) {
-    const uint64_t h = key_hash(key[p], T.seed);
-    f[p] = key_fields(h, T.log2b);
-    pk[p] = f[p].tag | (((uint32_t)(h >> 24) & 0xfffu) << 16);
+    f[p] = key_fields(key_hash(key[p], T.seed), T.log2b);
+    pk[p] = f[p].tag | (f[p].bidx << 16);
     quad_fetch<0>(c[p], T.tab, ok[p] ? f[p].p : kNoFetch, j);
     if (MODE == kModeBoth) quad_fetch<0>(d[p], T.tab, ok[p] ? f[p].a : kNoFetch, j);
   }

@@ -61,6 +61,10 @@ namespace {
 constexpr uint32_t kSpinLimit = 1u << 20;  // loop iterations per key
 constexpr uint32_t kMaxWalks = 64;         // path searches per key
 constexpr uint32_t kNoBucket = 0xffffffffu;
+// A cuckoo path entry: bucket (below 2^29) | slot << 29.
+constexpr uint32_t kPathSlotShift = 29;
+constexpr uint32_t kPathBucketMask = (1u << kPathSlotShift) - 1u;
+static_assert(kMaxLog2Buckets <= kPathSlotShift, "path entries hold a bucket index");
 
 __device__ __forceinline__ uint8_t *bucket_ptr(uint8_t *bk, uint32_t b) {
   return bk + (uint64_t)b * kBucketBytes;
@@ -570,7 +574,7 @@ __device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value, const KeyFi
 // left, then any) and the walk continues at its other bucket.  The same
 // two memory round trips per step as a plain walk, but far fewer steps: at
 // load 0.9 the longest paths shrink from tens of displacements to a few.
-// path[i] holds bucket | slot << 24 of the i-th victim; *last receives the
+// path[i] holds bucket | slot << 29 of the i-th victim; *last receives the
 // bucket with a free slot that ends the path.  Returns the path length, or
 // -1.
 __device__ __attribute__((noinline)) int walk(const uint8_t *bk, uint32_t start, uint64_t rbase, uint32_t max_kicks,
@@ -589,7 +593,7 @@ __device__ __attribute__((noinline)) int walk(const uint8_t *bk, uint32_t start,
     uint32_t used = 0;
     for (uint32_t i = 0; i < step; ++i) {
       const uint32_t e = path[i];
-      if ((e & 0xffffffu) == cur) used |= 1u << (e >> 24);
+      if ((e & kPathBucketMask) == cur) used |= 1u << (e >> kPathSlotShift);
     }
     const uint32_t sec = meta_sec(meta);
     uint32_t cand = meta_busy(meta) & ~used;
@@ -608,7 +612,7 @@ __device__ __attribute__((noinline)) int walk(const uint8_t *bk, uint32_t start,
     if (room) {
       const uint32_t pick = (room & sec) ? (room & sec) : room;
       const uint32_t v = nth_bit(pick, (uint32_t)(r % (uint64_t)__builtin_popcount(pick)));
-      path[step] = cur | (v << 24);
+      path[step] = cur | (v << kPathSlotShift);
       *last = other[v];
       return (int)step + 1;
     }
@@ -619,7 +623,7 @@ __device__ __attribute__((noinline)) int walk(const uint8_t *bk, uint32_t start,
     const uint32_t home = pref & sec;
     const uint32_t pick = home ? home : (pref ? pref : cand);
     const uint32_t v = nth_bit(pick, (uint32_t)(r % (uint64_t)__builtin_popcount(pick)));
-    path[step] = cur | (v << 24);
+    path[step] = cur | (v << kPathSlotShift);
     prev = cur;
     cur = other[v];
   }
@@ -718,8 +722,8 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
       }
     } else {
       const uint32_t e = path[next - 1];
-      const uint32_t x = e & 0xffffffu, s = e >> 24;
-      const uint32_t y = (next == len) ? last : (path[next] & 0xffffffu);
+      const uint32_t x = e & kPathBucketMask, s = e >> kPathSlotShift;
+      const uint32_t y = (next == len) ? last : (path[next] & kPathBucketMask);
       const int r = move_entry(bk, x, s, y, log2b, seed, plain);
       if (r == 1) {
         if (--next == 0) state = DIRECT;

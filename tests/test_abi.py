@@ -58,7 +58,7 @@ def test_argument_checks_need_no_device(lib):
     h = ctypes.c_void_p()
     assert lib.ckpp_create(None, 10, 1, 500, 0, 0) == ckpp.EINVAL
     assert lib.ckpp_create(ctypes.byref(h), 0, 1, 500, 0, 0) == ckpp.EINVAL
-    assert lib.ckpp_create(ctypes.byref(h), 25, 1, 500, 0, 0) == ckpp.EINVAL
+    assert lib.ckpp_create(ctypes.byref(h), 30, 1, 500, 0, 0) == ckpp.EINVAL
     assert lib.ckpp_create(ctypes.byref(h), 10, 1, 500, 4, 0) == ckpp.EINVAL
     assert lib.ckpp_insert_batch(None, None, None, 5, None, None, None) == ckpp.EINVAL
     assert lib.ckpp_lookup_batch(None, None, 5, 0, None, None, None) == ckpp.EINVAL

@@ -1,0 +1,55 @@
+"""A table above 2^24 buckets: 2^25 buckets (8 GiB, 268M slots) filled to
+load 0.9 by the GPU inserts in 4M-key batches.  Above 2^24 buckets the
+alternate bucket and the two filter bits come from a second word of the
+hash, so the image check is also the parity check of that split: the
+oracle's invariant checker recomputes every stored key's primary,
+alternate, tag and filter bits with its own split and finds each entry in
+one of its two buckets, every displaced entry counted in its primary and
+covered by that primary's filter.  Lookups of inserted and fresh keys
+answer as the dictionary does, in every mode."""
+
+import numpy as np
+import pytest
+
+from gpu_util import say, to_dev, u64, u8, vals_dev
+from oracle import oracle as O
+from paper_1712_09624_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+B = 25
+
+
+def test_table_above_2_24_buckets():
+    import torch
+    from paper_1712_09624_amd.ckpp import Table
+    n = W.keys_at_load(B, 0.9)
+    say(f"2^{B} buckets: generating {n} keys")
+    keys = W.distinct_five_tuples(n, 31, check=False)
+    vals = W.insertion_values(n)
+    t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=0)
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    say(f"2^{B} buckets: build to load 0.9 in 4M-key batches")
+    for s in range(0, n, 1 << 22):
+        e = min(n, s + (1 << 22))
+        t.insert(to_dev(keys[s:e]), vals_dev(vals[s:e]), nfailed=nf)
+    torch.cuda.synchronize()
+    assert int(nf.item()) == 0
+    st = t.stats()
+    assert st["live"] == n and st["locked"] == 0 and st["retry_exhausted"] == 0
+    # displaced entries exist, so the alternate bucket and the filter bits
+    # of the second hash word are exercised
+    assert 0.05 < st["f_sec"] < 0.3
+    pos = (W.raw_u64(32, 0, 1 << 22) % np.uint64(n)).astype(np.int64)
+    neg = W.five_tuples(1 << 22, 33, stream=W.STREAM_NEGATIVE)
+    for mode in ("cuckoopp", "both", "optimistic"):
+        say(f"2^{B} buckets: lookups, mode {mode}")
+        f, v = t.lookup(to_dev(keys[pos]), mode)
+        assert u8(f).all() and np.array_equal(u64(v), vals[pos])
+        f, v = t.lookup(to_dev(neg), mode)
+        assert not u8(f).any() and not u64(v).any()
+    say(f"2^{B} buckets: export and image invariants")
+    b, k = t.export()
+    t.close()
+    rc, msg = O.check_image(b, k, B, W.HASH_SEED, False)
+    assert rc == 0, msg
