@@ -53,3 +53,40 @@ def test_table_above_2_24_buckets():
     t.close()
     rc, msg = O.check_image(b, k, B, W.HASH_SEED, False)
     assert rc == 0, msg
+
+
+def test_largest_table():
+    """The largest table, 2^29 buckets (128 GiB, 4.3G slots): keys inserted,
+    found with their values, fresh keys missed, half of the keys deleted and
+    then missed, in every mode; the statistics count what is left."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Table
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info(0)
+    if free < (136 << 30):
+        pytest.skip(f"needs 136 GiB of free device memory, {free >> 30} GiB free")
+    Bmax = 29
+    n = 1 << 22
+    keys = W.distinct_five_tuples(n, 41)
+    vals = W.insertion_values(n, 1 << 40)
+    say(f"2^{Bmax} buckets: create and insert {n} keys")
+    t = Table(Bmax, W.HASH_SEED, W.MAX_KICKS, device=0)
+    st, nf = t.insert(to_dev(keys), vals_dev(vals))
+    assert int(nf.item()) == 0 and (u8(st) == O.INSERTED).all()
+    fresh = W.five_tuples(n, 42, stream=W.STREAM_NEGATIVE)
+    dk, df = to_dev(keys), to_dev(fresh)
+    for mode in ("cuckoopp", "both", "optimistic"):
+        say(f"2^{Bmax} buckets: lookups, mode {mode}")
+        f, v = t.lookup(dk, mode)
+        assert u8(f).all() and np.array_equal(u64(v), vals)
+        f, v = t.lookup(df, mode)
+        assert not u8(f).any() and not u64(v).any()
+    say(f"2^{Bmax} buckets: delete half")
+    d = u8(t.delete(dk[: n // 2]))
+    assert d.all()
+    f, v = t.lookup(dk, "cuckoopp")
+    f, v = u8(f), u64(v)
+    assert not f[: n // 2].any() and f[n // 2:].all() and np.array_equal(v[n // 2:], vals[n // 2:])
+    s = t.stats()
+    assert s["nbuckets"] == 1 << Bmax and s["live"] == n - n // 2 and s["locked"] == 0
+    t.close()
