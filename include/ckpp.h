@@ -423,8 +423,16 @@ typedef struct {
     uint32_t blocks_per_cu; /* persistent grid: 1..4 blocks of 256 threads
                                per compute unit, all co-resident */
     uint32_t idle_ms;       /* 1..60000 */
-    uint32_t reserved;      /* 0 */
+    uint32_t ttl;           /* table without timers: 0.  Table with timers:
+                               the lifetime of entries, 1..1023 time units
+                               (an insert at time now gives its entry
+                               expiration time now + ttl), or-ed with
+                               CKPP_SERVER_REFRESH to have every lookup that
+                               finds an entry set its expiration time to
+                               now + ttl as well (Sec. 4.2) */
 } ckpp_server_config_t;
+
+#define CKPP_SERVER_REFRESH (1u << 16)
 
 /* Device rings owned by the server (freed by ckpp_server_destroy). */
 typedef struct {
@@ -465,8 +473,8 @@ typedef struct {
 
 /* Creates a server on table t (the table must not be used by other calls
  * while the server exists) and launches its loop.
- * Errors: CKPP_EINVAL (bad config, a table with timers), CKPP_ENOMEM,
- * CKPP_EDEVICE. */
+ * Errors: CKPP_EINVAL (bad config: a ttl out of range for the table's kind
+ * among others), CKPP_ENOMEM, CKPP_EDEVICE. */
 int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_config_t *cfg);
 
 int ckpp_server_rings(const ckpp_server *s, ckpp_server_rings_t *out);
@@ -503,6 +511,23 @@ int ckpp_server_status(ckpp_server *s, ckpp_server_status_t *out);
 /* Waits until bursts 0..burst are complete.  Errors: CKPP_ETIMEOUT,
  * CKPP_EDEVICE (the loop aborted). */
 int ckpp_server_wait(ckpp_server *s, uint64_t burst, uint32_t timeout_ms);
+
+/* Servers on tables with timers (Sec. 4.2): sets the time (as in
+ * ckpp_lookup_batch_at, modulo 2^16) of the bursts submitted after this
+ * call; every operation of a burst runs at its burst's time (a round takes
+ * bursts of one time only).  The time starts at 0; the first call may set
+ * any time, each later one must advance it by less than 16384 units
+ * ((now - previous) mod 2^16 < 16384; the same time is a no-op).  The
+ * server runs the anti-revival scan of ckpp_expire_scan itself, as the
+ * first phase of a round at the new time, on the first call and whenever
+ * the time has advanced 16384 units or more since its last scan: the call
+ * then submits an empty burst for it (so it may return CKPP_EBUSY when 4096
+ * bursts are in flight; nothing changes then).  As for the batch calls, no
+ * entry of the table may have expired 64512 units or more before the first
+ * time set (the scan keeps that true afterwards).
+ * Errors: CKPP_EINVAL (null, a server without timers, a step of 16384 or
+ * more), CKPP_EBUSY, CKPP_EDEVICE. */
+int ckpp_server_set_time(ckpp_server *s, uint16_t now);
 
 /* Open-loop replay (measurement): submits burst i of a pre-staged stream at
  * h_arrival_s[i] seconds after the call (later if the budget does not admit

@@ -110,7 +110,7 @@ class _ServerConfig(ctypes.Structure):
         ("mode", ctypes.c_uint32),
         ("blocks_per_cu", ctypes.c_uint32),
         ("idle_ms", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("ttl", ctypes.c_uint32),
     ]
 
 
@@ -149,6 +149,7 @@ class _ServerStatus(ctypes.Structure):
 
 EBUSY, ETIMEOUT = 4, 5
 SERVER_STOPPED, SERVER_RUNNING, SERVER_EXITING, SERVER_ABORTED = 0, 1, 2, 3
+SERVER_REFRESH = 1 << 16
 
 # launch shape a new plan starts with (ckpp_plan_create sets the same)
 PLAN_STATIC, PLAN_DYNAMIC = 0, 1
@@ -193,6 +194,7 @@ SIGNATURES = [
     ("ckpp_server_submit", _I, [_VP, _U32, _U32, _U32, ctypes.POINTER(_U64)]),
     ("ckpp_server_status", _I, [_VP, ctypes.POINTER(_ServerStatus)]),
     ("ckpp_server_wait", _I, [_VP, _U64, _U32]),
+    ("ckpp_server_set_time", _I, [_VP, ctypes.c_uint16]),
     ("ckpp_server_replay", _I, [_VP, _U64, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_double]),
     ("ckpp_server_destroy", _I, [_VP]),
     ("ckpp_probe_random_reads", _I, [_VP, _U64, _U32, _U64, _U32, _U32, _U32, _U32, _U64, _VP,
@@ -580,12 +582,15 @@ class Server:
     KINDS = {"lookup": 0, "insert": 1, "delete": 2}
 
     def __init__(self, table, capacity=1 << 20, budget=None, mode="cuckoopp", blocks_per_cu=1,
-                 idle_ms=200):
+                 idle_ms=200, ttl=0, refresh=False):
+        """ttl / refresh: tables with timers only (the entry lifetime, and
+        whether lookups that find an entry renew it)."""
         self.lib = load()
         self.table = table
         cfg = _ServerConfig(int(capacity), int(budget or capacity),
                             MODES[mode] if isinstance(mode, str) else int(mode),
-                            int(blocks_per_cu), int(idle_ms), 0)
+                            int(blocks_per_cu), int(idle_ms),
+                            int(ttl) | (SERVER_REFRESH if refresh else 0))
         h = ctypes.c_void_p()
         _check(self.lib.ckpp_server_create(ctypes.byref(h), table.handle, ctypes.byref(cfg)),
                "ckpp_server_create")
@@ -662,6 +667,15 @@ class Server:
             return None
         _check(rc, "ckpp_server_submit")
         return int(b.value)
+
+    def set_time(self, now):
+        """Time of the bursts submitted from now on (tables with timers);
+        False when the burst that carries a due scan is not admitted yet."""
+        rc = self.lib.ckpp_server_set_time(self._h, int(now) & 0xffff)
+        if rc == EBUSY:
+            return False
+        _check(rc, "ckpp_server_set_time")
+        return True
 
     def wait(self, burst, timeout_ms=10000):
         _check(self.lib.ckpp_server_wait(self._h, int(burst), int(timeout_ms)), "ckpp_server_wait")

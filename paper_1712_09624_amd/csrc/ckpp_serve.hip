@@ -26,6 +26,15 @@
 //   end       each block makes its results visible to the host (system-
 //             scope release) before it arrives at the next boundary
 //
+// On a table with timers (Sec. 4.2) every burst carries the server's time
+// at its submission, and a round takes only bursts of one time, so all of
+// its operations run at that time: lookups find entries alive then (and may
+// push their expiration times to now + ttl), inserts give their entries
+// expiration time now + ttl, deletes remove alive and expired entries of
+// their keys.  A round whose first burst asks for it (ckpp_server_set_time
+// does, at least once every 16384 time units) starts with the anti-revival
+// scan, two grid-wide steps separated by barriers, before its lookups.
+//
 // The barriers use no atomics (each block stores its arrival in a flag line
 // of its own; one wave polls them), and every polling load is relaxed, with
 // one acquire fence after the wait: on this GPU an acquire load invalidates
@@ -67,15 +76,23 @@ constexpr uint32_t kCmdRun = 1, kCmdExit = 2, kCmdDeferred = 3;
 constexpr uint64_t kMaxSetEntries = 1ull << 22;
 // Result byte of a delete waiting for the round's inserts.
 constexpr uint8_t kDeferred = 0xffu;
+// A time change of the server is less than this; its anti-revival scan is
+// due once the time is this far past the last one.
+constexpr uint16_t kMaxTimeStep = 16384;
 
 // Pinned host memory shared by the host and the loop.
+// tails[k][3] of a burst: its time (bits 0..15), whether its round starts
+// with the anti-revival scan (bit 16), and the number of time changes before
+// it (bits 24..63; rounds never span two of them).
+constexpr uint32_t kScanBit = 16, kTimeIndexShift = 24;
 struct ServeHost {
   uint64_t submitted;  // host -> loop: bursts submitted
   uint64_t completed;  // loop -> host: bursts whose results are visible
   uint64_t rounds;     // loop -> host
   uint32_t stop;       // host -> loop: exit once idle
   uint32_t state;      // loop -> host: CKPP_SERVER_*
-  uint64_t tails[kQueue][4];  // after burst k, at k % kQueue: lookup, insert, delete tails
+  // after burst k, at k % kQueue: lookup, insert, delete tails; time word
+  uint64_t tails[kQueue][4];
 };
 
 // Device memory of the loop (survives relaunches).
@@ -92,6 +109,8 @@ struct ServeDev {
   uint32_t abort;             // a wait ran out of time
   uint32_t gen;               // barrier: last epoch the leader released
   uint32_t deferred;          // some delete of the round waits for its inserts
+  uint32_t now;               // the round's time (tables with timers)
+  uint32_t scan;              // the round starts with the anti-revival scan
 };
 
 // Barrier flags: block b stores the epoch it reached at arrive[b * kFlagStride]
@@ -122,6 +141,10 @@ struct ServeArgs {
   uint4 *set_keys;    // the round's insert keys, open addressing
   uint32_t *set_tag;  // entry in use by the round whose tag it holds
   uint64_t set_mask;  // entries - 1
+  uint32_t timed;     // the table has timers
+  uint32_t ttl;       // entry lifetime in time units (timers)
+  uint32_t refresh;   // lookups that find an entry set its expiration time
+  uint64_t nb;        // buckets
 };
 
 __device__ __forceinline__ uint64_t now_ticks() { return __builtin_amdgcn_s_memrealtime(); }
@@ -241,6 +264,28 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   d->t_wait += now_ticks() - t0;
   // the tails the host wrote before it published `s`
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+  if (a.timed) {
+    // the round takes the bursts done .. take - 1 that share burst done's
+    // time: the time index does not decrease with the burst number, so the
+    // last such burst is found by bisection (usually none is needed)
+    auto word = [&](uint64_t b) {
+      return __hip_atomic_load(&h->tails[b % kQueue][3], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
+    };
+    const uint64_t first = word(d->done);
+    const uint64_t idx = first >> kTimeIndexShift;
+    if ((word(s - 1u) >> kTimeIndexShift) != idx) {
+      uint64_t lo = d->done, hi = s - 1u;  // idx(lo) == idx != idx(hi)
+      while (hi - lo > 1u) {
+        const uint64_t mid = lo + (hi - lo) / 2u;
+        if ((word(mid) >> kTimeIndexShift) == idx) lo = mid;
+        else hi = mid;
+      }
+      s = lo + 1u;
+    }
+    d->now = (uint32_t)(first & 0xffffu);
+    d->scan = (uint32_t)(first >> kScanBit) & 1u;
+  }
   const uint64_t *t = h->tails[(s - 1u) % kQueue];
   d->lk0 = d->lk1;
   d->in0 = d->in1;
@@ -252,8 +297,11 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   return kCmdRun;
 }
 
-template <uint32_t MODE>
-__device__ void lookup_phase(const ServeArgs &a, const Wave &w, uint64_t l0, uint64_t l1) {
+// TIMED: lookups at time `now` (T carries it, the refresh flag and the
+// refreshed expiration time).
+template <uint32_t MODE, bool TIMED>
+__device__ void lookup_phase(const ServeArgs &a, const TableRef &T, const Wave &w, uint64_t l0,
+                             uint64_t l1) {
   const uint64_t nwaves = (uint64_t)gridDim.x * kWaves;
   const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
   uint64_t i = l0 + wave * 64u + w.lane;
@@ -261,7 +309,7 @@ __device__ void lookup_phase(const ServeArgs &a, const Wave &w, uint64_t l0, uin
   for (; i - w.lane < l1; i += nwaves * 64u) {
     const uint64_t slot = i & a.mask;
     uint4 knext;
-    lds_pass<MODE>(w, a.T, key, i < l1, a.lk_found + slot, a.lk_vals + slot, [&] {
+    lds_pass<MODE, TIMED>(w, T, key, i < l1, a.lk_found + slot, a.lk_vals + slot, [&] {
       const uint64_t in = i + nwaves * 64u;
       knext = in < l1 ? load_stream(a.lk_keys + (in & a.mask)) : zero4();
     });
@@ -306,14 +354,18 @@ __device__ bool set_has(const ServeArgs &a, uint4 k, uint32_t tag) {
   return false;
 }
 
-__device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1) {
+// TIMED: inserts at time `now`, whose entries expire at now + ttl.
+template <bool TIMED>
+__device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1, uint32_t now) {
   const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= a.path_lanes) return;
   uint32_t *path = a.paths + g * (uint64_t)(a.max_kicks ? a.max_kicks : 1u);
+  const uint32_t expiry = (now + a.ttl) & 0xffffu;
   for (uint64_t j = i0 + g; j < i1; j += a.path_lanes) {
     const uint64_t slot = j & a.mask;
-    const InsertOutcome o = insert_one(a.bk, a.in_keys[slot], a.in_vals[slot], a.T.log2b, a.T.seed,
-                                       a.max_kicks, a.plain != 0u, path);
+    const InsertOutcome o =
+        insert_one<TIMED>(a.bk, a.in_keys[slot], a.in_vals[slot], a.T.log2b, a.T.seed,
+                          a.max_kicks, a.plain != 0u, path, expiry, now);
     a.in_status[slot] = (uint8_t)o.status;
     if (o.spun) atomicAdd(a.nspin, 1ull);
   }
@@ -324,9 +376,10 @@ __device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1) {
 // that inserts and deletes run side by side).  filter: a delete of a key
 // the round also inserts is deferred (its result byte set to kDeferred)
 // until every insert of the round is done.  deferred_only: runs just the
-// deferred deletes (the same lane took them).
+// deferred deletes (the same lane took them).  TIMED: deletes at time `now`.
+template <bool TIMED>
 __device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1, bool filter,
-                             uint32_t tag, bool deferred_only) {
+                             uint32_t tag, bool deferred_only, uint32_t now) {
   const uint64_t nlanes = (uint64_t)gridDim.x * kBlock;
   const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   bool deferred = false;
@@ -340,7 +393,8 @@ __device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1, bool 
       continue;
     }
     bool spun = false;
-    a.de_found[slot] = (uint8_t)delete_one(a.bk, k, a.T.log2b, a.T.seed, a.plain != 0u, &spun);
+    a.de_found[slot] =
+        (uint8_t)delete_one<TIMED>(a.bk, k, a.T.log2b, a.T.seed, a.plain != 0u, &spun, now);
     if (spun) atomicAdd(a.nspin, 1ull);
   }
   if (deferred)
@@ -356,9 +410,11 @@ __device__ bool phase_barrier(const ServeArgs &a, uint32_t epoch, uint32_t phase
     if (threadIdx.x < 64u) {
       const bool ok = gather(a, epoch, kPhaseMs * kTicksPerMs);
       if (threadIdx.x == 0) {
-        // the phase that just ended: lookups (first barrier) or inserts
+        // the phase that just ended: lookups, inserts, or a step of the
+        // anti-revival scan (counted with the round boundaries)
         const uint64_t t = now_ticks();
-        *(phase == 0 ? &a.dev->t_lookup : &a.dev->t_insert) += t - a.dev->t_mark;
+        *(phase == 0 ? &a.dev->t_lookup : phase == 1 ? &a.dev->t_insert : &a.dev->t_boundary) +=
+            t - a.dev->t_mark;
         a.dev->t_mark = t;
         release_epoch(a.dev, epoch);
         *s_ok = ok ? 1u : 0u;
@@ -371,10 +427,12 @@ __device__ bool phase_barrier(const ServeArgs &a, uint32_t epoch, uint32_t phase
   return *s_ok != 0u;
 }
 
-template <uint32_t NB, uint32_t MODE>
+// TIMED: the table has timers (the round's time and scan flag come with
+// its ranges).
+template <uint32_t NB, uint32_t MODE, bool TIMED>
 __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
   __shared__ uint4 s_lines[kWaves * NB * kWaveQuarters];
-  __shared__ uint64_t s_range[6];
+  __shared__ uint64_t s_range[8];
   __shared__ uint32_t s_cmd, s_ok;
   const Wave w = wave_lines<NB>(s_lines);
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
@@ -438,16 +496,35 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
         s_range[3] = d->in1;
         s_range[4] = d->de0;
         s_range[5] = d->de1;
+        s_range[6] = TIMED ? d->now : 0u;
+        s_range[7] = TIMED && s_cmd == kCmdRun ? d->scan : 0u;
       }
     }
     __syncthreads();
     if (s_cmd != kCmdRun && s_cmd != kCmdDeferred) break;
     const uint64_t l0 = s_range[0], l1 = s_range[1], i0 = s_range[2], i1 = s_range[3];
     const uint64_t d0 = s_range[4], d1 = s_range[5];
+    const uint32_t now = (uint32_t)s_range[6];
     if (s_cmd == kCmdDeferred) {
-      delete_phase(a, d0, d1, false, 0u, true);
+      delete_phase<TIMED>(a, d0, d1, false, 0u, true, now);
       last_phase = 2u;
     } else {
+      if (TIMED && s_range[7]) {
+        // anti-revival scan: expired entries out, then the filters of
+        // buckets whose moved counters reached zero emptied
+        const uint64_t gtid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+        const uint64_t gthreads = (uint64_t)gridDim.x * kBlock;
+        expire_slots_pass(a.bk, a.nb, now, a.plain != 0u, gtid, gthreads);
+        if (!phase_barrier(a, ++epoch, 2u, &s_ok)) break;
+        expire_filters_pass(a.bk, a.nb, gtid, gthreads);
+        if (!phase_barrier(a, ++epoch, 2u, &s_ok)) break;
+      }
+      TableRef T = a.T;
+      if (TIMED) {
+        T.now = now;
+        T.refresh = a.refresh;
+        T.expiry = (now + a.ttl) & 0xffffu;
+      }
       // a round with inserts and deletes runs them side by side, deferring
       // the deletes of keys it also inserts, when the updates are few enough
       // for each to get a lane of its own with half the lanes to spare
@@ -460,19 +537,19 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
       const bool merge = ins && del && 2u * (i1 - i0) <= a.set_mask + 1u &&
                          2u * ((i1 - i0) + (d1 - d0)) <= lanes;
       const uint32_t tag = epoch;  // unique to this round
-      lookup_phase<MODE>(a, w, l0, l1);
+      lookup_phase<MODE, TIMED>(a, T, w, l0, l1);
       if (merge) set_build(a, i0, i1, tag);
       last_phase = 0u;
       if (ins || del) {
         if (!phase_barrier(a, ++epoch, 0u, &s_ok)) break;
         if (!ins || !del || merge) {
-          insert_phase(a, i0, i1);
-          delete_phase(a, d0, d1, merge, tag, false);
+          insert_phase<TIMED>(a, i0, i1, now);
+          delete_phase<TIMED>(a, d0, d1, merge, tag, false, now);
           last_phase = ins ? 1u : 2u;
         } else {
-          insert_phase(a, i0, i1);
+          insert_phase<TIMED>(a, i0, i1, now);
           if (!phase_barrier(a, ++epoch, 1u, &s_ok)) break;
-          delete_phase(a, d0, d1, false, 0u, false);
+          delete_phase<TIMED>(a, d0, d1, false, 0u, false, now);
           last_phase = 2u;
         }
       }
@@ -514,6 +591,12 @@ struct ckpp_server {
   std::vector<uint64_t> burst_tails;  // kQueue x 3: cumulative tails after burst k
   uint64_t launches;
   bool launched;
+  // tables with timers: the time of bursts submitted from now on, the time
+  // of the last requested scan, time changes so far, whether a time was set
+  uint16_t now;
+  uint16_t last_scan;
+  uint64_t time_index;
+  bool time_set;
 };
 
 namespace {
@@ -524,16 +607,22 @@ using ckpp::dev_status;
 std::atomic<uint64_t> *host_u64(uint64_t *p) { return reinterpret_cast<std::atomic<uint64_t> *>(p); }
 std::atomic<uint32_t> *host_u32(uint32_t *p) { return reinterpret_cast<std::atomic<uint32_t> *>(p); }
 
+template <bool TIMED>
+const void *loop_kernel(uint32_t mode) {
+  if (mode == ckpp::kModeBoth)
+    return reinterpret_cast<const void *>(&ckpp::serve_loop<2, ckpp::kModeBoth, TIMED>);
+  if (mode == ckpp::kModeOptimistic)
+    return reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeOptimistic, TIMED>);
+  return reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeCuckoopp, TIMED>);
+}
+
+const void *loop_kernel(uint32_t mode, bool timed) {
+  return timed ? loop_kernel<true>(mode) : loop_kernel<false>(mode);
+}
+
 hipError_t launch_loop(ckpp_server *s) {
   void *kargs[] = {&s->args};
-  const void *fn;
-  const bool two = s->mode == ckpp::kModeBoth;
-  if (two)
-    fn = reinterpret_cast<const void *>(&ckpp::serve_loop<2, ckpp::kModeBoth>);
-  else if (s->mode == ckpp::kModeOptimistic)
-    fn = reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeOptimistic>);
-  else
-    fn = reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeCuckoopp>);
+  const void *fn = loop_kernel(s->mode, s->args.timed != 0u);
   host_u32(&s->host->state)->store(CKPP_SERVER_RUNNING, std::memory_order_seq_cst);
   hipError_t e = hipLaunchCooperativeKernel(fn, dim3(s->grid), dim3(ckpp::kBlock), kargs, 0,
                                             s->stream);
@@ -595,12 +684,15 @@ extern "C" {
 int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_config_t *cfg) {
   if (!out) return CKPP_EINVAL;
   *out = nullptr;
-  if (!t || !cfg || (t->flags & CKPP_TIMERS)) return CKPP_EINVAL;
+  if (!t || !cfg) return CKPP_EINVAL;
   const ckpp_server_config_t &c = *cfg;
+  const bool timed = (t->flags & CKPP_TIMERS) != 0u;
+  const uint32_t ttl = c.ttl & ~CKPP_SERVER_REFRESH;
+  if (timed ? (ttl < 1 || ttl > 1023) : c.ttl != 0) return CKPP_EINVAL;
   if (!pow2(c.capacity) || c.capacity < 64 || c.capacity > (1ull << 30)) return CKPP_EINVAL;
   if (c.budget == 0 || c.budget > c.capacity) return CKPP_EINVAL;
   if (c.mode > CKPP_LOOKUP_OPTIMISTIC || c.blocks_per_cu < 1 || c.blocks_per_cu > 4) return CKPP_EINVAL;
-  if (c.idle_ms < 1 || c.idle_ms > 60000 || c.reserved != 0) return CKPP_EINVAL;
+  if (c.idle_ms < 1 || c.idle_ms > 60000) return CKPP_EINVAL;
   DeviceGuard g(t->device);
   if (!g.ok()) return CKPP_EDEVICE;
   ckpp_server *s = new (std::nothrow) ckpp_server();
@@ -625,9 +717,7 @@ int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_confi
   if (e == hipSuccess) e = hipMalloc(&r.d_delete_found, C);
   // the loop kernel's grid: co-resident blocks only
   int per_cu = 0;
-  const void *fn = s->mode == CKPP_LOOKUP_BOTH
-                       ? reinterpret_cast<const void *>(&ckpp::serve_loop<2, ckpp::kModeBoth>)
-                       : reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeCuckoopp>);
+  const void *fn = loop_kernel(s->mode, timed);
   if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, ckpp::kBlock, 0);
   if (e == hipSuccess && per_cu < 1) e = hipErrorInvalidConfiguration;
   const uint32_t bpc = std::min<uint32_t>(c.blocks_per_cu, (uint32_t)std::max(per_cu, 1));
@@ -677,6 +767,10 @@ int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_confi
   a.set_keys = s->set_keys;
   a.set_tag = s->set_tag;
   a.set_mask = set_entries - 1u;
+  a.timed = timed ? 1u : 0u;
+  a.ttl = timed ? ttl : 0u;
+  a.refresh = timed && (c.ttl & CKPP_SERVER_REFRESH) ? 1u : 0u;
+  a.nb = 1ull << t->log2_buckets;
   e = launch_loop(s);
   if (e != hipSuccess) {
     free_server(s);
@@ -775,8 +869,9 @@ namespace {
 
 // Records a burst's tails for the loop without publishing it; CKPP_EBUSY
 // when it does not fit the budget or the queue.  `done`: bursts completed.
+// scan: the burst's round starts with the anti-revival scan.
 int stage_burst(ckpp_server *s, uint64_t done, uint32_t n_lookup, uint32_t n_insert,
-                uint32_t n_delete) {
+                uint32_t n_delete, bool scan = false) {
   if (s->submitted - done >= ckpp::kQueue) return CKPP_EBUSY;
   // ops in flight of each kind after this burst
   const uint64_t *dt = done ? &s->burst_tails[3 * ((done - 1) % ckpp::kQueue)] : nullptr;
@@ -793,6 +888,9 @@ int stage_burst(ckpp_server *s, uint64_t done, uint32_t n_lookup, uint32_t n_ins
     s->burst_tails[3 * (b % ckpp::kQueue) + k] = nt[k];
     s->tails[k] = nt[k];
   }
+  const uint64_t tw = (s->time_index << ckpp::kTimeIndexShift) |
+                      ((uint64_t)(scan ? 1u : 0u) << ckpp::kScanBit) | s->now;
+  host_u64(&slot[3])->store(tw, std::memory_order_relaxed);
   s->submitted = b + 1;
   return CKPP_OK;
 }
@@ -818,6 +916,32 @@ int ckpp_server_submit(ckpp_server *s, uint32_t n_lookup, uint32_t n_insert, uin
   if (rc != CKPP_OK) return rc;
   if (burst) *burst = s->submitted - 1;
   return publish(s);
+}
+
+int ckpp_server_set_time(ckpp_server *s, uint16_t now) {
+  if (!s || !s->args.timed) return CKPP_EINVAL;
+  if (s->time_set && ((uint16_t)(now - s->now) >= ckpp::kMaxTimeStep)) return CKPP_EINVAL;
+  if (s->time_set && now == s->now) return CKPP_OK;
+  // the scan is due when this time is 16384 or more past the last one (an
+  // expired entry looks alive again 64512 units after it expired, and no
+  // time change exceeds 16383, so the scans are at most 32767 apart)
+  const bool scan = !s->time_set || (uint16_t)(now - s->last_scan) >= ckpp::kMaxTimeStep;
+  const uint16_t old_now = s->now;
+  const uint64_t old_index = s->time_index;
+  s->now = now;
+  s->time_index += 1;
+  if (scan) {
+    const uint64_t done = host_u64(&s->host->completed)->load(std::memory_order_acquire);
+    const int rc = stage_burst(s, done, 0u, 0u, 0u, true);
+    if (rc != CKPP_OK) {
+      s->now = old_now;
+      s->time_index = old_index;
+      return rc;
+    }
+    s->last_scan = now;
+  }
+  s->time_set = true;
+  return scan ? publish(s) : CKPP_OK;
 }
 
 int ckpp_server_wait(ckpp_server *s, uint64_t burst, uint32_t timeout_ms) {

@@ -47,71 +47,24 @@ __global__ void __launch_bounds__(256)
 }
 
 // Anti-revival scan (Sec. 4.2), first kernel: every bucket removes its
-// expired entries.  The table is read as a stream: 16 neighbouring lanes
-// read one bucket's 256 bytes, one 16-byte quarter each (a wavefront reads
-// four consecutive buckets per instruction, 1 KiB, fully coalesced).  Lane
-// 1 of the group holds the metadata word, lanes 6, 7, 12 and 13 the value
-// words (two slots each, the expiration time in the high 16 bits), lanes 14
-// and 15 the other buckets of the slots; the group shares them through
-// cross-lane reads.  Only the group's lane 0 changes the bucket's busy and
-// sec bits (an atomic AND); the moved counter of the primary bucket of a
-// removed entry that sat in its secondary drops by one through an atomic
-// subtraction on that bucket's meta word (the counter is its low 16 bits
-// and is at least 1 while the entry is counted there), done by the lane
-// that holds the entry's other bucket, so no lock is needed.  The filters
-// of counters that reach zero are emptied by the second kernel.
+// expired entries (expire_slots_pass: the table is read as a stream, 16
+// lanes per bucket, a wavefront reading four consecutive buckets, 1 KiB,
+// per instruction).  The filters of counters that reach zero are emptied
+// by the second kernel.
 __global__ void __launch_bounds__(256)
     expire_slots_kernel(uint8_t *bk, uint64_t nb, uint32_t now, uint32_t plain_flag,
                         unsigned long long *removed) {
-  const bool plain = plain_flag != 0u;
-  const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g0 = lane & 48u;
-  const uint64_t groups = (uint64_t)gridDim.x * (blockDim.x / 16u);
-  uint64_t count = 0;
-  for (uint64_t b = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 16u; b < nb;
-       b += groups) {
-    const uint4 q = reinterpret_cast<const uint4 *>(bucket_ptr(bk, (uint32_t)b))[r];
-    const uint32_t meta = (uint32_t)__shfl((int)q.z, (int)(g0 + 1u));
-    // expired bits of this lane's two value words (lanes 6, 7, 12, 13)
-    uint32_t mine = 0u;
-    const uint32_t s0 = r == 6u ? 0u : r == 7u ? 2u : r == 12u ? 4u : 6u;
-    if (r == 6u || r == 7u || r == 12u || r == 13u) {
-      if ((((q.y >> 16) - now) & 0xffffu) >= kMaxDelay) mine |= 1u << s0;
-      if ((((q.w >> 16) - now) & 0xffffu) >= kMaxDelay) mine |= 2u << s0;
-    }
-    const uint32_t exp = meta_busy(meta) &
-                         ((uint32_t)__shfl((int)mine, (int)(g0 + 6u)) |
-                          (uint32_t)__shfl((int)mine, (int)(g0 + 7u)) |
-                          (uint32_t)__shfl((int)mine, (int)(g0 + 12u)) |
-                          (uint32_t)__shfl((int)mine, (int)(g0 + 13u)));
-    if (!exp) continue;
-    if (r == 0u) {
-      __hip_atomic_fetch_and(meta_ptr(bk, (uint32_t)b).p, ~((exp << 16) | (exp << 24)),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      count += (uint64_t)__builtin_popcount(exp);
-    }
-    if (!plain && (r == 14u || r == 15u)) {
-      const uint32_t base = r == 14u ? 0u : 4u;
-      const uint32_t oth[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-      for (uint32_t k = 0; k < 4; ++k) {
-        const uint32_t y = oth[k];
-        if (((exp & meta_sec(meta)) >> (base + k)) & 1u && y < nb)  // y < nb: always, on a
-                                                                   // table that keeps its invariants
-          __hip_atomic_fetch_sub(meta_ptr(bk, y).p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-  }
+  const uint64_t count =
+      expire_slots_pass(bk, nb, now, plain_flag != 0u, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                        (uint64_t)gridDim.x * blockDim.x);
   if (count && removed) atomicAdd(removed, (unsigned long long)count);
 }
 
 // Second kernel: a bucket whose moved counter is zero has an empty filter
 // (Sec. 4.1: the filter is reset when its counter returns to zero).
 __global__ void __launch_bounds__(256) expire_filters_kernel(uint8_t *bk, uint64_t nb) {
-  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
-       b += (uint64_t)gridDim.x * blockDim.x) {
-    if (meta_moved(*meta_ptr(bk, (uint32_t)b)) == 0u && *bloom_ptr(bk, (uint32_t)b) != 0ull)
-      *bloom_ptr(bk, (uint32_t)b) = 0ull;
-  }
+  expire_filters_pass(bk, nb, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                      (uint64_t)gridDim.x * blockDim.x);
 }
 
 }  // namespace
