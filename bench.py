@@ -55,6 +55,9 @@ def parse():
                     help="lookup rate over loads x negative rates x modes (2^24 and 2^20 buckets)")
     ap.add_argument("--serve", type=int, default=0, metavar="BURSTS",
                     help="serving workload, BURSTS bursts per run: peak, then 25/50/75/100%% offered")
+    ap.add_argument("--serve-timers", action="store_true",
+                    help="with --serve: the table has timers (lookups renew entries; the loop "
+                         "runs the anti-revival scan)")
     ap.add_argument("--many-tables", type=int, default=0, metavar="N",
                     help="batching workload over N tables: per-table calls vs one plan launch")
     ap.add_argument("--insert-workload", action="store_true",
@@ -692,20 +695,31 @@ def serve_stream(nbursts, seed, keys, universe, vals, del_base):
             "dels": keys[dels], "del_next": del_base + int(nd.sum())}
 
 
+SERVE_NOW0, SERVE_TTL, SERVE_TICK = 1000, 1023, 50
+
+
 def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0),
-                budget=1 << 20, capacity=1 << 25):
+                budget=1 << 20, capacity=1 << 25, timers=False):
     """Serving workload: a 2^24-bucket table at load 0.85 whose first 100M
     keys are the flow universe; a closed-loop run measures the loop's peak,
     then open-loop Poisson runs offer 25/50/75/100 % of it.  Every run's
-    lookups, inserts and deletes are checked against the ground truth."""
+    lookups, inserts and deletes are checked against the ground truth.
+    timers: the table has timers (every key built to expire at time
+    SERVE_NOW0 + SERVE_TTL); the server's entries live SERVE_TTL units and
+    lookups renew them; run r runs at time SERVE_NOW0 + SERVE_TICK (r + 1),
+    so every key stays alive.  The first time set starts with the loop's
+    anti-revival scan of the whole table, timed on its own."""
     import torch
     from paper_1712_09624_amd.ckpp import Server
-    t, keys, vals, build_s = build_table(B, load, 11, dev)
+    n = W.keys_at_load(B, load)
+    expiry = np.full(n, SERVE_NOW0 + SERVE_TTL, np.uint16) if timers else None
+    t, keys, vals, build_s = build_table(B, load, 11, dev, expiry=expiry, now=SERVE_NOW0)
     universe = min(SERVE_UNIVERSE, len(keys))
-    srv = Server(t, capacity=capacity, budget=budget, blocks_per_cu=1, idle_ms=2000)
+    srv = Server(t, capacity=capacity, budget=budget, blocks_per_cu=1, idle_ms=2000,
+                 ttl=SERVE_TTL if timers else 0, refresh=timers)
     out = {"log2_buckets": B, "load": load, "stored_keys": len(keys), "universe": universe,
            "budget_ops": budget, "ring_capacity": capacity, "bursts_per_run": nbursts,
-           "grid_blocks": srv.status()["grid"], "runs": []}
+           "grid_blocks": srv.status()["grid"], "timers": timers, "runs": []}
     del_base = universe
     peak_lps = None
     for run, frac in enumerate((None,) + tuple(fracs)):
@@ -721,6 +735,19 @@ def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0
         if len(st["dels"]):
             srv.put("delete", pos[2], to_dev(st["dels"], dev))
         mean_l = float(st["nl"].mean())
+        if timers:
+            s_scan = srv.status()
+            t0 = time.perf_counter()
+            if not srv.set_time(SERVE_NOW0 + SERVE_TICK * (run + 1)):
+                raise RuntimeError("the time change was not admitted")
+            s_set = srv.status()
+            if s_set["submitted"] > s_scan["submitted"]:  # the scan's empty burst
+                srv.wait(s_set["submitted"] - 1, 60000)
+                s_done = srv.status()
+                out["scan"] = {"host_ms": (time.perf_counter() - t0) * 1e3,
+                               "loop_ms": (s_done["boundary_ns"] - s_scan["boundary_ns"]) / 1e6,
+                               "table_gib": (256 << B) / 2**30}
+                log(f"scan in the loop: {out['scan']}")
         if frac is None:
             arrival = np.zeros(nbursts)
         else:
@@ -758,6 +785,9 @@ def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0
         out["runs"].append(rec)
         log(f"serve run {run}: {rec}")
     srv.close()
+    if timers:
+        t.close()
+        return out
     # the same kind of stream through the plain batch calls, burst by burst
     # (lookup, insert and delete batch of each burst, then a synchronization)
     nplain = min(5000, nbursts)
@@ -928,7 +958,8 @@ def main():
         copy_calibration(dev)
         return
     if args.serve:
-        print(json.dumps({"serve": serve_bench(dev, args.serve)}), flush=True)
+        print(json.dumps({"serve": serve_bench(dev, args.serve, timers=args.serve_timers)}),
+              flush=True)
         return
     if args.many_tables:
         print(json.dumps({"many_tables": many_table_bench(dev, args.many_tables)}), flush=True)

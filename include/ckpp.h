@@ -204,7 +204,7 @@ int ckpp_delete_batch_at(ckpp_table *t, const void *d_keys, uint64_t n, uint16_t
  * the filter maintenance of a delete (moved counters of the primaries of
  * removed displaced entries decrease; filters whose counter reaches zero are
  * emptied).  *d_removed (one u64, nullable) is incremented by the number of
- * entries removed.  Reads the whole table (two kernels).
+ * entries removed.  Reads the whole table once (one kernel).
  * Errors: CKPP_EINVAL (table without timers, misaligned d_removed). */
 int ckpp_expire_scan(ckpp_table *t, uint16_t now, uint64_t *d_removed, void *stream);
 

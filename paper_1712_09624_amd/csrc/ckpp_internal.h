@@ -100,7 +100,7 @@ hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t
                          uint8_t *d_status, uint64_t *d_nfailed, hipStream_t s);
 hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n,
                          const TimerArgs *timers, uint8_t *d_found, hipStream_t s);
-// Removes every entry expired at `now` (two kernels: slots, then filters).
+// Removes every entry expired at `now` (one pass over the table).
 hipError_t launch_expire_scan(const ckpp_table *t, uint32_t now, uint64_t *d_removed,
                               hipStream_t s);
 hipError_t launch_stats(const ckpp_table *t, uint64_t *d_acc, hipStream_t s);

@@ -33,7 +33,7 @@
 // expiration time now + ttl, deletes remove alive and expired entries of
 // their keys.  A round whose first burst asks for it (ckpp_server_set_time
 // does, at least once every 16384 time units) starts with the anti-revival
-// scan, two grid-wide steps separated by barriers, before its lookups.
+// scan over the whole grid, and a barrier, before its lookups.
 //
 // The barriers use no atomics (each block stores its arrival in a flag line
 // of its own; one wave polls them), and every polling load is relaxed, with
@@ -79,6 +79,9 @@ constexpr uint8_t kDeferred = 0xffu;
 // A time change of the server is less than this; its anti-revival scan is
 // due once the time is this far past the last one.
 constexpr uint16_t kMaxTimeStep = 16384;
+// Buckets each lane group of the loop's scan reads ahead (the loop has one
+// block per compute unit, so each lane keeps several loads in flight).
+constexpr uint32_t kScanUnroll = 16;
 
 // Pinned host memory shared by the host and the loop.
 // tails[k][3] of a burst: its time (bits 0..15), whether its round starts
@@ -510,13 +513,11 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
       last_phase = 2u;
     } else {
       if (TIMED && s_range[7]) {
-        // anti-revival scan: expired entries out, then the filters of
-        // buckets whose moved counters reached zero emptied
+        // anti-revival scan: expired entries out, with the counter and
+        // filter maintenance of a delete; a barrier before the lookups
         const uint64_t gtid = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
         const uint64_t gthreads = (uint64_t)gridDim.x * kBlock;
-        expire_slots_pass(a.bk, a.nb, now, a.plain != 0u, gtid, gthreads);
-        if (!phase_barrier(a, ++epoch, 2u, &s_ok)) break;
-        expire_filters_pass(a.bk, a.nb, gtid, gthreads);
+        expire_slots_pass<kScanUnroll>(a.bk, a.nb, now, a.plain != 0u, gtid, gthreads);
         if (!phase_barrier(a, ++epoch, 2u, &s_ok)) break;
       }
       TableRef T = a.T;

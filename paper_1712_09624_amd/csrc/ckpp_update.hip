@@ -46,11 +46,10 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// Anti-revival scan (Sec. 4.2), first kernel: every bucket removes its
-// expired entries (expire_slots_pass: the table is read as a stream, 16
-// lanes per bucket, a wavefront reading four consecutive buckets, 1 KiB,
-// per instruction).  The filters of counters that reach zero are emptied
-// by the second kernel.
+// Anti-revival scan (Sec. 4.2): every bucket removes its expired entries,
+// with the counter and filter maintenance of a delete (expire_slots_pass:
+// the table is read as a stream, 16 lanes per bucket, a wavefront reading
+// four consecutive buckets, 1 KiB, per instruction).
 __global__ void __launch_bounds__(256)
     expire_slots_kernel(uint8_t *bk, uint64_t nb, uint32_t now, uint32_t plain_flag,
                         unsigned long long *removed) {
@@ -58,13 +57,6 @@ __global__ void __launch_bounds__(256)
       expire_slots_pass(bk, nb, now, plain_flag != 0u, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
                         (uint64_t)gridDim.x * blockDim.x);
   if (count && removed) atomicAdd(removed, (unsigned long long)count);
-}
-
-// Second kernel: a bucket whose moved counter is zero has an empty filter
-// (Sec. 4.1: the filter is reset when its counter returns to zero).
-__global__ void __launch_bounds__(256) expire_filters_kernel(uint8_t *bk, uint64_t nb) {
-  expire_filters_pass(bk, nb, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x,
-                      (uint64_t)gridDim.x * blockDim.x);
 }
 
 }  // namespace
@@ -139,10 +131,6 @@ hipError_t launch_expire_scan(const ckpp_table *t, uint32_t now, uint64_t *d_rem
   hipLaunchKernelGGL(expire_slots_kernel, dim3((uint32_t)grid), dim3(block), 0, s, t->d_table, nb,
                      now, (t->flags & CKPP_PLAIN) ? 1u : 0u,
                      reinterpret_cast<unsigned long long *>(d_removed));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(expire_filters_kernel, dim3((uint32_t)grid), dim3(block), 0, s, t->d_table,
-                     nb);
   return hipGetLastError();
 }
 

@@ -784,69 +784,81 @@ __device__ int delete_one(uint8_t *bk, uint4 key, uint32_t log2b, uint64_t seed,
   return r == kBusy ? 0 : r;
 }
 
-// Anti-revival scan (Sec. 4.2), first step, over buckets [0, nb) by the
-// lanes gtid of a grid of gthreads (blocks of 256): 16 neighbouring lanes
-// read one bucket's 256 bytes, one 16-byte quarter each, and share the
-// metadata word (lane 1), the value words (lanes 6, 7, 12, 13: the time in
-// the high 16 bits) and the other buckets (lanes 14, 15) through
-// cross-lane reads.  Lane 0 of the group clears the bucket's expired slots
-// (busy and sec bits) with an atomic AND; the moved counter of the primary
-// bucket of a removed entry that sat in its secondary drops by one through
-// an atomic subtraction on that bucket's meta word (the counter is its low
-// 16 bits and is at least 1 while the entry is counted there), done by the
-// lane that holds the entry's other bucket, so no lock is needed.  Returns
-// the entries this lane removed.
+// Anti-revival scan (Sec. 4.2) over buckets [0, nb) by the lanes gtid of a
+// grid of gthreads (blocks of 256): 16 neighbouring lanes read one bucket's
+// 256 bytes, one 16-byte quarter each, and share the metadata word (lane
+// 1), the value words (lanes 6, 7, 12, 13: the time in the high 16 bits)
+// and the other buckets (lanes 14, 15) through cross-lane reads.  Lane 0 of
+// the group clears the bucket's expired slots (busy and sec bits) with an
+// atomic AND; the moved counter of the primary bucket of a removed entry
+// that sat in its secondary drops by one through an atomic subtraction on
+// that bucket's meta word (the counter is its low 16 bits and is at least 1
+// while the entry is counted there), done by the lane that holds the
+// entry's other bucket, so no lock is needed.  The subtraction that takes a
+// counter from 1 to 0 empties that bucket's filter (Sec. 4.1: the filter is
+// reset when its counter returns to zero): while the scan runs nothing
+// raises a counter, so zero is final.  The caller runs nothing else on the
+// table meanwhile.  U: the buckets a group reads before it examines the
+// first (loads in flight per lane, for grids with few waves).  Returns the
+// entries this lane removed.
+template <uint32_t U = 1>
 __device__ __forceinline__ uint64_t expire_slots_pass(uint8_t *bk, uint64_t nb, uint32_t now,
                                                       bool plain, uint64_t gtid,
                                                       uint64_t gthreads) {
   const uint32_t lane = threadIdx.x & 63u, r = lane & 15u, g0 = lane & 48u;
   const uint64_t groups = gthreads / 16u;
   uint64_t count = 0;
-  for (uint64_t b = gtid / 16u; b < nb; b += groups) {
-    const uint4 q = reinterpret_cast<const uint4 *>(bucket_ptr(bk, (uint32_t)b))[r];
-    const uint32_t meta = (uint32_t)__shfl((int)q.z, (int)(g0 + 1u));
-    // expired bits of this lane's two value words (lanes 6, 7, 12, 13)
-    uint32_t mine = 0u;
-    const uint32_t s0 = r == 6u ? 0u : r == 7u ? 2u : r == 12u ? 4u : 6u;
-    if (r == 6u || r == 7u || r == 12u || r == 13u) {
-      if ((((q.y >> 16) - now) & 0xffffu) >= kMaxDelay) mine |= 1u << s0;
-      if ((((q.w >> 16) - now) & 0xffffu) >= kMaxDelay) mine |= 2u << s0;
-    }
-    const uint32_t exp = meta_busy(meta) &
-                         ((uint32_t)__shfl((int)mine, (int)(g0 + 6u)) |
-                          (uint32_t)__shfl((int)mine, (int)(g0 + 7u)) |
-                          (uint32_t)__shfl((int)mine, (int)(g0 + 12u)) |
-                          (uint32_t)__shfl((int)mine, (int)(g0 + 13u)));
-    if (!exp) continue;
-    if (r == 0u) {
-      __hip_atomic_fetch_and(meta_ptr(bk, (uint32_t)b).p, ~((exp << 16) | (exp << 24)),
-                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      count += (uint64_t)__builtin_popcount(exp);
-    }
-    if (!plain && (r == 14u || r == 15u)) {
-      const uint32_t base = r == 14u ? 0u : 4u;
-      const uint32_t oth[4] = {q.x, q.y, q.z, q.w};
+  for (uint64_t b0 = gtid / 16u; b0 < nb; b0 += U * groups) {
+    // every load is issued before the first is used: indexes past the end
+    // read the last bucket instead (no branch around a load, which would
+    // wait for it inside the branch), and those buckets are skipped below
+    uint4 qs[U];
 #pragma unroll
-      for (uint32_t k = 0; k < 4; ++k) {
-        const uint32_t y = oth[k];
-        // y < nb: always, on a table that keeps its invariants
-        if (((exp & meta_sec(meta)) >> (base + k)) & 1u && y < nb)
-          __hip_atomic_fetch_sub(meta_ptr(bk, y).p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t u = 0; u < U; ++u) {
+      const uint64_t b = b0 + u * groups;
+      qs[u] = reinterpret_cast<const uint4 *>(bucket_ptr(bk, (uint32_t)(b < nb ? b : nb - 1u)))[r];
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < U; ++u) {
+      const uint64_t b = b0 + u * groups;
+      if (b >= nb) break;
+      const uint4 q = qs[u];
+      const uint32_t meta = (uint32_t)__shfl((int)q.z, (int)(g0 + 1u));
+      // expired bits of this lane's two value words (lanes 6, 7, 12, 13)
+      uint32_t mine = 0u;
+      const uint32_t s0 = r == 6u ? 0u : r == 7u ? 2u : r == 12u ? 4u : 6u;
+      if (r == 6u || r == 7u || r == 12u || r == 13u) {
+        if ((((q.y >> 16) - now) & 0xffffu) >= kMaxDelay) mine |= 1u << s0;
+        if ((((q.w >> 16) - now) & 0xffffu) >= kMaxDelay) mine |= 2u << s0;
+      }
+      const uint32_t exp = meta_busy(meta) &
+                           ((uint32_t)__shfl((int)mine, (int)(g0 + 6u)) |
+                            (uint32_t)__shfl((int)mine, (int)(g0 + 7u)) |
+                            (uint32_t)__shfl((int)mine, (int)(g0 + 12u)) |
+                            (uint32_t)__shfl((int)mine, (int)(g0 + 13u)));
+      if (!exp) continue;
+      if (r == 0u) {
+        __hip_atomic_fetch_and(meta_ptr(bk, (uint32_t)b).p, ~((exp << 16) | (exp << 24)),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        count += (uint64_t)__builtin_popcount(exp);
+      }
+      if (!plain && (r == 14u || r == 15u)) {
+        const uint32_t base = r == 14u ? 0u : 4u;
+        const uint32_t oth[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (uint32_t k = 0; k < 4; ++k) {
+          const uint32_t y = oth[k];
+          // y < nb: always, on a table that keeps its invariants
+          if (((exp & meta_sec(meta)) >> (base + k)) & 1u && y < nb) {
+            const uint32_t old = __hip_atomic_fetch_sub(meta_ptr(bk, y).p, 1u, __ATOMIC_RELAXED,
+                                                        __HIP_MEMORY_SCOPE_AGENT);
+            if (meta_moved(old) == 1u) *bloom_ptr(bk, y) = 0ull;
+          }
+        }
       }
     }
   }
   return count;
-}
-
-// Second step, after every lane has done the first: a bucket whose moved
-// counter is zero has an empty filter (Sec. 4.1: the filter is reset when
-// its counter returns to zero).
-__device__ __forceinline__ void expire_filters_pass(uint8_t *bk, uint64_t nb, uint64_t gtid,
-                                                    uint64_t gthreads) {
-  for (uint64_t b = gtid; b < nb; b += gthreads) {
-    if (meta_moved(*meta_ptr(bk, (uint32_t)b)) == 0u && *bloom_ptr(bk, (uint32_t)b) != 0ull)
-      *bloom_ptr(bk, (uint32_t)b) = 0ull;
-  }
 }
 
 }  // namespace
