@@ -52,18 +52,26 @@ constexpr uint32_t kNoTime = 0x10000u;
 
 // A slot answers the lookup iff its full key equals the searched key and,
 // with timers, its entry is alive at `now` (Sec. 4.2: expired entries are
-// not considered); on a hit sets hit, val (the value without the time) and
-// slot.
+// not considered); on a hit sets hit, val (the stored word, time included:
+// hit_value gives the answer) and slot.
 template <bool TIMED>
 __device__ __forceinline__ void take_word(uint64_t w, uint32_t s, uint32_t now, bool &hit,
                                           uint64_t &val, uint32_t &slot) {
   const bool timed = TIMED && now < kNoTime;
   if (!timed || word_alive(w, now)) {
     hit = true;
-    val = timed ? (w & kValueMask) : w;
+    val = w;
     slot = s;
   }
 }
+
+// The answer of a hit whose stored word is w: the word without its time on a
+// table with timers, else the word.
+template <bool TIMED>
+__device__ __forceinline__ uint64_t hit_value(uint64_t w, uint32_t now) {
+  return TIMED && now < kNoTime ? (w & kValueMask) : w;
+}
+
 
 // Compares the key with the candidate slots `cand` (ascending) of a first
 // line (mine[0..7]).
@@ -126,6 +134,14 @@ struct TableRef {
   uint32_t refresh = 0u;
   uint32_t expiry = 0u;
 };
+
+// A renewing lookup (Sec. 4.2) that found the entry with stored word w
+// writes its new expiration time only when the time differs: rewriting the
+// same time would dirty the line for nothing (hot keys found again and
+// again at one time).
+__device__ __forceinline__ bool needs_refresh(const TableRef &T, uint64_t w) {
+  return (uint32_t)(w >> kTimerShift) != T.expiry;
+}
 
 // Writes the new expiration time of the entry in slot s of bucket b: the
 // high 16 bits of its value word, nothing else.  Lookups of the same batch
@@ -193,10 +209,11 @@ __device__ __forceinline__ void lds_pass(const Wave &w, const TableRef &T, uint4
       if (need) match_line1<TIMED>(mine_a, cand2 & 0xf0u, key, T.now, hit, val, slot);
     }
   }
-  if (TIMED && T.refresh && ok && hit) refresh_entry(T, hit_primary ? f.p : f.a, slot);
+  if (TIMED && T.refresh && ok && hit && needs_refresh(T, val))
+    refresh_entry(T, hit_primary ? f.p : f.a, slot);
   if (ok) {
     __builtin_nontemporal_store((uint8_t)(hit ? 1 : 0), found);
-    __builtin_nontemporal_store(hit ? val : 0ull, val_out);
+    __builtin_nontemporal_store(hit ? hit_value<TIMED>(val, T.now) : 0ull, val_out);
   }
 }
 
@@ -312,16 +329,18 @@ __device__ __forceinline__ void dual_pass(const Wave &w, const TableRef &T, uint
     }
   }
   if (TIMED && T.refresh) {
-    if (A.ok && A.hit) refresh_entry(T, A.hit_primary ? A.f.p : A.f.a, A.slot);
-    if (Bq.ok && Bq.hit) refresh_entry(T, Bq.hit_primary ? Bq.f.p : Bq.f.a, Bq.slot);
+    if (A.ok && A.hit && needs_refresh(T, A.val))
+      refresh_entry(T, A.hit_primary ? A.f.p : A.f.a, A.slot);
+    if (Bq.ok && Bq.hit && needs_refresh(T, Bq.val))
+      refresh_entry(T, Bq.hit_primary ? Bq.f.p : Bq.f.a, Bq.slot);
   }
   if (A.ok) {
     __builtin_nontemporal_store((uint8_t)(A.hit ? 1 : 0), fa);
-    __builtin_nontemporal_store(A.hit ? A.val : 0ull, va);
+    __builtin_nontemporal_store(A.hit ? hit_value<TIMED>(A.val, T.now) : 0ull, va);
   }
   if (Bq.ok) {
     __builtin_nontemporal_store((uint8_t)(Bq.hit ? 1 : 0), fb);
-    __builtin_nontemporal_store(Bq.hit ? Bq.val : 0ull, vb);
+    __builtin_nontemporal_store(Bq.hit ? hit_value<TIMED>(Bq.val, T.now) : 0ull, vb);
   }
 }
 
@@ -446,10 +465,11 @@ __device__ __forceinline__ void reg_pass(const TableRef &T, const uint4 (&key)[P
 #pragma unroll
   for (uint32_t j = 0; j < PER; ++j) {
     if (!L.ok[j]) continue;
-    if (TIMED && T.refresh && L.hit[j])
+    if (TIMED && T.refresh && L.hit[j] && needs_refresh(T, L.val[j]))
       refresh_entry(T, L.hit_primary[j] ? L.f[j].p : L.f[j].a, L.slot[j]);
     __builtin_nontemporal_store((uint8_t)(L.hit[j] ? 1 : 0), found + 64u * j);
-    __builtin_nontemporal_store(L.hit[j] ? L.val[j] : 0ull, vals + 64u * j);
+    __builtin_nontemporal_store(L.hit[j] ? hit_value<TIMED>(L.val[j], T.now) : 0ull,
+                                vals + 64u * j);
   }
 }
 
@@ -548,8 +568,8 @@ __device__ __forceinline__ void quad_pick(const uint4 (&c)[2], uint32_t j, uint3
     }
     if (live != 0u) {
       const uint32_t s = (uint32_t)__builtin_ctz(live), i = s - first;
-      const uint64_t wi = (i & 2u) ? ((i & 1u) ? w[3] : w[2]) : ((i & 1u) ? w[1] : w[0]);
-      const uint64_t v = timed ? (wi & kValueMask) : wi;
+      // the stored word, time included (hit_value gives the answer)
+      const uint64_t v = (i & 2u) ? ((i & 1u) ? w[3] : w[2]) : ((i & 1u) ? w[1] : w[0]);
       res = 1u | (s << 1);
       lo = (uint32_t)v;
       hi = (uint32_t)(v >> 32);
@@ -715,10 +735,10 @@ __device__ __forceinline__ void quad_pass(const TableRef &T, const uint4 (&key)[
 #pragma unroll
   for (uint32_t p = 0; p < PER; ++p) {
     if (!ok[p]) continue;
-    if (TIMED && T.refresh && hit[p])
+    if (TIMED && T.refresh && hit[p] && needs_refresh(T, val[p]))
       refresh_entry(T, hit_primary[p] ? f[p].p : f[p].a, slot[p]);
     __builtin_nontemporal_store((uint8_t)(hit[p] ? 1 : 0), found + 64u * p);
-    __builtin_nontemporal_store(hit[p] ? val[p] : 0ull, vals + 64u * p);
+    __builtin_nontemporal_store(hit[p] ? hit_value<TIMED>(val[p], T.now) : 0ull, vals + 64u * p);
   }
 }
 

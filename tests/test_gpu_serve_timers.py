@@ -37,14 +37,20 @@ def timed_oracle_and_table(B, load, now0, seed, plain):
     return ref, t, keys
 
 
-@pytest.mark.parametrize("plain,refresh", [(False, True), (True, True), (False, False)])
-def test_timed_server_matches_oracle(plain, refresh):
+OMODES = {"cuckoopp": O.MODE_CUCKOOPP, "both": O.MODE_BOTH, "optimistic": O.MODE_OPTIMISTIC}
+
+
+@pytest.mark.parametrize("plain,refresh,mode", [(False, True, "cuckoopp"), (True, True, "both"),
+                                                (False, False, "cuckoopp"),
+                                                (False, True, "optimistic"),
+                                                (False, True, "both")])
+def test_timed_server_matches_oracle(plain, refresh, mode):
     import torch
     from paper_1712_09624_amd.ckpp import Server
     B, ttl, now = 11, 300, 65000
     ref, t, keys = timed_oracle_and_table(B, 0.6, now, 40 + plain, plain)
-    omode = O.MODE_BOTH if plain else O.MODE_CUCKOOPP
-    rng = np.random.default_rng(7 + plain + 2 * refresh)
+    omode = OMODES[mode]
+    rng = np.random.default_rng(7 + plain + 2 * refresh + 4 * len(mode))
     fresh = W.five_tuples(200000, 41, W.STREAM_FRESH)
     fi = 0
     pool = [k for k in keys]  # keys a burst may look up or delete
@@ -53,7 +59,7 @@ def test_timed_server_matches_oracle(plain, refresh):
     # together pass 64512 units, wrapping the clock twice
     steps = [0, 40, 120, 250, 14000, 90, 14000, 14000, 14000, 200, 14000, 60, 9000]
     last_scan = None
-    with Server(t, capacity=1 << 13, idle_ms=500, ttl=ttl, refresh=refresh) as srv:
+    with Server(t, capacity=1 << 13, mode=mode, idle_ms=500, ttl=ttl, refresh=refresh) as srv:
         for si, step in enumerate(steps):
             now = (now + step) & 0xFFFF
             assert srv.set_time(now)
@@ -90,7 +96,7 @@ def test_timed_server_matches_oracle(plain, refresh):
                 df = ref.delete_at(dels, now) if len(dels) else np.zeros(0, np.uint8)
                 want.append((f.astype(np.uint8), v.astype(np.uint64), st.astype(np.uint8),
                              df.astype(np.uint8)))
-            say(f"timed server plain={plain} refresh={refresh} step {si}: now={now} "
+            say(f"timed server plain={plain} refresh={refresh} mode={mode} step {si}: now={now} "
                 f"scan={last_scan == now} bursts={[(len(x[0]), len(x[1]), len(x[3])) for x in bursts]}")
             placed = []
             for look, ins, ivals, dels in bursts:
