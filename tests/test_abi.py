@@ -84,6 +84,7 @@ def test_argument_checks_need_no_device(lib):
     assert lib.ckpp_server_create(None, None, None) == ckpp.EINVAL
     assert lib.ckpp_server_submit(None, 1, 0, 0, None) == ckpp.EINVAL
     assert lib.ckpp_server_put(None, 0, 0, None, None, 1, None) == ckpp.EINVAL
+    assert lib.ckpp_server_set_time(None, 0) == ckpp.EINVAL
     assert lib.ckpp_server_destroy(None) == ckpp.OK
 
 
