@@ -268,9 +268,10 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   // the tails the host wrote before it published `s`
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
   if (a.timed) {
-    // the round takes the bursts done .. take - 1 that share burst done's
-    // time: the time index does not decrease with the burst number, so the
-    // last such burst is found by bisection (usually none is needed)
+    // the round takes only the bursts from `done` on that share burst
+    // done's time (s is cut back to the first burst after them): the time
+    // index does not decrease with the burst number, so the last such burst
+    // is found by bisection (usually none is needed)
     auto word = [&](uint64_t b) {
       return __hip_atomic_load(&h->tails[b % kQueue][3], __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_SYSTEM);
