@@ -176,3 +176,51 @@ def test_timed_server_argument_checks():
         assert srv.status()["submitted"] == 1
     t.close()
     u.close()
+
+
+def test_timed_server_scan_relaunches_an_idle_loop():
+    """The loop exits when idle; a time change that makes the scan due
+    submits its burst, which relaunches the loop, and the scan runs before
+    the next burst: entries that expired before the new time are gone
+    (the oracle agrees on every answer and on the stored-entry count)."""
+    import time
+    import torch
+    from paper_1712_09624_amd import ckpp
+    from paper_1712_09624_amd.ckpp import Server
+    B, now = 9, 1000
+    ref, t, keys = timed_oracle_and_table(B, 0.5, now, 77, False)
+    with Server(t, capacity=1 << 12, idle_ms=20, ttl=100) as srv:
+        assert srv.set_time(now)  # first time: a scan
+        ref.expire_scan(now)
+        fresh = W.distinct_five_tuples(64, 78, stream=W.STREAM_FRESH)
+        vals = np.arange(64, dtype=np.uint64) + np.uint64(5)
+        counts, first = srv.put_burst(insert_keys=to_dev(fresh), insert_values=vals_dev(vals))
+        srv.wait(srv.submit(*counts), 10000)
+        want = ref.insert_at(fresh, vals, np.full(64, now + 100, np.uint16), now)
+        got = srv.get("insert", first[1], counts[1])
+        torch.cuda.current_stream().synchronize()
+        assert np.array_equal(u8(got), want)
+        # let the loop leave, then step the time twice: the second step is
+        # 16384 past the last scan, so it submits the scan's burst
+        deadline = time.time() + 10
+        while srv.status()["state"] != ckpp.SERVER_STOPPED and time.time() < deadline:
+            time.sleep(0.01)
+        assert srv.status()["state"] == ckpp.SERVER_STOPPED
+        launches = srv.status()["launches"]
+        assert srv.set_time(now + 9000)
+        assert srv.status()["launches"] == launches  # no scan due yet: nothing submitted
+        assert srv.set_time(now + 17000)
+        ref.expire_scan(now + 17000)
+        say("timed server: lookups after the relaunching scan")
+        probe = np.concatenate([keys, fresh])
+        counts, first = srv.put_burst(lookup_keys=to_dev(probe))
+        srv.wait(srv.submit(*counts), 10000)
+        f, v = srv.get("lookup", first[0], counts[0])
+        torch.cuda.current_stream().synchronize()
+        wf, wv = ref.lookup_at(probe, now + 17000, O.MODE_CUCKOOPP)
+        assert np.array_equal(u8(f), wf) and np.array_equal(u64(v), wv)
+        assert not wf.any()  # every entry had expired
+        assert srv.status()["launches"] > launches
+    # the loop's scan left only what the oracle's scans left: nothing
+    assert t.stats()["live"] == ref.stats()["live"] == 0
+    t.close()
