@@ -257,8 +257,10 @@ def timers_leg(dev, B, load, n, dpos, dneg, pos_idx, untimed):
     alive: the answers equal those of the table without timers, so the time
     difference is the overhead of the timer check), at now0 + 512 (about
     half the entries expired), and at now0 + 512 with a refresh of every
-    entry found.  Then the anti-revival scan over the whole table once every
-    entry has expired.  Answers are checked on a sample: found iff the key's
+    entry found (each timed call sets a time other than the previous call's,
+    so every hit writes; then once more with the time the entries already
+    hold, which writes nothing).  Then the anti-revival scan over the whole
+    table once every entry has expired.  Answers are checked on a sample: found iff the key's
     entry is alive, value = insertion index."""
     import torch
     now0 = 65000
@@ -274,8 +276,20 @@ def timers_leg(dev, B, load, n, dpos, dneg, pos_idx, untimed):
     for label, now, refresh in (("", now0, None), ("half_expired_", half, None),
                                 ("refresh_", half, (half + 1023) & 0xFFFF)):
         for name, d in (("pos", dpos), ("neg", dneg)):
-            ms = timed(lambda: t.lookup_at(d, now, found=f, values=v, refresh=refresh), 5, dev)
+            last = [refresh]
+
+            def run():
+                if refresh is not None:
+                    # alternate between two times in the window
+                    last[0] = (refresh - 1) & 0xFFFF if last[0] == refresh else refresh
+                t.lookup_at(d, now, found=f, values=v, refresh=last[0])
+
+            ms = timed(run, 5, dev)
             out[f"{label}{name}_glookups"] = n / (ms * 1e-3) / 1e9
+            if refresh is not None and name == "pos":
+                ms = timed(lambda: t.lookup_at(d, now, found=f, values=v, refresh=last[0]), 5,
+                           dev)
+                out["refresh_unchanged_pos_glookups"] = n / (ms * 1e-3) / 1e9
             fo = f.cpu().numpy()[chk]
             if name == "neg":
                 ok = not fo.any()
@@ -289,7 +303,7 @@ def timers_leg(dev, B, load, n, dpos, dneg, pos_idx, untimed):
                     vo[want == 1], vals[pos_idx[chk]][want == 1])
                 if refresh is not None:
                     found_rows = np.unique(pos_idx[f.cpu().numpy() == 1])
-                    exp[found_rows] = refresh
+                    exp[found_rows] = last[0]
             if not ok:
                 raise RuntimeError(f"timed lookups ({label}{name}) returned a wrong answer")
     for name in ("pos", "neg"):
@@ -659,8 +673,15 @@ def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
     refresh = (now0 + 1000) & 0xFFFF
     plan.lookup(keys_d, found, vals_d, now=now0, refresh=refresh)
     check("refreshing plan with timers")
-    out["plan_timed_refresh_us"] = timed(
-        lambda: plan.lookup(keys_d, found, vals_d, now=now0, refresh=refresh), reps, dev) * 1e3
+    # each timed launch sets a time other than the previous launch's, so
+    # every hit writes (a hit that finds the time already set writes nothing)
+    last = [refresh]
+
+    def run_refresh():
+        last[0] = (refresh - 1) & 0xFFFF if last[0] == refresh else refresh
+        plan.lookup(keys_d, found, vals_d, now=now0, refresh=last[0])
+
+    out["plan_timed_refresh_us"] = timed(run_refresh, reps, dev) * 1e3
     out["plan_timed_overhead"] = out["plan_timed_us"] / out["plan_eager_us"] - 1.0
     plan.close()
     for t in tables:
