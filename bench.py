@@ -55,6 +55,10 @@ def parse():
                     help="lookup rate over loads x negative rates x modes (2^24 and 2^20 buckets)")
     ap.add_argument("--serve", type=int, default=0, metavar="BURSTS",
                     help="serving workload, BURSTS bursts per run: peak, then 25/50/75/100%% offered")
+    ap.add_argument("--serve-log2-buckets", type=int, default=24,
+                    help="with --serve: table size (2^B buckets; the table must hold more keys "
+                         "than the 100M-flow universe, for the deletes)")
+    ap.add_argument("--serve-load", type=float, default=0.85, help="with --serve: table load")
     ap.add_argument("--serve-timers", action="store_true",
                     help="with --serve: the table has timers (lookups renew entries; the loop "
                          "runs the anti-revival scan)")
@@ -979,7 +983,8 @@ def main():
         copy_calibration(dev)
         return
     if args.serve:
-        print(json.dumps({"serve": serve_bench(dev, args.serve, timers=args.serve_timers)}),
+        print(json.dumps({"serve": serve_bench(dev, args.serve, B=args.serve_log2_buckets,
+                                                load=args.serve_load, timers=args.serve_timers)}),
               flush=True)
         return
     if args.many_tables:
