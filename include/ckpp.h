@@ -406,8 +406,9 @@ int ckpp_plan_info(const ckpp_plan *p, ckpp_plan_info_t *out);
  * delete of the same round frees, which only matters when the table is
  * full).  Each
  * operation is the Sec. 2 / Sec. 4.1 operation of ckpp_lookup_batch,
- * ckpp_insert_batch or ckpp_delete_batch; results land in the rings at the
- * operation's position.  Admission: a burst is accepted only while the
+ * ckpp_insert_batch or ckpp_delete_batch (on a table with timers, that of
+ * the _at call at its burst's time: see ckpp_server_set_time and the ttl of
+ * the config); results land in the rings at the operation's position.  Admission: a burst is accepted only while the
  * operations submitted and not completed stay within the budget of each
  * ring (and fewer than 4096 bursts are in flight); otherwise CKPP_EBUSY.
  * Ring position of operation number i of a kind: i mod capacity.
