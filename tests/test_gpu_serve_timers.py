@@ -224,3 +224,60 @@ def test_timed_server_scan_relaunches_an_idle_loop():
     # the loop's scan left only what the oracle's scans left: nothing
     assert t.stats()["live"] == ref.stats()["live"] == 0
     t.close()
+
+
+def test_timed_server_insert_and_delete_of_one_key_in_a_round():
+    """On a table with timers, a burst that inserts keys and deletes some of
+    them: the deletes wait for the round's inserts, report found (the fresh
+    entries are alive at the burst's time), and the keys end absent; stored
+    keys deleted alongside report whether they were alive.  Results and the
+    final dictionary equal the oracle's after the same bursts one by one."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Server
+    B, ttl, now = 10, 200, 3000
+    ref, t, keys = timed_oracle_and_table(B, 0.5, now - 500, 31, False)
+    fresh = W.distinct_five_tuples(2000, 32, stream=W.STREAM_FRESH)
+    bursts = []
+    for b in range(8):
+        ins = fresh[250 * b: 250 * b + 60]
+        dels = np.concatenate([ins[:20], keys[40 * b: 40 * b + 10]])  # own inserts + stored keys
+        look = np.concatenate([keys[1000 + 30 * b: 1000 + 30 * b + 30],
+                               fresh[250 * b + 200: 250 * b + 230]])
+        ivals = np.arange(60, dtype=np.uint64) + np.uint64(10**9 * (b + 1))
+        bursts.append((np.ascontiguousarray(look), np.ascontiguousarray(ins), ivals,
+                       np.ascontiguousarray(dels)))
+    e = (now + ttl) & 0xFFFF
+    ref.expire_scan(now)
+    want = []
+    for look, ins, ivals, dels in bursts:
+        f, v = ref.lookup_at(look, now, O.MODE_CUCKOOPP, refresh=e)
+        st = ref.insert_at(ins, ivals, np.full(len(ins), e, np.uint16), now)
+        df = ref.delete_at(dels, now)
+        want.append((f.astype(np.uint8), v.astype(np.uint64), st.astype(np.uint8),
+                     df.astype(np.uint8)))
+    assert any(w[3][20:].any() for w in want) and not all(w[3][20:].all() for w in want)
+    with Server(t, capacity=1 << 12, idle_ms=500, ttl=ttl, refresh=True) as srv:
+        assert srv.set_time(now)
+        say("timed server: bursts inserting and deleting the same keys, back to back")
+        placed = [srv.put_burst(lookup_keys=to_dev(look), insert_keys=to_dev(ins),
+                                insert_values=vals_dev(ivals), delete_keys=to_dev(dels))
+                  for look, ins, ivals, dels in bursts]
+        ids = [srv.submit(*c) for c, _ in placed]
+        srv.wait(ids[-1], 10000)
+        for i, ((c, first), w) in enumerate(zip(placed, want)):
+            f, v = srv.get("lookup", first[0], c[0])
+            st = srv.get("insert", first[1], c[1])
+            df = srv.get("delete", first[2], c[2])
+            torch.cuda.current_stream().synchronize()
+            for g, x, name in zip((u8(f), u64(v), u8(st), u8(df)), w,
+                                  ("lookup found", "lookup values", "insert status",
+                                   "delete found")):
+                assert np.array_equal(g, x), f"burst {i}: {name} differs"
+    probe = np.concatenate([keys, fresh])
+    wf, wv = ref.lookup_at(probe, now, O.MODE_CUCKOOPP)
+    gf, gv = t.lookup_at(to_dev(probe), now)
+    assert np.array_equal(u8(gf), wf) and np.array_equal(u64(gv), wv)
+    bk, kv = t.export()
+    rc, msg = O.check_image(bk, kv, B, W.HASH_SEED, False, timed=True)
+    assert rc == 0, msg
+    t.close()
