@@ -11,9 +11,10 @@
 //             the leader publishes the previous round's completion, waits
 //             for submitted bursts (or exits after idle_ms without any),
 //             writes the round's op ranges and releases the barrier
-//   lookups   every wave runs 64-lookup passes over the round's lookup range
-//             (the lookup passes of the batch kernels, unchanged); then the
-//             round's insert keys go into a set
+//   lookups   every wave runs passes of 128 lookups (64 in the pessimistic
+//             mode) over the round's lookup range (the lookup passes of the
+//             batch kernels, unchanged); then the round's insert keys go into
+//             a set
 //   updates   after a barrier, the inserts (one lane per key, the batch
 //             insert's state machine, unchanged, at most `path_lanes` lanes)
 //             and the deletes (one lane per key, from the other end of the
@@ -301,6 +302,9 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   return kCmdRun;
 }
 
+// The round's lookups [l0, l1), each wave taking 128 at a time (two per
+// lane: the passes of the batch kernel's default form) or, in the
+// pessimistic mode, 64 (one per lane, both buckets' lines at once).
 // TIMED: lookups at time `now` (T carries it, the refresh flag and the
 // refreshed expiration time).
 template <uint32_t MODE, bool TIMED>
@@ -308,16 +312,36 @@ __device__ void lookup_phase(const ServeArgs &a, const TableRef &T, const Wave &
                              uint64_t l1) {
   const uint64_t nwaves = (uint64_t)gridDim.x * kWaves;
   const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  uint64_t i = l0 + wave * 64u + w.lane;
-  uint4 key = i < l1 ? load_stream(a.lk_keys + (i & a.mask)) : zero4();
-  for (; i - w.lane < l1; i += nwaves * 64u) {
-    const uint64_t slot = i & a.mask;
-    uint4 knext;
-    lds_pass<MODE, TIMED>(w, T, key, i < l1, a.lk_found + slot, a.lk_vals + slot, [&] {
-      const uint64_t in = i + nwaves * 64u;
-      knext = in < l1 ? load_stream(a.lk_keys + (in & a.mask)) : zero4();
-    });
-    key = knext;
+  if constexpr (MODE == kModeBoth) {
+    uint64_t i = l0 + wave * 64u + w.lane;
+    uint4 key = i < l1 ? load_stream(a.lk_keys + (i & a.mask)) : zero4();
+    for (; i - w.lane < l1; i += nwaves * 64u) {
+      const uint64_t slot = i & a.mask;
+      uint4 knext;
+      lds_pass<MODE, TIMED>(w, T, key, i < l1, a.lk_found + slot, a.lk_vals + slot, [&] {
+        const uint64_t in = i + nwaves * 64u;
+        knext = in < l1 ? load_stream(a.lk_keys + (in & a.mask)) : zero4();
+      });
+      key = knext;
+    }
+  } else {
+    const uint64_t step = nwaves * 128u;
+    uint64_t i = l0 + wave * 128u + w.lane;  // lookup A of this lane; B is i + 64
+    uint4 ka = i < l1 ? load_stream(a.lk_keys + (i & a.mask)) : zero4();
+    uint4 kb = i + 64u < l1 ? load_stream(a.lk_keys + ((i + 64u) & a.mask)) : zero4();
+    for (; i - w.lane < l1; i += step) {
+      const uint64_t sa = i & a.mask, sb = (i + 64u) & a.mask;
+      uint4 na, nb;
+      dual_pass<MODE, TIMED>(w, T, ka, i < l1, kb, i + 64u < l1, a.lk_found + sa, a.lk_vals + sa,
+                             a.lk_found + sb, a.lk_vals + sb, [&] {
+                               const uint64_t n = i + step;
+                               na = n < l1 ? load_stream(a.lk_keys + (n & a.mask)) : zero4();
+                               nb = n + 64u < l1 ? load_stream(a.lk_keys + ((n + 64u) & a.mask))
+                                                 : zero4();
+                             });
+      ka = na;
+      kb = nb;
+    }
   }
 }
 
