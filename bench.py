@@ -59,6 +59,8 @@ def parse():
                     help="with --serve: table size (2^B buckets; the table must hold more keys "
                          "than the 100M-flow universe, for the deletes)")
     ap.add_argument("--serve-load", type=float, default=0.85, help="with --serve: table load")
+    ap.add_argument("--serve-blocks-per-cu", type=int, default=1,
+                    help="with --serve: blocks of the loop kernel per compute unit (1..4)")
     ap.add_argument("--serve-timers", action="store_true",
                     help="with --serve: the table has timers (lookups renew entries; the loop "
                          "runs the anti-revival scan)")
@@ -724,7 +726,7 @@ SERVE_NOW0, SERVE_TTL, SERVE_TICK = 1000, 1023, 50
 
 
 def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0),
-                budget=1 << 20, capacity=1 << 25, timers=False):
+                budget=1 << 20, capacity=1 << 25, timers=False, blocks_per_cu=1):
     """Serving workload: a 2^24-bucket table at load 0.85 whose first 100M
     keys are the flow universe; a closed-loop run measures the loop's peak,
     then open-loop Poisson runs offer 25/50/75/100 % of it.  Every run's
@@ -740,7 +742,7 @@ def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0
     expiry = np.full(n, SERVE_NOW0 + SERVE_TTL, np.uint16) if timers else None
     t, keys, vals, build_s = build_table(B, load, 11, dev, expiry=expiry, now=SERVE_NOW0)
     universe = min(SERVE_UNIVERSE, len(keys))
-    srv = Server(t, capacity=capacity, budget=budget, blocks_per_cu=1, idle_ms=2000,
+    srv = Server(t, capacity=capacity, budget=budget, blocks_per_cu=blocks_per_cu, idle_ms=2000,
                  ttl=SERVE_TTL if timers else 0, refresh=timers)
     out = {"log2_buckets": B, "load": load, "stored_keys": len(keys), "universe": universe,
            "budget_ops": budget, "ring_capacity": capacity, "bursts_per_run": nbursts,
@@ -984,7 +986,8 @@ def main():
         return
     if args.serve:
         print(json.dumps({"serve": serve_bench(dev, args.serve, B=args.serve_log2_buckets,
-                                                load=args.serve_load, timers=args.serve_timers)}),
+                                                load=args.serve_load, timers=args.serve_timers,
+                                                blocks_per_cu=args.serve_blocks_per_cu)}),
               flush=True)
         return
     if args.many_tables:
