@@ -535,7 +535,8 @@ int ckpp_server_set_time(ckpp_server *s, uint16_t now);
  * it yet, in order), and records when it was admitted and when the host saw
  * it complete, in seconds after the call (h_admit_s, h_done_s: nbursts
  * each).  The stream's ops must already be in the rings at the positions
- * the bursts will take.  Errors: CKPP_ETIMEOUT (not all done within
+ * the bursts will take.  On a server with timers every burst runs at the
+ * time set before the call.  Errors: CKPP_ETIMEOUT (not all done within
  * timeout_s), CKPP_EDEVICE. */
 int ckpp_server_replay(ckpp_server *s, uint64_t nbursts, const uint32_t *h_nlookup,
                        const uint32_t *h_ninsert, const uint32_t *h_ndelete,
