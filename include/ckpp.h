@@ -413,7 +413,8 @@ int ckpp_plan_info(const ckpp_plan *p, ckpp_plan_info_t *out);
  * ring (and fewer than 4096 bursts are in flight); otherwise CKPP_EBUSY.
  * Ring position of operation number i of a kind: i mod capacity.
  * When no burst arrives for idle_ms the kernel exits; the next submit
- * relaunches it. */
+ * relaunches it.  The calls on one server share its submission state: make
+ * them from one host thread at a time. */
 typedef struct ckpp_server ckpp_server;
 
 typedef struct {
