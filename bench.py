@@ -278,6 +278,12 @@ def timers_leg(dev, B, load, n, dpos, dneg, pos_idx, untimed):
     out = {"log2_buckets": B, "load": load, "lookups": n, "build_s": build_s,
            "expiry": "uniform over [now0, now0 + 1023], now0 = 65000 (the window wraps)"}
     chk = np.arange(0, n, max(1, n // 65536))
+    # the anti-revival scan at now0, when every entry is alive: a read of the
+    # whole table that removes nothing
+    removed0 = torch.zeros(1, dtype=torch.int64, device=dev)
+    out["scan_nothing_ms"] = timed(lambda: t.expire_scan(now0, removed=removed0), 3, dev)
+    if int(removed0.item()) != 0:
+        raise RuntimeError("the scan removed entries that were alive")
     half = (now0 + 512) & 0xFFFF
     for label, now, refresh in (("", now0, None), ("half_expired_", half, None),
                                 ("refresh_", half, (half + 1023) & 0xFFFF)):
