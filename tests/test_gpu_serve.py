@@ -253,3 +253,57 @@ def test_server_insert_and_delete_of_one_key_in_a_round():
     gf, gv = t.lookup(to_dev(probe))
     assert np.array_equal(u8(gf), wf) and np.array_equal(u64(gv), wv)
     t.close()
+
+
+def test_server_on_a_table_above_2_24_buckets():
+    """A server on a 2^25-bucket table (8 GiB; the alternate bucket and the
+    filter bits come from a second hash word), checked against the ground
+    truth, which holds at any size: stored keys are found with their values,
+    fresh keys are not, inserts of fresh keys report INSERTED and are found
+    by later bursts, deletes of stored keys report found and the keys are
+    gone afterwards."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Server, Table
+    B = 25
+    n = W.keys_at_load(B, 0.05)
+    keys = W.distinct_five_tuples(n, 61, check=False)
+    vals = W.insertion_values(n)
+    t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=0)
+    say(f"server on 2^{B} buckets: building {n} keys")
+    for s in range(0, n, 1 << 22):
+        st, nf = t.insert(to_dev(keys[s:s + (1 << 22)]), vals_dev(vals[s:s + (1 << 22)]))
+        torch.cuda.synchronize()
+        assert int(nf.item()) == 0
+    rng = np.random.default_rng(62)
+    fresh = W.distinct_five_tuples(4096, 63, stream=W.STREAM_FRESH)
+    with Server(t, capacity=1 << 14, idle_ms=500) as srv:
+        # burst 1: lookups of stored and fresh keys, inserts of fresh keys,
+        # deletes of stored keys that no lookup of the burst reads
+        rows = rng.choice(n, size=3000, replace=False)
+        look = np.concatenate([keys[rows[:2000]], fresh[2048:3048]])
+        dels = keys[rows[2000:2500]]
+        ins = fresh[:2048]
+        ivals = np.arange(2048, dtype=np.uint64) + np.uint64(7 << 40)
+        counts, first = srv.put_burst(lookup_keys=to_dev(look), insert_keys=to_dev(ins),
+                                      insert_values=vals_dev(ivals), delete_keys=to_dev(dels))
+        srv.wait(srv.submit(*counts), 10000)
+        f, v = srv.get("lookup", first[0], counts[0])
+        st = srv.get("insert", first[1], counts[1])
+        df = srv.get("delete", first[2], counts[2])
+        torch.cuda.current_stream().synchronize()
+        f, v, st, df = u8(f), u64(v), u8(st), u8(df)
+        assert f[:2000].all() and np.array_equal(v[:2000], vals[rows[:2000]])
+        assert not f[2000:].any()
+        assert (st == O.INSERTED).all() and df.all()
+        # burst 2: the inserted keys are found, the deleted ones are gone
+        look2 = np.concatenate([ins, dels])
+        counts, first = srv.put_burst(lookup_keys=to_dev(look2))
+        srv.wait(srv.submit(*counts), 10000)
+        f, v = srv.get("lookup", first[0], counts[0])
+        torch.cuda.current_stream().synchronize()
+        f, v = u8(f), u64(v)
+        assert f[:2048].all() and np.array_equal(v[:2048], ivals)
+        assert not f[2048:].any()
+    s = t.stats()
+    assert s["live"] == n + 2048 - 500 and s["locked"] == 0
+    t.close()
