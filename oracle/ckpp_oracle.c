@@ -489,8 +489,7 @@ static void orc_remove_slot(orc_table *t, uint64_t b, int s)
  * lowest free slot of the primary bucket; else the lowest free slot of the
  * secondary bucket, adding the key to the primary's bloom filter; else a
  * cuckoo path is computed and applied, freeing a slot of the primary.
- * With timers (Sec. 4.2) a value of 2^48 or more fails (status FAILED,
- * table unchanged), only alive entries are "present", the key's
+ * With timers (Sec. 4.2) only alive entries are "present", the key's
  * expiration time is set (also on an update), an expired copy of the key
  * is overwritten where it stands, and a slot holding an expired entry
  * counts as free: the expired entry is removed first (lazy deletion).
@@ -499,10 +498,6 @@ static void orc_remove_slot(orc_table *t, uint64_t b, int s)
 int orc_insert_at(orc_table *t, const uint8_t *key, uint64_t value, uint16_t expiry,
                   uint16_t now)
 {
-    /* a table with timers holds values below 2^48 (the expiration time
-     * shares the value's 64-bit word in the GPU layout); a wider value is
-     * refused and nothing changes */
-    if (t->timed && (value >> 48) != 0) return ORC_FAILED;
     uint64_t h = orc_hash(key, t->seed);
     orc_split_t sp;
     orc_split(h, t->log2_buckets, &sp);
@@ -744,8 +739,8 @@ uint64_t orc_stats_size(void) { return sizeof(orc_stats_t); }
  *   I4 for every such key both of its bits are set in bloom[b]
  *   I5 moved[b] == 0 implies bloom[b] == 0
  *   I6 the pad word of every busy slot is zero on a table without timers;
- *      with timers it holds only a 16-bit expiration time and the value
- *      is below 2^48
+ *      with timers it holds only a 16-bit expiration time (the value may
+ *      take all 64 bits: Sec. 4.3 keeps the times beside the tags)
  *   I9 lock words are zero and sec is a subset of busy
  * Statement of I3-I5 follows Sec. 4.1 (bloom filter, moved counter and its
  * reset at zero).  flags: bit 0 plain table, bit 1 table with timers. */
@@ -781,7 +776,7 @@ int orc_check_image(const uint8_t *buckets, const uint8_t *kvbytes, uint32_t log
             if (!(bk[b].busy & (1u << s))) continue;
             const uint8_t *key = kv[b * ORC_SLOTS + (uint64_t)s].key;
             const orc_kv *rec = &kv[b * ORC_SLOTS + (uint64_t)s];
-            if (timed ? ((rec->pad >> 16) != 0 || (rec->value >> 48) != 0) : rec->pad != 0) {
+            if (timed ? (rec->pad >> 16) != 0 : rec->pad != 0) {
                 snprintf(msg, msglen, "I6: bucket %llu slot %d value %016llx pad %016llx",
                          (unsigned long long)b, s, (unsigned long long)rec->value,
                          (unsigned long long)rec->pad);

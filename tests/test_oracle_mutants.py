@@ -54,7 +54,8 @@ MUTANTS = [
      "if (!(bk->busy & (1u << s))) return s;"),
     ("refresh_not_written", "if (refresh && t->timed) orc_rec(t, b, s)->pad = expiry;", ";"),
     ("scan_keeps_expired", "orc_remove_slot(t, b, s);\n                removed++;", "removed++;"),
-    ("timed_value_width_unchecked", "if (t->timed && (value >> 48) != 0) return ORC_FAILED;", ";"),
+    ("timed_value_shares_time_word", "    r->value = value;\n",
+     "    r->value = t->timed ? ((value & 0xFFFFFFFFFFFFull) | ((uint64_t)expiry << 48)) : value;\n"),
     ("update_keeps_old_expiry", "if (t->timed) orc_rec(t, b, s)->pad = expiry;\n", "\n"),
 ]
 
