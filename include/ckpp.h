@@ -44,9 +44,15 @@
  * Hash (the paper uses CityHash64, Sec. 5): with the key read as
  * little-endian u64 halves lo and hi, h = f(f(lo ^ seed) ^ hi), where f is
  * the SplitMix64 output finalizer (Steele, Lea, Flood, OOPSLA 2014).
- * Primary bucket p = h mod 2^B; alternate a = (h >> 24) mod 2^B, xor 1 if
- * equal to p; tag = h >> 48; bloom bits (h >> 24) mod 64 and (h >> 30) mod
- * 64, two values from the secondary-hash field (Sec. 4.1).
+ * Primary bucket p = h mod 2^B and tag = h >> 48.  The alternate bucket and
+ * the two bloom bits come from the secondary-hash field (Sec. 4.1):
+ *   B <= 24: a = (h >> 24) mod 2^B; bloom bits (h >> 24) mod 64 and
+ *            (h >> 30) mod 64;
+ *   B >  24: that field would overlap p, so a second word
+ *            g = f(h ^ 0xc2b2ae3d27d4eb4f) is used: a = g mod 2^B; bloom bits
+ *            (g >> 32) mod 64 and (g >> 38) mod 64 (the constant is an
+ *            arbitrary odd salt, the xxHash64 second prime);
+ * and in both cases a = a xor 1 when a == p.
  */
 #ifndef CKPP_H
 #define CKPP_H
@@ -70,13 +76,20 @@ enum {
     CKPP_ETIMEOUT = 5 /* a wait ran out of time */
 };
 
-/* Per-key insert status (written to d_status). */
+/* Per-key insert status (written to d_status).  CKPP_RETRY is also the
+ * per-key delete outcome of a delete that gave up (see ckpp_delete_batch). */
 enum {
     CKPP_INSERTED = 0, /* the key was absent and now holds its value */
     CKPP_UPDATED = 1,  /* the key was present; its value was replaced */
-    CKPP_FAILED = 2,   /* no cuckoo path within max_kicks (or the retry
-                          bound on contended locks was reached): the
+    CKPP_FAILED = 2,   /* no cuckoo path within max_kicks (Sec. 2): the
                           table's key/value contents are unchanged */
+    CKPP_RETRY = 3,    /* gave up after the table's retry limit of attempts
+                          on bucket locks held by concurrent lanes of the
+                          same batch (ckpp_set_retry_limit): nothing was
+                          stored or changed for this key -- a present key
+                          keeps its old value; the cuckoo moves made on
+                          its behalf only relocated other entries.  The key
+                          may be submitted again. */
 };
 
 /* Flags of ckpp_create. */
@@ -84,10 +97,13 @@ enum {
                          moved counter is kept; lookups read both buckets
                          (the comparison baseline of Sec. 3) */
 #define CKPP_TIMERS 2u /* table with timers (Sec. 4.2): every entry carries a
-                          16-bit expiration time; values are below 2^48.  Such
-                          a table is used through the *_at calls below (and
-                          export/import, stats, clear, hash); the other batch
-                          calls, plans and servers refuse it (CKPP_EINVAL). */
+                          16-bit expiration time.  Device-layout limit: values
+                          must be below 2^48 (see the timers section below).
+                          Such a table is used through the *_at batch calls,
+                          ckpp_plan_lookup_at, servers whose config sets a
+                          ttl, and export/import, stats, clear and hash; the
+                          untimed batch calls and ckpp_plan_lookup refuse it
+                          (CKPP_EINVAL). */
 
 /* Lookup modes (Sec. 3 and Sec. 4.1).  All modes give the same answers. */
 enum {
@@ -124,8 +140,9 @@ int ckpp_clear(ckpp_table *t, void *stream);
  * frees a slot (moves from primary to secondary add to the filter, moves
  * back subtract from the counter and reset the filter at zero).  Keys of one
  * batch must be pairwise distinct (the result is unspecified otherwise).
- * d_status (n bytes, nullable) receives CKPP_INSERTED / UPDATED / FAILED;
- * d_nfailed (one u64, nullable) is incremented by the number of FAILED keys.
+ * d_status (n bytes, nullable) receives CKPP_INSERTED / UPDATED / FAILED /
+ * RETRY; d_nfailed (one u64, nullable) is incremented by the number of
+ * FAILED keys (RETRY keys are counted in ckpp_stats_t.retry_exhausted).
  * The cuckoo-path scratch of the call (4 * max_kicks bytes per launched
  * lane, at most 2^16 lanes) is a buffer of the table's own, allocated on
  * the first batch that uses it and freed with the table; it holds as many
@@ -151,8 +168,12 @@ int ckpp_lookup_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mo
 /* Batched delete (Sec. 4.1, deletion): each present key is removed; if it
  * sat in its secondary bucket the moved counter of its primary is
  * decremented and the primary's filter reset when it reaches zero.
- * d_found (n bytes, nullable) receives 1 if the key was present.  When a key
- * appears twice in one batch exactly one of its entries reports 1. */
+ * d_found (n bytes, nullable) receives 1 if the key was present (and is now
+ * removed), 0 if it was absent, or CKPP_RETRY (3) if the delete gave up
+ * after the table's retry limit of attempts on bucket locks held by
+ * concurrent lanes: nothing was removed and the key may still be present.
+ * When a key appears twice in one batch exactly one of its entries
+ * reports 1. */
 int ckpp_delete_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_found,
                       void *stream);
 
@@ -166,9 +187,15 @@ int ckpp_delete_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint8_t *d_
  * entry is removed with the filter maintenance of a delete).  An expired
  * entry would look alive again 64512 units after it expired (the 16-bit
  * time wraps); ckpp_expire_scan removes every expired entry and must run at
- * least once every 64512 units.  In device memory the time occupies the high
- * 16 bits of the entry's value word, so it is read with the value (no extra
- * memory access for lookups) and values are limited to 48 bits. */
+ * least once every 64512 units.
+ * Device-layout limit (a precondition of this library, not of the paper,
+ * whose entries keep their times in separate 16-bit fields beside the tags,
+ * Sec. 4.3): in device memory the time occupies the high 16 bits of the
+ * entry's value word, so that a lookup reads it with the value (no extra
+ * memory access), and values must be below 2^48.  An insert of a wider
+ * value stores nothing and reports CKPP_FAILED for that key (a present key
+ * keeps its old value and time); ckpp_import refuses an image with a wider
+ * value in an occupied slot. */
 
 /* Batched insert on a table with timers: as ckpp_insert_batch, where only
  * alive entries are present (an alive key is UPDATED; a key whose entry has
@@ -218,10 +245,23 @@ int ckpp_export(const ckpp_table *t, void *h_buckets, void *h_kv, void *stream);
  * The image must satisfy the table's invariants (each entry in one of its
  * two buckets with its tag and other bucket, exact moved counters, no
  * filter false negative, zero locks); lookups on any other image are
- * unspecified.  On a table with timers every record's value must be below
- * 2^48 and its reserved word below 2^16, else CKPP_EINVAL (table
- * unchanged). */
+ * unspecified.  An image that fails ckpp_check_image is refused with
+ * CKPP_EINVAL and the table is unchanged.  On a table with timers a free
+ * slot's record keeps only the low 48 bits of its value (free records are
+ * never read). */
 int ckpp_import(ckpp_table *t, const void *h_buckets, const void *h_kv, void *stream);
+
+/* Host-only check of an image for a table of 2^log2_buckets buckets with
+ * the given create flags (no device is used): CKPP_OK when every lock word
+ * is zero, every sec mask lies within its busy mask, every occupied slot's
+ * other bucket is below 2^log2_buckets (so that inserts, deletes and the
+ * scan, which follow other[], stay inside the table) and, with
+ * CKPP_TIMERS, every occupied slot's value is below 2^48 and its reserved
+ * word below 2^16 (the device layout's limit); else CKPP_EINVAL.  This is
+ * the check ckpp_import applies; it does not verify the remaining
+ * invariants.  Sizes as in ckpp_export. */
+int ckpp_check_image(uint32_t log2_buckets, uint32_t flags, const void *h_buckets,
+                     const void *h_kv);
 
 /* Table statistics (Sec. 3 entries in secondary; Sec. 4.1 moved counters;
  * Sec. 5.3 filter false-positive rate).  The rate a uniformly random absent
@@ -240,9 +280,10 @@ typedef struct {
     uint64_t locked;        /* buckets whose lock word is non-zero */
     uint64_t high_slots;    /* occupied slots 4..7 */
     uint64_t high_slots_secondary; /* of which entries in their secondary */
-    uint64_t retry_exhausted; /* keys of earlier insert/delete batches that
-                                 gave up after the retry bound on contended
-                                 locks (reported FAILED / not found) */
+    uint64_t retry_exhausted; /* keys of earlier insert/delete batches (and
+                                 served bursts) that gave up after the retry
+                                 limit on contended locks: each reported
+                                 CKPP_RETRY */
     uint64_t moved_hist[CKPP_MOVED_BINS];
 } ckpp_stats_t;
 
@@ -298,6 +339,17 @@ typedef struct {
 
 int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg);
 int ckpp_get_lookup_launch(const ckpp_table *t, ckpp_launch_t *cfg);
+
+/* Retry limit of inserts and deletes (this library's bound; the paper's
+ * table has one writer per core, Sec. 2, and never meets a held lock): the
+ * number of attempts one key makes on bucket locks that other lanes of its
+ * batch (or of its serving round) hold before it gives up with CKPP_RETRY.
+ * Locks are never waited on, so every attempt ends.  1 <= limit <= 2^20;
+ * a new table starts at 2^20, where no test or workload of this library has
+ * reached it.  Applies to later batches and to servers created afterwards.
+ * Errors: CKPP_EINVAL (null table, limit out of range). */
+int ckpp_set_retry_limit(ckpp_table *t, uint32_t limit);
+int ckpp_get_retry_limit(const ckpp_table *t, uint32_t *limit);
 
 /* ---- Many tables, one launch -------------------------------------------
  * A plan serves the lookup batches of many tables (each one a Sec. 2 /
@@ -382,7 +434,10 @@ int ckpp_plan_lookup_at(ckpp_plan *p, const void *d_keys, uint8_t *d_found, uint
                         uint16_t now, uint32_t refresh, uint16_t expiry, void *stream);
 
 /* Sets the launch shape (rebuilds the work items: synchronizes the device,
- * not for use under graph capture).  Errors: CKPP_EINVAL (out of range). */
+ * not for use under graph capture).  The work items move to new device
+ * memory, so a HIP graph captured from an earlier ckpp_plan_lookup of this
+ * plan must not be launched afterwards (capture it again).
+ * Errors: CKPP_EINVAL (out of range). */
 int ckpp_plan_set_launch(ckpp_plan *p, const ckpp_plan_launch_t *cfg);
 int ckpp_plan_get_launch(const ckpp_plan *p, ckpp_plan_launch_t *cfg);
 int ckpp_plan_info(const ckpp_plan *p, ckpp_plan_info_t *out);
@@ -443,9 +498,10 @@ typedef struct {
     uint64_t *d_lookup_values;  /* capacity u64 */
     void *d_insert_keys;        /* capacity x 16 bytes */
     uint64_t *d_insert_values;  /* capacity u64 */
-    uint8_t *d_insert_status;   /* capacity bytes (CKPP_INSERTED/UPDATED/FAILED) */
+    uint8_t *d_insert_status;   /* capacity bytes (CKPP_INSERTED/UPDATED/FAILED/RETRY) */
     void *d_delete_keys;        /* capacity x 16 bytes */
-    uint8_t *d_delete_found;    /* capacity bytes */
+    uint8_t *d_delete_found;    /* capacity bytes (0, 1 or CKPP_RETRY, as in
+                                   ckpp_delete_batch) */
     uint64_t capacity;
 } ckpp_server_rings_t;
 

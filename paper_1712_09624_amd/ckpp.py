@@ -18,8 +18,12 @@ LIB_PATH = os.path.join(HERE, "libckpp.so")
 
 OK, EINVAL, ENOMEM, EDEVICE = 0, 1, 2, 3
 INSERTED, UPDATED, FAILED = 0, 1, 2
+# gave up after the table's retry limit on contended locks (insert status, and
+# the delete outcome beside 0/1): nothing changed for that key
+RETRY = 3
+MAX_RETRY_LIMIT = 1 << 20
 PLAIN = 1
-TIMERS = 2  # entries carry 16-bit expiration times (Sec. 4.2); values < 2^48
+TIMERS = 2  # entries carry 16-bit expiration times (Sec. 4.2); device limit: values < 2^48
 MAX_DELAY = 1024
 LOOKUP_DEFAULT, LOOKUP_BOTH, LOOKUP_OPTIMISTIC = 0, 1, 2
 MODES = {"cuckoopp": LOOKUP_DEFAULT, "default": LOOKUP_DEFAULT, "both": LOOKUP_BOTH,
@@ -179,6 +183,9 @@ SIGNATURES = [
     ("ckpp_info", _I, [_VP, ctypes.POINTER(_Info)]),
     ("ckpp_set_lookup_launch", _I, [_VP, ctypes.POINTER(_Launch)]),
     ("ckpp_get_lookup_launch", _I, [_VP, ctypes.POINTER(_Launch)]),
+    ("ckpp_set_retry_limit", _I, [_VP, _U32]),
+    ("ckpp_get_retry_limit", _I, [_VP, ctypes.POINTER(_U32)]),
+    ("ckpp_check_image", _I, [_U32, _U32, _VP, _VP]),
     ("ckpp_plan_create", _I, [ctypes.POINTER(_VP), ctypes.POINTER(_VP), _U32, _VP, _VP, _VP]),
     ("ckpp_plan_destroy", _I, [_VP]),
     ("ckpp_plan_lookup", _I, [_VP, _VP, _VP, _VP, _VP]),
@@ -255,6 +262,21 @@ def _keys_ptr(keys) -> tuple[int, int]:
         raise CkppError("keys must be 16-byte aligned")
     del torch
     return keys.data_ptr(), nbytes // 16
+
+
+def check_image(log2_buckets: int, buckets: np.ndarray, kv: np.ndarray, plain: bool = False,
+                timers: bool = False) -> bool:
+    """Host-only image check of ckpp_check_image (the one ckpp_import
+    applies): True when the library would accept the image."""
+    b = np.ascontiguousarray(buckets, dtype=np.uint8).reshape(-1)
+    k = np.ascontiguousarray(kv, dtype=np.uint8).reshape(-1)
+    if b.size != 64 << log2_buckets or k.size != 256 << log2_buckets:
+        raise CkppError("image size does not match the bucket count")
+    flags = (PLAIN if plain else 0) | (TIMERS if timers else 0)
+    rc = load().ckpp_check_image(int(log2_buckets), flags, b.ctypes.data, k.ctypes.data)
+    if rc not in (OK, EINVAL):
+        _check(rc, "ckpp_check_image")
+    return rc == OK
 
 
 class Table:
@@ -434,6 +456,15 @@ class Table:
             raise CkppError("image size does not match the table")
         rc = self.lib.ckpp_import(self._h, b.ctypes.data, k.ctypes.data, _stream_handle(stream))
         _check(rc, "ckpp_import")
+
+    def set_retry_limit(self, limit: int):
+        """Attempts per key on contended bucket locks before CKPP_RETRY."""
+        _check(self.lib.ckpp_set_retry_limit(self._h, int(limit)), "ckpp_set_retry_limit")
+
+    def retry_limit(self) -> int:
+        out = ctypes.c_uint32()
+        _check(self.lib.ckpp_get_retry_limit(self._h, ctypes.byref(out)), "ckpp_get_retry_limit")
+        return int(out.value)
 
     def stats(self, stream=None) -> dict:
         st = _Stats()

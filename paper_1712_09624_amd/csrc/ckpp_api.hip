@@ -51,14 +51,57 @@ void parallel_range(uint64_t n, F f) {
 
 constexpr uint64_t kValueBits48 = (1ull << 48) - 1ull;
 
-// image (64-byte buckets + 32-byte records) -> device layout.  With timers
-// the device value word is value | expiration time << 48 (the image keeps
-// the time in the record's reserved word).  Returns false (the staging copy
-// then is not used) when a timed record's value or time is out of range.
-bool image_to_device(const uint8_t *hb, const uint8_t *hk, uint8_t *dev, uint64_t nb,
-                     bool timed) {
+// What an image must satisfy before the library copies it to the device:
+// every lock word zero, sec a subset of busy, and for every occupied slot an
+// other bucket inside the table (inserts and the scan follow other[] into
+// other buckets, so a wild index would send them outside the table's
+// memory); on a table with timers, every occupied slot's value below 2^48
+// and its reserved word a 16-bit time (the device layout's limit).  The rest
+// of the invariants (each entry in one of its two buckets, exact moved
+// counters, no filter false negative) are the caller's to keep: lookups on
+// an image that breaks them are unspecified but stay inside the table.
+bool image_valid(const uint8_t *hb, const uint8_t *hk, uint64_t nb, bool timed) {
   std::atomic<bool> ok{true};
   parallel_range(nb, [=, &ok](uint64_t lo, uint64_t hi) {
+    for (uint64_t b = lo; b < hi && ok.load(std::memory_order_relaxed); ++b) {
+      const uint8_t *src = hb + 64 * b;
+      const uint8_t busy = src[26], sec = src[27];
+      uint32_t lock;
+      memcpy(&lock, src + 28, 4);
+      if (lock != 0u || (sec & ~busy) != 0) {
+        ok.store(false);
+        break;
+      }
+      for (uint32_t s = 0; s < 8; ++s) {
+        if (!((busy >> s) & 1u)) continue;
+        uint32_t other;
+        memcpy(&other, src + 32 + 4 * s, 4);
+        bool good = other < nb;
+        if (timed) {
+          const uint8_t *r = hk + 32 * (8 * b + s);
+          uint64_t v, pad;
+          memcpy(&v, r + 16, 8);
+          memcpy(&pad, r + 24, 8);
+          good = good && (v >> 48) == 0 && (pad >> 16) == 0;
+        }
+        if (!good) {
+          ok.store(false);
+          break;
+        }
+      }
+    }
+  });
+  return ok.load();
+}
+
+// image (64-byte buckets + 32-byte records) -> device layout.  With timers
+// the device value word is value | expiration time << 48 (the image keeps
+// the time in the record's reserved word); image_valid has checked that the
+// occupied slots' values and times fit (a free slot's record, never read,
+// keeps only those bits).
+void image_to_device(const uint8_t *hb, const uint8_t *hk, uint8_t *dev, uint64_t nb,
+                     bool timed) {
+  parallel_range(nb, [=](uint64_t lo, uint64_t hi) {
     for (uint64_t b = lo; b < hi; ++b) {
       uint8_t *d = dev + 256 * b;
       const uint8_t *src = hb + 64 * b;
@@ -70,15 +113,11 @@ bool image_to_device(const uint8_t *hb, const uint8_t *hk, uint8_t *dev, uint64_
         uint64_t v, pad;
         memcpy(&v, r + 16, 8);
         memcpy(&pad, r + 24, 8);
-        if (timed) {
-          if ((v >> 48) != 0 || (pad >> 16) != 0) ok.store(false);
-          v = (v & kValueBits48) | ((pad & 0xffffull) << 48);
-        }
+        if (timed) v = (v & kValueBits48) | ((pad & 0xffffull) << 48);
         memcpy(d + dev_value_offset(s), &v, 8);
       }
     }
   });
-  return ok.load();
 }
 
 // device layout -> image (the records' reserved 8 bytes are written as 0,
@@ -147,6 +186,7 @@ int ckpp_create(ckpp_table **out, uint32_t log2_buckets, uint64_t hash_seed, uin
   t->flags = flags;
   t->device = device;
   t->seed = hash_seed;
+  t->retry_limit = ckpp::kMaxRetryLimit;
   t->lookup_launch.lanes_per_lookup = 8;
   t->lookup_launch.lookups_per_lane = 2;
   t->lookup_launch.block = 128;
@@ -321,17 +361,28 @@ int ckpp_export(const ckpp_table *t, void *h_buckets, void *h_kv, void *stream) 
   return dev_status(e);
 }
 
+int ckpp_check_image(uint32_t log2_buckets, uint32_t flags, const void *h_buckets,
+                     const void *h_kv) {
+  if (!h_buckets || !h_kv) return CKPP_EINVAL;
+  if (log2_buckets < 1 || log2_buckets > kMaxLog2Buckets) return CKPP_EINVAL;
+  if (flags & ~(CKPP_PLAIN | CKPP_TIMERS)) return CKPP_EINVAL;
+  return image_valid(static_cast<const uint8_t *>(h_buckets), static_cast<const uint8_t *>(h_kv),
+                     1ull << log2_buckets, (flags & CKPP_TIMERS) != 0)
+             ? CKPP_OK
+             : CKPP_EINVAL;
+}
+
 int ckpp_import(ckpp_table *t, const void *h_buckets, const void *h_kv, void *stream) {
   if (!t || !h_buckets || !h_kv) return CKPP_EINVAL;
+  if (!image_valid(static_cast<const uint8_t *>(h_buckets), static_cast<const uint8_t *>(h_kv),
+                   nbuckets(t), timed(t)))
+    return CKPP_EINVAL;
   DeviceGuard g(t->device);
   if (!g.ok()) return CKPP_EDEVICE;
   uint8_t *stage = new (std::nothrow) uint8_t[table_bytes(t)];
   if (!stage) return CKPP_ENOMEM;
-  if (!image_to_device(static_cast<const uint8_t *>(h_buckets),
-                       static_cast<const uint8_t *>(h_kv), stage, nbuckets(t), timed(t))) {
-    delete[] stage;
-    return CKPP_EINVAL;
-  }
+  image_to_device(static_cast<const uint8_t *>(h_buckets), static_cast<const uint8_t *>(h_kv),
+                  stage, nbuckets(t), timed(t));
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   hipError_t e = hipMemcpyAsync(t->d_table, stage, table_bytes(t), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -403,6 +454,18 @@ int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg) {
 int ckpp_get_lookup_launch(const ckpp_table *t, ckpp_launch_t *cfg) {
   if (!t || !cfg) return CKPP_EINVAL;
   *cfg = t->lookup_launch;
+  return CKPP_OK;
+}
+
+int ckpp_set_retry_limit(ckpp_table *t, uint32_t limit) {
+  if (!t || limit < 1u || limit > ckpp::kMaxRetryLimit) return CKPP_EINVAL;
+  t->retry_limit = limit;
+  return CKPP_OK;
+}
+
+int ckpp_get_retry_limit(const ckpp_table *t, uint32_t *limit) {
+  if (!t || !limit) return CKPP_EINVAL;
+  *limit = t->retry_limit;
   return CKPP_OK;
 }
 

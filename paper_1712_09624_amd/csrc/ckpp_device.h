@@ -20,7 +20,9 @@
 // On a table with timers (Sec. 4.2) the value word of a slot holds the value
 // in its low 48 bits and the entry's 16-bit expiration time in its high 16
 // bits: the time is read with the value, in the line that holds the key, so
-// checking it costs a lookup no extra memory request.
+// checking it costs a lookup no extra memory request.  Values of such a
+// table are therefore limited to 48 bits (a documented precondition; the
+// paper keeps the times beside the tags, Sec. 4.3).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -58,11 +60,16 @@ __device__ __forceinline__ uint64_t key_hash(uint4 k, uint64_t seed) {
   return mix64(mix64(lo ^ seed) ^ hi);
 }
 
+// Salt of the second hash word of tables above 2^24 buckets: an arbitrary
+// odd 64-bit constant (the second prime of xxHash64), so that g is a mix of h
+// independent of the first.
+constexpr uint64_t kSecondWordSalt = 0xc2b2ae3d27d4eb4full;
+
 // Fields of a key derived from its hash for 2^log2b buckets: primary p,
 // alternate a (never equal to p), 16-bit tag, and the two bloom bits, taken
 // from the alternate-bucket field (Sec. 4.1).  That field is h >> 24 up to
 // 2^24 buckets; above, where it would overlap p, a second word
-// g = mix(h ^ 0xc2b2ae3d27d4eb4f) gives a = g mod 2^B and the bloom bit
+// g = mix(h ^ kSecondWordSalt) gives a = g mod 2^B and the bloom bit
 // indices (g >> 32) mod 64 and (g >> 38) mod 64.  bidx packs the two
 // indices (first | second << 6).
 struct KeyFields {
@@ -82,7 +89,7 @@ __device__ __forceinline__ KeyFields key_fields(uint64_t h, uint32_t log2b) {
   uint32_t a = (uint32_t)field & mask;
   uint32_t b1 = (uint32_t)field & 63u, b2 = (uint32_t)(field >> 6) & 63u;
   if (log2b > 24u) {
-    const uint64_t g = mix64(h ^ 0xc2b2ae3d27d4eb4full);
+    const uint64_t g = mix64(h ^ kSecondWordSalt);
     a = (uint32_t)g & mask;
     b1 = (uint32_t)(g >> 32) & 63u;
     b2 = (uint32_t)(g >> 38) & 63u;

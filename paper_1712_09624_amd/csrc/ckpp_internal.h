@@ -18,6 +18,7 @@ struct ckpp_table {
                             // lanes), allocated on the first batch that fits it
   uint32_t own_path_lanes;
   uint64_t *d_stats;    // device accumulator of ckpp_stats_t
+  uint32_t retry_limit; // attempts per key on contended locks (ckpp_set_retry_limit)
   ckpp_launch_t lookup_launch;
   int num_cus;
 };
@@ -50,6 +51,10 @@ struct PlanItem {
 // Largest table: 2^29 buckets (128 GiB, 2^32 slots); bucket indices fit in
 // 29 bits.
 constexpr uint32_t kMaxLog2Buckets = 29;
+
+// Attempts an insert or delete makes on contended bucket locks before it
+// gives up with CKPP_RETRY: the default and largest retry limit.
+constexpr uint32_t kMaxRetryLimit = 1u << 20;
 
 constexpr uint32_t kModeCuckoopp = 0;
 constexpr uint32_t kModeBoth = 1;

@@ -140,6 +140,7 @@ struct ServeArgs {
   uint8_t *de_found;
   uint32_t *paths;
   uint32_t path_lanes;
+  uint32_t spin_limit;  // the table's retry limit per insert/delete
   uint64_t idle_ticks;
   unsigned long long *nspin;
   uint4 *set_keys;    // the round's insert keys, open addressing
@@ -349,7 +350,7 @@ __device__ void lookup_phase(const ServeArgs &a, const TableRef &T, const Wave &
 // entry belongs to the round whose tag it carries, so the set is never
 // cleared.  Built before a barrier, read after it.
 __device__ __forceinline__ uint64_t set_slot(const ServeArgs &a, uint4 k) {
-  return key_hash(k, 0x9e3779b97f4a7c15ull) & a.set_mask;
+  return key_hash(k, kGolden) & a.set_mask;
 }
 
 __device__ void set_build(const ServeArgs &a, uint64_t i0, uint64_t i1, uint32_t tag) {
@@ -393,7 +394,7 @@ __device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1, uint3
     const uint64_t slot = j & a.mask;
     const InsertOutcome o =
         insert_one<TIMED>(a.bk, a.in_keys[slot], a.in_vals[slot], a.T.log2b, a.T.seed,
-                          a.max_kicks, a.plain != 0u, path, expiry, now);
+                          a.max_kicks, a.plain != 0u, path, a.spin_limit, expiry, now);
     a.in_status[slot] = (uint8_t)o.status;
     if (o.spun) atomicAdd(a.nspin, 1ull);
   }
@@ -422,7 +423,8 @@ __device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1, bool 
     }
     bool spun = false;
     a.de_found[slot] =
-        (uint8_t)delete_one<TIMED>(a.bk, k, a.T.log2b, a.T.seed, a.plain != 0u, &spun, now);
+        (uint8_t)delete_one<TIMED>(a.bk, k, a.T.log2b, a.T.seed, a.plain != 0u, a.spin_limit,
+                                   &spun, now);
     if (spun) atomicAdd(a.nspin, 1ull);
   }
   if (deferred)
@@ -788,6 +790,7 @@ int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_confi
   a.de_found = r.d_delete_found;
   a.paths = s->paths;
   a.path_lanes = path_lanes;
+  a.spin_limit = t->retry_limit;
   a.idle_ticks = (uint64_t)c.idle_ms * ckpp::kTicksPerMs;
   a.nspin = reinterpret_cast<unsigned long long *>(t->d_stats) + 127;
   a.set_keys = s->set_keys;

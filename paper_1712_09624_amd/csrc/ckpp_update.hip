@@ -14,7 +14,7 @@ __global__ void __launch_bounds__(256)
     insert_kernel(uint8_t *bk, const uint4 *__restrict__ keys,
                   const uint64_t *__restrict__ vals, const uint16_t *__restrict__ expiry,
                   uint32_t now, uint64_t n, uint32_t log2b, uint64_t seed,
-                  uint32_t max_kicks, uint32_t plain_flag, uint32_t *paths,
+                  uint32_t max_kicks, uint32_t plain_flag, uint32_t spin_limit, uint32_t *paths,
                   uint8_t *__restrict__ status, unsigned long long *nfailed,
                   unsigned long long *nspin) {
   const bool plain = plain_flag != 0u;
@@ -23,7 +23,7 @@ __global__ void __launch_bounds__(256)
   uint32_t *path = paths + lane * (uint64_t)(max_kicks ? max_kicks : 1u);
   for (uint64_t i = lane; i < n; i += nlanes) {
     const InsertOutcome o = insert_one<TIMED>(bk, keys[i], vals[i], log2b, seed, max_kicks, plain,
-                                              path, TIMED ? expiry[i] : 0u, now);
+                                              path, spin_limit, TIMED ? expiry[i] : 0u, now);
     if (status) status[i] = (uint8_t)o.status;
     if (o.status == CKPP_FAILED && nfailed) atomicAdd(nfailed, 1ull);
     if (o.spun && nspin) atomicAdd(nspin, 1ull);
@@ -33,14 +33,14 @@ __global__ void __launch_bounds__(256)
 template <bool TIMED>
 __global__ void __launch_bounds__(256)
     delete_kernel(uint8_t *bk, const uint4 *__restrict__ keys, uint64_t n, uint32_t now,
-                  uint32_t log2b, uint64_t seed, uint32_t plain_flag,
+                  uint32_t log2b, uint64_t seed, uint32_t plain_flag, uint32_t spin_limit,
                   uint8_t *__restrict__ found, unsigned long long *nspin) {
   const bool plain = plain_flag != 0u;
   const uint64_t lane = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t nlanes = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = lane; i < n; i += nlanes) {
     bool spun = false;
-    const int r = delete_one<TIMED>(bk, keys[i], log2b, seed, plain, &spun, now);
+    const int r = delete_one<TIMED>(bk, keys[i], log2b, seed, plain, spin_limit, &spun, now);
     if (spun && nspin) atomicAdd(nspin, 1ull);
     if (found) found[i] = (uint8_t)r;
   }
@@ -92,11 +92,11 @@ hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t
   if (timers)
     hipLaunchKernelGGL(insert_kernel<true>, dim3(grid), dim3(block), 0, s, t->d_table, keys,
                        d_values, d_expiry, timers->now, n, t->log2_buckets, t->seed, t->max_kicks,
-                       plain, paths, d_status, nfailed, nspin);
+                       plain, t->retry_limit, paths, d_status, nfailed, nspin);
   else
     hipLaunchKernelGGL(insert_kernel<false>, dim3(grid), dim3(block), 0, s, t->d_table, keys,
                        d_values, nullptr, 0u, n, t->log2_buckets, t->seed, t->max_kicks, plain,
-                       paths, d_status, nfailed, nspin);
+                       t->retry_limit, paths, d_status, nfailed, nspin);
   e = hipGetLastError();
   if (own) return e;
   const hipError_t f = hipFreeAsync(paths, s);
@@ -113,10 +113,10 @@ hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n,
   const uint4 *keys = reinterpret_cast<const uint4 *>(d_keys);
   if (timers)
     hipLaunchKernelGGL(delete_kernel<true>, dim3(grid), dim3(block), 0, s, t->d_table, keys, n,
-                       timers->now, t->log2_buckets, t->seed, plain, d_found, nspin);
+                       timers->now, t->log2_buckets, t->seed, plain, t->retry_limit, d_found, nspin);
   else
     hipLaunchKernelGGL(delete_kernel<false>, dim3(grid), dim3(block), 0, s, t->d_table, keys, n,
-                       0u, t->log2_buckets, t->seed, plain, d_found, nspin);
+                       0u, t->log2_buckets, t->seed, plain, t->retry_limit, d_found, nspin);
   return hipGetLastError();
 }
 

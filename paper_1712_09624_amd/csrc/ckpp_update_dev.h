@@ -36,8 +36,9 @@
 //           resets its filter at zero (Sec. 4.1).  A stale path returns to
 //           DIRECT (the moves done so far are valid moves); when the path is
 //           applied, p has a free slot and the key returns to DIRECT.
-// Every loop is bounded: walks by max_kicks, retries by a fixed limit whose
-// exhaustion reports FAILED and is counted separately.
+// Every loop is bounded: walks by max_kicks, retries by the table's retry
+// limit, whose exhaustion reports CKPP_RETRY for that key (nothing changed
+// for it) and is counted separately.
 //
 // Timers (Sec. 4.2, tables with timers only): an entry's expiration time
 // sits in the high 16 bits of its value word, so every move carries it
@@ -58,7 +59,14 @@
 namespace ckpp {
 namespace {
 
-constexpr uint32_t kSpinLimit = 1u << 20;  // loop iterations per key
+// Random draws of the path search: counter-based SplitMix64 streams keyed
+// by the key's hash.  kGolden is SplitMix64's own increment (2^64 / golden
+// ratio); the other two are arbitrary odd salts that separate the streams
+// (the multiplier of the PCG/MMIX generator, and a second golden-ratio-like
+// odd constant), with no arithmetic role beyond that.
+constexpr uint64_t kGolden = 0x9e3779b97f4a7c15ull;
+constexpr uint64_t kDisplaceSalt = 0x5851f42d4c957f2dull;
+constexpr uint64_t kWalkSalt = 0xd1b54a32d192ed03ull;
 constexpr uint32_t kMaxWalks = 64;         // path searches per key
 constexpr uint32_t kNoBucket = 0xffffffffu;
 // A cuckoo path entry: bucket (below 2^29) | slot << 29.
@@ -389,7 +397,7 @@ __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32
   uint32_t v = kSlots, y1 = kNoBucket, t = kSlots, y2 = kNoBucket;
   if (room) {
     const uint32_t pick = (room & sec) ? (room & sec) : room;
-    v = nth_bit(pick, (uint32_t)(mix64(h ^ 0x5851f42d4c957f2dull) %
+    v = nth_bit(pick, (uint32_t)(mix64(h ^ kDisplaceSalt) %
                                  (uint64_t)__builtin_popcount(pick)));
     y1 = other[v];
   } else {
@@ -608,7 +616,7 @@ __device__ __attribute__((noinline)) int walk(const uint8_t *bk, uint32_t start,
         if (meta_busy(om) != 0xffu) room |= 1u << s;
       }
     }
-    const uint64_t r = mix64(rbase + (uint64_t)(step + 1) * 0x9e3779b97f4a7c15ull);
+    const uint64_t r = mix64(rbase + (uint64_t)(step + 1) * kGolden);
     if (room) {
       const uint32_t pick = (room & sec) ? (room & sec) : room;
       const uint32_t v = nth_bit(pick, (uint32_t)(r % (uint64_t)__builtin_popcount(pick)));
@@ -670,20 +678,24 @@ __device__ __attribute__((noinline)) int move_entry(uint8_t *bk, uint32_t x, uin
 }
 
 // Outcome of one key's insert: its status, and whether the retry bound ran
-// out (then the status is CKPP_FAILED).
+// out (then the status is CKPP_RETRY).
 struct InsertOutcome {
   int status;
   bool spun;
 };
 
 // Runs one key through the DIRECT / WALK / MOVE state machine until it is
-// placed, updated or fails.  path: this lane's scratch, max(1, max_kicks)
-// words.  TIMED: the table has timers; the entry gets expiration time
-// `expiry`, and a value of 2^48 or more fails at once.
+// placed, updated or fails, for at most spin_limit iterations (then
+// CKPP_RETRY: the key's value is neither stored nor changed; the moves
+// applied so far only relocated other entries).  path: this lane's scratch,
+// max(1, max_kicks) words.  TIMED: the table has timers; the entry gets
+// expiration time `expiry`, and a value of 2^48 or more (the device layout's
+// limit) fails at once with nothing changed.
 template <bool TIMED = false>
 __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint32_t log2b,
                                     uint64_t seed, uint32_t max_kicks, bool plain,
-                                    uint32_t *path, uint32_t expiry = 0u, uint32_t now = 0u) {
+                                    uint32_t *path, uint32_t spin_limit, uint32_t expiry = 0u,
+                                    uint32_t now = 0u) {
   if (TIMED && (value >> kTimerShift) != 0ull) return InsertOutcome{CKPP_FAILED, false};
   const uint64_t word = TIMED ? (value | ((uint64_t)(expiry & 0xffffu) << kTimerShift)) : value;
   const uint64_t h = key_hash(key, seed);
@@ -693,8 +705,8 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
   uint32_t len = 0, next = 0, last = 0, walks = 0, iters = 0;
   bool spun = false;
   while (result < 0) {
-    if (++iters > kSpinLimit) {
-      result = CKPP_FAILED;
+    if (++iters > spin_limit) {
+      result = CKPP_RETRY;
       spun = true;
       break;
     }
@@ -710,7 +722,7 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
         result = CKPP_FAILED;
         break;
       }
-      const int L = walk(bk, f.p, h ^ ((uint64_t)walks * 0xd1b54a32d192ed03ull), max_kicks, plain,
+      const int L = walk(bk, f.p, h ^ ((uint64_t)walks * kWalkSalt), max_kicks, plain,
                          path, &last);
       ++walks;
       if (L <= 0) {
@@ -768,20 +780,21 @@ __device__ int delete_direct(uint8_t *bk, uint4 key, const KeyFields &f, bool pl
 }
 
 
-// Deletes one key: 1 if it was removed, 0 if absent; *spun is set when the
-// retry bound ran out (then 0 is returned).
+// Deletes one key: 1 if it was removed, 0 if absent, CKPP_RETRY (nothing
+// removed; the key may still be present) when its bucket locks stayed taken
+// by other lanes for spin_limit attempts; *spun is set in that case.
 template <bool TIMED = false>
 __device__ int delete_one(uint8_t *bk, uint4 key, uint32_t log2b, uint64_t seed, bool plain,
-                          bool *spun, uint32_t now = 0u) {
+                          uint32_t spin_limit, bool *spun, uint32_t now = 0u) {
   const KeyFields f = key_fields(key_hash(key, seed), log2b);
   int r = kBusy;
   uint32_t iters = 0;
-  while (r == kBusy && iters < kSpinLimit) {
+  while (r == kBusy && iters < spin_limit) {
     ++iters;
     r = delete_direct<TIMED>(bk, key, f, plain, now);
   }
   *spun = r == kBusy;
-  return r == kBusy ? 0 : r;
+  return r == kBusy ? CKPP_RETRY : r;
 }
 
 // Anti-revival scan (Sec. 4.2) over buckets [0, nb) by the lanes gtid of a

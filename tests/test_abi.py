@@ -68,6 +68,9 @@ def test_argument_checks_need_no_device(lib):
     assert lib.ckpp_delete_batch_at(None, None, 5, 0, None, None) == ckpp.EINVAL
     assert lib.ckpp_expire_scan(None, 0, None, None) == ckpp.EINVAL
     assert lib.ckpp_set_lookup_launch(None, None) == ckpp.EINVAL
+    assert lib.ckpp_set_retry_limit(None, 5) == ckpp.EINVAL
+    assert lib.ckpp_get_retry_limit(None, None) == ckpp.EINVAL
+    assert lib.ckpp_check_image(10, 0, None, None) == ckpp.EINVAL
     assert lib.ckpp_destroy(None) == ckpp.OK
     assert lib.ckpp_probe_random_reads(None, 64, 64, 1, 1, 0, 256, 1, 0, None, None) == ckpp.EINVAL
     offs = (ctypes.c_uint64 * 1)(0)
@@ -127,3 +130,54 @@ int main(void) {
     assert sz_sr == ctypes.sizeof(ckpp._ServerRings)
     assert sz_ss == ctypes.sizeof(ckpp._ServerStatus)
     assert off_lns == ckpp._ServerStatus.lookup_ns.offset
+
+
+def test_check_image_rejects_wild_images(lib):
+    """ckpp_check_image (the check ckpp_import applies, host-only): an image
+    the oracle built is accepted; a lock word left set, a sec bit outside
+    busy, an occupied slot whose other bucket lies outside the table, and on
+    a table with timers an occupied slot's value of 2^48 or more or a
+    reserved word above 16 bits are refused; a wide value in a free slot is
+    not looked at."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1712_09624_amd import workload as W
+    B = 6
+    n = W.keys_at_load(B, 0.8)
+    keys = W.distinct_five_tuples(n, 11)
+    for timed in (False, True):
+        ref = O.OracleTable(B, W.HASH_SEED, W.MAX_KICKS, timed=timed)
+        if timed:
+            ref.insert_at(keys, W.insertion_values(n), np.full(n, 300, np.uint16), 0)
+        else:
+            ref.insert(keys, W.insertion_values(n))
+        b, k = ref.image()
+        assert ckpp.check_image(B, b, k, timers=timed)
+        bk = b.reshape(-1, 64)
+        rec = k.reshape(-1, 32)
+        busy = bk[:, 26]
+        bb = int(np.flatnonzero(busy)[0])
+        s0 = int(np.flatnonzero([(busy[bb] >> i) & 1 for i in range(8)])[0])
+
+        def refused(bm=None, km=None):
+            b2, k2 = bk.copy(), rec.copy()
+            if bm:
+                bm(b2)
+            if km:
+                km(k2)
+            return not ckpp.check_image(B, b2, k2, timers=timed)
+
+        assert refused(bm=lambda x: x.__setitem__((bb, 29), 1))               # lock word
+        free = int(np.flatnonzero(busy != 0xFF)[0])
+        fslot = int(next(i for i in range(8) if not (busy[free] >> i) & 1))
+        assert refused(bm=lambda x: x.__setitem__((free, 27), x[free, 27] | (1 << fslot)))
+        big = np.frombuffer(np.uint32(1 << B).tobytes(), np.uint8)
+        assert refused(bm=lambda x: x.__setitem__((bb, slice(32 + 4 * s0, 36 + 4 * s0)), big))
+        if timed:
+            r = bb * 8 + s0
+            assert refused(km=lambda x: x.__setitem__((r, 23), 1))            # value >= 2^56
+            assert refused(km=lambda x: x.__setitem__((r, 26), 1))            # time >= 2^16
+            fr = free * 8 + fslot
+            k3 = rec.copy()
+            k3[fr, 23] = 0x80
+            assert ckpp.check_image(B, bk, k3, timers=True)

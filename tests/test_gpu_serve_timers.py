@@ -82,7 +82,9 @@ def test_timed_server_matches_oracle(plain, refresh, mode):
                 ins = fresh[fi:fi + ni]
                 fi += ni
                 ivals = rng.integers(0, 1 << 48, size=ni, dtype=np.int64).astype(np.uint64)
-                ivals[rng.random(ni) < 0.05] |= np.uint64(1 << 50)  # too wide: FAILED
+                # values of 2^48 or more: refused by the device layout of
+                # tables with timers (FAILED, nothing changes for the key)
+                ivals[rng.random(ni) < 0.05] |= np.uint64(1 << 50)
                 dels = np.stack([pool[i] for i in dpick[b]]) if len(dpick[b]) else fresh[:0]
                 bursts.append((np.ascontiguousarray(look), np.ascontiguousarray(ins), ivals,
                                np.ascontiguousarray(dels)))
@@ -91,8 +93,11 @@ def test_timed_server_matches_oracle(plain, refresh, mode):
             e = (now + ttl) & 0xFFFF
             for look, ins, ivals, dels in bursts:
                 f, v = ref.lookup_at(look, now, omode, refresh=e if refresh else None)
-                st = (ref.insert_at(ins, ivals, np.full(len(ins), e, np.uint16), now)
-                      if len(ins) else np.zeros(0, np.uint8))
+                st = np.full(len(ins), O.FAILED, np.uint8)
+                fits = (ivals >> np.uint64(48)) == 0
+                if fits.any():
+                    st[fits] = ref.insert_at(ins[fits], ivals[fits],
+                                             np.full(int(fits.sum()), e, np.uint16), now)
                 df = ref.delete_at(dels, now) if len(dels) else np.zeros(0, np.uint8)
                 want.append((f.astype(np.uint8), v.astype(np.uint64), st.astype(np.uint8),
                              df.astype(np.uint8)))

@@ -199,12 +199,15 @@ def test_lazy_reuse_two_buckets():
 
 @pytest.mark.parametrize("B,plain", [(4, False), (10, False), (8, True)])
 def test_timed_dictionary_vs_oracle(B, plain):
-    """Random batches of inserts (some values too wide), refreshing lookups
-    and deletes while the clock advances and wraps, with a scan at least
-    every 30000 units, on the GPU and on the oracle: every insert status and
-    every key's answer agree after each round; the GPU image keeps its
-    invariants.  The universe is 85% of the slots, so no insert fails for
-    lack of room and the statuses are unique."""
+    """Random batches of inserts, refreshing lookups and deletes while the
+    clock advances and wraps, with a scan at least every 30000 units, on the
+    GPU and on the oracle: every insert status and every key's answer agree
+    after each round; the GPU image keeps its invariants.  The universe is
+    85% of the slots, so no insert fails for lack of room and the statuses
+    are unique.  Some insert values are 2^48 or more: the GPU's device
+    layout refuses them (a documented precondition of its tables with
+    timers: status FAILED, nothing changes for that key), which the test
+    models by giving the oracle only the other keys of the batch."""
     import torch
     rng = np.random.default_rng(B)
     cap = 8 << B
@@ -230,9 +233,12 @@ def test_timed_dictionary_vs_oracle(B, plain):
             since_scan += step
         elif op == "ins":
             vals = rng.integers(0, 1 << 48, size=k, dtype=np.int64).astype(np.uint64)
-            vals[rng.random(k) < 0.03] |= np.uint64(1 << 62)
+            wide = rng.random(k) < 0.03
+            vals[wide] |= np.uint64(1 << 62)
             exp = ((now + rng.integers(0, 1024, size=k)) & 0xFFFF).astype(np.uint16)
-            want = ref.insert_at(keys, vals, exp, now)
+            want = np.full(k, O.FAILED, np.uint8)
+            if (~wide).any():
+                want[~wide] = ref.insert_at(keys[~wide], vals[~wide], exp[~wide], now)
             st, nf = t.insert_at(to_dev(keys), vals_dev(vals), exp_dev(exp), now)
             torch.cuda.synchronize()
             assert np.array_equal(u8(st), want), "insert statuses differ"
@@ -255,6 +261,70 @@ def test_timed_dictionary_vs_oracle(B, plain):
         check_timed_image(t, B, plain)
     st = t.stats()
     assert st["locked"] == 0 and st["retry_exhausted"] == 0
+    t.close()
+
+
+@pytest.mark.parametrize("B", [3, 9])
+def test_wide_values_device_limit(B):
+    """The device-layout limit of tables with timers, as include/ckpp.h states
+    it: an insert of a value of 2^48 or more stores nothing and reports
+    FAILED for that key (counted in nfailed) -- an absent key stays absent,
+    a present key keeps its old value and time -- while the other keys of
+    the batch are inserted or updated as usual; and ckpp_import refuses an
+    image (built by the oracle, whose dictionary takes 64-bit values) with
+    such a value in an occupied slot, leaving the table unchanged."""
+    import torch
+    rng = np.random.default_rng(40 + B)
+    now = 700
+    n = int(0.5 * (8 << B))
+    keys = W.distinct_five_tuples(n, 90 + B)
+    vals = rng.integers(0, 1 << 48, size=n, dtype=np.int64).astype(np.uint64)
+    exp = ((now + rng.integers(0, 1024, size=n)) & 0xFFFF).astype(np.uint16)
+    t = new_timed(B)
+    say(f"wide values B={B}: first batch")
+    st, nf = t.insert_at(to_dev(keys), vals_dev(vals), exp_dev(exp), now)
+    torch.cuda.synchronize()
+    assert (u8(st) == O.INSERTED).all() and int(nf.item()) == 0
+    # a second batch: updates of half of the keys and fresh keys, a third of
+    # each with a value of 2^48 or more
+    fresh = W.distinct_five_tuples(n // 2, 95 + B, stream=W.STREAM_FRESH)
+    k2 = np.concatenate([keys[: n // 2], fresh])
+    v2 = rng.integers(0, 1 << 48, size=len(k2), dtype=np.int64).astype(np.uint64)
+    wide = rng.random(len(k2)) < 1 / 3
+    wide[0] = wide[-1] = True
+    v2[wide] |= rng.integers(1, 1 << 16, size=int(wide.sum()),
+                             dtype=np.int64).astype(np.uint64) << np.uint64(48)
+    e2 = np.full(len(k2), (now + 5) & 0xFFFF, np.uint16)
+    say(f"wide values B={B}: mixed batch")
+    st, nf = t.insert_at(to_dev(k2), vals_dev(v2), exp_dev(e2), now)
+    torch.cuda.synchronize()
+    st = u8(st)
+    assert (st[wide] == O.FAILED).all(), "a value of 2^48 or more must be refused"
+    upd = ~wide & (np.arange(len(k2)) < n // 2)
+    assert (st[upd] == O.UPDATED).all() and (st[~wide & ~upd] == O.INSERTED).all()
+    assert int(nf.item()) == int(wide.sum())
+    # the dictionary: refused updates keep the old value, refused fresh keys
+    # are absent
+    want = {kk.tobytes(): int(v) for kk, v in zip(keys, vals)}
+    for i in np.flatnonzero(~wide):
+        want[k2[i].tobytes()] = int(v2[i])
+    probe = np.concatenate([keys, fresh])
+    f, v = t.lookup_at(to_dev(probe), now)
+    assert np.array_equal(u8(f), np.array([p.tobytes() in want for p in probe], np.uint8))
+    assert np.array_equal(u64(v), np.array([want.get(p.tobytes(), 0) for p in probe], np.uint64))
+    check_timed_image(t, B)
+    # an oracle image holding a wide value is refused; the table is unchanged
+    ref = O.OracleTable(B, W.HASH_SEED, W.MAX_KICKS, timed=True)
+    ref.insert_at(k2, v2, e2, now)
+    rb, rk = ref.image()
+    from paper_1712_09624_amd.ckpp import CkppError, check_image
+    assert not check_image(B, rb, rk, timers=True)
+    assert check_image(B, rb, rk, timers=False)
+    gb, gk = t.export()
+    with pytest.raises(CkppError):
+        t.import_image(rb, rk)
+    gb2, gk2 = t.export()
+    assert np.array_equal(gb, gb2) and np.array_equal(gk, gk2)
     t.close()
 
 

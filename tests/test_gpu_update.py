@@ -179,6 +179,56 @@ def test_contention_overfill(B, over):
     t.close()
 
 
+def test_retry_limit_per_key_outcome():
+    """The per-key outcome of giving up on contended locks.  Sixteen keys of
+    a 2-bucket table all need the same two bucket locks; with a retry limit
+    of one attempt, the lanes that find a lock held report CKPP_RETRY: those
+    keys are absent afterwards (nothing stored, not counted as FAILED), the
+    others are INSERTED with their values, and the table keeps its
+    invariants.  A delete batch under the same limit reports RETRY for the
+    keys it did not remove, which are still found.  Locks are never waited
+    on, so every kernel ends; at the default limit the retried keys then
+    succeed."""
+    import torch
+    from paper_1712_09624_amd.ckpp import MAX_RETRY_LIMIT, RETRY
+    keys = W.distinct_five_tuples(16, 140)
+    vals = W.insertion_values(16, 50)
+    t = new_table(1)
+    assert t.retry_limit() == MAX_RETRY_LIMIT
+    t.set_retry_limit(1)
+    assert t.retry_limit() == 1
+    say("retry limit 1: contended insert of 16 keys into 2 buckets")
+    st, nfail = insert_batches(t, keys, vals, 16)
+    assert set(np.unique(st)) <= {O.INSERTED, RETRY}
+    ins = st == O.INSERTED
+    assert ins.any() and (~ins).any(), f"statuses {st}"
+    assert nfail == 0
+    assert t.stats()["retry_exhausted"] == int((~ins).sum())
+    f, v = t.lookup(to_dev(keys))
+    assert np.array_equal(u8(f), ins.astype(np.uint8))
+    assert np.array_equal(u64(v), np.where(ins, vals, 0).astype(np.uint64))
+    check_gpu_image(t, 1)
+    say("default limit: the retried keys")
+    t.set_retry_limit(MAX_RETRY_LIMIT)
+    st2, _ = insert_batches(t, keys[~ins], vals[~ins], 16)
+    assert (st2 == O.INSERTED).all()
+    t.set_retry_limit(1)
+    say("retry limit 1: contended delete of the 16 keys")
+    d = u8(t.delete(to_dev(keys)))
+    torch.cuda.synchronize()
+    assert set(np.unique(d)) <= {0, 1, RETRY}
+    removed = d == 1
+    assert removed.any() and (d == RETRY).any() and not (d == 0).any(), f"outcomes {d}"
+    f, v = t.lookup(to_dev(keys))
+    assert np.array_equal(u8(f), (~removed).astype(np.uint8))
+    check_gpu_image(t, 1)
+    t.set_retry_limit(MAX_RETRY_LIMIT)
+    d2 = u8(t.delete(to_dev(keys)))
+    assert np.array_equal(d2, (~removed).astype(np.uint8))
+    assert t.stats()["live"] == 0
+    t.close()
+
+
 def test_duplicate_deletes_in_one_batch():
     B = 8
     n = W.keys_at_load(B, 0.9)
