@@ -124,6 +124,32 @@ def expected_lines(stats: dict) -> dict:
 
 
 STREAM_BYTES = 16 + 1 + 8  # key in, found + value out, per lookup
+ALG_LINE = 64  # the method's unit of memory access: a 64-byte cache line
+
+
+def algorithmic_lines_64(stats: dict) -> dict:
+    """Lines of 64 bytes a lookup must touch in the paper's layout (a 64-byte
+    bucket line, and a separate 32-byte key/value record, Sec. 4.3), the
+    unit of the roofline's algorithmic bytes: a positive Cuckoo++ lookup
+    reads its primary bucket and the record of its key, plus the secondary
+    bucket when the key was displaced there (f_sec), 2 + f_sec; a negative
+    one reads its primary bucket, plus the secondary when the filter passes
+    (FPR), 1 + FPR (Sec. 4.1).  Each probed bucket adds a record read per
+    false 16-bit tag match, eps = (busy slots per bucket) * 2^-16.  The
+    pessimistic lookup always reads both buckets: 3 + eps positive, 2 + 2 eps
+    negative; the optimistic one reads the secondary whenever the key is not
+    in the primary."""
+    nb, live = stats["nbuckets"], max(1, stats["live"])
+    f_sec, fpr = stats["f_sec"], stats["expected_fpr"]
+    eps = (live / nb) / 65536.0
+    return {
+        "cuckoopp_pos": 2.0 + f_sec + eps * (1.0 + f_sec),
+        "cuckoopp_neg": 1.0 + fpr + eps * (1.0 + fpr),
+        "plain_pos": 3.0 + eps,
+        "plain_neg": 2.0 + 2.0 * eps,
+        "optimistic_pos": 2.0 + f_sec + eps * (1.0 + f_sec),
+        "optimistic_neg": 2.0 + 2.0 * eps,
+    }
 
 
 def build_table(B, load, seed, dev, batch=1 << 22, expiry=None, now=0):
@@ -337,66 +363,158 @@ def timers_leg(dev, B, load, n, dpos, dneg, pos_idx, untimed):
     return out
 
 
-def burst_latency(t, pos_keys_dev, neg_keys_dev, dev, nbursts=2000):
-    """Submit-to-completion time of single synchronous lookup bursts, sizes
-    log-uniform in [1, 2048], each half positive and half negative."""
+def burst_latency(dev, keys, B=24, load=0.85, nbursts=10_000, neg_rate=0.5, warm=100):
+    """Single-kernel burst latency on a 2^B-bucket table at `load`: nbursts
+    synchronous lookup_batch calls, burst sizes log-uniform in [1, 2048]
+    (the serving workload's burst-size law), each lookup of a burst
+    independently negative with probability neg_rate (positives uniform over
+    the stored keys); p50/p99 of submit -> completion on the host clock.
+    The table holds the first keys_at_load(B, load) keys of `keys` (the
+    benchmark's key stream).  The first `warm` bursts are not counted."""
     import torch
-    sizes = W.log_uniform_sizes(nbursts, 1, 2048, 5, 0)
-    f = torch.empty(4096, dtype=torch.uint8, device=dev)
-    v = torch.empty(4096, dtype=torch.int64, device=dev)
+    n = W.keys_at_load(B, load)
+    from paper_1712_09624_amd.ckpp import Table
+    t = Table(B, W.HASH_SEED, W.MAX_KICKS, device=dev.index)
+    nfail = torch.zeros(1, dtype=torch.int64, device=dev)
+    for s0 in range(0, n, 1 << 22):
+        s1 = min(n, s0 + (1 << 22))
+        t.insert(to_dev(keys[s0:s1], dev),
+                 to_dev(W.insertion_values(s1 - s0, s0).view(np.int64), dev), nfailed=nfail)
+    torch.cuda.synchronize()
+    if int(nfail.item()):
+        raise RuntimeError("inserts failed while building the burst-latency table")
+    sizes = W.log_uniform_sizes(nbursts + warm, 1, 2048, 5, 0)
+    total = int(sizes.sum())
+    mix, isneg, idx = W.lookup_mix(keys[:n], total, neg_rate, 6)
+    dmix = to_dev(mix, dev)
+    f = torch.empty(total, dtype=torch.uint8, device=dev)
+    v = torch.empty(total, dtype=torch.int64, device=dev)
+    offs = np.concatenate([[0], np.cumsum(sizes)])
     lat = []
-    for i, s in enumerate(sizes):
-        s = int(s)
-        src = pos_keys_dev if i % 2 == 0 else neg_keys_dev
-        off = (i * 4096) % (src.shape[0] - 4096)
-        q = src[off:off + s]
+    for i in range(len(sizes)):
+        a, b = int(offs[i]), int(offs[i + 1])
+        q = dmix[a:b]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        t.lookup(q, "cuckoopp", found=f[:s], values=v[:s])
+        t.lookup(q, "cuckoopp", found=f[a:b], values=v[a:b])
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t0)
-    lat = np.array(lat[50:]) * 1e6
+    fo = f.cpu().numpy()
+    vo = v.cpu().numpy().view(np.uint64)
+    want_v = np.where(isneg, 0, idx).astype(np.uint64)  # values = insertion index
+    if not (np.array_equal(fo, (~isneg).astype(np.uint8)) and np.array_equal(vo, want_v)):
+        raise RuntimeError("burst lookups returned a wrong answer")
+    t.close()
+    lat = np.array(lat[warm:]) * 1e6
+    counted = int(offs[-1] - offs[warm])
     return {"p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
-            "bursts": int(len(lat)), "sizes": "log-uniform [1, 2048]"}
+            "mean_us": float(lat.mean()), "bursts": int(len(lat)),
+            "sizes": "log-uniform [1, 2048]", "mean_burst": counted / len(lat),
+            "log2_buckets": B, "load": load, "neg_rate": neg_rate,
+            "realized_neg_rate": float(isneg[int(offs[warm]):].mean()),
+            "form": "one synchronous ckpp_lookup_batch per burst (submit -> completion)"}
 
 
-def cpu_baseline(B=22, load=0.9, n=1 << 22, threads=None):
-    """The oracle (single-threaded C, as it stands) timed on the host: once
-    on one thread, then with the same lookups split over `threads` host
-    threads (each a plain oracle lookup call on its own slice; the calls
-    release the interpreter lock and only read the table).  The
-    multi-threaded rate is the reported value."""
+def host_cpu() -> dict:
+    """The host's CPU: model, sockets, physical cores (lscpu), the CPUs this
+    process may run on (affinity, and the cgroup's CPU quota when one is
+    set), and its memory size (/proc/meminfo)."""
+    import subprocess
+    info = {}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = dict(line.split(":", 1) for line in txt.splitlines() if ":" in line)
+        kv = {k.strip(): v.strip() for k, v in kv.items()}
+        info["model"] = kv.get("Model name")
+        sockets = int(kv.get("Socket(s)", "1") or 1)
+        cps = int(kv.get("Core(s) per socket", "0") or 0)
+        info["sockets"] = sockets
+        info["physical_cores"] = sockets * cps
+        info["threads_per_core"] = int(kv.get("Thread(s) per core", "1") or 1)
+        info["numa_nodes"] = int(kv.get("NUMA node(s)", "1") or 1)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    try:
+        aff = sorted(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = list(range(os.cpu_count() or 1))
+    info["cpus_allowed"] = len(aff)
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as fh:
+            q, per = fh.read().split()
+            if q != "max":
+                quota = int(q) / int(per)
+    except (OSError, ValueError):
+        pass
+    info["cgroup_cpu_quota"] = quota
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal:"):
+                    info["mem_total_gib"] = int(line.split()[1]) / 2**20
+    except OSError:
+        pass
+    # cores this process may use: the allowed CPUs, at most the quota, one
+    # thread per physical core, and at most the host's CPU share for this
+    # job when the environment states one (OMP_NUM_THREADS: a shared host
+    # gives each GPU's jobs a share of its cores)
+    usable = len(aff)
+    if quota:
+        usable = min(usable, max(1, int(quota)))
+    usable = max(1, usable // max(1, info.get("threads_per_core", 1)))
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    if share.isdigit() and int(share) > 0:
+        info["cpu_share"] = int(share)
+        usable = min(usable, int(share))
+    info["usable_cores"] = usable
+    return info
+
+
+def cpu_baseline(keys, pos, neg, B=24, load=0.9, single_sample=1 << 22):
+    """The oracle (single-threaded C, as it stands) timed on the host on the
+    benchmark's own workload: the oracle builds its own 2^B-bucket table
+    from the same key stream (single-threaded; setup, reported), then runs
+    the same positive and negative lookup streams split over one host
+    thread per usable physical core (each a plain oracle lookup call on its
+    own slice; the calls release the interpreter lock and only read the
+    table).  The multi-threaded rate is the reported value; the one-thread
+    rate is timed on the first single_sample lookups of each stream."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
-    if threads is None:
-        threads = max(1, min(16, os.cpu_count() or 1))
+    cpu = host_cpu()
+    threads = cpu["usable_cores"]
     nk = W.keys_at_load(B, load)
-    keys = W.distinct_five_tuples(nk, 1, check=False)
     t = O.OracleTable(B, W.HASH_SEED, W.MAX_KICKS)
     t0 = time.perf_counter()
-    st = t.insert(keys, W.insertion_values(nk))
+    st = t.insert(keys[:nk], W.insertion_values(nk))
     t_ins = time.perf_counter() - t0
-    assert (st == O.INSERTED).all()
-    pos, _, _ = W.lookup_mix(keys, n, 0.0, 2)
-    neg = W.five_tuples(n, 3, stream=W.STREAM_NEGATIVE)
+    if not (st == O.INSERTED).all():
+        raise RuntimeError("the oracle failed to build the benchmark table")
+    n = len(pos)
+    m = min(single_sample, n)
     t0 = time.perf_counter()
-    fp, _, _, _ = t.lookup(pos)
-    fn, _, _, _ = t.lookup(neg)
+    fp, _, _, _ = t.lookup(pos[:m])
+    fn, _, _, _ = t.lookup(neg[:m])
     dt1 = time.perf_counter() - t0
-    assert fp.all() and not fn.any()
-    chunks = [a for q in (pos, neg) for a in np.array_split(q, threads)]
+    if not (fp.all() and not fn.any()):
+        raise RuntimeError("oracle lookups returned a wrong answer")
+    chunks = [a for q in (pos, neg) for a in np.array_split(q, 4 * threads)]
     with ThreadPoolExecutor(max_workers=threads) as ex:
         t0 = time.perf_counter()
         res = list(ex.map(lambda q: t.lookup(q)[0], chunks))
         dtn = time.perf_counter() - t0
-    assert int(sum(int(r.sum()) for r in res)) == n
+    if int(sum(int(r.sum()) for r in res)) != n:
+        raise RuntimeError("oracle lookups returned a wrong answer")
     t.close()
     return {"value": 2 * n / dtn / 1e9, "unit": "Glookups/s", "cores": threads, "kind": "oracle",
-            "sample": f"oracle table of 2^{B} buckets x 8 slots at load {load} "
-                      f"({nk} keys, the paper's 32M-entry size; built in {t_ins:.1f}s), "
-                      f"{n} positive + {n} negative Cuckoo++ lookups, split over {threads} host "
-                      f"threads",
-            "single_thread_value": 2 * n / dt1 / 1e9, "insert_per_s": nk / t_ins}
+            "sample": f"the benchmark's own workload: an oracle table of 2^{B} buckets x 8 "
+                      f"slots at load {load} built from the same {nk} keys ({t_ins:.1f} s, "
+                      f"one thread), the same {n} positive + {n} negative Cuckoo++ lookups "
+                      f"split over {threads} host threads on {cpu.get('model')}",
+            "single_thread_value": 2 * m / dt1 / 1e9,
+            "single_thread_sample": f"{m} positive + {m} negative lookups",
+            "insert_per_s": nk / t_ins, "host": cpu}
 
 
 def copy_calibration(dev):
@@ -1094,21 +1212,34 @@ def main():
     ms_per_step = elapsed * 1e3 / args.steps
     value = 2.0 * n / (ms_per_step * 1e-3) / 1e9
 
-    # roofline of the dominant kernel (the Cuckoo++ lookup: two launches/step)
-    bytes_pos = n * (LINE * lines["cuckoopp_pos"] + STREAM_BYTES)
-    bytes_neg = n * (LINE * lines["cuckoopp_neg"] + STREAM_BYTES)
-    achieved = (bytes_pos + bytes_neg) / ((ms["pos"] + ms["neg"]) * 1e-3) / 1e9
+    # roofline of the dominant kernel (the Cuckoo++ lookup: two launches per
+    # step), on the method's algorithmic bytes: 64-byte lines per lookup
+    # (algorithmic_lines_64) plus the 25 streamed bytes, per launch, over the
+    # mean launch duration measured with events on the kernels' stream
+    alg = algorithmic_lines_64(stats)
+    bytes_pos = n * (ALG_LINE * alg["cuckoopp_pos"] + STREAM_BYTES)
+    bytes_neg = n * (ALG_LINE * alg["cuckoopp_neg"] + STREAM_BYTES)
+    avg_ms = (ms["pos"] + ms["neg"]) / 2
+    achieved = (bytes_pos + bytes_neg) / 2 / (avg_ms * 1e-3) / 1e9
+    # the same launches counted in the device layout's 128-byte lines (the
+    # unit a random miss fills on this GPU; see lines_per_lookup)
+    dev_bytes = n * (LINE * (lines["cuckoopp_pos"] + lines["cuckoopp_neg"]) + 2 * STREAM_BYTES) / 2
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "kernel": f"{ckpp.lookup_kernel_name(launch)}<waves={launch['block'] // 64}, Cuckoo++>",
                 "algorithmic_bytes_per_launch": (bytes_pos + bytes_neg) / 2,
-                "avg_launch_ms": (ms["pos"] + ms["neg"]) / 2}
+                "algorithmic_lines_64B": {"pos": alg["cuckoopp_pos"], "neg": alg["cuckoopp_neg"]},
+                "avg_launch_ms": avg_ms,
+                "device_layout_bytes_per_launch": dev_bytes,
+                "frac_128B_granule": dev_bytes / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     tf = os.path.join(ROOT, "profiles", "lookup_traffic.json")
     if os.path.exists(tf):
         with open(tf) as fh:
             tr = json.load(fh)
         if tr.get("source_digest") == lookup_source_digest() and tr.get("launch") == launch:
             roofline["traffic"] = tr["hbm_bytes_per_launch"]
+            roofline["traffic_over_algorithmic"] = (tr["hbm_bytes_per_launch"]
+                                                    / roofline["algorithmic_bytes_per_launch"])
 
     stats["f_high"] = stats["high_slots"] / max(1, stats["live"])
     out = {
@@ -1128,6 +1259,7 @@ def main():
             "cuckoopp_pos_glookups": n / (ms["pos"] * 1e-3) / 1e9,
             "cuckoopp_neg_glookups": n / (ms["neg"] * 1e-3) / 1e9,
             "lines_per_lookup": lines,
+            "algorithmic_lines_64B": alg,
         },
         "table": {"live": stats["live"], "f_sec": stats["f_sec"], "f_high": stats["f_high"],
                   "expected_fpr": stats["expected_fpr"],
@@ -1154,8 +1286,9 @@ def main():
             best = max(rate, lk[f"plain_{name}_glookups"])
             lk[f"cuckoopp_over_best_plain_{name}"] = lk[f"cuckoopp_{name}_glookups"] / best
         t.set_lookup_launch(**launch)
-        out["burst_latency"] = burst_latency(t, dpos, dneg, dev)
         t.close()
+        log("burst latency")
+        out["burst_latency"] = burst_latency(dev, keys, B)
         log("tables with timers")
         out["timers"] = timers_leg(dev, B, load, n, dpos, dneg, pos_idx, lk)
         del dpos, dneg, f_pos, v_pos, f_neg, v_neg
@@ -1167,11 +1300,13 @@ def main():
         for k in ("cuckoopp_pos", "cuckoopp_neg", "plain_pos", "plain_neg", "optimistic_pos",
                   "optimistic_neg"):
             lk[f"{k}_frac_random_line_peak"] = lk[f"{k}_glookups"] * 1e9 * lines[k] / p128
+        roofline["frac_random_line_peak_pos"] = lk["cuckoopp_pos_frac_random_line_peak"]
+        roofline["frac_random_line_peak_neg"] = lk["cuckoopp_neg_frac_random_line_peak"]
         out["cache_resident_table"] = cache_resident_table(dev, n, 20)
         out["mall_resident_table"] = cache_resident_table(dev, n, 19)
         if not args.no_cpu_baseline:
             log("timing the oracle on the host")
-            out["cpu_baseline"] = cpu_baseline()
+            out["cpu_baseline"] = cpu_baseline(keys, pos, neg, B, load)
     else:
         t.close()
     print(json.dumps(out), flush=True)
