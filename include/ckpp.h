@@ -156,6 +156,24 @@ int ckpp_clear(ckpp_table *t, void *stream);
 int ckpp_insert_batch(ckpp_table *t, const void *d_keys, const uint64_t *d_values, uint64_t n,
                       uint8_t *d_status, uint64_t *d_nfailed, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the insert
+ * of ckpp_insert_batch, same arguments, results and errors, that allocates
+ * nothing.  Its cuckoo-path scratch is a fixed 8 MiB array in the library's
+ * device memory, one per GPU, held until the process ends (instead of the
+ * table's own buffer or the stream-ordered pool), so a launch uses at most
+ * as many lanes as fit it: 8 MiB / (4 * max_kicks) lanes, in whole blocks
+ * of 256 (4096 lanes at max_kicks 500; at least 256 for every max_kicks the
+ * library accepts).  The array keeps the last call's contents; nothing in it
+ * needs to start at zero (each lane writes its path before reading it).
+ * Calls on one GPU share that array: two such calls that overlap in time
+ * on the same GPU (on different streams, or from different threads) race
+ * and corrupt each other's paths, so order them (one stream).  Not for
+ * tables with timers.  Errors: as ckpp_insert_batch, CKPP_EINVAL also on a
+ * table with timers, CKPP_EDEVICE if the array's address cannot be found. */
+int ckpp_insert_batch_noalloc(ckpp_table *t, const void *d_keys, const uint64_t *d_values,
+                              uint64_t n, uint8_t *d_status, uint64_t *d_nfailed, void *stream);
+
 /* Batched lookup (Sec. 2, lookup; Sec. 4.1, pruning): d_found[i] = 1 and
  * d_values[i] = the key's value if key i is in the table, else 0 and 0.
  * mode is one of CKPP_LOOKUP_*.  d_found (n bytes) and d_values (n u64)

@@ -169,6 +169,7 @@ SIGNATURES = [
     ("ckpp_destroy", _I, [_VP]),
     ("ckpp_clear", _I, [_VP, _VP]),
     ("ckpp_insert_batch", _I, [_VP, _VP, _VP, _U64, _VP, _VP, _VP]),
+    ("ckpp_insert_batch_noalloc", _I, [_VP, _VP, _VP, _U64, _VP, _VP, _VP]),
     ("ckpp_lookup_batch", _I, [_VP, _VP, _U64, _U32, _VP, _VP, _VP]),
     ("ckpp_delete_batch", _I, [_VP, _VP, _U64, _VP, _VP]),
     ("ckpp_insert_batch_at", _I, [_VP, _VP, _VP, _VP, _U64, ctypes.c_uint16, _VP, _VP, _VP]),
@@ -342,6 +343,20 @@ class Table:
         rc = self.lib.ckpp_insert_batch(self._h, kp, values.data_ptr(), n, status.data_ptr(),
                                         nfailed.data_ptr(), _stream_handle(stream))
         _check(rc, "ckpp_insert_batch")
+        return status, nfailed
+
+    def insert_noalloc(self, keys, values, status, nfailed, stream=None):
+        """ckpp_insert_batch_noalloc: the insert without any allocation; the
+        caller passes the status (u8[n]) and nfailed (i64[1]) buffers."""
+        kp, n = _keys_ptr(keys)
+        if values.numel() != n or values.element_size() != 8 or not values.is_contiguous():
+            raise CkppError("values must be n contiguous 64-bit integers")
+        if status.numel() < n or nfailed.numel() < 1:
+            raise CkppError("status needs n bytes and nfailed one 64-bit word")
+        rc = self.lib.ckpp_insert_batch_noalloc(self._h, kp, values.data_ptr(), n,
+                                                status.data_ptr(), nfailed.data_ptr(),
+                                                _stream_handle(stream))
+        _check(rc, "ckpp_insert_batch_noalloc")
         return status, nfailed
 
     def lookup(self, keys, mode="cuckoopp", found=None, values=None, stream=None):

@@ -299,6 +299,18 @@ int ckpp_insert_batch(ckpp_table *t, const void *d_keys, const uint64_t *d_value
   return insert_common(t, d_keys, d_values, nullptr, nullptr, n, d_status, d_nfailed, stream);
 }
 
+int ckpp_insert_batch_noalloc(ckpp_table *t, const void *d_keys, const uint64_t *d_values,
+                              uint64_t n, uint8_t *d_status, uint64_t *d_nfailed, void *stream) {
+  if (!t || timed(t)) return CKPP_EINVAL;
+  if (n == 0) return CKPP_OK;
+  if (!d_keys || !d_values || !aligned(d_keys, 16) || !aligned(d_values, 8)) return CKPP_EINVAL;
+  if (d_nfailed && !aligned(d_nfailed, 8)) return CKPP_EINVAL;
+  DeviceGuard g(t->device);
+  if (!g.ok()) return CKPP_EDEVICE;
+  return ckpp::insert_noalloc(t, d_keys, d_values, n, d_status, d_nfailed,
+                              reinterpret_cast<hipStream_t>(stream));
+}
+
 int ckpp_lookup_batch(ckpp_table *t, const void *d_keys, uint64_t n, uint32_t mode,
                       uint8_t *d_found, uint64_t *d_values, void *stream) {
   if (!t || timed(t)) return CKPP_EINVAL;

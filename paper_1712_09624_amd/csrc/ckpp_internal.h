@@ -105,6 +105,10 @@ hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t
                          uint8_t *d_status, uint64_t *d_nfailed, hipStream_t s);
 hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n,
                          const TimerArgs *timers, uint8_t *d_found, hipStream_t s);
+// The insert without any allocation (ckpp_insert_batch_noalloc): returns a
+// CKPP_* status.
+int insert_noalloc(const ckpp_table *t, const void *d_keys, const uint64_t *d_values, uint64_t n,
+                   uint8_t *d_status, uint64_t *d_nfailed, hipStream_t s);
 // Removes every entry expired at `now` (one pass over the table).
 hipError_t launch_expire_scan(const ckpp_table *t, uint32_t now, uint64_t *d_removed,
                               hipStream_t s);

@@ -2,10 +2,19 @@
 // per key at a time on a persistent grid; the per-key state machines are in
 // ckpp_update_dev.h.
 
+#include <mutex>
+
 #include "ckpp_update_dev.h"
 
 namespace ckpp {
 namespace {
+
+// Cuckoo-path scratch of ckpp_insert_batch_noalloc: a fixed array in each
+// device's memory, held for the life of the process.  Host code never uses
+// its name as an address: the device address comes from
+// hipGetSymbolAddress, once per device (scratch_on).
+constexpr uint64_t kScratchBytes = 8ull << 20;
+static __device__ __align__(256) uint32_t scratch[kScratchBytes / sizeof(uint32_t)];
 
 // TIMED: the table has timers; expiry[i] is key i's expiration time and
 // `now` the current time (Sec. 4.2).
@@ -101,6 +110,52 @@ hipError_t launch_insert(const ckpp_table *t, const void *d_keys, const uint64_t
   if (own) return e;
   const hipError_t f = hipFreeAsync(paths, s);
   return e != hipSuccess ? e : f;
+}
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[kMaxScratchDevices];
+
+// Device address of `scratch` on the current device `dev`, looked up once
+// per device with that device current; null if the lookup fails.
+uint32_t *scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<uint32_t *>(p);
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+// The insert of launch_insert with its path scratch in `scratch`: at most
+// as many lanes as fit kScratchBytes (whole blocks of 256), no allocation.
+int insert_noalloc(const ckpp_table *t, const void *d_keys, const uint64_t *d_values, uint64_t n,
+                   uint8_t *d_status, uint64_t *d_nfailed, hipStream_t s) {
+  const uint64_t per_lane = (uint64_t)(t->max_kicks ? t->max_kicks : 1u);
+  const uint32_t block = 256;
+  const uint64_t fit = kScratchBytes / (per_lane * sizeof(uint32_t)) / block * block;
+  if (fit == 0) return CKPP_EINVAL;  // a path longer than the whole array
+  uint32_t *paths = scratch_on(t->device);
+  if (!paths) return CKPP_EDEVICE;
+  uint64_t lanes = n < t->path_lanes ? n : t->path_lanes;
+  if (lanes > fit) lanes = fit;
+  const uint32_t grid = (uint32_t)((lanes + block - 1) / block);
+  unsigned long long *nspin = reinterpret_cast<unsigned long long *>(t->d_stats) + 127;
+  const uint32_t plain = (t->flags & CKPP_PLAIN) ? 1u : 0u;
+  hipLaunchKernelGGL(insert_kernel<false>, dim3(grid), dim3(block), 0, s, t->d_table,
+                     reinterpret_cast<const uint4 *>(d_keys), d_values, nullptr, 0u, n,
+                     t->log2_buckets, t->seed, t->max_kicks, plain, t->retry_limit, paths,
+                     d_status, reinterpret_cast<unsigned long long *>(d_nfailed), nspin);
+  return dev_status(hipGetLastError());
 }
 
 hipError_t launch_delete(const ckpp_table *t, const void *d_keys, uint64_t n,
