@@ -760,6 +760,29 @@ def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
         g_plan.replay()
         check("plan graph replay")
     out["plan_graph_us"] = timed(g_plan.replay, reps, dev) * 1e3
+    # a graph replay submits one launch from the host; when that submission
+    # takes longer than the kernel, the device idles between replays.  A
+    # graph of `reps` launches replayed once shows the launch's own time,
+    # and the host's submission time of one replay is timed on the host
+    g_many = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g_many):
+        for _ in range(reps):
+            plan.lookup(keys_d, found, vals_d)
+    g_many.replay()
+    check("plan graph of many launches")
+    out["plan_graph_batched_us"] = timed(g_many.replay, 3, dev) * 1e3 / reps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g_plan.replay()
+    out["plan_graph_host_submit_us"] = (time.perf_counter() - t0) * 1e6 / reps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.lookup(keys_d, found, vals_d)
+    out["plan_eager_host_submit_us"] = (time.perf_counter() - t0) * 1e6 / reps
+    torch.cuda.synchronize()
+    del g_many
     del s
     for k in ("per_table_eager", "per_table_graph", "plan_eager", "plan_graph"):
         out[k + "_glookups"] = total / (out[k + "_us"] * 1e-6) / 1e9
