@@ -383,14 +383,28 @@ __device__ bool set_has(const ServeArgs &a, uint4 k, uint32_t tag) {
   return false;
 }
 
-// TIMED: inserts at time `now`, whose entries expire at now + ttl.
+// Rank of lane g among `lanes` lanes (whole wavefronts) when the lanes are
+// taken column by column: lane 0 of every wavefront, then lane 1 of every
+// wavefront, and so on (from the top lane down when `top`).  A round's few
+// updates then spread over every wavefront of the grid, a handful per
+// wavefront, instead of filling whole wavefronts of the first blocks: a
+// wavefront's 64 lanes run their operations in lockstep, each waiting for
+// the slowest, and the memory requests of the round spread over all
+// compute units.
+__device__ __forceinline__ uint64_t column_rank(uint64_t g, uint64_t lanes, bool top) {
+  const uint64_t waves = lanes / 64u, lane = g & 63u;
+  return (top ? 63u - lane : lane) * waves + g / 64u;
+}
+
+// TIMED: inserts at time `now`, whose entries expire at now + ttl.  Lanes
+// g < path_lanes (whole wavefronts) take the inserts, in column rank.
 template <bool TIMED>
 __device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1, uint32_t now) {
   const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (g >= a.path_lanes) return;
   uint32_t *path = a.paths + g * (uint64_t)(a.max_kicks ? a.max_kicks : 1u);
   const uint32_t expiry = (now + a.ttl) & 0xffffu;
-  for (uint64_t j = i0 + g; j < i1; j += a.path_lanes) {
+  for (uint64_t j = i0 + column_rank(g, a.path_lanes, false); j < i1; j += a.path_lanes) {
     const uint64_t slot = j & a.mask;
     const InsertOutcome o =
         insert_one<TIMED>(a.bk, a.in_keys[slot], a.in_vals[slot], a.T.log2b, a.T.seed,
@@ -400,9 +414,10 @@ __device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1, uint3
   }
 }
 
-// The round's deletes.  Lane g takes the deletes at offsets nlanes - 1 - g,
-// 2 nlanes - 1 - g, ... (the far end of the grid from the insert lanes, so
-// that inserts and deletes run side by side).  filter: a delete of a key
+// The round's deletes.  Every lane of the grid takes the deletes at offsets
+// r, r + nlanes, ..., r its column rank from the top lane down (the other
+// end of each wavefront from the insert lanes, so that inserts and deletes
+// run side by side).  filter: a delete of a key
 // the round also inserts is deferred (its result byte set to kDeferred)
 // until every insert of the round is done.  deferred_only: runs just the
 // deferred deletes (the same lane took them).  TIMED: deletes at time `now`.
@@ -412,7 +427,7 @@ __device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1, bool 
   const uint64_t nlanes = (uint64_t)gridDim.x * kBlock;
   const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   bool deferred = false;
-  for (uint64_t o = nlanes - 1u - g; d0 + o < d1; o += nlanes) {
+  for (uint64_t o = column_rank(g, nlanes, true); d0 + o < d1; o += nlanes) {
     const uint64_t slot = (d0 + o) & a.mask;
     if (deferred_only && a.de_found[slot] != kDeferred) continue;
     const uint4 k = a.de_keys[slot];

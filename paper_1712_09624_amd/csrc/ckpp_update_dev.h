@@ -111,21 +111,42 @@ __device__ __forceinline__ void section_end() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-// Takes the locks of buckets x != y in ascending order, or none.  The
-// order makes retries live: of two lanes that need the same pair, the one
-// that takes the lower lock first can always try the higher one, whereas
-// two lanes taking the two locks at once could each get one, give both
-// back, and repeat in lockstep forever.  On success the caller's later
-// reads see every write made under these locks by earlier holders.
-__device__ __forceinline__ bool lock_two(uint8_t *bk, uint32_t x, uint32_t y) {
+constexpr int kBusy = -2;  // a lock was taken by another lane: retry
+
+// Takes the locks of buckets x != y, or none.  A device-scope
+// compare-and-swap costs a round trip of about a microsecond, so a lane's
+// first attempt on a pair (first) issues both at once.  Two lanes taking
+// the two locks at once could each get one, give both back, and repeat in
+// lockstep forever, so every retry takes them in ascending order instead:
+// of two lanes that need the same pair, the one that takes the lower lock
+// first can always try the higher one.  A lane makes one first attempt per
+// pair, so the simultaneous form can get in another lane's way only once.
+// A lane that does not get both gives back what it got, so no lane keeps a
+// lock across attempts.  On success the caller's later reads see every
+// write made under these locks by earlier holders.
+__device__ __forceinline__ bool lock_pair(uint8_t *bk, uint32_t x, uint32_t y, bool first) {
   const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
-  if (!try_lock(bk, lo)) return false;
-  if (!try_lock(bk, hi)) {
-    unlock(bk, lo);
-    return false;
+  bool ok_lo, ok_hi;
+  if (first) {
+    // both issued with no branch between them, so neither waits for the
+    // other (the higher one first, so that the compiler does not share the
+    // lower one's with the in-order form below and make the higher wait)
+    uint32_t e0 = 0u, e1 = 0u;
+    ok_hi = __hip_atomic_compare_exchange_strong(lock_word(bk, hi), &e1, 1u, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    ok_lo = __hip_atomic_compare_exchange_strong(lock_word(bk, lo), &e0, 1u, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    ok_lo = try_lock(bk, lo);
+    ok_hi = ok_lo && try_lock(bk, hi);
   }
-  section_begin();
-  return true;
+  if (ok_lo && ok_hi) {
+    section_begin();
+    return true;
+  }
+  if (ok_lo) unlock(bk, lo);
+  if (ok_hi) unlock(bk, hi);
+  return false;
 }
 
 // Publishes the writes made under the locks, then drops both locks.
@@ -246,7 +267,6 @@ __device__ __forceinline__ uint64_t load_relaxed(const uint8_t *p) {
 // removal) are kept out of line: inlined, they raise the register count and
 // slow the direct path every key takes (measured: 2^24 build to load 0.95 in
 // 211 ms inlined, 181 ms out of line).
-constexpr int kBusy = -2;    // a lock was taken by another lane: retry
 constexpr int kNeedPath = -1;
 
 // Busy slots of bucket b whose entries have expired at `now`.
@@ -463,10 +483,11 @@ __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32
 }
 
 // DIRECT step of a table with timers; word = value | expiry << 48.
+// first: the key's first attempt on its pair (lock_pair).
 __device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const KeyFields &f,
                                    uint64_t h, uint32_t log2b, uint64_t seed, bool plain,
-                                   uint32_t now) {
-  if (!lock_two(bk, f.p, f.a)) return kBusy;
+                                   uint32_t now, bool first) {
+  if (!lock_pair(bk, f.p, f.a, first)) return kBusy;
   const Head hp = read_head(bk, f.p);
   const Head ha = read_head(bk, f.a);
   int r = kNeedPath;
@@ -530,8 +551,9 @@ __device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const 
 }
 
 __device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value, const KeyFields &f,
-                             uint64_t h, uint32_t log2b, uint64_t seed, bool plain) {
-  if (!lock_two(bk, f.p, f.a)) return kBusy;
+                             uint64_t h, uint32_t log2b, uint64_t seed, bool plain,
+                             bool first) {
+  if (!lock_pair(bk, f.p, f.a, first)) return kBusy;
   const Head hp = read_head(bk, f.p);
   const Head ha = read_head(bk, f.a);
   int r;
@@ -640,10 +662,11 @@ __device__ __attribute__((noinline)) int walk(const uint8_t *bk, uint32_t start,
 
 // Moves the entry of slot s of bucket x to a free slot of bucket y, its
 // other bucket.  Returns 1 when done, 0 when the state no longer matches
-// the path, kBusy when a lock was taken.
+// the path, kBusy when a lock was taken.  first: the first attempt on this
+// move (lock_pair).
 __device__ __attribute__((noinline)) int move_entry(uint8_t *bk, uint32_t x, uint32_t s, uint32_t y,
-                          uint32_t log2b, uint64_t seed, bool plain) {
-  if (x == y || !lock_two(bk, x, y)) return kBusy;
+                          uint32_t log2b, uint64_t seed, bool plain, bool first) {
+  if (x == y || !lock_pair(bk, x, y, first)) return kBusy;
   int r = 0;
   const uint32_t mx = *meta_ptr(bk, x), my = *meta_ptr(bk, y);
   const uint32_t busy_x = meta_busy(mx), busy_y = meta_busy(my);
@@ -703,6 +726,7 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
   enum { DIRECT, WALK, MOVE };
   int state = DIRECT, result = -1;
   uint32_t len = 0, next = 0, last = 0, walks = 0, iters = 0;
+  bool retry = false;  // the last step found a lock taken (lock_pair)
   bool spun = false;
   while (result < 0) {
     if (++iters > spin_limit) {
@@ -711,8 +735,10 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
       break;
     }
     if (state == DIRECT) {
-      const int r = TIMED ? insert_direct_timed(bk, key, word, f, h, log2b, seed, plain, now)
-                          : insert_direct(bk, key, value, f, h, log2b, seed, plain);
+      const int r =
+          TIMED ? insert_direct_timed(bk, key, word, f, h, log2b, seed, plain, now, !retry)
+                : insert_direct(bk, key, value, f, h, log2b, seed, plain, !retry);
+      retry = r == kBusy;
       if (r >= 0)
         result = r;
       else if (r == kNeedPath)
@@ -736,7 +762,8 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
       const uint32_t e = path[next - 1];
       const uint32_t x = e & kPathBucketMask, s = e >> kPathSlotShift;
       const uint32_t y = (next == len) ? last : (path[next] & kPathBucketMask);
-      const int r = move_entry(bk, x, s, y, log2b, seed, plain);
+      const int r = move_entry(bk, x, s, y, log2b, seed, plain, !retry);
+      retry = r == kBusy;
       if (r == 1) {
         if (--next == 0) state = DIRECT;
       } else if (r == 0) {
@@ -749,10 +776,11 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
 
 // Returns 1 if the key was removed, 0 if absent, kBusy to retry.  TIMED:
 // an expired entry of the key is removed too, but reports 0 (Sec. 4.2).
+// first: the first attempt on the key's pair (lock_pair).
 template <bool TIMED>
 __device__ int delete_direct(uint8_t *bk, uint4 key, const KeyFields &f, bool plain,
-                             uint32_t now) {
-  if (!lock_two(bk, f.p, f.a)) return kBusy;
+                             uint32_t now, bool first) {
+  if (!lock_pair(bk, f.p, f.a, first)) return kBusy;
   const Head hp = read_head(bk, f.p);
   int r = 0;
   int s = find_slot(bk, f.p, hp, key, f.tag);
@@ -790,8 +818,8 @@ __device__ int delete_one(uint8_t *bk, uint4 key, uint32_t log2b, uint64_t seed,
   int r = kBusy;
   uint32_t iters = 0;
   while (r == kBusy && iters < spin_limit) {
+    r = delete_direct<TIMED>(bk, key, f, plain, now, iters == 0u);
     ++iters;
-    r = delete_direct<TIMED>(bk, key, f, plain, now);
   }
   *spun = r == kBusy;
   return r == kBusy ? CKPP_RETRY : r;
