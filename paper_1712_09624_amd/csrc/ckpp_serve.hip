@@ -346,6 +346,19 @@ __device__ void lookup_phase(const ServeArgs &a, const TableRef &T, const Wave &
   }
 }
 
+// Rank of lane g among `lanes` lanes (whole wavefronts) when the lanes are
+// taken column by column: lane 0 of every wavefront, then lane 1 of every
+// wavefront, and so on (from the top lane down when `top`).  A round's few
+// updates then spread over every wavefront of the grid, a handful per
+// wavefront, instead of filling whole wavefronts of the first blocks: a
+// wavefront's 64 lanes run their operations in lockstep, each waiting for
+// the slowest, and the memory requests of the round spread over all
+// compute units.
+__device__ __forceinline__ uint64_t column_rank(uint64_t g, uint64_t lanes, bool top) {
+  const uint64_t waves = lanes / 64u, lane = g & 63u;
+  return (top ? 63u - lane : lane) * waves + g / 64u;
+}
+
 // The round's insert keys in a set (open addressing, linear probing): an
 // entry belongs to the round whose tag it carries, so the set is never
 // cleared.  Built before a barrier, read after it.
@@ -355,14 +368,18 @@ __device__ __forceinline__ uint64_t set_slot(const ServeArgs &a, uint4 k) {
 
 __device__ void set_build(const ServeArgs &a, uint64_t i0, uint64_t i1, uint32_t tag) {
   const uint64_t nlanes = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t j = i0 + (uint64_t)blockIdx.x * kBlock + threadIdx.x; j < i1; j += nlanes) {
+  const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (uint64_t j = i0 + column_rank(g, nlanes, false); j < i1; j += nlanes) {
     const uint4 k = a.in_keys[j & a.mask];
     uint64_t pos = set_slot(a, k);
     for (uint64_t probe = 0; probe <= a.set_mask; ++probe, pos = (pos + 1u) & a.set_mask) {
-      uint32_t t = __hip_atomic_load(a.set_tag + pos, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (t == tag) continue;  // taken by another key of this round
-      if (__hip_atomic_compare_exchange_strong(a.set_tag + pos, &t, tag, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+      // one atomic per probe: an entry last tagged by an earlier round is
+      // free and now this key's; one already carrying this round's tag
+      // belongs to another key of the round (writing the same tag over it
+      // changes nothing)
+      const uint32_t t = __hip_atomic_exchange(a.set_tag + pos, tag, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+      if (t != tag) {
         uint32_t *dst = reinterpret_cast<uint32_t *>(a.set_keys + pos);
         __hip_atomic_store(dst + 0, k.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(dst + 1, k.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -381,19 +398,6 @@ __device__ bool set_has(const ServeArgs &a, uint4 k, uint32_t tag) {
     if (key_eq(a.set_keys[pos], k)) return true;
   }
   return false;
-}
-
-// Rank of lane g among `lanes` lanes (whole wavefronts) when the lanes are
-// taken column by column: lane 0 of every wavefront, then lane 1 of every
-// wavefront, and so on (from the top lane down when `top`).  A round's few
-// updates then spread over every wavefront of the grid, a handful per
-// wavefront, instead of filling whole wavefronts of the first blocks: a
-// wavefront's 64 lanes run their operations in lockstep, each waiting for
-// the slowest, and the memory requests of the round spread over all
-// compute units.
-__device__ __forceinline__ uint64_t column_rank(uint64_t g, uint64_t lanes, bool top) {
-  const uint64_t waves = lanes / 64u, lane = g & 63u;
-  return (top ? 63u - lane : lane) * waves + g / 64u;
 }
 
 // TIMED: inserts at time `now`, whose entries expire at now + ttl.  Lanes

@@ -111,42 +111,21 @@ __device__ __forceinline__ void section_end() {
   __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-constexpr int kBusy = -2;  // a lock was taken by another lane: retry
-
-// Takes the locks of buckets x != y, or none.  A device-scope
-// compare-and-swap costs a round trip of about a microsecond, so a lane's
-// first attempt on a pair (first) issues both at once.  Two lanes taking
-// the two locks at once could each get one, give both back, and repeat in
-// lockstep forever, so every retry takes them in ascending order instead:
-// of two lanes that need the same pair, the one that takes the lower lock
-// first can always try the higher one.  A lane makes one first attempt per
-// pair, so the simultaneous form can get in another lane's way only once.
-// A lane that does not get both gives back what it got, so no lane keeps a
-// lock across attempts.  On success the caller's later reads see every
-// write made under these locks by earlier holders.
-__device__ __forceinline__ bool lock_pair(uint8_t *bk, uint32_t x, uint32_t y, bool first) {
+// Takes the locks of buckets x != y in ascending order, or none.  The
+// order makes retries live: of two lanes that need the same pair, the one
+// that takes the lower lock first can always try the higher one, whereas
+// two lanes taking the two locks at once could each get one, give both
+// back, and repeat in lockstep forever.  On success the caller's later
+// reads see every write made under these locks by earlier holders.
+__device__ __forceinline__ bool lock_two(uint8_t *bk, uint32_t x, uint32_t y) {
   const uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
-  bool ok_lo, ok_hi;
-  if (first) {
-    // both issued with no branch between them, so neither waits for the
-    // other (the higher one first, so that the compiler does not share the
-    // lower one's with the in-order form below and make the higher wait)
-    uint32_t e0 = 0u, e1 = 0u;
-    ok_hi = __hip_atomic_compare_exchange_strong(lock_word(bk, hi), &e1, 1u, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    ok_lo = __hip_atomic_compare_exchange_strong(lock_word(bk, lo), &e0, 1u, __ATOMIC_RELAXED,
-                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    ok_lo = try_lock(bk, lo);
-    ok_hi = ok_lo && try_lock(bk, hi);
+  if (!try_lock(bk, lo)) return false;
+  if (!try_lock(bk, hi)) {
+    unlock(bk, lo);
+    return false;
   }
-  if (ok_lo && ok_hi) {
-    section_begin();
-    return true;
-  }
-  if (ok_lo) unlock(bk, lo);
-  if (ok_hi) unlock(bk, hi);
-  return false;
+  section_begin();
+  return true;
 }
 
 // Publishes the writes made under the locks, then drops both locks.
@@ -267,6 +246,7 @@ __device__ __forceinline__ uint64_t load_relaxed(const uint8_t *p) {
 // removal) are kept out of line: inlined, they raise the register count and
 // slow the direct path every key takes (measured: 2^24 build to load 0.95 in
 // 211 ms inlined, 181 ms out of line).
+constexpr int kBusy = -2;    // a lock was taken by another lane: retry
 constexpr int kNeedPath = -1;
 
 // Busy slots of bucket b whose entries have expired at `now`.
@@ -365,7 +345,9 @@ __device__ __forceinline__ uint32_t movable(uint32_t meta, bool plain) {
 
 // The other buckets of bucket b's entries and, for the entries in `cand`,
 // which of those buckets have a free slot (their metadata words loaded
-// together, without locks).
+// together, without locks).  Every slot's load is issued, a non-candidate
+// reading bucket b itself, so that no load waits inside a branch: two round
+// trips in all.
 __device__ __forceinline__ uint32_t room_of(const uint8_t *bk, uint32_t b, uint32_t cand,
                                             uint32_t (&other)[kSlots]) {
 #pragma unroll
@@ -374,15 +356,27 @@ __device__ __forceinline__ uint32_t room_of(const uint8_t *bk, uint32_t b, uint3
     other[2 * w] = (uint32_t)o;
     other[2 * w + 1] = (uint32_t)(o >> 32);
   }
+  uint32_t om[kSlots];
+#pragma unroll
+  for (uint32_t s = 0; s < kSlots; ++s)
+    om[s] = (uint32_t)load_relaxed(bucket_ptr(bk, ((cand >> s) & 1u) ? other[s] : b) +
+                                   kMetaOffset);
   uint32_t room = 0;
 #pragma unroll
-  for (uint32_t s = 0; s < kSlots; ++s) {
-    if ((cand >> s) & 1u) {
-      const uint32_t om = (uint32_t)load_relaxed(bucket_ptr(bk, other[s]) + kMetaOffset);
-      if (meta_busy(om) != 0xffu) room |= 1u << s;
-    }
-  }
+  for (uint32_t s = 0; s < kSlots; ++s)
+    if (((cand >> s) & 1u) && meta_busy(om[s]) != 0xffu) room |= 1u << s;
   return room;
+}
+
+// a[i] for a small array indexed by a value known only at run time, as an
+// OR of masked elements: an array indexed that way (or by a chain of
+// selects, which the compiler turns back into an index) would live in
+// scratch memory, and each load into it would wait for the one before.
+__device__ __forceinline__ uint32_t pick_slot(const uint32_t (&a)[kSlots], uint32_t i) {
+  uint32_t r = 0;
+#pragma unroll
+  for (uint32_t s = 0; s < kSlots; ++s) r |= a[s] & (0u - (uint32_t)(s == i));
+  return r;
 }
 
 // Takes the lock of bucket b unless the caller holds it already.
@@ -411,34 +405,77 @@ __device__ __forceinline__ void unlock_extra(uint8_t *bk, uint32_t b, const KeyF
 __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32_t log2b, uint64_t seed, bool plain,
                                    const KeyFields &f, uint64_t h, uint4 key, uint64_t word,
                                    uint32_t mp) {
-  const uint32_t cand = movable(mp, plain), sec = meta_sec(mp);
+  const uint32_t cand = movable(mp, plain), sec = meta_sec(mp), p = f.p;
   uint32_t other[kSlots];
-  const uint32_t room = room_of(bk, f.p, cand, other);
+  const uint32_t room = room_of(bk, p, cand, other);
   uint32_t v = kSlots, y1 = kNoBucket, t = kSlots, y2 = kNoBucket;
   if (room) {
     const uint32_t pick = (room & sec) ? (room & sec) : room;
     v = nth_bit(pick, (uint32_t)(mix64(h ^ kDisplaceSalt) %
                                  (uint64_t)__builtin_popcount(pick)));
-    y1 = other[v];
+    y1 = pick_slot(other, v);
   } else {
-    // second level: entries of p going home first
+    // second level, every candidate at once (two round trips in all, where
+    // a candidate at a time costs three each: this search is the slowest
+    // step of the inserts that need it): the metadata word and other[] of
+    // each candidate's other bucket y1, then the metadata words of those
+    // buckets' other buckets.  Loads are issued for every slot, candidate or
+    // not (a non-candidate reads bucket p), so that none waits inside a
+    // branch.  The choice is the one-at-a-time order: the first candidate,
+    // entries of p going home first, whose y1 has an entry that can move on
+    // to a bucket with a free slot (an entry of y1 going home preferred).
+    uint32_t m1[kSlots], o1[kSlots][kSlots];
+#pragma unroll
+    for (uint32_t s = 0; s < kSlots; ++s) {
+      const uint8_t *b1 = bucket_ptr(bk, ((cand >> s) & 1u) ? other[s] : p);
+      m1[s] = (uint32_t)load_relaxed(b1 + kMetaOffset);
+#pragma unroll
+      for (uint32_t w = 0; w < 4; ++w) {
+        const uint64_t o = load_relaxed(b1 + kOtherOffset + 8 * w);
+        o1[s][2 * w] = (uint32_t)o;
+        o1[s][2 * w + 1] = (uint32_t)(o >> 32);
+      }
+    }
+    uint32_t om[kSlots][kSlots];
+#pragma unroll
+    for (uint32_t s = 0; s < kSlots; ++s) {
+      const uint32_t mv = ((cand >> s) & 1u) ? movable(m1[s], plain) : 0u;
+#pragma unroll
+      for (uint32_t u = 0; u < kSlots; ++u)
+        om[s][u] = (uint32_t)load_relaxed(bucket_ptr(bk, ((mv >> u) & 1u) ? o1[s][u] : p) +
+                                          kMetaOffset);
+    }
+    // room bits and sec masks of the y1s, packed 8 bits per candidate (so
+    // the choice below indexes no array)
+    uint64_t room1 = 0, sec1 = 0;
+#pragma unroll
+    for (uint32_t s = 0; s < kSlots; ++s) {
+      const uint32_t mv = ((cand >> s) & 1u) ? movable(m1[s], plain) : 0u;
+      uint32_t r = 0u;
+#pragma unroll
+      for (uint32_t u = 0; u < kSlots; ++u)
+        if (((mv >> u) & 1u) && meta_busy(om[s][u]) != 0xffu) r |= 1u << u;
+      room1 |= (uint64_t)r << (8u * s);
+      sec1 |= (uint64_t)meta_sec(m1[s]) << (8u * s);
+    }
     for (uint32_t order = 0; order < 2 && t == kSlots; ++order) {
       for (uint32_t c = cand & (order ? ~sec : sec); c && t == kSlots; c &= c - 1u) {
         const uint32_t s = (uint32_t)__builtin_ctz(c);
-        const uint32_t b1 = other[s];
-        const uint32_t m1 = (uint32_t)load_relaxed(bucket_ptr(bk, b1) + kMetaOffset);
-        uint32_t other1[kSlots];
-        const uint32_t r1 = room_of(bk, b1, movable(m1, plain), other1);
-        if (r1) {
-          const uint32_t pick = (r1 & meta_sec(m1)) ? (r1 & meta_sec(m1)) : r1;
+        const uint32_t r = (uint32_t)(room1 >> (8u * s)) & 0xffu;
+        if (r) {
+          const uint32_t sc = (uint32_t)(sec1 >> (8u * s)) & 0xffu;
+          const uint32_t pick = (r & sc) ? (r & sc) : r;
           v = s;
-          y1 = b1;
           t = (uint32_t)__builtin_ctz(pick);
-          y2 = other1[t];
         }
       }
     }
     if (t == kSlots) return false;
+    // y1 = other[v], y2 = o1[v][t], selected without indexing by v and t
+    y1 = pick_slot(other, v);
+    y2 = 0;
+#pragma unroll
+    for (uint32_t s = 0; s < kSlots; ++s) y2 |= pick_slot(o1[s], t) & (0u - (uint32_t)(s == v));
   }
   // lock the buckets beyond p and a (both compare-and-swaps issued
   // together: a failure here is not retried but falls back to the walk, so
@@ -483,11 +520,10 @@ __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32
 }
 
 // DIRECT step of a table with timers; word = value | expiry << 48.
-// first: the key's first attempt on its pair (lock_pair).
 __device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const KeyFields &f,
                                    uint64_t h, uint32_t log2b, uint64_t seed, bool plain,
-                                   uint32_t now, bool first) {
-  if (!lock_pair(bk, f.p, f.a, first)) return kBusy;
+                                   uint32_t now) {
+  if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   const Head ha = read_head(bk, f.a);
   int r = kNeedPath;
@@ -551,9 +587,8 @@ __device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const 
 }
 
 __device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value, const KeyFields &f,
-                             uint64_t h, uint32_t log2b, uint64_t seed, bool plain,
-                             bool first) {
-  if (!lock_pair(bk, f.p, f.a, first)) return kBusy;
+                             uint64_t h, uint32_t log2b, uint64_t seed, bool plain) {
+  if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   const Head ha = read_head(bk, f.a);
   int r;
@@ -629,21 +664,24 @@ __device__ __attribute__((noinline)) int walk(const uint8_t *bk, uint32_t start,
     uint32_t cand = meta_busy(meta) & ~used;
     if (!plain && meta_moved(meta) >= 0xffffu) cand &= sec;  // no owner may leave
     if (!cand) return -1;
-    // lookahead: which candidates' other buckets have a free slot
+    // lookahead: which candidates' other buckets have a free slot (every
+    // slot's load issued, a non-candidate reading the current bucket, so
+    // that all are in flight together)
+    uint32_t om[kSlots];
+#pragma unroll
+    for (uint32_t s = 0; s < kSlots; ++s)
+      om[s] = (uint32_t)load_relaxed(bucket_ptr(bk, ((cand >> s) & 1u) ? other[s] : cur) +
+                                     kMetaOffset);
     uint32_t room = 0;
 #pragma unroll
-    for (uint32_t s = 0; s < kSlots; ++s) {
-      if ((cand >> s) & 1u) {
-        const uint32_t om = (uint32_t)load_relaxed(bucket_ptr(bk, other[s]) + kMetaOffset);
-        if (meta_busy(om) != 0xffu) room |= 1u << s;
-      }
-    }
+    for (uint32_t s = 0; s < kSlots; ++s)
+      if (((cand >> s) & 1u) && meta_busy(om[s]) != 0xffu) room |= 1u << s;
     const uint64_t r = mix64(rbase + (uint64_t)(step + 1) * kGolden);
     if (room) {
       const uint32_t pick = (room & sec) ? (room & sec) : room;
       const uint32_t v = nth_bit(pick, (uint32_t)(r % (uint64_t)__builtin_popcount(pick)));
       path[step] = cur | (v << kPathSlotShift);
-      *last = other[v];
+      *last = pick_slot(other, v);
       return (int)step + 1;
     }
     uint32_t pref = 0;
@@ -655,18 +693,17 @@ __device__ __attribute__((noinline)) int walk(const uint8_t *bk, uint32_t start,
     const uint32_t v = nth_bit(pick, (uint32_t)(r % (uint64_t)__builtin_popcount(pick)));
     path[step] = cur | (v << kPathSlotShift);
     prev = cur;
-    cur = other[v];
+    cur = pick_slot(other, v);
   }
   return -1;
 }
 
 // Moves the entry of slot s of bucket x to a free slot of bucket y, its
 // other bucket.  Returns 1 when done, 0 when the state no longer matches
-// the path, kBusy when a lock was taken.  first: the first attempt on this
-// move (lock_pair).
+// the path, kBusy when a lock was taken.
 __device__ __attribute__((noinline)) int move_entry(uint8_t *bk, uint32_t x, uint32_t s, uint32_t y,
-                          uint32_t log2b, uint64_t seed, bool plain, bool first) {
-  if (x == y || !lock_pair(bk, x, y, first)) return kBusy;
+                          uint32_t log2b, uint64_t seed, bool plain) {
+  if (x == y || !lock_two(bk, x, y)) return kBusy;
   int r = 0;
   const uint32_t mx = *meta_ptr(bk, x), my = *meta_ptr(bk, y);
   const uint32_t busy_x = meta_busy(mx), busy_y = meta_busy(my);
@@ -726,7 +763,6 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
   enum { DIRECT, WALK, MOVE };
   int state = DIRECT, result = -1;
   uint32_t len = 0, next = 0, last = 0, walks = 0, iters = 0;
-  bool retry = false;  // the last step found a lock taken (lock_pair)
   bool spun = false;
   while (result < 0) {
     if (++iters > spin_limit) {
@@ -735,10 +771,8 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
       break;
     }
     if (state == DIRECT) {
-      const int r =
-          TIMED ? insert_direct_timed(bk, key, word, f, h, log2b, seed, plain, now, !retry)
-                : insert_direct(bk, key, value, f, h, log2b, seed, plain, !retry);
-      retry = r == kBusy;
+      const int r = TIMED ? insert_direct_timed(bk, key, word, f, h, log2b, seed, plain, now)
+                          : insert_direct(bk, key, value, f, h, log2b, seed, plain);
       if (r >= 0)
         result = r;
       else if (r == kNeedPath)
@@ -762,8 +796,7 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
       const uint32_t e = path[next - 1];
       const uint32_t x = e & kPathBucketMask, s = e >> kPathSlotShift;
       const uint32_t y = (next == len) ? last : (path[next] & kPathBucketMask);
-      const int r = move_entry(bk, x, s, y, log2b, seed, plain, !retry);
-      retry = r == kBusy;
+      const int r = move_entry(bk, x, s, y, log2b, seed, plain);
       if (r == 1) {
         if (--next == 0) state = DIRECT;
       } else if (r == 0) {
@@ -776,11 +809,10 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
 
 // Returns 1 if the key was removed, 0 if absent, kBusy to retry.  TIMED:
 // an expired entry of the key is removed too, but reports 0 (Sec. 4.2).
-// first: the first attempt on the key's pair (lock_pair).
 template <bool TIMED>
 __device__ int delete_direct(uint8_t *bk, uint4 key, const KeyFields &f, bool plain,
-                             uint32_t now, bool first) {
-  if (!lock_pair(bk, f.p, f.a, first)) return kBusy;
+                             uint32_t now) {
+  if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   int r = 0;
   int s = find_slot(bk, f.p, hp, key, f.tag);
@@ -818,8 +850,8 @@ __device__ int delete_one(uint8_t *bk, uint4 key, uint32_t log2b, uint64_t seed,
   int r = kBusy;
   uint32_t iters = 0;
   while (r == kBusy && iters < spin_limit) {
-    r = delete_direct<TIMED>(bk, key, f, plain, now, iters == 0u);
     ++iters;
+    r = delete_direct<TIMED>(bk, key, f, plain, now);
   }
   *spun = r == kBusy;
   return r == kBusy ? CKPP_RETRY : r;
