@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--core-only", action="store_true",
                     help="only the timed steps (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--latency", action="store_true",
+                    help="latency of one dependent access of each kind the updates make")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sweep", action="store_true",
@@ -66,10 +68,20 @@ def parse():
                          "runs the anti-revival scan)")
     ap.add_argument("--many-tables", type=int, default=0, metavar="N",
                     help="batching workload over N tables: per-table calls vs one plan launch")
+    ap.add_argument("--plan-shape", default=None, metavar="L,P,B,C,I,S",
+                    help="with --many-tables: only the plan at this shape (lanes per lookup, "
+                         "lookups per lane, block, blocks per CU, passes per item, schedule)")
     ap.add_argument("--insert-workload", action="store_true",
                     help="insert rate vs load in 65536-key batches, then delete 20%% and re-insert")
     ap.add_argument("--summarize-profiles", metavar="DIR", default=None,
                     help="write profiles/ summaries from rocprofv3 CSV output under DIR")
+    ap.add_argument("--summarize-serve", metavar="JSON", default=None,
+                    help="write the serving summary in profiles/ from a saved --serve 50000 line")
+    ap.add_argument("--summarize-serve-trace", metavar="DIR", default=None,
+                    help="with --summarize-serve: rocprofv3 output of the loop's kernel trace")
+    ap.add_argument("--summarize-plan-profiles", metavar="DIR", default=None,
+                    help="write the plan kernel's profiles/ summary from rocprofv3 CSV output "
+                         "under DIR")
     ap.add_argument("--tune", action="store_true",
                     help="time every lookup launch shape, print them, keep the fastest")
     ap.add_argument("--lanes", type=int, default=None)
@@ -261,7 +273,7 @@ def cache_resident_table(dev, lookups, B=20):
     a buffer of the table's size."""
     import torch
     t, keys, _, _ = build_table(B, 0.9, 77, dev)
-    n = min(lookups, 1 << 24)
+    n = lookups
     pos, _, _ = W.lookup_mix(keys, n, 0.0, 78)
     neg = W.five_tuples(n, 79, stream=W.STREAM_NEGATIVE)
     dp, dn = to_dev(pos, dev), to_dev(neg, dev)
@@ -517,6 +529,33 @@ def cpu_baseline(keys, pos, neg, B=24, load=0.9, single_sample=1 << 22):
             "insert_per_s": nk / t_ins, "host": cpu}
 
 
+def latency_probe(dev, steps=4000):
+    """Latency of one dependent access of each kind the insert and delete
+    paths make (ckpp_probe_latency: plain load, agent-scope atomic load,
+    compare-and-swap, load + store + wait, two compare-and-swaps at once),
+    on an idle GPU, over a 4 GiB buffer (HBM) and a 1 MiB one (cache), in
+    ns per step."""
+    import torch
+    from paper_1712_09624_amd import ckpp
+    out = {}
+    for label, nbytes in (("4GiB", 4 << 30), ("1MiB", 1 << 20)):
+        buf = torch.zeros(nbytes // 8, dtype=torch.int64, device=dev)
+        res = torch.zeros(2, dtype=torch.int64, device=dev)
+        r = {}
+        for i, kind in enumerate(ckpp.LATENCY_KINDS):
+            # step k visits line mix64(seed + k + value): seeds 2^32 apart give
+            # the warm-up and the timed chain (and each kind) lines of their own
+            ckpp.probe_latency(buf, kind, steps, ((2 * i + 1) << 32), res)   # warm-up
+            ckpp.probe_latency(buf, kind, steps, ((2 * i + 2) << 32), res)
+            torch.cuda.synchronize()
+            r[kind + "_ns"] = int(res[0].item()) * 10.0 / steps
+        out[label] = r
+        log(f"latency {label}: " + " ".join(f"{k} {v:.0f}" for k, v in r.items()))
+        del buf
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration(dev):
     import torch
     a = torch.empty(1 << 27, dtype=torch.int64, device=dev)  # 1 GiB
@@ -530,19 +569,19 @@ def copy_calibration(dev):
 
 def sweep(dev, lookups, probe_peak):
     """Lookup rate of Cuckoo++ and plain lookups over loads {0.6 .. 0.95} and
-    negative rates {0 .. 1}, on a 2^25-bucket (8 GiB, above the 2^24 buckets
-    where the hash split changes), a 2^24-bucket (4 GiB, HBM-resident), a
-    2^20-bucket (256 MiB, the size of the last-level cache) and a
-    2^19-bucket (128 MiB, cache-resident) table built incrementally.  Each
-    point's frac is given against the HBM random-line peak and against the
-    random-line peak measured on a buffer of the table's size."""
+    negative rates {0 .. 1}, `lookups` (2^26) per point, on a 2^24-bucket
+    (4 GiB, HBM-resident), a 2^20-bucket (256 MiB, the size of the
+    last-level cache) and a 2^19-bucket (128 MiB, cache-resident) table
+    built incrementally.  Each point's frac is given against the HBM
+    random-line peak and against the random-line peak measured on a buffer
+    of the table's size, and on the method's algorithmic bytes (64-byte
+    lines) against 8 TB/s.  Ends with a table of the points on stderr."""
     import torch
     from paper_1712_09624_amd.ckpp import Table
     loads = (0.6, 0.7, 0.8, 0.9, 0.95)
     rates = (0.0, 0.25, 0.5, 0.75, 1.0)
     rows = []
-    for B, nlook in ((25, lookups), (24, lookups), (20, min(lookups, 1 << 24)),
-                     (19, min(lookups, 1 << 24))):
+    for B, nlook in ((24, lookups), (20, lookups), (19, lookups)):
         size_peak = probe_line_peak(dev, 256 << B)
         log(f"sweep B={B}: random-line peak on a {256 << B >> 20} MiB buffer "
             f"{size_peak / 1e9:.2f} G/s")
@@ -564,6 +603,7 @@ def sweep(dev, lookups, probe_peak):
             torch.cuda.synchronize()
             st = t.stats()
             lines = expected_lines(st)
+            alg = algorithmic_lines_64(st)
             pick = W.raw_u64(50 + B, int(ld * 100), nlook) % np.uint64(n)
             pos_pool = to_dev(keys[pick.astype(np.int64)], dev)
             for r in rates:
@@ -572,12 +612,16 @@ def sweep(dev, lookups, probe_peak):
                 for mode, lk in (("cuckoopp", "cuckoopp"), ("both", "plain")):
                     ms = timed(lambda: t.lookup(q, mode, found=f, values=v), 3, dev)
                     req = (1 - r) * lines[f"{lk}_pos"] + r * lines[f"{lk}_neg"]
+                    alg_lines = (1 - r) * alg[f"{lk}_pos"] + r * alg[f"{lk}_neg"]
                     rate = nlook / (ms * 1e-3)
                     rows.append({"log2_buckets": B, "load": ld, "neg_rate": r, "mode": lk,
                                  "glookups": rate / 1e9, "lines_per_lookup": req,
                                  "frac_random_line_peak": rate * req / probe_peak,
                                  "same_size_peak_per_s": size_peak,
                                  "frac_same_size_peak": rate * req / size_peak,
+                                 "alg_lines_64B": alg_lines,
+                                 "frac_hbm_8TBps": rate * (ALG_LINE * alg_lines + STREAM_BYTES)
+                                 / (HBM_PEAK_GBS * 1e9),
                                  "failed_inserts": int(nf.item())})
             del pos_pool
             log(f"sweep B={B} load={ld}: " + " ".join(
@@ -585,6 +629,12 @@ def sweep(dev, lookups, probe_peak):
         t.close()
         del neg_pool
         torch.cuda.empty_cache()
+    log(f"{'B':>3} {'load':>5} {'r':>5} {'mode':>9} {'Glk/s':>7} {'lines128':>8} "
+        f"{'frac_peak':>9} {'frac_size':>9} {'lines64':>7} {'frac8TB':>7}")
+    for x in rows:
+        log(f"{x['log2_buckets']:>3} {x['load']:>5.2f} {x['neg_rate']:>5.2f} {x['mode']:>9} "
+            f"{x['glookups']:>7.2f} {x['lines_per_lookup']:>8.3f} {x['frac_random_line_peak']:>9.3f} "
+            f"{x['frac_same_size_peak']:>9.3f} {x['alg_lines_64B']:>7.3f} {x['frac_hbm_8TBps']:>7.3f}")
     return rows
 
 
@@ -652,14 +702,17 @@ def insert_workload(dev, B=24, batch=65536):
             "retry_exhausted": stats["retry_exhausted"]}
 
 
-def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
+def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3, shape=None):
     """Batching workload: ntables independent tables (bucket counts
     log-uniform over 2^10..2^18, loads U[0.6, 0.95], lookup batches
     U[32, 4096], negative rates U[0, 1]), every table's batch served
     (a) by one lookup call per table, eagerly and captured in a HIP graph,
     and (b) by one plan launch, eagerly and captured in a HIP graph, after
     the plan's launch shape is autotuned.  All four give the same answers,
-    checked against the workload's ground truth."""
+    checked against the workload's ground truth.  shape (lanes per lookup,
+    lookups per lane, block, blocks per CU, passes per item, schedule): only
+    the plan at that shape, `reps` launches, nothing else (for profiler
+    runs)."""
     import torch
     from paper_1712_09624_amd import tune
     from paper_1712_09624_amd.ckpp import Plan, Table
@@ -694,12 +747,19 @@ def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
         raise RuntimeError(f"{int(nfail.item())} inserts failed while building the tables")
     # algorithmic lines per lookup of each table, from its own statistics
     neg_rate = np.array([1.0 - float(f.mean()) if len(f) else 0.0 for f in want_f])
+    lines64 = []
     for i, t in enumerate(tables):
-        el = expected_lines(t.stats())
+        st = t.stats()
+        el, a64 = expected_lines(st), algorithmic_lines_64(st)
         lines.append(counts[i] * ((1.0 - neg_rate[i]) * el["cuckoopp_pos"]
                                   + neg_rate[i] * el["cuckoopp_neg"]))
+        lines64.append(counts[i] * ((1.0 - neg_rate[i]) * a64["cuckoopp_pos"]
+                                    + neg_rate[i] * a64["cuckoopp_neg"]))
     total = int(sum(counts))
-    alg_bytes = LINE * float(sum(lines)) + STREAM_BYTES * total
+    # the method's algorithmic bytes (64-byte lines), and the device layout's
+    # 128-byte lines
+    alg_bytes = ALG_LINE * float(sum(lines64)) + STREAM_BYTES * total
+    dev_bytes = LINE * float(sum(lines)) + STREAM_BYTES * total
     keys_d = to_dev(np.concatenate(chunks), dev)
     wf, wv = np.concatenate(want_f), np.concatenate(want_v)
     found = torch.empty(total, dtype=torch.uint8, device=dev)
@@ -720,7 +780,19 @@ def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
 
     out = {"tables": ntables, "keys": nkeys, "lookups": total, "build_s": build_s,
            "device_table_bytes": int(sum(256 << int(b) for b in cfg["log2_buckets"])),
-           "algorithmic_bytes": alg_bytes}
+           "algorithmic_bytes": alg_bytes, "device_layout_bytes": dev_bytes}
+    if shape is not None:
+        plan = Plan(tables, offsets, counts)
+        lanes, per, block, bpc, passes, sched = shape
+        plan.set_launch(per, block, bpc, passes, sched, lanes)
+        plan.lookup(keys_d, found, vals_d)
+        check("plan (given shape)")
+        out["plan_shape"] = plan.get_launch()
+        out["plan_us"] = timed(lambda: plan.lookup(keys_d, found, vals_d), reps, dev) * 1e3
+        plan.close()
+        for t in tables:
+            t.close()
+        return out
     s = torch.cuda.current_stream(dev)
     # (a) one call per table
     per_table()
@@ -790,6 +862,7 @@ def many_table_bench(dev, ntables=1024, seed=4, reps=20, tune_reps=3):
     out["plan_graph_over_per_table_eager"] = out["per_table_eager_us"] / out["plan_graph_us"]
     out["plan_achieved_GBps"] = alg_bytes / (out["plan_eager_us"] * 1e-6) / 1e9
     out["plan_frac_hbm_peak"] = out["plan_achieved_GBps"] / HBM_PEAK_GBS
+    out["plan_frac_128B_granule"] = dev_bytes / (out["plan_eager_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
     del g_plan, g_tab
     tuned = plan.get_launch()
     plan.close()
@@ -1113,10 +1186,119 @@ def summarize_profiles(d):
     print("\n".join(out + lines))
 
 
+PLAN_PROFILE_CMD = "python3 bench.py --many-tables 1024 --plan-shape 1,1,128,8,1,0"
+
+
+def summarize_plan_profiles(d):
+    """Writes the profiles/ summary of the plan kernel from the rocprofv3 CSV
+    output under d of: a kernel trace (d/plan_trace), FETCH_SIZE
+    (d/plan_fetch), WRITE_SIZE (d/plan_write) and the read-request sizes
+    (d/plan_req), each of PLAN_PROFILE_CMD, and the 1 GiB copy calibration
+    of the lookup profiles (d/p4_copy_{fetch,write}, the PROFILE_CMDS
+    "copy" runs)."""
+    import csv
+    rows = [r for r in csv.DictReader(open(os.path.join(d, "plan_trace", "plan_kernel_stats.csv")))
+            if "lookup_plan" in r["Name"]]
+    r = rows[0]
+    fetch = [v["FETCH_SIZE"] for v in _pmc(os.path.join(d, "plan_fetch", "plan_counter_collection.csv"),
+                                             "lookup_plan")]
+    write = [v["WRITE_SIZE"] for v in _pmc(os.path.join(d, "plan_write", "plan_counter_collection.csv"),
+                                             "lookup_plan")]
+    req = _pmc(os.path.join(d, "plan_req", "plan_counter_collection.csv"), "lookup_plan")
+    cpf = _pmc(os.path.join(d, "p4_copy_fetch", "copy_counter_collection.csv"), "copyBuffer")
+    cpw = _pmc(os.path.join(d, "p4_copy_write", "copy_counter_collection.csv"), "copyBuffer")
+    f_fetch = (1 << 30) / (cpf[0]["FETCH_SIZE"] * 1024)
+    f_write = (1 << 30) / (cpw[0]["WRITE_SIZE"] * 1024)
+    fb = float(np.mean(fetch)) * 1024 * f_fetch
+    wb = float(np.mean(write)) * 1024 * f_write
+    nreq = float(np.mean([v["TCC_EA0_RDREQ_sum"] for v in req]))
+    n128 = float(np.mean([v["TCC_EA0_RDREQ_128B_sum"] for v in req]))
+    n64 = float(np.mean([v["TCC_EA0_RDREQ_64B_sum"] for v in req]))
+    n32 = float(np.mean([v["TCC_EA0_RDREQ_32B_sum"] for v in req]))
+    lines = [
+        "# lookup_plan: 1024 tables (2^10..2^18 buckets, loads 0.6..0.95, batches 32..4096,",
+        "#   negative rates 0..1; 2,144,563 lookups) in one launch at the tuned shape",
+        "#   (1 lane per lookup, 1 lookup per lane, block 128, 8 blocks/CU, 1 pass/item, static)",
+        "# commands (repository root, TMPDIR=/tmp, one counter group per run):",
+        f"#   rocprofv3 --kernel-trace --stats --output-format csv -d {d}/plan_trace -o plan -- "
+        f"{PLAN_PROFILE_CMD}",
+        f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d {d}/plan_fetch -o plan -- "
+        f"{PLAN_PROFILE_CMD}",
+        f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d {d}/plan_write -o plan -- "
+        f"{PLAN_PROFILE_CMD}",
+        f"#   rocprofv3 --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum "
+        f"TCC_EA0_RDREQ_128B_sum --output-format csv -d {d}/plan_req -o plan -- {PLAN_PROFILE_CMD}",
+        "#   calibration: the copy runs of the lookup profiles (FETCH_SIZE x "
+        f"{f_fetch:.4f}, WRITE_SIZE x {f_write:.4f})",
+        f"kernel trace: {int(r['Calls'])} launches, average {float(r['AverageNs']) / 1e3:.1f} us, "
+        f"min {float(r['MinNs']) / 1e3:.1f}, max {float(r['MaxNs']) / 1e3:.1f}",
+        f"HBM traffic per launch (calibrated): fetch {fb / 1e6:.1f} MB, write {wb / 1e6:.1f} MB",
+        f"read requests per launch: {nreq:.0f} (128 B: {n128:.0f}, 64 B: {n64:.0f}, "
+        f"32 B: {n32:.0f}); {nreq / 2144563:.3f} per lookup",
+    ]
+    with open(os.path.join(ROOT, "profiles", "lookup_plan_1024_tables_trace_traffic.txt"), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_serve(path, trace_dir=None):
+    """Writes profiles/serve_b24_load0.85_zipf1.1.txt from the JSON line of
+    `python3 bench.py --serve 50000` saved at `path` (and, with trace_dir,
+    the loop kernel's line of a rocprofv3 kernel trace of
+    `python3 bench.py --serve 20000` under trace_dir/serve_trace)."""
+    import csv
+    rec = [json.loads(x) for x in open(path) if x.startswith("{")][-1]["serve"]
+    out = ["# Serving loop (persistent cooperative kernel, rounds of lookups | inserts | deletes), MI355X, ROCm 7.2",
+           "# table 2^24 buckets x 8 slots at load 0.85 (114,085,069 keys); flow universe = first 100M keys;",
+           "# bursts log-uniform in [1, 2048] ops: 0.9 n lookups (Zipf s=1.1 over the universe), 0.1 n inserts of",
+           "# new flows, 0.05 n deletes of expired flows (stored keys outside the universe); "
+           f"{rec['bursts_per_run']:,} bursts per run;",
+           f"# admission budget {rec['budget_ops']} ops per kind; loop grid {rec['grid_blocks']} blocks x 256 threads;",
+           "# every lookup, insert status and delete result of every run checked against the ground truth",
+           "# command (repository root): python3 bench.py --serve 50000",
+           "# a round's updates are spread over every wavefront (lane 0 of each, then lane 1, ...); an insert",
+           "#   whose primary is full searches one- and two-step displacements with all candidates' loads at once;",
+           "#   lookups run 4, 2 or 1 per lane per pass in registers (the loop keeps one wavefront per SIMD)",
+           "# latency = host-observed completion - arrival; us/round = the loop's own clock per phase (insert:",
+           "#   inserts, or inserts and deletes side by side in rounds with few updates; delete: deletes after)",
+           f"{'offered':>10} {'Glookups/s':>11} {'p50_us':>9} {'p99_us':>9} {'rounds':>7} {'bursts/rnd':>10} "
+           f"{'lookup':>7} {'insert':>7} {'delete':>7} {'bound.':>6}"]
+    for r in rec["runs"]:
+        off = "peak" if r["offered"] == "closed loop (peak)" else f"{int(round(r['offered'] * 100))}%"
+        u = r["us_per_round"]
+        out.append(f"{off:>10} {r['glookups']:>11.3f} {r['p50_us']:>9.1f} {r['p99_us']:>9.1f} "
+                   f"{r['rounds']:>7} {r['bursts_per_round']:>10.0f} {u['lookup']:>7.1f} "
+                   f"{u['insert']:>7.1f} {u['delete']:>7.1f} {u['boundary']:>6.1f}")
+    out.append("# the peak run submits all bursts at once (closed loop): its latency is queueing behind the budget")
+    pc = rec.get("plain_calls")
+    if pc:
+        out.append(f"# the same kind of stream ({pc['bursts']} bursts) through the plain batch calls, one "
+                   "burst at a time (lookup, insert and delete batch, then a synchronization), checked:")
+        out.append(f"{'plain-calls':>10} {pc['glookups']:>11.4f} {pc['p50_us']:>9.1f} {pc['p99_us']:>9.1f}")
+    if trace_dir:
+        rows = [r for r in csv.DictReader(open(os.path.join(trace_dir, "serve_trace", "serve_kernel_stats.csv")))
+                if "serve_loop" in r["Name"]]
+        for r in rows:
+            out.append(f"# kernel trace (rocprofv3 --kernel-trace --stats --output-format csv -d "
+                       f"{trace_dir}/serve_trace -o serve -- python3 bench.py --serve 20000):")
+            out.append(f"#   serve_loop: {r['Calls']} launch(es), {float(r['TotalDurationNs']) / 1e9:.3f} s "
+                       "resident (the loop stays on the device through all runs and idles between them;")
+            out.append("#   its per-phase times are the loop's own clocks above)")
+    with open(os.path.join(ROOT, "profiles", "serve_b24_load0.85_zipf1.1.txt"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main():
     args = parse()
+    if args.summarize_serve:
+        summarize_serve(args.summarize_serve, args.summarize_serve_trace)
+        return
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles)
+        return
+    if args.summarize_plan_profiles:
+        summarize_plan_profiles(args.summarize_plan_profiles)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the table is "
@@ -1131,6 +1313,9 @@ def main():
     if args.copy_calib:
         copy_calibration(dev)
         return
+    if args.latency:
+        print(json.dumps({"latency_ns": latency_probe(dev)}), flush=True)
+        return
     if args.serve:
         print(json.dumps({"serve": serve_bench(dev, args.serve, B=args.serve_log2_buckets,
                                                 load=args.serve_load, timers=args.serve_timers,
@@ -1138,7 +1323,9 @@ def main():
               flush=True)
         return
     if args.many_tables:
-        print(json.dumps({"many_tables": many_table_bench(dev, args.many_tables)}), flush=True)
+        shape = tuple(int(x) for x in args.plan_shape.split(",")) if args.plan_shape else None
+        print(json.dumps({"many_tables": many_table_bench(dev, args.many_tables, shape=shape)}),
+              flush=True)
         return
     if args.insert_workload:
         print(json.dumps({"insert_workload": insert_workload(dev)}), flush=True)

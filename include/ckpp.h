@@ -636,6 +636,22 @@ int ckpp_probe_random_reads(const void *d_buf, uint64_t bytes, uint32_t granule,
                             uint32_t per_lane, uint32_t cooperative, uint32_t block, uint32_t grid,
                             uint64_t seed, uint64_t *d_sink, void *stream);
 
+/* Measurement kernel for the latency of the insert and delete paths: one
+ * lane makes `steps` dependent accesses to 128-byte lines chosen by a
+ * hash of the previous access's value (so none can start before the one
+ * before it ends), in d_buf (`bytes` long, a multiple of 256, 256-byte
+ * aligned).  kind 0: plain load; 1: relaxed agent-scope atomic load; 2:
+ * relaxed agent-scope compare-and-swap (expects 1, writes 1: it changes no
+ * word); 3: atomic load, the same value stored back with an atomic store,
+ * and a wait for the store to complete; 4: two compare-and-swaps of kind 2
+ * on lines half the buffer apart, issued together.  The buffer's contents are not
+ * changed.  d_out[0] receives the elapsed real-time counter ticks (100 MHz:
+ * 10 ns each), d_out[1] a fold of the values read.  The caller times
+ * nothing: ticks / steps is the latency of one step.  Errors: CKPP_EINVAL
+ * (null or misaligned pointers, a size or kind out of range, steps 0). */
+int ckpp_probe_latency(void *d_buf, uint64_t bytes, uint32_t kind, uint32_t steps, uint64_t seed,
+                       uint64_t *d_out, void *stream);
+
 /* Human-readable name of a status code. */
 const char *ckpp_strerror(int code);
 

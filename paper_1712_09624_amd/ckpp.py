@@ -207,6 +207,7 @@ SIGNATURES = [
     ("ckpp_server_destroy", _I, [_VP]),
     ("ckpp_probe_random_reads", _I, [_VP, _U64, _U32, _U64, _U32, _U32, _U32, _U32, _U64, _VP,
                                      _VP]),
+    ("ckpp_probe_latency", _I, [_VP, _U64, _U32, _U32, _U64, _VP, _VP]),
     ("ckpp_strerror", ctypes.c_char_p, [_I]),
 ]
 
@@ -765,3 +766,17 @@ def probe_random_reads(buf, granule: int, nreads: int, per_lane: int, block: int
                                      ctypes.c_uint64(seed), sink.data_ptr(),
                                      _stream_handle(stream))
     _check(rc, "ckpp_probe_random_reads")
+
+
+LATENCY_KINDS = ("load", "atomic_load", "cas", "load_store_wait", "cas_pair")
+
+
+def probe_latency(buf, kind: str, steps: int, seed: int, out, stream=None):
+    """Launches the dependent-access latency probe over the device tensor
+    ``buf`` (kinds: LATENCY_KINDS); ``out`` (two int64) receives the elapsed
+    10 ns ticks and a fold of the values read."""
+    lib = load()
+    nbytes = buf.numel() * buf.element_size()
+    rc = lib.ckpp_probe_latency(buf.data_ptr(), nbytes, LATENCY_KINDS.index(kind), int(steps),
+                                ctypes.c_uint64(seed), out.data_ptr(), _stream_handle(stream))
+    _check(rc, "ckpp_probe_latency")

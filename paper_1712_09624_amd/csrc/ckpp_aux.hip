@@ -1,4 +1,5 @@
-// ckpp_aux.hip -- statistics, hashing, zero-fill and the random-read probe.
+// ckpp_aux.hip -- statistics, hashing, zero-fill, the random-read probe and
+// the dependent-access latency probe.
 
 #include "ckpp_device.h"
 #include "ckpp_internal.h"
@@ -128,7 +129,74 @@ hipError_t probe_g(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t
   return probe_q<8, COOP>(d_buf, units, nreads, per_lane, block, grid, seed, d_sink, s);
 }
 
+// Latency probe: one lane follows a chain of `steps` dependent accesses,
+// one request per step.
+// Step k reads (kind 0: a plain load; 1: a relaxed agent-scope atomic load,
+// the accesses of a critical section; 2: a relaxed agent-scope
+// compare-and-swap that expects 1 and writes 1, the lock's operation,
+// which never changes a word holding anything else and leaves a 1 as it
+// is; 3: an atomic load, then the same value stored back with an atomic
+// store and a wait until the store is complete, the end of a critical
+// section; 4: two compare-and-swaps issued together, on lines half the
+// buffer apart, a lock pair's first attempt) the 16-byte-aligned word of 128-byte line
+// mix64(seed + k + value of step k - 1) mod lines, so every access waits
+// for the one before it.  The buffer's contents are not changed.
+// out[0] = elapsed real-time counter ticks (100 MHz), out[1] = a fold of the
+// values read.
+template <int KIND>
+__global__ void __launch_bounds__(64)
+    latency_kernel(uint64_t *buf, uint64_t lines, uint32_t steps, uint64_t seed, uint64_t *out) {
+  if (threadIdx.x != 0) return;  // one lane: one request per step
+  uint64_t v = 0, fold = 0;
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  for (uint32_t k = 0; k < steps; ++k) {
+    const uint64_t line = __umul64hi(mix64(seed + k + v), lines);
+    uint64_t *w = buf + line * 16u;
+    if (KIND == 0) {
+      v = *reinterpret_cast<volatile uint64_t *>(w);
+    } else if (KIND == 1) {
+      v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else if (KIND == 2) {
+      uint64_t e = 1u;
+      __hip_atomic_compare_exchange_strong(w, &e, 1ull, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      v = e;
+    } else if (KIND == 3) {
+      v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);
+    } else {
+      // a line half the buffer away (a lock pair's buckets are far apart)
+      const uint64_t far = line + lines / 2u;
+      uint64_t *w2 = buf + (far < lines ? far : far - lines) * 16u;
+      uint64_t e = 1u, e2 = 1u;
+      __hip_atomic_compare_exchange_strong(w, &e, 1ull, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_compare_exchange_strong(w2, &e2, 1ull, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+      v = e ^ e2;
+    }
+    fold ^= v;
+  }
+  out[0] = __builtin_amdgcn_s_memrealtime() - t0;
+  out[1] = fold;
+}
+
 }  // namespace
+
+hipError_t launch_latency(void *d_buf, uint64_t bytes, uint32_t kind, uint32_t steps,
+                          uint64_t seed, uint64_t *d_out, hipStream_t s) {
+  uint64_t *b = static_cast<uint64_t *>(d_buf);
+  const uint64_t lines = bytes / 128u;
+  switch (kind) {
+    case 0: hipLaunchKernelGGL(latency_kernel<0>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
+    case 1: hipLaunchKernelGGL(latency_kernel<1>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
+    case 2: hipLaunchKernelGGL(latency_kernel<2>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
+    case 3: hipLaunchKernelGGL(latency_kernel<3>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
+    default: hipLaunchKernelGGL(latency_kernel<4>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_stats(const ckpp_table *t, uint64_t *d_acc, hipStream_t s) {
   const uint64_t nb = 1ull << t->log2_buckets;

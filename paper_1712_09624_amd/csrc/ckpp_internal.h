@@ -116,6 +116,9 @@ hipError_t launch_stats(const ckpp_table *t, uint64_t *d_acc, hipStream_t s);
 hipError_t launch_hash(const ckpp_table *t, const void *d_keys, uint64_t n, uint64_t *d_hash,
                        hipStream_t s);
 hipError_t launch_fill_zero(void *d, uint64_t bytes, hipStream_t s);
+// The dependent-access latency probe (ckpp_probe_latency).
+hipError_t launch_latency(void *d_buf, uint64_t bytes, uint32_t kind, uint32_t steps,
+                          uint64_t seed, uint64_t *d_out, hipStream_t s);
 hipError_t launch_probe(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t nreads,
                         uint32_t per_lane, uint32_t cooperative, uint32_t block, uint32_t grid,
                         uint64_t seed, uint64_t *d_sink, hipStream_t s);

@@ -73,6 +73,7 @@ def test_argument_checks_need_no_device(lib):
     assert lib.ckpp_check_image(10, 0, None, None) == ckpp.EINVAL
     assert lib.ckpp_destroy(None) == ckpp.OK
     assert lib.ckpp_probe_random_reads(None, 64, 64, 1, 1, 0, 256, 1, 0, None, None) == ckpp.EINVAL
+    assert lib.ckpp_probe_latency(None, 256, 0, 1, 0, None, None) == ckpp.EINVAL
     offs = (ctypes.c_uint64 * 1)(0)
     cnts = (ctypes.c_uint64 * 1)(1)
     tabs = (ctypes.c_void_p * 1)(None)
