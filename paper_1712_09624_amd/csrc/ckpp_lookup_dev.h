@@ -16,21 +16,40 @@ constexpr uint32_t kWaveQuarters = 64 * 8;
 
 // Cooperative fetch of one 128-byte line (half `half` of the bucket) for
 // every lookup of the wave whose `bucket` is not kNoFetch: in round k the
-// lanes 8g..8g+7 read the line of lookup 8k+g, lane r its quarter r, and
-// the line lands at lines[8(8k+g) .. 8(8k+g)+8).
+// lanes 8g..8g+7 read the line of lookup 8k+g, and the line lands at
+// lines[8(8k+g) .. 8(8k+g)+8), its quarters rotated (Mine): lane r reads
+// quarter r ^ g, which lands at position r.  The eight lanes' requests still
+// cover the whole line, one 128-byte request.  The buckets of the eight
+// rounds are gathered first and waited for once: a wave that waits for each
+// exchange before its load spends most of its time in those waits when it
+// is alone on its SIMD.
 __device__ __forceinline__ void fetch_lines(uint4 *lines, const uint4 *tab, uint32_t bucket,
                                             uint32_t half, uint32_t g, uint32_t r) {
+  uint32_t b[8];
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k)
+    b[k] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
 #pragma unroll
   for (uint32_t k = 0; k < 8; ++k) {
-    const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
-    if (b != kNoFetch) {
-      const uint4 *src = tab + (uint64_t)b * kQuartersPerBucket + 8u * half + r;
+    if (b[k] != kNoFetch) {
+      const uint4 *src = tab + (uint64_t)b[k] * kQuartersPerBucket + 8u * half + (r ^ g);
       __builtin_amdgcn_global_load_lds(
           (const void __attribute__((address_space(1))) *)src,
           (void __attribute__((address_space(3))) *)(lines + 64u * k), 16, 0, 0);
     }
   }
 }
+
+// A lane's own line in the wave's LDS lines: quarter q of lookup j's line
+// sits at 8j + (q ^ (j & 7)), so that when every lane reads the same
+// quarter of its own line (the lines 128 bytes apart), eight neighbouring
+// lanes hit eight different groups of LDS banks instead of one.
+struct Mine {
+  const uint4 *p;  // the line's first position
+  uint32_t sw;     // j & 7
+  __device__ __forceinline__ uint4 operator[](uint32_t q) const { return p[q ^ sw]; }
+  __device__ __forceinline__ Mine operator+(uint32_t quarters) const { return Mine{p + quarters, sw}; }
+};
 
 // Waits until the lines requested by this wave have landed in LDS (the
 // loads' counter drains once the data is written there); the compiler may
@@ -76,7 +95,7 @@ __device__ __forceinline__ uint64_t hit_value(uint64_t w, uint32_t now) {
 // Compares the key with the candidate slots `cand` (ascending) of a first
 // line (mine[0..7]).
 template <bool TIMED>
-__device__ __forceinline__ void match_line0(const uint4 *mine, uint32_t cand, uint4 key,
+__device__ __forceinline__ void match_line0(Mine mine, uint32_t cand, uint4 key,
                                             uint32_t now, bool &hit, uint64_t &val,
                                             uint32_t &slot) {
   while (cand != 0u && !hit) {
@@ -89,7 +108,7 @@ __device__ __forceinline__ void match_line0(const uint4 *mine, uint32_t cand, ui
 
 // Same for slots 4..7 on a second line (mine[0..7]).
 template <bool TIMED>
-__device__ __forceinline__ void match_line1(const uint4 *mine, uint32_t cand, uint4 key,
+__device__ __forceinline__ void match_line1(Mine mine, uint32_t cand, uint4 key,
                                             uint32_t now, bool &hit, uint64_t &val,
                                             uint32_t &slot) {
   while (cand != 0u && !hit) {
@@ -106,7 +125,7 @@ __device__ __forceinline__ void match_line1(const uint4 *mine, uint32_t cand, ui
 // buckets at once (the same buffer when the kernel keeps one per wave).
 struct Wave {
   uint4 *lines, *lines_a;
-  const uint4 *mine, *mine_a;
+  Mine mine, mine_a;
   uint32_t lane, g, r;
 };
 
@@ -118,8 +137,8 @@ __device__ __forceinline__ Wave wave_lines(uint4 *s_lines) {
   w.r = w.lane & 7u;
   w.lines = s_lines + (threadIdx.x >> 6) * NB * kWaveQuarters;
   w.lines_a = w.lines + (NB - 1) * kWaveQuarters;
-  w.mine = w.lines + 8u * w.lane;
-  w.mine_a = w.lines_a + 8u * w.lane;
+  w.mine = Mine{w.lines + 8u * w.lane, w.r};
+  w.mine_a = Mine{w.lines_a + 8u * w.lane, w.r};
   return w;
 }
 
@@ -167,7 +186,7 @@ __device__ __forceinline__ void lds_pass(const Wave &w, const TableRef &T, uint4
   // the secondary's lines: the second buffer in the pessimistic mode (fetched
   // with the primary), else the first one again (fetched after it)
   uint4 *const lines_a = MODE == kModeBoth ? w.lines_a : w.lines;
-  const uint4 *const mine_a = MODE == kModeBoth ? w.mine_a : w.mine;
+  const Mine mine_a = MODE == kModeBoth ? w.mine_a : w.mine;
   const KeyFields f = key_fields(key_hash(key, T.seed), T.log2b);
   // first line of the primary (and, pessimistic mode, the secondary)
   fetch_lines(w.lines, T.tab, ok ? f.p : kNoFetch, 0u, w.g, w.r);
@@ -222,11 +241,14 @@ __device__ __forceinline__ void lds_pass(const Wave &w, const TableRef &T, uint4
 // the quarters to LDS in exactly the layout fetch_lines produces.
 __device__ __forceinline__ void fetch_lines_reg(uint4 (&q)[8], const uint4 *tab, uint32_t bucket,
                                                 uint32_t half, uint32_t g, uint32_t r) {
+  uint32_t b[8];
+#pragma unroll
+  for (uint32_t k = 0; k < 8; ++k)
+    b[k] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
 #pragma unroll
   for (uint32_t k = 0; k < 8; ++k) {
-    const uint32_t b = (uint32_t)__builtin_amdgcn_ds_bpermute((int)((8u * k + g) << 2), (int)bucket);
     q[k] = zero4();
-    if (b != kNoFetch) q[k] = tab[(uint64_t)b * kQuartersPerBucket + 8u * half + r];
+    if (b[k] != kNoFetch) q[k] = tab[(uint64_t)b[k] * kQuartersPerBucket + 8u * half + (r ^ g)];
   }
 }
 
@@ -246,7 +268,7 @@ struct Look {
 };
 
 template <bool TIMED>
-__device__ __forceinline__ void first_line(const uint4 *mine, Look &L, uint32_t mode,
+__device__ __forceinline__ void first_line(Mine mine, Look &L, uint32_t mode,
                                            uint32_t now) {
   const uint4 t0 = mine[0], t1 = mine[1];
   L.cand = L.ok ? (tag_eq_mask(t0, L.f.tag) & meta_busy(t1.z)) : 0u;
@@ -266,7 +288,7 @@ __device__ __forceinline__ void dual_pass(const Wave &w, const TableRef &T, uint
   static_assert(MODE != kModeBoth, "the pessimistic mode runs in lds_pass");
   const uint32_t lane = w.lane, g = w.g, r = w.r;
   uint4 *lines = w.lines;
-  const uint4 *mine = w.mine;
+  const Mine mine = w.mine;
   Look A, Bq;
   A.key = ka;
   Bq.key = kb;
@@ -400,14 +422,13 @@ __device__ __forceinline__ void reg_match(const uint4 *tab, RegLooks<PER> &L, co
   }
 }
 
-// One pass of a wave over 64 * PER lookups: lookup j of lane l is lookup
-// 64 j + l of the tile, its results at found[64 j] / vals[64 j] (the
-// caller offsets both by the lane).  `pre` runs once the first heads are
-// requested.
+// One pass of a wave over 64 * PER lookups, PER per lane (the lane's
+// key[j], a real lookup iff ok[j]); lookup j's answer goes to *found[j] /
+// *vals[j].  `pre` runs once the first heads are requested.
 template <uint32_t MODE, bool TIMED, uint32_t PER, class Pre>
-__device__ __forceinline__ void reg_pass(const TableRef &T, const uint4 (&key)[PER],
-                                         const bool (&ok)[PER], uint8_t *found, uint64_t *vals,
-                                         Pre &&pre) {
+__device__ __forceinline__ void reg_pass_to(const TableRef &T, const uint4 (&key)[PER],
+                                            const bool (&ok)[PER], uint8_t *const (&found)[PER],
+                                            uint64_t *const (&vals)[PER], Pre &&pre) {
   RegLooks<PER> L;
   uint32_t b[PER];
   uint4 g0[PER], g1[PER];  // pessimistic mode: head of the secondary, fetched with the primary
@@ -467,10 +488,26 @@ __device__ __forceinline__ void reg_pass(const TableRef &T, const uint4 (&key)[P
     if (!L.ok[j]) continue;
     if (TIMED && T.refresh && L.hit[j] && needs_refresh(T, L.val[j]))
       refresh_entry(T, L.hit_primary[j] ? L.f[j].p : L.f[j].a, L.slot[j]);
-    __builtin_nontemporal_store((uint8_t)(L.hit[j] ? 1 : 0), found + 64u * j);
-    __builtin_nontemporal_store(L.hit[j] ? hit_value<TIMED>(L.val[j], T.now) : 0ull,
-                                vals + 64u * j);
+    __builtin_nontemporal_store((uint8_t)(L.hit[j] ? 1 : 0), found[j]);
+    __builtin_nontemporal_store(L.hit[j] ? hit_value<TIMED>(L.val[j], T.now) : 0ull, vals[j]);
   }
+}
+
+// reg_pass_to over a tile: lookup j of lane l is lookup 64 j + l of the
+// tile, its results at found[64 j] / vals[64 j] (the caller offsets both by
+// the lane).
+template <uint32_t MODE, bool TIMED, uint32_t PER, class Pre>
+__device__ __forceinline__ void reg_pass(const TableRef &T, const uint4 (&key)[PER],
+                                         const bool (&ok)[PER], uint8_t *found, uint64_t *vals,
+                                         Pre &&pre) {
+  uint8_t *fo[PER];
+  uint64_t *vo[PER];
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j) {
+    fo[j] = found + 64u * j;
+    vo[j] = vals + 64u * j;
+  }
+  reg_pass_to<MODE, TIMED, PER>(T, key, ok, fo, vo, pre);
 }
 
 // ---- Four lanes per lookup, lines in registers ----------------------------

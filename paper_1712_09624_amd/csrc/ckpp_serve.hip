@@ -303,47 +303,61 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   return kCmdRun;
 }
 
-// The round's lookups [l0, l1), each wave taking 128 at a time (two per
-// lane: the passes of the batch kernel's default form) or, in the
-// pessimistic mode, 64 (one per lane, both buckets' lines at once).
-// TIMED: lookups at time `now` (T carries it, the refresh flag and the
-// refreshed expiration time).
+// Lookups [l0, l1) of a round, PER per lane at a time in registers
+// (reg_pass_to), the next PER keys loaded while a pass's first heads are in
+// flight.  Lookup j of a lane's pass is i + 64 j, its ring slot (i + 64 j)
+// & mask.
+template <uint32_t PER, uint32_t MODE, bool TIMED>
+__device__ void reg_lookups(const ServeArgs &a, const TableRef &T, uint32_t lane, uint64_t wave,
+                            uint64_t nwaves, uint64_t l0, uint64_t l1) {
+  const uint64_t step = nwaves * 64u * PER;
+  uint64_t i = l0 + wave * 64u * PER + lane;
+  uint4 k[PER];
+#pragma unroll
+  for (uint32_t j = 0; j < PER; ++j)
+    k[j] = i + 64u * j < l1 ? load_stream(a.lk_keys + ((i + 64u * j) & a.mask)) : zero4();
+  for (; i - lane < l1; i += step) {
+    bool ok[PER];
+    uint8_t *fo[PER];
+    uint64_t *vo[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+      const uint64_t slot = (i + 64u * j) & a.mask;
+      ok[j] = i + 64u * j < l1;
+      fo[j] = a.lk_found + slot;
+      vo[j] = a.lk_vals + slot;
+    }
+    uint4 nk[PER];
+    reg_pass_to<MODE, TIMED, PER>(T, k, ok, fo, vo, [&] {
+#pragma unroll
+      for (uint32_t j = 0; j < PER; ++j) {
+        const uint64_t n = i + step + 64u * j;
+        nk[j] = n < l1 ? load_stream(a.lk_keys + (n & a.mask)) : zero4();
+      }
+    });
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) k[j] = nk[j];
+  }
+}
+
+// The round's lookups [l0, l1), PER per lane per pass in registers
+// (reg_pass_to, every mode): 4 when every lane of the grid has at least 4,
+// else 2 or 1, so that a round's lookups spread over every wavefront (8 per
+// lane measured slower than 4 on the loop's peak workload).
+// The loop keeps one wavefront per SIMD, where the batch kernel's LDS form
+// (eight lanes fetching each line into LDS) spends its time in the lane
+// exchanges and waits of that fetch; in registers a lookup's pass takes a
+// few loads of its own.  TIMED: lookups at time `now` (T carries it, the
+// refresh flag and the refreshed expiration time).
 template <uint32_t MODE, bool TIMED>
-__device__ void lookup_phase(const ServeArgs &a, const TableRef &T, const Wave &w, uint64_t l0,
-                             uint64_t l1) {
+__device__ void lookup_phase(const ServeArgs &a, const TableRef &T, uint64_t l0, uint64_t l1) {
   const uint64_t nwaves = (uint64_t)gridDim.x * kWaves;
   const uint64_t wave = (uint64_t)blockIdx.x * kWaves + (threadIdx.x >> 6);
-  if constexpr (MODE == kModeBoth) {
-    uint64_t i = l0 + wave * 64u + w.lane;
-    uint4 key = i < l1 ? load_stream(a.lk_keys + (i & a.mask)) : zero4();
-    for (; i - w.lane < l1; i += nwaves * 64u) {
-      const uint64_t slot = i & a.mask;
-      uint4 knext;
-      lds_pass<MODE, TIMED>(w, T, key, i < l1, a.lk_found + slot, a.lk_vals + slot, [&] {
-        const uint64_t in = i + nwaves * 64u;
-        knext = in < l1 ? load_stream(a.lk_keys + (in & a.mask)) : zero4();
-      });
-      key = knext;
-    }
-  } else {
-    const uint64_t step = nwaves * 128u;
-    uint64_t i = l0 + wave * 128u + w.lane;  // lookup A of this lane; B is i + 64
-    uint4 ka = i < l1 ? load_stream(a.lk_keys + (i & a.mask)) : zero4();
-    uint4 kb = i + 64u < l1 ? load_stream(a.lk_keys + ((i + 64u) & a.mask)) : zero4();
-    for (; i - w.lane < l1; i += step) {
-      const uint64_t sa = i & a.mask, sb = (i + 64u) & a.mask;
-      uint4 na, nb;
-      dual_pass<MODE, TIMED>(w, T, ka, i < l1, kb, i + 64u < l1, a.lk_found + sa, a.lk_vals + sa,
-                             a.lk_found + sb, a.lk_vals + sb, [&] {
-                               const uint64_t n = i + step;
-                               na = n < l1 ? load_stream(a.lk_keys + (n & a.mask)) : zero4();
-                               nb = n + 64u < l1 ? load_stream(a.lk_keys + ((n + 64u) & a.mask))
-                                                 : zero4();
-                             });
-      ka = na;
-      kb = nb;
-    }
-  }
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t n = l1 - l0, lanes = nwaves * 64u;
+  if (n >= 4u * lanes) reg_lookups<4, MODE, TIMED>(a, T, lane, wave, nwaves, l0, l1);
+  else if (n >= 2u * lanes) reg_lookups<2, MODE, TIMED>(a, T, lane, wave, nwaves, l0, l1);
+  else reg_lookups<1, MODE, TIMED>(a, T, lane, wave, nwaves, l0, l1);
 }
 
 // Rank of lane g among `lanes` lanes (whole wavefronts) when the lanes are
@@ -358,6 +372,8 @@ __device__ __forceinline__ uint64_t column_rank(uint64_t g, uint64_t lanes, bool
   const uint64_t waves = lanes / 64u, lane = g & 63u;
   return (top ? 63u - lane : lane) * waves + g / 64u;
 }
+
+
 
 // The round's insert keys in a set (open addressing, linear probing): an
 // entry belongs to the round whose tag it carries, so the set is never
@@ -420,11 +436,14 @@ __device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1, uint3
 
 // The round's deletes.  Every lane of the grid takes the deletes at offsets
 // r, r + nlanes, ..., r its column rank from the top lane down (the other
-// end of each wavefront from the insert lanes, so that inserts and deletes
-// run side by side).  filter: a delete of a key
-// the round also inserts is deferred (its result byte set to kDeferred)
-// until every insert of the round is done.  deferred_only: runs just the
-// deferred deletes (the same lane took them).  TIMED: deletes at time `now`.
+// end of each wavefront from the insert lanes).  Inserts and deletes of a
+// round share the wavefronts rather than taking one half of them each:
+// a wavefront's time grows with the number of its lanes that run an
+// update, since lanes in different states of an update run their steps one
+// group after another.  filter: a delete of a key the round also inserts
+// is deferred (its result byte set to kDeferred) until every insert of the
+// round is done.  deferred_only: runs just the deferred deletes.  TIMED:
+// deletes at time `now`.
 template <bool TIMED>
 __device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1, bool filter,
                              uint32_t tag, bool deferred_only, uint32_t now) {
@@ -478,12 +497,10 @@ __device__ bool phase_barrier(const ServeArgs &a, uint32_t epoch, uint32_t phase
 
 // TIMED: the table has timers (the round's time and scan flag come with
 // its ranges).
-template <uint32_t NB, uint32_t MODE, bool TIMED>
+template <uint32_t MODE, bool TIMED>
 __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
-  __shared__ uint4 s_lines[kWaves * NB * kWaveQuarters];
   __shared__ uint64_t s_range[8];
   __shared__ uint32_t s_cmd, s_ok;
-  const Wave w = wave_lines<NB>(s_lines);
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   ServeDev *d = a.dev;
   // epochs continue from the last launch's (nothing writes gen until every
@@ -584,7 +601,7 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
       const bool merge = ins && del && 2u * (i1 - i0) <= a.set_mask + 1u &&
                          2u * ((i1 - i0) + (d1 - d0)) <= lanes;
       const uint32_t tag = epoch;  // unique to this round
-      lookup_phase<MODE, TIMED>(a, T, w, l0, l1);
+      lookup_phase<MODE, TIMED>(a, T, l0, l1);
       if (merge) set_build(a, i0, i1, tag);
       last_phase = 0u;
       if (ins || del) {
@@ -657,10 +674,10 @@ std::atomic<uint32_t> *host_u32(uint32_t *p) { return reinterpret_cast<std::atom
 template <bool TIMED>
 const void *loop_kernel(uint32_t mode) {
   if (mode == ckpp::kModeBoth)
-    return reinterpret_cast<const void *>(&ckpp::serve_loop<2, ckpp::kModeBoth, TIMED>);
+    return reinterpret_cast<const void *>(&ckpp::serve_loop<ckpp::kModeBoth, TIMED>);
   if (mode == ckpp::kModeOptimistic)
-    return reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeOptimistic, TIMED>);
-  return reinterpret_cast<const void *>(&ckpp::serve_loop<1, ckpp::kModeCuckoopp, TIMED>);
+    return reinterpret_cast<const void *>(&ckpp::serve_loop<ckpp::kModeOptimistic, TIMED>);
+  return reinterpret_cast<const void *>(&ckpp::serve_loop<ckpp::kModeCuckoopp, TIMED>);
 }
 
 const void *loop_kernel(uint32_t mode, bool timed) {
