@@ -415,67 +415,52 @@ __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32
                                  (uint64_t)__builtin_popcount(pick)));
     y1 = pick_slot(other, v);
   } else {
-    // second level, every candidate at once (two round trips in all, where
-    // a candidate at a time costs three each: this search is the slowest
-    // step of the inserts that need it): the metadata word and other[] of
-    // each candidate's other bucket y1, then the metadata words of those
-    // buckets' other buckets.  Loads are issued for every slot, candidate or
-    // not (a non-candidate reads bucket p), so that none waits inside a
-    // branch.  The choice is the one-at-a-time order: the first candidate,
-    // entries of p going home first, whose y1 has an entry that can move on
-    // to a bucket with a free slot (an entry of y1 going home preferred).
-    uint32_t m1[kSlots], o1[kSlots][kSlots];
-#pragma unroll
-    for (uint32_t s = 0; s < kSlots; ++s) {
-      const uint8_t *b1 = bucket_ptr(bk, ((cand >> s) & 1u) ? other[s] : p);
-      m1[s] = (uint32_t)load_relaxed(b1 + kMetaOffset);
-#pragma unroll
-      for (uint32_t w = 0; w < 4; ++w) {
-        const uint64_t o = load_relaxed(b1 + kOtherOffset + 8 * w);
-        o1[s][2 * w] = (uint32_t)o;
-        o1[s][2 * w + 1] = (uint32_t)(o >> 32);
-      }
-    }
-    uint32_t om[kSlots][kSlots];
-#pragma unroll
-    for (uint32_t s = 0; s < kSlots; ++s) {
-      const uint32_t mv = ((cand >> s) & 1u) ? movable(m1[s], plain) : 0u;
-#pragma unroll
-      for (uint32_t u = 0; u < kSlots; ++u)
-        om[s][u] = (uint32_t)load_relaxed(bucket_ptr(bk, ((mv >> u) & 1u) ? o1[s][u] : p) +
-                                          kMetaOffset);
-    }
-    // room bits and sec masks of the y1s, packed 8 bits per candidate (so
-    // the choice below indexes no array)
-    uint64_t room1 = 0, sec1 = 0;
-#pragma unroll
-    for (uint32_t s = 0; s < kSlots; ++s) {
-      const uint32_t mv = ((cand >> s) & 1u) ? movable(m1[s], plain) : 0u;
-      uint32_t r = 0u;
-#pragma unroll
-      for (uint32_t u = 0; u < kSlots; ++u)
-        if (((mv >> u) & 1u) && meta_busy(om[s][u]) != 0xffu) r |= 1u << u;
-      room1 |= (uint64_t)r << (8u * s);
-      sec1 |= (uint64_t)meta_sec(m1[s]) << (8u * s);
-    }
+    // second level, one candidate at a time in the order of the choice
+    // (entries of p going home first), two round trips each: the metadata
+    // word and other[] of the candidate's other bucket y1, then the
+    // metadata words of y1's entries' other buckets, all of a round trip's
+    // loads issued together (a non-movable slot reads y1 itself, so that
+    // none waits inside a branch).  The first candidate whose y1 has an
+    // entry that can move on to a bucket with a free slot wins (an entry of
+    // y1 going home preferred); at the loads of the table's working loads
+    // that is nearly always the first one tried.  Searching every candidate
+    // at once takes 104 loads; measured on MI355X, one wavefront's lane
+    // spends some 20 us issuing them and choosing, against about 1 us for a
+    // candidate's two round trips.
     for (uint32_t order = 0; order < 2 && t == kSlots; ++order) {
       for (uint32_t c = cand & (order ? ~sec : sec); c && t == kSlots; c &= c - 1u) {
         const uint32_t s = (uint32_t)__builtin_ctz(c);
-        const uint32_t r = (uint32_t)(room1 >> (8u * s)) & 0xffu;
+        const uint32_t b1 = pick_slot(other, s);
+        const uint8_t *base1 = bucket_ptr(bk, b1);
+        const uint32_t m1 = (uint32_t)load_relaxed(base1 + kMetaOffset);
+        uint32_t o1[kSlots];
+#pragma unroll
+        for (uint32_t w = 0; w < 4; ++w) {
+          const uint64_t o = load_relaxed(base1 + kOtherOffset + 8 * w);
+          o1[2 * w] = (uint32_t)o;
+          o1[2 * w + 1] = (uint32_t)(o >> 32);
+        }
+        const uint32_t mv = movable(m1, plain);
+        uint32_t om[kSlots];
+#pragma unroll
+        for (uint32_t u = 0; u < kSlots; ++u)
+          om[u] = (uint32_t)load_relaxed(bucket_ptr(bk, ((mv >> u) & 1u) ? o1[u] : b1) +
+                                         kMetaOffset);
+        uint32_t r = 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < kSlots; ++u)
+          if (((mv >> u) & 1u) && meta_busy(om[u]) != 0xffu) r |= 1u << u;
         if (r) {
-          const uint32_t sc = (uint32_t)(sec1 >> (8u * s)) & 0xffu;
+          const uint32_t sc = meta_sec(m1);
           const uint32_t pick = (r & sc) ? (r & sc) : r;
           v = s;
           t = (uint32_t)__builtin_ctz(pick);
+          y1 = b1;
+          y2 = pick_slot(o1, t);
         }
       }
     }
     if (t == kSlots) return false;
-    // y1 = other[v], y2 = o1[v][t], selected without indexing by v and t
-    y1 = pick_slot(other, v);
-    y2 = 0;
-#pragma unroll
-    for (uint32_t s = 0; s < kSlots; ++s) y2 |= pick_slot(o1[s], t) & (0u - (uint32_t)(s == v));
   }
   // lock the buckets beyond p and a (both compare-and-swaps issued
   // together: a failure here is not retried but falls back to the walk, so
@@ -698,12 +683,14 @@ __device__ __attribute__((noinline)) int walk(const uint8_t *bk, uint32_t start,
   return -1;
 }
 
-// Moves the entry of slot s of bucket x to a free slot of bucket y, its
-// other bucket.  Returns 1 when done, 0 when the state no longer matches
-// the path, kBusy when a lock was taken.
-__device__ __attribute__((noinline)) int move_entry(uint8_t *bk, uint32_t x, uint32_t s, uint32_t y,
-                          uint32_t log2b, uint64_t seed, bool plain) {
-  if (x == y || !lock_two(bk, x, y)) return kBusy;
+// Under the locks of x and y: moves the entry of slot s of bucket x to a
+// free slot of bucket y, its other bucket, if the state still matches the
+// path (the slot is taken, its entry's other bucket is y, y has a free
+// slot, and an entry leaving its primary does not overflow the moved
+// counter), with the filter maintenance of Sec. 4.1.  Returns 1 when
+// moved, 0 when the state no longer matches (nothing changed).
+__device__ int move_checked(uint8_t *bk, uint32_t x, uint32_t s, uint32_t y, uint32_t log2b,
+                            uint64_t seed, bool plain) {
   int r = 0;
   const uint32_t mx = *meta_ptr(bk, x), my = *meta_ptr(bk, y);
   const uint32_t busy_x = meta_busy(mx), busy_y = meta_busy(my);
@@ -733,7 +720,104 @@ __device__ __attribute__((noinline)) int move_entry(uint8_t *bk, uint32_t x, uin
       r = 1;
     }
   }
+  return r;
+}
+
+// One displacement of the MOVE state: move_checked under the lock pair of
+// x and y.  Returns 1 when done, 0 when the state no longer matches the
+// path, kBusy when a lock was taken.
+__device__ __attribute__((noinline)) int move_entry(uint8_t *bk, uint32_t x, uint32_t s, uint32_t y,
+                          uint32_t log2b, uint64_t seed, bool plain) {
+  if (x == y || !lock_two(bk, x, y)) return kBusy;
+  const int r = move_checked(bk, x, s, y, log2b, seed, plain);
   unlock_two(bk, x, y);
+  return r;
+}
+
+// Longest cuckoo path applied in one critical section (apply_path).
+constexpr uint32_t kSectionPath = 8;
+
+// Applies a cuckoo path of len <= kSectionPath displacements (path[0..len)
+// as the walk wrote it, `last` the bucket that ends it) in one critical
+// section, where the MOVE state takes a lock pair, a re-check and a release
+// per displacement: every bucket of the path is locked, all the lock
+// requests issued together and none waited for; then the moves run last to
+// first, each with move_checked's re-check.  A lock held by another lane
+// gives back every lock taken and returns kBusy with nothing moved (the
+// caller then moves step by step, taking the pairs in ascending order,
+// which keeps concurrent keys live).  A re-check that fails stops the moves
+// and returns 0 (the moves already made stand: each is a valid move on its
+// own, as in the MOVE state); 1 when every displacement is made.
+//
+// The lock requests are atomic ORs of 1 into the lock words (a lock is
+// taken by the request that reads 0), one per entry of b[0..kSectionPath]
+// whatever the path's length, so that none sits behind a branch: entries
+// past the path, and repeats of a bucket, request b[0]'s or that bucket's
+// lock again.  A lane's requests to one word are performed in order, so a
+// repeat reads 1 when an earlier request of the lane took the lock; it can
+// read 0 only when the earlier one found the lock held by another lane that
+// has let it go since, and then this lane holds it through the repeat and
+// gives it back with the others.
+__device__ __attribute__((noinline)) int apply_path(uint8_t *bk, const uint32_t *path,
+                                                    uint32_t len, uint32_t last, uint32_t log2b,
+                                                    uint64_t seed, bool plain) {
+  uint32_t b[kSectionPath + 1], sl[kSectionPath];
+#pragma unroll
+  for (uint32_t i = 0; i < kSectionPath; ++i) {
+    const uint32_t e = i < len ? path[i] : 0u;
+    b[i] = i < len ? (e & kPathBucketMask) : kNoBucket;
+    sl[i] = e >> kPathSlotShift;
+  }
+  // `last` follows the path's buckets; entries past it request b[0] again
+  b[kSectionPath] = kNoBucket;
+#pragma unroll
+  for (uint32_t i = 0; i <= kSectionPath; ++i) {
+    if (i == len) b[i] = last;
+  }
+  uint32_t addr[kSectionPath + 1];
+  bool first[kSectionPath + 1];  // the first entry of its bucket within the path
+#pragma unroll
+  for (uint32_t i = 0; i <= kSectionPath; ++i) {
+    bool dup = b[i] == kNoBucket;
+#pragma unroll
+    for (uint32_t j = 0; j < i; ++j) dup = dup || b[j] == b[i];
+    first[i] = !dup;
+    addr[i] = b[i] == kNoBucket ? b[0] : b[i];
+  }
+  bool took[kSectionPath + 1];
+#pragma unroll
+  for (uint32_t i = 0; i <= kSectionPath; ++i)
+    took[i] = __hip_atomic_fetch_or(lock_word(bk, addr[i]), 1u, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT) == 0u;
+  bool all = true;
+#pragma unroll
+  for (uint32_t i = 0; i <= kSectionPath; ++i) all = all && (took[i] || !first[i]);
+  if (!all) {
+#pragma unroll
+    for (uint32_t i = 0; i <= kSectionPath; ++i)
+      if (took[i]) unlock(bk, addr[i]);
+    return kBusy;
+  }
+  section_begin();
+  int r = 1;
+  for (uint32_t k = len; k > 0 && r == 1; --k) {
+    const uint32_t i = k - 1u;
+    uint32_t x = 0u, s = 0u, y = 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < kSectionPath; ++j) {
+      if (j == i) {
+        x = b[j];
+        s = sl[j];
+        y = b[j + 1];
+      }
+    }
+    r = x == y ? 0 : move_checked(bk, x, s, y, log2b, seed, plain);
+  }
+  section_end();
+  // every bucket's lock was taken by its first request (the repeats read 1)
+#pragma unroll
+  for (uint32_t i = 0; i <= kSectionPath; ++i)
+    if (took[i]) unlock(bk, addr[i]);
   return r;
 }
 
@@ -791,6 +875,11 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
         len = (uint32_t)L;
         next = len;
         state = MOVE;
+        // a short path in one critical section; step by step if a lock is
+        // held (then nothing was moved)
+        if (len <= kSectionPath &&
+            apply_path(bk, path, len, last, log2b, seed, plain) != kBusy)
+          state = DIRECT;
       }
     } else {
       const uint32_t e = path[next - 1];
