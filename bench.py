@@ -79,6 +79,14 @@ def parse():
                     help="write the serving summary in profiles/ from a saved --serve 50000 line")
     ap.add_argument("--summarize-serve-trace", metavar="DIR", default=None,
                     help="with --summarize-serve: rocprofv3 output of the loop's kernel trace")
+    ap.add_argument("--summarize-serve-counters", metavar="DIR", default=None,
+                    help="with --summarize-serve: rocprofv3 --pmc output of the loop "
+                         "(DIR/serve_a, DIR/serve_b) and the copy calibration (DIR/p4_copy_*)")
+    ap.add_argument("--summarize-latency", metavar="JSON", default=None,
+                    help="write the latency probe summary in profiles/ from a saved --latency line")
+    ap.add_argument("--summarize-insert-workload", metavar="JSON", default=None,
+                    help="write the insert workload summary in profiles/ from a saved "
+                         "--insert-workload line")
     ap.add_argument("--summarize-plan-profiles", metavar="DIR", default=None,
                     help="write the plan kernel's profiles/ summary from rocprofv3 CSV output "
                          "under DIR")
@@ -532,9 +540,9 @@ def cpu_baseline(keys, pos, neg, B=24, load=0.9, single_sample=1 << 22):
 def latency_probe(dev, steps=4000):
     """Latency of one dependent access of each kind the insert and delete
     paths make (ckpp_probe_latency: plain load, agent-scope atomic load,
-    compare-and-swap, load + store + wait, two compare-and-swaps at once),
-    on an idle GPU, over a 4 GiB buffer (HBM) and a 1 MiB one (cache), in
-    ns per step."""
+    compare-and-swap, load + store + wait, two compare-and-swaps at once,
+    and 32 independent loads at once, plain or atomic), on an idle GPU,
+    over a 4 GiB buffer (HBM) and a 1 MiB one (cache), in ns per step."""
     import torch
     from paper_1712_09624_amd import ckpp
     out = {}
@@ -1241,11 +1249,135 @@ def summarize_plan_profiles(d):
     print("\n".join(lines))
 
 
-def summarize_serve(path, trace_dir=None):
+SERVE_COUNTER_CMDS = {
+    "serve_a": "FETCH_SIZE SQ_WAVE_CYCLES SQ_WAIT_INST_ANY SQ_WAIT_ANY SQ_BUSY_CYCLES "
+               "SQC_ICACHE_MISSES SQC_ICACHE_HITS",
+    "serve_b": "WRITE_SIZE TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_128B_sum",
+}
+
+
+def serve_counter_lines(d):
+    """Summary lines of the serving loop's counter runs under d (one
+    rocprofv3 --pmc run per SERVE_COUNTER_CMDS entry of
+    `python3 bench.py --serve 20000`, plus the 1 GiB copy calibration of the
+    lookup profiles): HBM bytes and read requests per operation served."""
+    import csv
+    tot, ops = {}, {}
+    for run in SERVE_COUNTER_CMDS:
+        for r in csv.DictReader(open(os.path.join(d, run, "serve_counter_collection.csv"))):
+            if "serve_loop" in r["Kernel_Name"]:
+                tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        log_path = os.path.join(d, run + ".log")
+        rec = [json.loads(x) for x in open(log_path) if x.startswith('{"serve"')][-1]["serve"]
+        ops[run] = (sum(r["ops"] for r in rec["runs"]), sum(r["lookups"] for r in rec["runs"]),
+                    sum(r["rounds"] for r in rec["runs"]))
+    cpf = _pmc(os.path.join(d, "p4_copy_fetch", "copy_counter_collection.csv"), "copyBuffer")
+    cpw = _pmc(os.path.join(d, "p4_copy_write", "copy_counter_collection.csv"), "copyBuffer")
+    f_fetch = (1 << 30) / (cpf[0]["FETCH_SIZE"] * 1024)
+    f_write = (1 << 30) / (cpw[0]["WRITE_SIZE"] * 1024)
+    na, la, ra = ops["serve_a"]
+    nb_, _, _ = ops["serve_b"]
+    fetch = tot["FETCH_SIZE"] * 1024 * f_fetch / na
+    write = tot["WRITE_SIZE"] * 1024 * f_write / nb_
+    req = tot["TCC_EA0_RDREQ_sum"] / nb_
+    r128 = tot["TCC_EA0_RDREQ_128B_sum"] / nb_
+    out = ["# loop counters (rocprofv3 --pmc, one run per group, each the loop's dispatches of",
+           "#   python3 bench.py --serve 20000; the profiler serializes dispatches, so the loop",
+           "#   idles out and relaunches between runs and the runs' timings do not count):"]
+    for run, cnt in SERVE_COUNTER_CMDS.items():
+        out.append(f"#   rocprofv3 --pmc {cnt} --output-format csv -d {d}/{run} -o serve -- "
+                   "python3 bench.py --serve 20000")
+    out += [f"#   calibration: FETCH_SIZE x {f_fetch:.4f}, WRITE_SIZE x {f_write:.4f} (1 GiB copy)",
+            f"HBM bytes per operation served: fetch {fetch:.0f}, write {write:.0f} "
+            f"({na:,} operations, {la:,} of them lookups, {ra} rounds)",
+            f"read requests per operation: {req:.2f} ({r128:.2f} of 128 bytes)",
+            f"instruction cache: {tot['SQC_ICACHE_MISSES']:.0f} misses in "
+            f"{tot['SQC_ICACHE_HITS']:.3g} hits; waves waiting for an instruction "
+            f"{100 * tot['SQ_WAIT_INST_ANY'] / tot['SQ_WAVE_CYCLES']:.1f}% of wave cycles, "
+            f"waiting on anything {100 * tot['SQ_WAIT_ANY'] / tot['SQ_WAVE_CYCLES']:.1f}%"]
+    return out
+
+
+def summarize_latency(path):
+    """Writes profiles/dependent_access_latency.txt from the JSON line of
+    `python3 bench.py --latency` saved at `path`."""
+    rec = [json.loads(x) for x in open(path) if x.startswith("{")][-1]["latency_ns"]
+    names = {"load_ns": "plain load", "atomic_load_ns": "relaxed agent-scope atomic load",
+             "cas_ns": "compare-and-swap (expects 1, writes 1)",
+             "load_store_wait_ns": "atomic load + atomic store + wait for the store",
+             "cas_pair_ns": "two compare-and-swaps issued together",
+             "load_batch32_ns": "32 independent plain loads, issued together",
+             "atomic_load_batch32_ns": "32 independent atomic loads, issued together"}
+    out = ["# Latency of one step of each access the insert and delete paths make, one lane of one",
+           "# wavefront on an idle MI355X (ckpp_probe_latency; steps chained by their values, 4000",
+           "# per kind; lines chosen at random in the buffer), ns per step",
+           "# command (repository root): python3 bench.py --latency",
+           f"{'access':<52} {'4 GiB (HBM)':>12} {'1 MiB (cache)':>14}"]
+    for k, name in names.items():
+        out.append(f"{name:<52} {rec['4GiB'][k]:>12.0f} {rec['1MiB'][k]:>14.0f}")
+    out.append("# a batch of independent loads from one lane completes at about 80 ns per load in")
+    out.append("#   either buffer: one lane's scattered loads are bounded by their issue, not by HBM")
+    with open(os.path.join(ROOT, "profiles", "dependent_access_latency.txt"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+# Earlier records of the same command, kept with the summary.
+INSERT_WORKLOAD_HISTORY = [
+    "# earlier path searches, same command: plain random walk (no lookahead) 734.9 ms = 173.5 M/s,",
+    "#   band 0.85: 55.6, band 0.90: 17.9, re-insert 81.5 M/s; walk with lookahead only: 228.8 ms =",
+    "#   557.3 M/s, band 0.85: 284.0, band 0.90: 180.2, re-insert 339.6 M/s; displacements inlined:",
+    "#   211.2 ms, band 0.05: 764, band 0.85: 404, band 0.90: 302, re-insert 472 M/s",
+    "#   pool-allocated path scratch for batches above 4096 lanes: 182.0 ms =",
+    "#   700.5 M/s, band 0.05: 950, band 0.90: 305, re-insert 522 M/s",
+    "#   agent-scope acquire/release fences around each critical section (an L2 invalidate and an L2",
+    "#   write-back per lock cycle): 170.6 ms = 747.2 M/s, band 0.05: 1026, band 0.90:",
+    "#   317, delete 1139 M/s, re-insert 547 M/s",
+    "#   two-level lookahead over every candidate at once (104 loads; previous record): 99.4 ms =",
+    "#   1282.2 M/s, band 0.85: 792.5, band 0.90: 510.5, re-insert 941.6 M/s",
+]
+
+
+def summarize_insert_workload(path):
+    """Writes profiles/insert_workload_b24.txt from the JSON line of
+    `python3 bench.py --insert-workload` saved at `path`."""
+    rec = [json.loads(x) for x in open(path) if x.startswith("{")][-1]
+    w = rec.get("insert_workload", rec)
+    out = ["# Batched insert workload on MI355X: empty 2^24-bucket table -> load 0.95 in batches of 65536",
+           "# keys (max kick chain 500), then delete of a random 20% and re-insert of as many fresh keys.",
+           "# Per-batch times from HIP events; delete/re-insert times wall-clock around the batch loops.",
+           "# cuckoo paths: up to two displacements done inside the locked DIRECT step when the primary's",
+           "#   entries (one level, else two levels of lookahead, one candidate at a time) reach a free",
+           "#   slot; else a random walk with one step of lookahead, whose path (up to 8 displacements)",
+           "#   is applied in one critical section; the rare paths are compiled out of line",
+           "# path scratch: a buffer of the table's own (up to 1/32 of the table's memory, here all 2^16 lanes",
+           "#   of a batch), allocated once; the stream-ordered pool only beyond that",
+           "# locks: table words under a lock read and written with device-coherent (agent-scope) accesses,",
+           "#   so taking and dropping a lock flushes no L2 cache",
+           "# command (repository root): python3 bench.py --insert-workload",
+           f"keys {w['keys']}  build {w['build_ms']:.1f} ms = {w['build_minserts_per_s']:.1f} M inserts/s  "
+           f"failed {w['build_failed']}",
+           f"delete {w['deleted']} (found {w['deleted_found']}) at {w['delete_minserts_per_s']:.0f} M/s",
+           f"re-insert {w['reinserted']} (failed {w['reinsert_failed']}) at "
+           f"{w['reinsert_minserts_per_s']:.1f} M/s",
+           f"final live {w['final_live']}  entries in secondary {w['f_sec']:.4f}  "
+           f"retry bound reached {w['retry_exhausted']}",
+           "insert rate by load band:",
+           " load from  M inserts/s"]
+    for b in w["per_load"]:
+        out.append(f"{b['load_from']:>10.2f} {b['minserts_per_s']:>13.1f}")
+    out += INSERT_WORKLOAD_HISTORY
+    with open(os.path.join(ROOT, "profiles", "insert_workload_b24.txt"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def summarize_serve(path, trace_dir=None, counter_dir=None):
     """Writes profiles/serve_b24_load0.85_zipf1.1.txt from the JSON line of
     `python3 bench.py --serve 50000` saved at `path` (and, with trace_dir,
     the loop kernel's line of a rocprofv3 kernel trace of
-    `python3 bench.py --serve 20000` under trace_dir/serve_trace)."""
+    `python3 bench.py --serve 20000` under trace_dir/serve_trace; with
+    counter_dir, serve_counter_lines of it)."""
     import csv
     rec = [json.loads(x) for x in open(path) if x.startswith("{")][-1]["serve"]
     out = ["# Serving loop (persistent cooperative kernel, rounds of lookups | inserts | deletes), MI355X, ROCm 7.2",
@@ -1284,6 +1416,8 @@ def summarize_serve(path, trace_dir=None):
             out.append(f"#   serve_loop: {r['Calls']} launch(es), {float(r['TotalDurationNs']) / 1e9:.3f} s "
                        "resident (the loop stays on the device through all runs and idles between them;")
             out.append("#   its per-phase times are the loop's own clocks above)")
+    if counter_dir:
+        out += serve_counter_lines(counter_dir)
     with open(os.path.join(ROOT, "profiles", "serve_b24_load0.85_zipf1.1.txt"), "w") as fh:
         fh.write("\n".join(out) + "\n")
     print("\n".join(out))
@@ -1292,7 +1426,14 @@ def summarize_serve(path, trace_dir=None):
 def main():
     args = parse()
     if args.summarize_serve:
-        summarize_serve(args.summarize_serve, args.summarize_serve_trace)
+        summarize_serve(args.summarize_serve, args.summarize_serve_trace,
+                        args.summarize_serve_counters)
+        return
+    if args.summarize_latency:
+        summarize_latency(args.summarize_latency)
+        return
+    if args.summarize_insert_workload:
+        summarize_insert_workload(args.summarize_insert_workload)
         return
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles)

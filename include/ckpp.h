@@ -644,8 +644,10 @@ int ckpp_probe_random_reads(const void *d_buf, uint64_t bytes, uint32_t granule,
  * relaxed agent-scope compare-and-swap (expects 1, writes 1: it changes no
  * word); 3: atomic load, the same value stored back with an atomic store,
  * and a wait for the store to complete; 4: two compare-and-swaps of kind 2
- * on lines half the buffer apart, issued together.  The buffer's contents are not
- * changed.  d_out[0] receives the elapsed real-time counter ticks (100 MHz:
+ * on lines half the buffer apart, issued together; 5: 32 plain loads of
+ * different lines, all issued before the first is waited for (the next
+ * step's lines depend on all 32 values); 6: the same with relaxed
+ * agent-scope atomic loads.  The buffer's contents are not changed.  d_out[0] receives the elapsed real-time counter ticks (100 MHz:
  * 10 ns each), d_out[1] a fold of the values read.  The caller times
  * nothing: ticks / steps is the latency of one step.  Errors: CKPP_EINVAL
  * (null or misaligned pointers, a size or kind out of range, steps 0). */

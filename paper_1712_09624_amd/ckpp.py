@@ -768,7 +768,8 @@ def probe_random_reads(buf, granule: int, nreads: int, per_lane: int, block: int
     _check(rc, "ckpp_probe_random_reads")
 
 
-LATENCY_KINDS = ("load", "atomic_load", "cas", "load_store_wait", "cas_pair")
+LATENCY_KINDS = ("load", "atomic_load", "cas", "load_store_wait", "cas_pair", "load_batch32",
+                 "atomic_load_batch32")
 
 
 def probe_latency(buf, kind: str, steps: int, seed: int, out, stream=None):

@@ -499,7 +499,7 @@ int ckpp_probe_random_reads(const void *d_buf, uint64_t bytes, uint32_t granule,
 int ckpp_probe_latency(void *d_buf, uint64_t bytes, uint32_t kind, uint32_t steps, uint64_t seed,
                        uint64_t *d_out, void *stream) {
   if (!d_buf || !d_out || !aligned(d_buf, 256) || !aligned(d_out, 8)) return CKPP_EINVAL;
-  if (bytes < 256 || bytes % 256 || kind > 4 || steps == 0) return CKPP_EINVAL;
+  if (bytes < 256 || bytes % 256 || kind > 6 || steps == 0) return CKPP_EINVAL;
   return dev_status(ckpp::launch_latency(d_buf, bytes, kind, steps, seed, d_out,
                                          reinterpret_cast<hipStream_t>(stream)));
 }

@@ -143,6 +143,8 @@ hipError_t probe_g(const void *d_buf, uint64_t bytes, uint32_t granule, uint64_t
 // for the one before it.  The buffer's contents are not changed.
 // out[0] = elapsed real-time counter ticks (100 MHz), out[1] = a fold of the
 // values read.
+constexpr uint32_t kLatencyBatch = 32;  // loads per step of kinds 5 and 6
+
 template <int KIND>
 __global__ void __launch_bounds__(64)
     latency_kernel(uint64_t *buf, uint64_t lines, uint32_t steps, uint64_t seed, uint64_t *out) {
@@ -165,6 +167,26 @@ __global__ void __launch_bounds__(64)
       v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_s_waitcnt(0);
+    } else if (KIND >= 5) {
+      // kLatencyBatch independent loads of different lines, all issued
+      // before the first is waited for: plain loads (5) and relaxed
+      // agent-scope atomic loads (6) through a global-memory pointer, and
+      // atomic loads through a generic pointer (7: the compiler then emits
+      // flat loads, which also count against the LDS counter)
+      uint64_t got[kLatencyBatch];
+#pragma unroll
+      for (uint32_t j = 0; j < kLatencyBatch; ++j) {
+        const uint64_t lj = __umul64hi(mix64(seed + (uint64_t)k * kLatencyBatch + j + v), lines);
+        uint64_t *wj = buf + lj * 16u;
+        __attribute__((address_space(1))) uint64_t *gj =
+            (__attribute__((address_space(1))) uint64_t *)wj;
+        if (KIND == 5) got[j] = *gj;
+        else if (KIND == 6) got[j] = __hip_atomic_load(gj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else got[j] = __hip_atomic_load(wj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      v = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < kLatencyBatch; ++j) v ^= got[j];
     } else {
       // a line half the buffer away (a lock pair's buckets are far apart)
       const uint64_t far = line + lines / 2u;
@@ -193,7 +215,10 @@ hipError_t launch_latency(void *d_buf, uint64_t bytes, uint32_t kind, uint32_t s
     case 1: hipLaunchKernelGGL(latency_kernel<1>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
     case 2: hipLaunchKernelGGL(latency_kernel<2>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
     case 3: hipLaunchKernelGGL(latency_kernel<3>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
-    default: hipLaunchKernelGGL(latency_kernel<4>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
+    case 4: hipLaunchKernelGGL(latency_kernel<4>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
+    case 5: hipLaunchKernelGGL(latency_kernel<5>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
+    case 6: hipLaunchKernelGGL(latency_kernel<6>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
+    default: hipLaunchKernelGGL(latency_kernel<7>, dim3(1), dim3(64), 0, s, b, lines, steps, seed, d_out); break;
   }
   return hipGetLastError();
 }
