@@ -453,11 +453,23 @@ __device__ __forceinline__ void reg_pass_to(const TableRef &T, const uint4 (&key
     }
   }
   pre();
+  // A lookup with no tag candidate in its primary cannot hit there: if it
+  // needs the secondary (the filter passes, or the mode always looks), the
+  // secondary's head is requested now, in the round trip of the other
+  // lookups' primary keys and values, instead of one round trip later.
+  // The requests are the same; only their order changes.
+  bool early[PER];
 #pragma unroll
   for (uint32_t j = 0; j < PER; ++j) {
     L.cand[j] = L.ok[j] ? (tag_eq_mask(L.h0[j], L.f[j].tag) & meta_busy(L.h1[j].z)) : 0u;
     L.pass[j] = MODE != kModeCuckoopp || bloom_pass(L.h1[j], L.f[j].bloom_bits);
     b[j] = L.f[j].p;
+    early[j] = MODE != kModeBoth && L.ok[j] && L.cand[j] == 0u && L.pass[j];
+    if (early[j]) {
+      const uint4 *q = T.tab + (uint64_t)L.f[j].a * kQuartersPerBucket;
+      g0[j] = q[0];
+      g1[j] = q[1];
+    }
   }
   reg_match<TIMED, PER>(T.tab, L, b, T.now);
   bool need_any = false;
@@ -468,7 +480,7 @@ __device__ __forceinline__ void reg_pass_to(const TableRef &T, const uint4 (&key
     L.cand[j] = 0u;
     b[j] = L.f[j].a;
     if (need) {
-      if (MODE != kModeBoth) {
+      if (MODE != kModeBoth && !early[j]) {
         const uint4 *q = T.tab + (uint64_t)L.f[j].a * kQuartersPerBucket;
         g0[j] = q[0];
         g1[j] = q[1];
