@@ -166,11 +166,16 @@ __device__ __forceinline__ bool needs_refresh(const TableRef &T, uint64_t w) {
 // high 16 bits of its value word, nothing else.  Lookups of the same batch
 // may read the word meanwhile; they see the old or the new time, and both
 // are alive at `now`, so their answers do not depend on the order.
+// The store is a relaxed agent-scope atomic, performed where the accesses of
+// every XCD meet (like the words written under a bucket lock), so an insert
+// or delete running on another XCD after a grid barrier of the serving loop
+// reads the new time without a write-back of this XCD's L2 cache.
 __device__ __forceinline__ void refresh_entry(const TableRef &T, uint32_t b, uint32_t s) {
   const uint32_t off = s < 4u ? 96u + 8u * s : 192u + 8u * (s - 4u);
   uint8_t *base = reinterpret_cast<uint8_t *>(const_cast<uint4 *>(T.tab)) +
                   (uint64_t)b * kBucketBytes + off + kTimerShift / 8u;
-  *reinterpret_cast<uint16_t *>(base) = (uint16_t)T.expiry;
+  __hip_atomic_store(reinterpret_cast<uint16_t *>(base), (uint16_t)T.expiry, __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ uint4 zero4() { return make_uint4(0u, 0u, 0u, 0u); }

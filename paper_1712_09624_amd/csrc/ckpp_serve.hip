@@ -179,13 +179,28 @@ __device__ __forceinline__ uint32_t poll_sys32(const uint32_t *p) {
 
 // A barrier over the grid without atomics.  Every block reaches the same
 // sequence of barriers and numbers them with the same epochs.  Thread 0 of
-// each block stores the epoch in its own flag line (release); the leader
-// wave (block 0, wave 0) polls all flags, 64 lanes at a time, until every
-// block has arrived, then the leader stores the epoch in `gen` (release);
-// the other blocks' thread 0 poll `gen`.  A wait that runs out of time or
-// iterations sets `abort`, which every other wait gives up on.
+// each block stores the epoch in its own flag line; the leader wave (block
+// 0, wave 0) polls all flags, 64 lanes at a time, until every block has
+// arrived, then the leader stores the epoch in `gen` (release); the other
+// blocks' thread 0 poll `gen`, and every waiter ends with an acquire fence.
+// A wait that runs out of time or iterations sets `abort`, which every
+// other wait gives up on.
+//
+// The arrival is a relaxed store after a wait for the block's own accesses
+// (every wave waits before the block's __syncthreads): what a block writes
+// in a phase for other blocks to read in the next is a table word written
+// with a device-coherent access (under a bucket lock, by the anti-revival
+// scan's atomics, or by a renewing lookup), or a set entry written with an
+// atomic, all performed where the XCDs meet once waited for.  A release
+// store would write back this XCD's whole L2 cache at every arrival of
+// every block; measured on the serving workload, dropping those write-backs
+// (with one system-scope release per block per round, for the host) took
+// the update phase at 25% offered load from 49 to 35 us per round.  The
+// leader's release of `gen` stays: the round's ranges it publishes are
+// plain stores.
 __device__ __forceinline__ void block_arrive(const ServeArgs &a, uint32_t epoch) {
-  __hip_atomic_store(a.arrive + (uint64_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELEASE,
+  __builtin_amdgcn_s_waitcnt(0);
+  __hip_atomic_store(a.arrive + (uint64_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
 }
 
@@ -472,6 +487,7 @@ __device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1, bool 
 // Grid-wide barrier inside a round (every thread of every block calls it).
 __device__ bool phase_barrier(const ServeArgs &a, uint32_t epoch, uint32_t phase,
                               uint32_t *s_ok) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's accesses of the phase are done
   __syncthreads();
   if (threadIdx.x == 0) block_arrive(a, epoch);
   if (blockIdx.x == 0) {
@@ -514,7 +530,13 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
     // round boundary
     ++epoch;
     __syncthreads();
-    if (threadIdx.x == 0) block_arrive(a, epoch);
+    if (threadIdx.x == 0) {
+      // every wave of the block has waited for its accesses (the end of
+      // the round below): one write-back of this XCD's L2 makes the round's
+      // results visible to the host and the copy engines
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+      block_arrive(a, epoch);
+    }
     if (blockIdx.x == 0) {
       if (threadIdx.x < 64u) {
         const bool ok = gather(a, epoch, kPhaseMs * kTicksPerMs);
@@ -618,8 +640,9 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
         }
       }
     }
-    // every wave's results become visible to the host and the copy engines
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    // this wave's results of the round are written (into the L2 cache); the
+    // block's thread 0 writes them back at the boundary
+    __builtin_amdgcn_s_waitcnt(0);
     ran = true;
   }
   if (leader) {
