@@ -82,6 +82,9 @@ def parse():
     ap.add_argument("--summarize-serve-counters", metavar="DIR", default=None,
                     help="with --summarize-serve: rocprofv3 --pmc output of the loop "
                          "(DIR/serve_a, DIR/serve_b) and the copy calibration (DIR/p4_copy_*)")
+    ap.add_argument("--summarize-serve-timers", metavar="JSON", default=None,
+                    help="write the timed serving summary in profiles/ from a saved "
+                         "--serve 50000 --serve-timers line")
     ap.add_argument("--summarize-latency", metavar="JSON", default=None,
                     help="write the latency probe summary in profiles/ from a saved --latency line")
     ap.add_argument("--summarize-insert-workload", metavar="JSON", default=None,
@@ -1372,6 +1375,46 @@ def summarize_insert_workload(path):
     print("\n".join(out))
 
 
+def summarize_serve_timers(path):
+    """Writes profiles/serve_b24_load0.85_zipf1.1_timers.txt from the JSON
+    line of `python3 bench.py --serve 50000 --serve-timers` saved at
+    `path`."""
+    rec = [json.loads(x) for x in open(path) if x.startswith("{")][-1]["serve"]
+    out = ["# Serving loop on a table with timers (persistent cooperative kernel, rounds of lookups | inserts |",
+           "# deletes), MI355X, ROCm 7.2",
+           f"# table 2^24 buckets x 8 slots at load 0.85 ({rec['stored_keys']:,} keys), every key expiring at "
+           f"time {SERVE_NOW0 + SERVE_TTL};",
+           f"# server: entries live {SERVE_TTL} units, every lookup that finds an entry renews it;",
+           f"# run r at time {SERVE_NOW0} + {SERVE_TICK} (r + 1): every key stays alive; flow universe = "
+           "first 100M keys;",
+           "# bursts log-uniform in [1, 2048] ops: 0.9 n lookups (Zipf s=1.1 over the universe), 0.1 n inserts of",
+           "# new flows, 0.05 n deletes of expired flows (stored keys outside the universe); "
+           f"{rec['bursts_per_run']:,} bursts per run;",
+           f"# admission budget {rec['budget_ops']} ops per kind; loop grid {rec['grid_blocks']} blocks x 256 threads;",
+           "# every lookup, insert status and delete result of every run checked against the ground truth",
+           "# command (repository root): python3 bench.py --serve 50000 --serve-timers",
+           "# latency = host-observed completion - arrival; us/round = the loop's own clock per phase",
+           f"{'offered':>10} {'Glookups/s':>11} {'p50_us':>9} {'p99_us':>9} {'rounds':>7} {'bursts/rnd':>10} "
+           f"{'lookup':>7} {'insert':>7} {'delete':>7} {'bound.':>6}"]
+    for r in rec["runs"]:
+        off = "peak" if r["offered"] == "closed loop (peak)" else f"{int(round(r['offered'] * 100))}%"
+        u = r["us_per_round"]
+        out.append(f"{off:>10} {r['glookups']:>11.3f} {r['p50_us']:>9.1f} {r['p99_us']:>9.1f} "
+                   f"{r['rounds']:>7} {r['bursts_per_round']:>10.0f} {u['lookup']:>7.1f} "
+                   f"{u['insert']:>7.1f} {u['delete']:>7.1f} {u['boundary']:>6.1f}")
+    sc = rec["scan"]
+    out += ["# the peak run submits all bursts at once (closed loop): its latency is queueing behind the budget",
+            "# anti-revival scan inside the loop (first time set; 4 GiB table, nothing expired, one",
+            f"#   pass, 16 buckets in flight per 16-lane group): {sc['loop_ms']:.2f} ms on the loop's clock, "
+            f"{sc['host_ms']:.2f} ms host-observed",
+            "# a renewing hit writes nothing when its entry already holds the new time (all rounds of a run",
+            "#   share one time); the time store is a relaxed agent-scope atomic",
+            "# the same workload without timers: serve_b24_load0.85_zipf1.1.txt"]
+    with open(os.path.join(ROOT, "profiles", "serve_b24_load0.85_zipf1.1_timers.txt"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def summarize_serve(path, trace_dir=None, counter_dir=None):
     """Writes profiles/serve_b24_load0.85_zipf1.1.txt from the JSON line of
     `python3 bench.py --serve 50000` saved at `path` (and, with trace_dir,
@@ -1390,7 +1433,8 @@ def summarize_serve(path, trace_dir=None, counter_dir=None):
            "# command (repository root): python3 bench.py --serve 50000",
            "# a round's updates are spread over every wavefront (lane 0 of each, then lane 1, ...); an insert",
            "#   whose primary is full searches one- and two-step displacements with all candidates' loads at once;",
-           "#   lookups run 4, 2 or 1 per lane per pass in registers (the loop keeps one wavefront per SIMD)",
+           "#   lookups run 4, 2 or 1 per lane per pass in registers (the loop keeps one wavefront per SIMD);",
+           "#   grid barriers: relaxed arrivals after a wait, one system-scope release per block per round",
            "# latency = host-observed completion - arrival; us/round = the loop's own clock per phase (insert:",
            "#   inserts, or inserts and deletes side by side in rounds with few updates; delete: deletes after)",
            f"{'offered':>10} {'Glookups/s':>11} {'p50_us':>9} {'p99_us':>9} {'rounds':>7} {'bursts/rnd':>10} "
@@ -1431,6 +1475,9 @@ def main():
         return
     if args.summarize_latency:
         summarize_latency(args.summarize_latency)
+        return
+    if args.summarize_serve_timers:
+        summarize_serve_timers(args.summarize_serve_timers)
         return
     if args.summarize_insert_workload:
         summarize_insert_workload(args.summarize_insert_workload)
