@@ -168,9 +168,12 @@ __global__ void __launch_bounds__(64 * WAVES)
     n2 = n3;
   }
   if (DYN && lane == 0u) {
-    // every ticket this wave will ever take is taken: count the wave out;
-    // the last one (which sees every other wave's tickets) rewinds both
-    const uint32_t out = __hip_atomic_fetch_add(ctr + 1, 1u, __ATOMIC_ACQ_REL,
+    // every ticket this wave will ever take is taken (each ticket's value
+    // was used, so its atomic was performed): count the wave out; the last
+    // one rewinds both.  Relaxed: the counters are the only words that need
+    // ordering, and an acquire-release here would write back and invalidate
+    // the XCD's L2 cache once per wave
+    const uint32_t out = __hip_atomic_fetch_add(ctr + 1, 1u, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
     if (out == gridDim.x * WAVES - 1u) {
       __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
