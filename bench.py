@@ -85,6 +85,9 @@ def parse():
     ap.add_argument("--summarize-serve-timers", metavar="JSON", default=None,
                     help="write the timed serving summary in profiles/ from a saved "
                          "--serve 50000 --serve-timers line")
+    ap.add_argument("--summarize-many-tables", metavar="JSON", default=None,
+                    help="write the many-table batching summary in profiles/ from a saved "
+                         "--many-tables 1024 line")
     ap.add_argument("--summarize-latency", metavar="JSON", default=None,
                     help="write the latency probe summary in profiles/ from a saved --latency line")
     ap.add_argument("--summarize-insert-workload", metavar="JSON", default=None,
@@ -1375,6 +1378,51 @@ def summarize_insert_workload(path):
     print("\n".join(out))
 
 
+def summarize_many_tables(path):
+    """Writes profiles/plan_1024_tables_batching.txt from the JSON line of
+    `python3 bench.py --many-tables 1024` saved at `path`."""
+    rec = [json.loads(x) for x in open(path) if x.startswith("{")][-1]
+    m = rec.get("many_tables", rec)
+    n = m["lookups"]
+    g = lambda us: n / (us * 1e-6) / 1e9
+    out = ["# Many-table batching: 1024 tables, one lookup batch each, served by one call per table",
+           "# versus one plan launch (persistent lookup_plan kernel), MI355X, ROCm 7.2",
+           "# workload: bucket counts 2^10..2^18 (exponent uniform), loads U[0.6, 0.95], batches U[32, 4096],",
+           "#   negative rates U[0, 1], seed 4; every answer checked against the workload's ground truth",
+           "# command (repository root): python3 bench.py --many-tables 1024",
+           f"tables {m['tables']}  keys {m['keys']}  lookups {n}  table bytes "
+           f"{m['device_table_bytes'] / 1e9:.1f} GB",
+           f"{'form':<44} {'us':>8} {'Glookups/s':>11}",
+           f"{'one call per table, eager':<44} {m['per_table_eager_us']:>8.1f} "
+           f"{g(m['per_table_eager_us']):>11.2f}",
+           f"{'one call per table, HIP graph':<44} {m['per_table_graph_us']:>8.1f} "
+           f"{g(m['per_table_graph_us']):>11.2f}",
+           f"{'plan, tuned shape, eager':<44} {m['plan_eager_us']:>8.1f} {g(m['plan_eager_us']):>11.2f}",
+           f"{'plan, tuned shape, HIP graph (one replay)':<44} {m['plan_graph_us']:>8.1f} "
+           f"{g(m['plan_graph_us']):>11.2f}",
+           f"{'plan, tuned shape, HIP graph (replays queued)':<44} {m['plan_graph_batched_us']:>8.1f} "
+           f"{g(m['plan_graph_batched_us']):>11.2f}",
+           f"plan at its first shape {m['plan_default_shape']}: {m['plan_default_us']:.1f} us",
+           f"tuned shape: {m['plan_tuned_shape']}",
+           f"{'plan, tables with timers, tuned shape':<44} {m['plan_timed_us']:>8.1f} "
+           f"{g(m['plan_timed_us']):>11.2f}",
+           f"{'plan, tables with timers, refreshing':<44} {m['plan_timed_refresh_us']:>8.1f} "
+           f"{g(m['plan_timed_refresh_us']):>11.2f}",
+           f"plan algorithmic bytes (64-byte lines) {m['algorithmic_bytes'] / 1e6:.1f} MB -> "
+           f"{m['algorithmic_bytes'] / (m['plan_eager_us'] * 1e-6) / 1e9:.0f} GB/s = "
+           f"{m['plan_frac_hbm_peak']:.3f} of 8 TB/s; in the device layout's 128-byte lines "
+           f"{m['device_layout_bytes'] / 1e6:.1f} MB = {m['plan_frac_128B_granule']:.3f}",
+           "# fastest shape per (lanes per lookup, lookups per lane, schedule 0 static / 1 dynamic):"]
+    best = m["plan_tune_best_of"]
+    items = best.items() if isinstance(best, dict) else best
+    for k, v in sorted(items, key=lambda kv: kv[1]["us"]):
+        out.append(f"#   {k}: {v['us']:.1f} us  block {v['block']} blocks/CU {v['blocks_per_cu']} "
+                   f"passes/item {v['passes_per_item']}")
+    with open(os.path.join(ROOT, "profiles", "plan_1024_tables_batching.txt"), "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def summarize_serve_timers(path):
     """Writes profiles/serve_b24_load0.85_zipf1.1_timers.txt from the JSON
     line of `python3 bench.py --serve 50000 --serve-timers` saved at
@@ -1478,6 +1526,9 @@ def main():
         return
     if args.summarize_serve_timers:
         summarize_serve_timers(args.summarize_serve_timers)
+        return
+    if args.summarize_many_tables:
+        summarize_many_tables(args.summarize_many_tables)
         return
     if args.summarize_insert_workload:
         summarize_insert_workload(args.summarize_insert_workload)
