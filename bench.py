@@ -1438,7 +1438,7 @@ def summarize_serve_timers(path):
            "# bursts log-uniform in [1, 2048] ops: 0.9 n lookups (Zipf s=1.1 over the universe), 0.1 n inserts of",
            "# new flows, 0.05 n deletes of expired flows (stored keys outside the universe); "
            f"{rec['bursts_per_run']:,} bursts per run;",
-           f"# admission budget {rec['budget_ops']} ops per kind; loop grid {rec['grid_blocks']} blocks x 256 threads;",
+           f"# admission budget {rec['budget_ops']} ops per kind; loop grid {rec['grid_blocks']} blocks x 512 threads;",
            "# every lookup, insert status and delete result of every run checked against the ground truth",
            "# command (repository root): python3 bench.py --serve 50000 --serve-timers",
            "# latency = host-observed completion - arrival; us/round = the loop's own clock per phase",
@@ -1476,12 +1476,12 @@ def summarize_serve(path, trace_dir=None, counter_dir=None):
            "# bursts log-uniform in [1, 2048] ops: 0.9 n lookups (Zipf s=1.1 over the universe), 0.1 n inserts of",
            "# new flows, 0.05 n deletes of expired flows (stored keys outside the universe); "
            f"{rec['bursts_per_run']:,} bursts per run;",
-           f"# admission budget {rec['budget_ops']} ops per kind; loop grid {rec['grid_blocks']} blocks x 256 threads;",
+           f"# admission budget {rec['budget_ops']} ops per kind; loop grid {rec['grid_blocks']} blocks x 512 threads;",
            "# every lookup, insert status and delete result of every run checked against the ground truth",
            "# command (repository root): python3 bench.py --serve 50000",
            "# a round's updates are spread over every wavefront (lane 0 of each, then lane 1, ...); an insert",
            "#   whose primary is full searches one- and two-step displacements with all candidates' loads at once;",
-           "#   lookups run 4, 2 or 1 per lane per pass in registers (the loop keeps one wavefront per SIMD);",
+           "#   lookups run 4, 2 or 1 per lane per pass in registers (the loop keeps two wavefronts per SIMD);",
            "#   grid barriers: relaxed arrivals after a wait, one system-scope release per block per round",
            "# latency = host-observed completion - arrival; us/round = the loop's own clock per phase (insert:",
            "#   inserts, or inserts and deletes side by side in rounds with few updates; delete: deletes after)",

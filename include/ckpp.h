@@ -495,8 +495,9 @@ typedef struct {
     uint64_t budget;        /* ops of one kind in flight at most (<= capacity) */
     uint32_t mode;          /* lookup mode, CKPP_LOOKUP_* (DEFAULT: Cuckoo++,
                                both buckets on a plain table) */
-    uint32_t blocks_per_cu; /* persistent grid: 1..4 blocks of 256 threads
-                               per compute unit, all co-resident */
+    uint32_t blocks_per_cu; /* persistent grid: 1..4 blocks of 512 threads
+                               per compute unit, capped at the number that
+                               can be co-resident (one on gfx950) */
     uint32_t idle_ms;       /* 1..60000 */
     uint32_t ttl;           /* table without timers: 0.  Table with timers:
                                the lifetime of entries, 1..1023 time units

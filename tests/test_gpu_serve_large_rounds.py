@@ -1,9 +1,9 @@
 """Serving rounds of every size class of the lookup phase, against the
 oracle, bit-exact: the phase runs 4, 2 or 1 lookups per lane per pass in
 registers, the most that every lane of the loop's grid has (on a 256-block
-grid of 65 536 lanes: 4 from 262 144 lookups in a round, 2 from 131 072).
-Bursts of 600 013, 300 007, 150 001 and 70 001 lookups (several passes, or
-one, and a ragged last one in each class), half of them of
+grid of 512-thread blocks, 131 072 lanes: 4 from 524 288 lookups in a round,
+2 from 262 144).  Bursts of 600 013, 300 007, 150 001 and 70 001 lookups
+(each size class, with a ragged last pass), half of them of
 stored keys, half fresh, the first with inserts and deletes in the same
 round, on a table without timers in the Cuckoo++, optimistic and
 pessimistic modes; and a 300 007-lookup burst on a table with timers whose
