@@ -1339,8 +1339,10 @@ INSERT_WORKLOAD_HISTORY = [
     "#   agent-scope acquire/release fences around each critical section (an L2 invalidate and an L2",
     "#   write-back per lock cycle): 170.6 ms = 747.2 M/s, band 0.05: 1026, band 0.90:",
     "#   317, delete 1139 M/s, re-insert 547 M/s",
-    "#   two-level lookahead over every candidate at once (104 loads; previous record): 99.4 ms =",
+    "#   two-level lookahead over every candidate at once (104 loads): 99.4 ms =",
     "#   1282.2 M/s, band 0.85: 792.5, band 0.90: 510.5, re-insert 941.6 M/s",
+    "#   one candidate at a time, walks for paths blocked by another lane's lock (previous record):",
+    "#   92.8 ms = 1373.9 M/s, band 0.85: 937.1, band 0.90: 633.5, re-insert 1115.6 M/s",
 ]
 
 
@@ -1354,8 +1356,9 @@ def summarize_insert_workload(path):
            "# Per-batch times from HIP events; delete/re-insert times wall-clock around the batch loops.",
            "# cuckoo paths: up to two displacements done inside the locked DIRECT step when the primary's",
            "#   entries (one level, else two levels of lookahead, one candidate at a time) reach a free",
-           "#   slot; else a random walk with one step of lookahead, whose path (up to 8 displacements)",
-           "#   is applied in one critical section; the rare paths are compiled out of line",
+           "#   slot (a path blocked by another lane's lock is retried, up to 4 times); else a random walk",
+           "#   with one step of lookahead, whose path (up to 8 displacements) is applied in one critical",
+           "#   section; the rare paths are compiled out of line",
            "# path scratch: a buffer of the table's own (up to 1/32 of the table's memory, here all 2^16 lanes",
            "#   of a batch), allocated once; the stream-ordered pool only beyond that",
            "# locks: table words under a lock read and written with device-coherent (agent-scope) accesses,",

@@ -247,6 +247,11 @@ __device__ __forceinline__ uint64_t load_relaxed(const uint8_t *p) {
 // slow the direct path every key takes (measured: 2^24 build to load 0.95 in
 // 211 ms inlined, 181 ms out of line).
 constexpr int kBusy = -2;    // a lock was taken by another lane: retry
+// DIRECT found a displacement path, but a bucket beyond the pair was locked
+// by another lane or changed before it was locked: retry DIRECT (at most
+// kDisplaceRetries times per key, then the walk).
+constexpr int kDisplaceBusy = -3;
+constexpr uint32_t kDisplaceRetries = 4;
 constexpr int kNeedPath = -1;
 
 // Busy slots of bucket b whose entries have expired at `now`.
@@ -400,9 +405,12 @@ __device__ __forceinline__ void unlock_extra(uint8_t *bk, uint32_t b, const KeyF
 // then cost one critical section instead of a walk, one locked move per
 // displacement and a second DIRECT step.  mp: p's meta word read under the
 // lock.  Returns true when the key was placed; false, with nothing changed,
-// when no such path exists or a lock is held by another lane (the caller
-// falls back to the walk).
-__device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32_t log2b, uint64_t seed, bool plain,
+// when no such path exists (the caller falls back to the walk); kBusy,
+// with nothing changed, when a bucket beyond the pair is locked by another
+// lane or its state changed before the lock (the caller may retry DIRECT:
+// another lane's move is brief, and a retry costs a few round trips where
+// the walk costs tens).
+__device__ __attribute__((noinline)) int displace_and_place(uint8_t *bk, uint32_t log2b, uint64_t seed, bool plain,
                                    const KeyFields &f, uint64_t h, uint4 key, uint64_t word,
                                    uint32_t mp) {
   const uint32_t cand = movable(mp, plain), sec = meta_sec(mp), p = f.p;
@@ -460,7 +468,7 @@ __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32
         }
       }
     }
-    if (t == kSlots) return false;
+    if (t == kSlots) return 0;
   }
   // lock the buckets beyond p and a (both compare-and-swaps issued
   // together: a failure here is not retried but falls back to the walk, so
@@ -470,7 +478,7 @@ __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32
   if (!(ok1 && ok2)) {
     if (ok1) unlock_extra(bk, y1, f);
     if (ok2 && y2 != kNoBucket) unlock_extra(bk, y2, f);
-    return false;
+    return kBusy;
   }
   section_begin();
   bool done = false;
@@ -501,13 +509,13 @@ __device__ __attribute__((noinline)) bool displace_and_place(uint8_t *bk, uint32
   section_end();
   if (y2 != kNoBucket) unlock_extra(bk, y2, f);
   unlock_extra(bk, y1, f);
-  return done;
+  return done ? 1 : kBusy;
 }
 
 // DIRECT step of a table with timers; word = value | expiry << 48.
 __device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const KeyFields &f,
                                    uint64_t h, uint32_t log2b, uint64_t seed, bool plain,
-                                   uint32_t now) {
+                                   uint32_t now, bool retry_displace) {
   if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   const Head ha = read_head(bk, f.a);
@@ -562,17 +570,22 @@ __device__ int insert_direct_timed(uint8_t *bk, uint4 key, uint64_t word, const 
     if (r == CKPP_INSERTED) {
       *meta_ptr(bk, f.p) = P.meta[0];
       *meta_ptr(bk, f.a) = P.meta[1];
-    } else if (r == kNeedPath &&
-               displace_and_place(bk, log2b, seed, plain, f, h, key, word, hp.q1.z)) {
-      r = CKPP_INSERTED;
+    } else if (r == kNeedPath) {
+      const int d = displace_and_place(bk, log2b, seed, plain, f, h, key, word, hp.q1.z);
+      if (d == 1) r = CKPP_INSERTED;
+      else if (d == kBusy && retry_displace) r = kDisplaceBusy;
     }
   }
   unlock_two(bk, f.p, f.a);
   return r;
 }
 
+// DIRECT step of a table without timers.  retry_displace: a displacement
+// path found but blocked by another lane's lock returns kDisplaceBusy (the
+// caller retries DIRECT) rather than kNeedPath.
 __device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value, const KeyFields &f,
-                             uint64_t h, uint32_t log2b, uint64_t seed, bool plain) {
+                             uint64_t h, uint32_t log2b, uint64_t seed, bool plain,
+                             bool retry_displace) {
   if (!lock_two(bk, f.p, f.a)) return kBusy;
   const Head hp = read_head(bk, f.p);
   const Head ha = read_head(bk, f.a);
@@ -603,10 +616,9 @@ __device__ int insert_direct(uint8_t *bk, uint4 key, uint64_t value, const KeyFi
         *meta_ptr(bk, f.p) = make_meta(meta_moved(mp) + 1u, busy_p, meta_sec(mp));
       }
       r = CKPP_INSERTED;
-    } else if (displace_and_place(bk, log2b, seed, plain, f, h, key, value, mp)) {
-      r = CKPP_INSERTED;
     } else {
-      r = kNeedPath;
+      const int d = displace_and_place(bk, log2b, seed, plain, f, h, key, value, mp);
+      r = d == 1 ? CKPP_INSERTED : (d == kBusy && retry_displace) ? kDisplaceBusy : kNeedPath;
     }
   }
   unlock_two(bk, f.p, f.a);
@@ -846,7 +858,7 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
   const KeyFields f = key_fields(h, log2b);
   enum { DIRECT, WALK, MOVE };
   int state = DIRECT, result = -1;
-  uint32_t len = 0, next = 0, last = 0, walks = 0, iters = 0;
+  uint32_t len = 0, next = 0, last = 0, walks = 0, iters = 0, dretries = 0;
   bool spun = false;
   while (result < 0) {
     if (++iters > spin_limit) {
@@ -855,12 +867,16 @@ __device__ InsertOutcome insert_one(uint8_t *bk, uint4 key, uint64_t value, uint
       break;
     }
     if (state == DIRECT) {
-      const int r = TIMED ? insert_direct_timed(bk, key, word, f, h, log2b, seed, plain, now)
-                          : insert_direct(bk, key, value, f, h, log2b, seed, plain);
+      const bool retry_displace = dretries < kDisplaceRetries;
+      const int r = TIMED ? insert_direct_timed(bk, key, word, f, h, log2b, seed, plain, now,
+                                                retry_displace)
+                          : insert_direct(bk, key, value, f, h, log2b, seed, plain, retry_displace);
       if (r >= 0)
         result = r;
       else if (r == kNeedPath)
         state = WALK;
+      else if (r == kDisplaceBusy)
+        ++dretries;  // DIRECT again
     } else if (state == WALK) {
       if (walks >= kMaxWalks) {
         result = CKPP_FAILED;
