@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency", action="store_true",
                     help="latency of one dependent access of each kind the updates make")
+    ap.add_argument("--burst-latency", action="store_true",
+                    help="only the burst-latency leg (plain calls and the serving loop)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run only a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--sweep", action="store_true",
@@ -427,9 +429,11 @@ def burst_latency(dev, keys, B=24, load=0.85, nbursts=10_000, neg_rate=0.5, warm
         lat.append(time.perf_counter() - t0)
     fo = f.cpu().numpy()
     vo = v.cpu().numpy().view(np.uint64)
+    want_f = (~isneg).astype(np.uint8)
     want_v = np.where(isneg, 0, idx).astype(np.uint64)  # values = insertion index
-    if not (np.array_equal(fo, (~isneg).astype(np.uint8)) and np.array_equal(vo, want_v)):
+    if not (np.array_equal(fo, want_f) and np.array_equal(vo, want_v)):
         raise RuntimeError("burst lookups returned a wrong answer")
+    loop = loop_burst_latency(t, dmix, sizes, warm, dev, want_f, want_v)
     t.close()
     lat = np.array(lat[warm:]) * 1e6
     counted = int(offs[-1] - offs[warm])
@@ -438,7 +442,41 @@ def burst_latency(dev, keys, B=24, load=0.85, nbursts=10_000, neg_rate=0.5, warm
             "sizes": "log-uniform [1, 2048]", "mean_burst": counted / len(lat),
             "log2_buckets": B, "load": load, "neg_rate": neg_rate,
             "realized_neg_rate": float(isneg[int(offs[warm]):].mean()),
-            "form": "one synchronous ckpp_lookup_batch per burst (submit -> completion)"}
+            "form": "one synchronous ckpp_lookup_batch per burst (submit -> completion)",
+            "serving_loop": loop}
+
+
+def loop_burst_latency(t, dmix, sizes, warm, dev, want_f, want_v, gap_us=100.0):
+    """The burst-latency bursts through the serving loop, one at a time:
+    the lookups are staged in the loop's ring first, then the native replay
+    submits burst i at time i * gap_us (far apart enough that each burst is
+    complete before the next arrives) and notes when the loop reports it
+    complete; latency = completion - arrival on the host clock (a submit is
+    a store to pinned host memory, a completion a load from it, so no HIP
+    call is on the path).  Every answer is checked."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Server
+    total = int(sizes.sum())
+    srv = Server(t, capacity=1 << (total - 1).bit_length(), budget=1 << 20, idle_ms=2000)
+    pos = srv.status()["lookup_tail"]
+    srv.put("lookup", pos, dmix)
+    n = len(sizes)
+    zero = np.zeros(n, np.uint32)
+    arrival = np.arange(n, dtype=np.float64) * (gap_us * 1e-6)
+    _, done = srv.replay(sizes.astype(np.uint32), zero, zero, arrival, 60.0)
+    f, v = srv.get("lookup", pos, total)
+    torch.cuda.current_stream(dev).synchronize()
+    if not (np.array_equal(f.cpu().numpy(), want_f)
+            and np.array_equal(v.cpu().numpy().view(np.uint64), want_v)):
+        raise RuntimeError("burst lookups through the serving loop returned a wrong answer")
+    srv.close()
+    lat = (done - arrival)[warm:] * 1e6
+    late = int((lat > gap_us).sum())
+    return {"p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+            "mean_us": float(lat.mean()), "bursts": int(len(lat)), "gap_us": gap_us,
+            "bursts_over_gap": late,
+            "form": "the same bursts submitted one at a time to the resident serving loop "
+                    "(arrival -> completion seen in host memory)"}
 
 
 def host_cpu() -> dict:
@@ -1557,6 +1595,12 @@ def main():
         return
     if args.latency:
         print(json.dumps({"latency_ns": latency_probe(dev)}), flush=True)
+        return
+    if args.burst_latency:
+        # the default run's key stream (its table's keys at load 0.9)
+        keys = W.distinct_five_tuples(W.keys_at_load(args.log2_buckets, args.load), 1)
+        print(json.dumps({"burst_latency": burst_latency(dev, keys, args.log2_buckets)}),
+              flush=True)
         return
     if args.serve:
         print(json.dumps({"serve": serve_bench(dev, args.serve, B=args.serve_log2_buckets,
