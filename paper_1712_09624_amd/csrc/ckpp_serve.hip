@@ -214,11 +214,15 @@ __device__ __forceinline__ void set_abort(ServeDev *d) {
 }
 
 // Non-leader blocks, thread 0: waits for the leader's release of `epoch`.
+// Each poll reads `gen` and `abort` in one round trip.
 __device__ bool wait_release(const ServeArgs &a, uint32_t epoch, uint64_t limit_ticks) {
   ServeDev *d = a.dev;
   const uint64_t t0 = now_ticks();
-  for (uint64_t it = 0; (int32_t)(poll32(&d->gen) - epoch) < 0; ++it) {
-    if (poll32(&d->abort)) return false;
+  for (uint64_t it = 0;; ++it) {
+    const uint32_t g = poll32(&d->gen);
+    const uint32_t ab = poll32(&d->abort);
+    if ((int32_t)(g - epoch) >= 0) break;
+    if (ab) return false;
     if (now_ticks() - t0 > limit_ticks || it > kMaxSpins) {
       set_abort(d);
       return false;
@@ -230,17 +234,31 @@ __device__ bool wait_release(const ServeArgs &a, uint32_t epoch, uint64_t limit_
 }
 
 // Leader wave (all 64 lanes of wave 0 of block 0): waits until every block
-// has stored `epoch`.  Uniform result.
+// has stored `epoch`.  Uniform result.  Each poll reads a lane's flags (four
+// blocks a lane; indexes past the grid read the last block's flag again)
+// and `abort` in one round trip: loads under a short-circuit `&&` would be
+// issued one after another.
+constexpr uint32_t kFlagsPerLane = 4;
 __device__ bool gather(const ServeArgs &a, uint32_t epoch, uint64_t limit_ticks) {
   ServeDev *d = a.dev;
   const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t last = gridDim.x - 1u;
   const uint64_t t0 = now_ticks();
   for (uint64_t it = 0;; ++it) {
+    const uint32_t ab = poll32(&d->abort);
     bool mine = true;
-    for (uint32_t b = lane; b < gridDim.x; b += 64u)
-      mine = mine && (int32_t)(poll32(a.arrive + (uint64_t)b * kFlagStride) - epoch) >= 0;
+    for (uint32_t b0 = 0; b0 < gridDim.x; b0 += 64u * kFlagsPerLane) {
+      uint32_t f[kFlagsPerLane];
+#pragma unroll
+      for (uint32_t k = 0; k < kFlagsPerLane; ++k) {
+        const uint32_t b = b0 + lane + 64u * k;
+        f[k] = poll32(a.arrive + (uint64_t)(b < last ? b : last) * kFlagStride);
+      }
+#pragma unroll
+      for (uint32_t k = 0; k < kFlagsPerLane; ++k) mine &= (int32_t)(f[k] - epoch) >= 0;
+    }
     if (__builtin_amdgcn_ballot_w64(!mine) == 0ull) break;
-    const bool stop = poll32(&d->abort) != 0u || now_ticks() - t0 > limit_ticks || it > kMaxSpins;
+    const bool stop = ab != 0u || now_ticks() - t0 > limit_ticks || it > kMaxSpins;
     if (__builtin_amdgcn_readfirstlane((int)stop)) {
       if (lane == 0u) set_abort(d);
       return false;
@@ -269,9 +287,11 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   const uint64_t t0 = now_ticks();
   uint64_t s = 0;
   for (uint64_t it = 0;; ++it) {
+    // both host words in one round trip
     s = poll_sys64(&h->submitted);
+    const uint32_t stop = poll_sys32(&h->stop);
     if (s > d->done) break;
-    if (poll_sys32(&h->stop)) return kCmdExit;
+    if (stop) return kCmdExit;
     if (now_ticks() - t0 > a.idle_ticks || it > kMaxSpins) {
       // tell the host the loop is leaving, then look once more: a burst
       // submitted before the host saw EXITING is still taken
@@ -574,24 +594,32 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
         }
       }
     } else if (threadIdx.x == 0) {
-      s_cmd = wait_release(a, epoch, a.idle_ticks + kPhaseMs * kTicksPerMs)
-                  ? __hip_atomic_load(&d->cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                  : kCmdExit;
+      // released: the command itself is read below
+      s_cmd = wait_release(a, epoch, a.idle_ticks + kPhaseMs * kTicksPerMs) ? kCmdRun : kCmdExit;
     }
     if (threadIdx.x == 0) {
-      if (poll32(&d->abort)) s_cmd = kCmdExit;
+      // the command, the abort flag and the round's ranges and time, which
+      // the leader wrote before its release, in one round trip
+      // (device-coherent loads, issued after the release was seen)
+      const uint32_t cmd = __hip_atomic_load(&d->cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t ab = poll32(&d->abort);
+      auto get = [](const uint64_t *p) {
+        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      };
+      const uint64_t r[6] = {get(&d->lk0), get(&d->lk1), get(&d->in0),
+                             get(&d->in1), get(&d->de0), get(&d->de1)};
+      const uint32_t tnow = TIMED ? poll32(&d->now) : 0u;
+      const uint32_t tscan = TIMED ? poll32(&d->scan) : 0u;
       // the round's ring entries were written by the host or a copy engine
       // while the kernel ran: drop any cached copy of them
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      if (ab) s_cmd = kCmdExit;
+      else if (s_cmd != kCmdExit) s_cmd = cmd;
       if (s_cmd == kCmdRun || s_cmd == kCmdDeferred) {
-        s_range[0] = d->lk0;
-        s_range[1] = d->lk1;
-        s_range[2] = d->in0;
-        s_range[3] = d->in1;
-        s_range[4] = d->de0;
-        s_range[5] = d->de1;
-        s_range[6] = TIMED ? d->now : 0u;
-        s_range[7] = TIMED && s_cmd == kCmdRun ? d->scan : 0u;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s_range[k] = r[k];
+        s_range[6] = tnow;
+        s_range[7] = s_cmd == kCmdRun ? tscan : 0u;
       }
     }
     __syncthreads();
