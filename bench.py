@@ -463,7 +463,12 @@ def loop_burst_latency(t, dmix, sizes, warm, dev, want_f, want_v, gap_us=100.0):
     n = len(sizes)
     zero = np.zeros(n, np.uint32)
     arrival = np.arange(n, dtype=np.float64) * (gap_us * 1e-6)
+    s_before = srv.status()
     _, done = srv.replay(sizes.astype(np.uint32), zero, zero, arrival, 60.0)
+    s_after = srv.status()
+    rounds = max(1, s_after["rounds"] - s_before["rounds"])
+    phase_us = {k[:-3]: (s_after[k] - s_before[k]) / 1e3 / rounds
+                for k in ("lookup_ns", "boundary_ns")}
     f, v = srv.get("lookup", pos, total)
     torch.cuda.current_stream(dev).synchronize()
     if not (np.array_equal(f.cpu().numpy(), want_f)
@@ -474,7 +479,8 @@ def loop_burst_latency(t, dmix, sizes, warm, dev, want_f, want_v, gap_us=100.0):
     late = int((lat > gap_us).sum())
     return {"p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
             "mean_us": float(lat.mean()), "bursts": int(len(lat)), "gap_us": gap_us,
-            "bursts_over_gap": late,
+            "bursts_over_gap": late, "rounds": s_after["rounds"] - s_before["rounds"],
+            "us_per_round": phase_us,
             "form": "the same bursts submitted one at a time to the resident serving loop "
                     "(arrival -> completion seen in host memory)"}
 
