@@ -49,6 +49,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstddef>
 #include <new>
 #include <stdint.h>
 #include <string.h>
@@ -94,15 +95,25 @@ constexpr uint32_t kScanUnroll = 16;
 // with the anti-revival scan (bit 16), and the number of time changes before
 // it (bits 24..63; rounds never span two of them).
 constexpr uint32_t kScanBit = 16, kTimeIndexShift = 24;
+// latest[k] of the last staged burst b: the low 48 bits of its tail of kind
+// k, and in bits 48..63 the tag kTagValid | (b mod 2^15).  A word is written
+// whole, but the three may be read at different moments: the loop uses them
+// only when all three carry the same tag.
+constexpr uint64_t kLow48 = (1ull << 48) - 1u;
+constexpr uint32_t kTagValid = 0x8000u, kTagMask = 0x7fffu;
 struct ServeHost {
   uint64_t submitted;  // host -> loop: bursts submitted
   uint64_t completed;  // loop -> host: bursts whose results are visible
   uint64_t rounds;     // loop -> host
   uint32_t stop;       // host -> loop: exit once idle
   uint32_t state;      // loop -> host: CKPP_SERVER_*
+  uint64_t latest[4];  // host -> loop: the last staged burst's tagged tails
   // after burst k, at k % kQueue: lookup, insert, delete tails; time word
   uint64_t tails[kQueue][4];
 };
+static_assert(offsetof(ServeHost, latest) + sizeof(uint64_t[4]) <= 64,
+              "the poll's words share one 64-byte line");
+static_assert(kQueue <= kTagMask + 1u, "a tag names one burst of those in flight");
 
 // Device memory of the loop (survives relaunches).
 struct ServeDev {
@@ -274,6 +285,17 @@ __device__ __forceinline__ void release_epoch(ServeDev *d, uint32_t epoch) {
   __hip_atomic_store(&d->gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The burst that the last staged burst's tagged tails (w) name, if all
+// three words carry the same tag and it is a burst from `done` on (fewer
+// than kQueue are in flight); else ~0.
+__device__ __forceinline__ uint64_t latest_burst(const uint64_t (&w)[3], uint64_t done) {
+  const uint32_t tag = (uint32_t)(w[0] >> 48);
+  if (!(tag & kTagValid) || (uint32_t)(w[1] >> 48) != tag || (uint32_t)(w[2] >> 48) != tag)
+    return ~0ull;
+  const uint64_t ahead = (tag - (uint32_t)done) & kTagMask;
+  return ahead < kQueue ? done + ahead : ~0ull;
+}
+
 // Leader at a round boundary (every block has arrived): publish the round
 // that just ended, wait for work, set the next round.  Returns the command.
 __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
@@ -285,11 +307,25 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
     sys_store64(&h->completed, d->done);
   }
   const uint64_t t0 = now_ticks();
-  uint64_t s = 0;
+  uint64_t s = 0, w[3];
+  bool have_tails = false;
   for (uint64_t it = 0;; ++it) {
-    // both host words in one round trip
+    // one round trip to host memory: the submitted count, the stop flag and
+    // the last staged burst's tagged tails (the line all four share)
     s = poll_sys64(&h->submitted);
     const uint32_t stop = poll_sys32(&h->stop);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) w[k] = poll_sys64(&h->latest[k]);
+    if (!a.timed) {
+      // the round takes every burst up to the last staged one, whose tails
+      // came with the poll (a staged burst's operations are in the rings)
+      const uint64_t b = latest_burst(w, d->done);
+      if (b != ~0ull) {
+        s = b + 1u;
+        have_tails = true;
+        break;
+      }
+    }
     if (s > d->done) break;
     if (stop) return kCmdExit;
     if (now_ticks() - t0 > a.idle_ticks || it > kMaxSpins) {
@@ -307,6 +343,18 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
     __builtin_amdgcn_s_sleep(4);
   }
   d->t_wait += now_ticks() - t0;
+  if (have_tails) {
+    // full tails from their low 48 bits: a round's operations of a kind
+    // number far fewer than 2^48
+    d->lk0 = d->lk1;
+    d->in0 = d->in1;
+    d->de0 = d->de1;
+    d->lk1 += (w[0] - d->lk1) & kLow48;
+    d->in1 += (w[1] - d->in1) & kLow48;
+    d->de1 += (w[2] - d->de1) & kLow48;
+    d->done = s;
+    return kCmdRun;
+  }
   // the tails the host wrote before it published `s`
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
   if (a.timed) {
@@ -613,8 +661,9 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
       // the round's ring entries were written by the host or a copy engine
       // while the kernel ran: drop any cached copy of them
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+      // (the leader's own block keeps the command it decided)
       if (ab) s_cmd = kCmdExit;
-      else if (s_cmd != kCmdExit) s_cmd = cmd;
+      else if (s_cmd != kCmdExit && blockIdx.x != 0u) s_cmd = cmd;
       if (s_cmd == kCmdRun || s_cmd == kCmdDeferred) {
 #pragma unroll
         for (int k = 0; k < 6; ++k) s_range[k] = r[k];
@@ -1013,6 +1062,11 @@ int stage_burst(ckpp_server *s, uint64_t done, uint32_t n_lookup, uint32_t n_ins
   const uint64_t tw = (s->time_index << ckpp::kTimeIndexShift) |
                       ((uint64_t)(scan ? 1u : 0u) << ckpp::kScanBit) | s->now;
   host_u64(&slot[3])->store(tw, std::memory_order_relaxed);
+  // the burst's ops are in the rings (put before it was staged): a loop
+  // that sees these words may take it before `submitted` is published
+  const uint64_t tag = (uint64_t)(ckpp::kTagValid | (uint32_t)(b & ckpp::kTagMask)) << 48;
+  for (int k = 0; k < 3; ++k)
+    host_u64(&s->host->latest[k])->store((nt[k] & ckpp::kLow48) | tag, std::memory_order_release);
   s->submitted = b + 1;
   return CKPP_OK;
 }

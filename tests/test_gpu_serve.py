@@ -215,6 +215,43 @@ def test_server_replay_open_loop():
     t.close()
 
 
+def test_server_many_small_bursts_past_the_tag_wrap():
+    """40,000 small bursts, more than the 2^15 burst numbers the tags of the
+    loop's latest-tails words tell apart, replayed 5 us apart so that rounds
+    take one or a few bursts each: every lookup, insert status and delete
+    result equals the oracle's, applied burst by burst."""
+    import torch
+    from paper_1712_09624_amd.ckpp import Server
+    ref, t, keys = oracle_and_table(16, 0.5, 9)
+    nb = 40000
+    bursts = make_bursts(keys, nb, 10, max_lookup=3, max_insert=2, max_delete=1)
+    want = oracle_run(ref, bursts)
+    cat = [np.concatenate([b[k] for b in bursts]) for k in range(4)]
+    counts = np.array([[len(b[0]), len(b[1]), len(b[3])] for b in bursts], dtype=np.uint32)
+    say(f"server replay of {nb} small bursts, 5 us apart")
+    with Server(t, capacity=1 << 17, idle_ms=2000) as srv:
+        st0 = srv.status()
+        pos = (st0["lookup_tail"], st0["insert_tail"], st0["delete_tail"])
+        srv.put("lookup", pos[0], to_dev(cat[0]))
+        srv.put("insert", pos[1], to_dev(cat[1]), vals_dev(cat[2]))
+        srv.put("delete", pos[2], to_dev(cat[3]))
+        arrival = np.arange(nb) * 5e-6
+        srv.replay(counts[:, 0], counts[:, 1], counts[:, 2], arrival, 60.0)
+        f, v = srv.get("lookup", pos[0], len(cat[0]))
+        st = srv.get("insert", pos[1], len(cat[1]))
+        df = srv.get("delete", pos[2], len(cat[3]))
+        torch.cuda.current_stream().synchronize()
+        status = srv.status()
+    assert status["completed"] == nb and status["submitted"] == nb
+    assert status["rounds"] < nb
+    got = (u8(f), u64(v), u8(st), u8(df))
+    for g, k, name in zip(got, range(4), ("lookup found", "lookup values", "insert status",
+                                          "delete found")):
+        w = np.concatenate([x[k] for x in want])
+        assert np.array_equal(g, w), f"{name} differs"
+    t.close()
+
+
 def test_server_insert_and_delete_of_one_key_in_a_round():
     """A burst that inserts keys and deletes some of them: the deletes wait
     for the round's inserts (they are deferred past them), report found, and
