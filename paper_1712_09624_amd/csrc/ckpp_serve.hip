@@ -50,6 +50,7 @@
 #include <atomic>
 #include <chrono>
 #include <cstddef>
+#include <emmintrin.h>
 #include <new>
 #include <stdint.h>
 #include <string.h>
@@ -95,11 +96,15 @@ constexpr uint32_t kScanUnroll = 16;
 // with the anti-revival scan (bit 16), and the number of time changes before
 // it (bits 24..63; rounds never span two of them).
 constexpr uint32_t kScanBit = 16, kTimeIndexShift = 24;
-// latest[k] of the last staged burst b: the low 48 bits of its tail of kind
-// k, and in bits 48..63 the tag kTagValid | (b mod 2^15).  A word is written
-// whole, but the three may be read at different moments: the loop uses them
-// only when all three carry the same tag.
-constexpr uint64_t kLow48 = (1ull << 48) - 1u;
+// latest[] of the last staged burst b, in one 16-byte block that the host
+// writes with one store and the loop reads with one load: latest[0] holds
+// the low 48 bits of b's lookup tail, latest[1] the low 24 bits of its
+// insert tail (bits 24..47) and of its delete tail (bits 0..23); bits 48..63
+// of both hold the tag kTagValid | (b mod 2^15).  The loop uses a block only
+// when both tags agree, and only on servers whose budget is under 2^24 ops
+// of a kind, so that a round's tails follow from these bits.
+constexpr uint64_t kLow48 = (1ull << 48) - 1u, kLow24 = (1ull << 24) - 1u;
+constexpr uint64_t kFastTailsBudget = 1ull << 24;
 constexpr uint32_t kTagValid = 0x8000u, kTagMask = 0x7fffu;
 struct ServeHost {
   uint64_t submitted;  // host -> loop: bursts submitted
@@ -107,11 +112,11 @@ struct ServeHost {
   uint64_t rounds;     // loop -> host
   uint32_t stop;       // host -> loop: exit once idle
   uint32_t state;      // loop -> host: CKPP_SERVER_*
-  uint64_t latest[4];  // host -> loop: the last staged burst's tagged tails
+  alignas(16) uint64_t latest[2];  // host -> loop: the last staged burst's tagged tails
   // after burst k, at k % kQueue: lookup, insert, delete tails; time word
   uint64_t tails[kQueue][4];
 };
-static_assert(offsetof(ServeHost, latest) + sizeof(uint64_t[4]) <= 64,
+static_assert(offsetof(ServeHost, latest) + sizeof(uint64_t[2]) <= 64,
               "the poll's words share one 64-byte line");
 static_assert(kQueue <= kTagMask + 1u, "a tag names one burst of those in flight");
 
@@ -163,6 +168,7 @@ struct ServeArgs {
   uint32_t *set_tag;  // entry in use by the round whose tag it holds
   uint64_t set_mask;  // entries - 1
   uint32_t timed;     // the table has timers
+  uint32_t fast_tails;  // no timers and a budget under 2^24: tails come with the poll
   uint32_t ttl;       // entry lifetime in time units (timers)
   uint32_t refresh;   // lookups that find an entry set its expiration time
   uint64_t nb;        // buckets
@@ -285,13 +291,13 @@ __device__ __forceinline__ void release_epoch(ServeDev *d, uint32_t epoch) {
   __hip_atomic_store(&d->gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// The burst that the last staged burst's tagged tails (w) name, if all
-// three words carry the same tag and it is a burst from `done` on (fewer
-// than kQueue are in flight); else ~0.
-__device__ __forceinline__ uint64_t latest_burst(const uint64_t (&w)[3], uint64_t done) {
-  const uint32_t tag = (uint32_t)(w[0] >> 48);
-  if (!(tag & kTagValid) || (uint32_t)(w[1] >> 48) != tag || (uint32_t)(w[2] >> 48) != tag)
-    return ~0ull;
+// The burst that the last staged burst's tagged tails (w) name, if both
+// words carry the same tag and it is a burst from `done` on (fewer than
+// kQueue are in flight); else ~0.
+typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint64_t latest_burst(u64x2 w, uint64_t done) {
+  const uint32_t tag = (uint32_t)(w.x >> 48);
+  if (!(tag & kTagValid) || (uint32_t)(w.y >> 48) != tag) return ~0ull;
   const uint64_t ahead = (tag - (uint32_t)done) & kTagMask;
   return ahead < kQueue ? done + ahead : ~0ull;
 }
@@ -307,20 +313,23 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
     sys_store64(&h->completed, d->done);
   }
   const uint64_t t0 = now_ticks();
-  uint64_t s = 0, w[3];
+  uint64_t s = 0;
+  u64x2 w = {0ull, 0ull};
   bool have_tails = false;
   for (uint64_t it = 0;; ++it) {
     // one round trip to host memory: the submitted count, the stop flag and
-    // the last staged burst's tagged tails (the line all four share)
+    // the last staged burst's tagged tails (one line; the tails in one
+    // 16-byte load of uncached host memory, volatile so that every poll
+    // reads it)
     s = poll_sys64(&h->submitted);
     const uint32_t stop = poll_sys32(&h->stop);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) w[k] = poll_sys64(&h->latest[k]);
-    if (!a.timed) {
-      // the round takes every burst up to the last staged one, whose tails
-      // came with the poll (a staged burst's operations are in the rings)
+    if (a.fast_tails) w = *reinterpret_cast<const volatile u64x2 *>(h->latest);
+    if (a.fast_tails && s > d->done) {
+      // submitted work is waiting: the round takes the bursts up to the
+      // last staged one (the last submitted one or a later one whose
+      // operations are in the rings too), whose tails came with the poll
       const uint64_t b = latest_burst(w, d->done);
-      if (b != ~0ull) {
+      if (b != ~0ull && b + 1u >= s) {
         s = b + 1u;
         have_tails = true;
         break;
@@ -344,14 +353,14 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   }
   d->t_wait += now_ticks() - t0;
   if (have_tails) {
-    // full tails from their low 48 bits: a round's operations of a kind
-    // number far fewer than 2^48
+    // full tails from their low bits: a round's operations of a kind are
+    // in flight together, at most the budget, under 2^24
     d->lk0 = d->lk1;
     d->in0 = d->in1;
     d->de0 = d->de1;
-    d->lk1 += (w[0] - d->lk1) & kLow48;
-    d->in1 += (w[1] - d->in1) & kLow48;
-    d->de1 += (w[2] - d->de1) & kLow48;
+    d->lk1 += (w.x - d->lk1) & kLow48;
+    d->in1 += ((w.y >> 24) - d->in1) & kLow24;
+    d->de1 += (w.y - d->de1) & kLow24;
     d->done = s;
     return kCmdRun;
   }
@@ -939,6 +948,7 @@ int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_confi
   a.set_tag = s->set_tag;
   a.set_mask = set_entries - 1u;
   a.timed = timed ? 1u : 0u;
+  a.fast_tails = !timed && c.budget < ckpp::kFastTailsBudget ? 1u : 0u;
   a.ttl = timed ? ttl : 0u;
   a.refresh = timed && (c.ttl & CKPP_SERVER_REFRESH) ? 1u : 0u;
   a.nb = 1ull << t->log2_buckets;
@@ -1062,11 +1072,18 @@ int stage_burst(ckpp_server *s, uint64_t done, uint32_t n_lookup, uint32_t n_ins
   const uint64_t tw = (s->time_index << ckpp::kTimeIndexShift) |
                       ((uint64_t)(scan ? 1u : 0u) << ckpp::kScanBit) | s->now;
   host_u64(&slot[3])->store(tw, std::memory_order_relaxed);
-  // the burst's ops are in the rings (put before it was staged): a loop
-  // that sees these words may take it before `submitted` is published
-  const uint64_t tag = (uint64_t)(ckpp::kTagValid | (uint32_t)(b & ckpp::kTagMask)) << 48;
-  for (int k = 0; k < 3; ++k)
-    host_u64(&s->host->latest[k])->store((nt[k] & ckpp::kLow48) | tag, std::memory_order_release);
+  // (operations are put in the rings before their burst is staged; the loop
+  // takes a staged burst early only while submitted ones wait)
+  if (s->args.fast_tails) {
+    const uint64_t tag = (uint64_t)(ckpp::kTagValid | (uint32_t)(b & ckpp::kTagMask)) << 48;
+    const uint64_t w0 = tag | (nt[0] & ckpp::kLow48);
+    const uint64_t w1 = tag | (nt[1] & ckpp::kLow24) << 24 | (nt[2] & ckpp::kLow24);
+    // one aligned 16-byte store (single-copy atomic on x86-64 processors
+    // with AVX; the tags catch a torn read anyway), after the stores above
+    std::atomic_thread_fence(std::memory_order_release);
+    _mm_store_si128(reinterpret_cast<__m128i *>(s->host->latest),
+                    _mm_set_epi64x((long long)w1, (long long)w0));
+  }
   s->submitted = b + 1;
   return CKPP_OK;
 }
