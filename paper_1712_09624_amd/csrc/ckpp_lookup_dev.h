@@ -429,8 +429,10 @@ __device__ __forceinline__ void reg_match(const uint4 *tab, RegLooks<PER> &L, co
 
 // One pass of a wave over 64 * PER lookups, PER per lane (the lane's
 // key[j], a real lookup iff ok[j]); lookup j's answer goes to *found[j] /
-// *vals[j].  `pre` runs once the first heads are requested.
-template <uint32_t MODE, bool TIMED, uint32_t PER, class Pre>
+// *vals[j].  `pre` runs once the first heads are requested.  SYS: the
+// answers are written through to memory (system-scope stores), visible to
+// the host once the wave has waited for its stores.
+template <uint32_t MODE, bool TIMED, uint32_t PER, bool SYS = false, class Pre>
 __device__ __forceinline__ void reg_pass_to(const TableRef &T, const uint4 (&key)[PER],
                                             const bool (&ok)[PER], uint8_t *const (&found)[PER],
                                             uint64_t *const (&vals)[PER], Pre &&pre) {
@@ -505,8 +507,15 @@ __device__ __forceinline__ void reg_pass_to(const TableRef &T, const uint4 (&key
     if (!L.ok[j]) continue;
     if (TIMED && T.refresh && L.hit[j] && needs_refresh(T, L.val[j]))
       refresh_entry(T, L.hit_primary[j] ? L.f[j].p : L.f[j].a, L.slot[j]);
-    __builtin_nontemporal_store((uint8_t)(L.hit[j] ? 1 : 0), found[j]);
-    __builtin_nontemporal_store(L.hit[j] ? hit_value<TIMED>(L.val[j], T.now) : 0ull, vals[j]);
+    const uint8_t fj = L.hit[j] ? 1 : 0;
+    const uint64_t vj = L.hit[j] ? hit_value<TIMED>(L.val[j], T.now) : 0ull;
+    if (SYS) {
+      __hip_atomic_store(found[j], fj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      __hip_atomic_store(vals[j], vj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    } else {
+      __builtin_nontemporal_store(fj, found[j]);
+      __builtin_nontemporal_store(vj, vals[j]);
+    }
   }
 }
 

@@ -24,8 +24,11 @@
 //             (every insert is done), the deferred deletes.  A round with
 //             more updates than lanes, or more inserts than the set holds,
 //             runs inserts, a barrier, deletes
-//   end       each block makes its results visible to the host (system-
-//             scope release) before it arrives at the next boundary
+//   end       every result (lookup answers, insert statuses, delete
+//             results) was written through to memory with a system-scope
+//             store, and each wave waits for its stores before its block
+//             arrives at the next boundary, so the leader publishes a round
+//             complete only once the host can read all of its results
 //
 // On a table with timers (Sec. 4.2) every burst carries the server's time
 // at its submission, and a round takes only bursts of one time, so all of
@@ -216,14 +219,22 @@ __device__ __forceinline__ uint32_t poll_sys32(const uint32_t *p) {
 // atomic, all performed where the XCDs meet once waited for.  A release
 // store would write back this XCD's whole L2 cache at every arrival of
 // every block; measured on the serving workload, dropping those write-backs
-// (with one system-scope release per block per round, for the host) took
-// the update phase at 25% offered load from 49 to 35 us per round.  The
+// (with one system-scope release per block per round, for the host, at the
+// time) took the update phase at 25% offered load from 49 to 35 us per
+// round.  The results for the host now need no write-back either: they are
+// written through (put_result, reg_pass_to's SYS stores).  The
 // leader's release of `gen` stays: the round's ranges it publishes are
 // plain stores.
 __device__ __forceinline__ void block_arrive(const ServeArgs &a, uint32_t epoch) {
   __builtin_amdgcn_s_waitcnt(0);
   __hip_atomic_store(a.arrive + (uint64_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELAXED,
                      __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// A result for the host: written through to memory (a system-scope
+// store), visible once the writing wave has waited for its stores.
+__device__ __forceinline__ void put_result(uint8_t *p, uint8_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __device__ __forceinline__ void set_abort(ServeDev *d) {
@@ -425,7 +436,7 @@ __device__ void reg_lookups(const ServeArgs &a, const TableRef &T, uint32_t lane
       vo[j] = a.lk_vals + slot;
     }
     uint4 nk[PER];
-    reg_pass_to<MODE, TIMED, PER>(T, k, ok, fo, vo, [&] {
+    reg_pass_to<MODE, TIMED, PER, true>(T, k, ok, fo, vo, [&] {
 #pragma unroll
       for (uint32_t j = 0; j < PER; ++j) {
         const uint64_t n = i + step + 64u * j;
@@ -527,7 +538,7 @@ __device__ void insert_phase(const ServeArgs &a, uint64_t i0, uint64_t i1, uint3
     const InsertOutcome o =
         insert_one<TIMED>(a.bk, a.in_keys[slot], a.in_vals[slot], a.T.log2b, a.T.seed,
                           a.max_kicks, a.plain != 0u, path, a.spin_limit, expiry, now);
-    a.in_status[slot] = (uint8_t)o.status;
+    put_result(a.in_status + slot, (uint8_t)o.status);
     if (o.spun) atomicAdd(a.nspin, 1ull);
   }
 }
@@ -550,17 +561,20 @@ __device__ void delete_phase(const ServeArgs &a, uint64_t d0, uint64_t d1, bool 
   bool deferred = false;
   for (uint64_t o = column_rank(g, nlanes, true); d0 + o < d1; o += nlanes) {
     const uint64_t slot = (d0 + o) & a.mask;
-    if (deferred_only && a.de_found[slot] != kDeferred) continue;
+    if (deferred_only &&
+        __hip_atomic_load(a.de_found + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) !=
+            kDeferred)
+      continue;
     const uint4 k = a.de_keys[slot];
     if (filter && set_has(a, k, tag)) {
-      a.de_found[slot] = kDeferred;
+      put_result(a.de_found + slot, kDeferred);
       deferred = true;
       continue;
     }
     bool spun = false;
-    a.de_found[slot] =
-        (uint8_t)delete_one<TIMED>(a.bk, k, a.T.log2b, a.T.seed, a.plain != 0u, a.spin_limit,
-                                   &spun, now);
+    put_result(a.de_found + slot,
+               (uint8_t)delete_one<TIMED>(a.bk, k, a.T.log2b, a.T.seed, a.plain != 0u,
+                                          a.spin_limit, &spun, now));
     if (spun) atomicAdd(a.nspin, 1ull);
   }
   if (deferred)
@@ -613,13 +627,9 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
     // round boundary
     ++epoch;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      // every wave of the block has waited for its accesses (the end of
-      // the round below): one write-back of this XCD's L2 makes the round's
-      // results visible to the host and the copy engines
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-      block_arrive(a, epoch);
-    }
+    // every wave of the block has waited for its accesses (the end of the
+    // round below), the results' write-through stores among them
+    if (threadIdx.x == 0) block_arrive(a, epoch);
     if (blockIdx.x == 0) {
       if (threadIdx.x < 64u) {
         const bool ok = gather(a, epoch, kPhaseMs * kTicksPerMs);
