@@ -10,7 +10,9 @@
 //   boundary  every block arrives at a grid barrier; once all have arrived
 //             the leader publishes the previous round's completion, waits
 //             for submitted bursts (or exits after idle_ms without any),
-//             writes the round's op ranges and releases the barrier
+//             writes the round record (command, op range ends, time; every
+//             word tagged with the boundary's epoch), which releases the
+//             other blocks
 //   lookups   every wave runs passes of 128 lookups (64 in the pessimistic
 //             mode) over the round's lookup range (the lookup passes of the
 //             batch kernels, unchanged); then the round's insert keys go into
@@ -133,12 +135,17 @@ struct ServeDev {
   // apart from waiting for work; time waiting for work
   uint64_t t_lookup, t_insert, t_delete, t_boundary, t_wait;
   uint64_t t_mark;            // when the leader last released a barrier
-  uint32_t cmd;               // kCmdRun / kCmdExit / kCmdDeferred for the blocks
   uint32_t abort;             // a wait ran out of time
   uint32_t gen;               // barrier: last epoch the leader released
   uint32_t deferred;          // some delete of the round waits for its inserts
   uint32_t now;               // the round's time (tables with timers)
   uint32_t scan;              // the round starts with the anti-revival scan
+  // the round record the leader writes at each boundary for the other
+  // blocks: every word carries the boundary's epoch (mod 2^16) in bits
+  // 48..63; rec[0]: the command (bits 32..47), the scan flag (bit 16) and
+  // the time (bits 0..15); rec[1..3]: the low 48 bits of the round's lookup,
+  // insert and delete range ends
+  uint64_t rec[4];
 };
 
 // Barrier flags: block b stores the epoch it reached at arrive[b * kFlagStride]
@@ -295,6 +302,48 @@ __device__ bool gather(const ServeArgs &a, uint32_t epoch, uint64_t limit_ticks)
   }
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return true;
+}
+
+// Leader at a round boundary: writes the round record for `epoch` with
+// device-coherent stores (each word names its epoch, so a block takes it
+// only whole; nothing else the blocks read was written since the last
+// barrier, so no write-back of this XCD's L2 is needed), and `gen`, from
+// which the next launch numbers its epochs.
+__device__ __forceinline__ void publish_round(ServeDev *d, uint32_t epoch, uint32_t cmd,
+                                              uint32_t scan, uint32_t now) {
+  const uint64_t tag = (uint64_t)(epoch & 0xffffu) << 48;
+  auto put = [](uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  put(&d->rec[1], tag | (d->lk1 & kLow48));
+  put(&d->rec[2], tag | (d->in1 & kLow48));
+  put(&d->rec[3], tag | (d->de1 & kLow48));
+  put(&d->rec[0], tag | (uint64_t)cmd << 32 | (uint64_t)scan << 16 | (now & 0xffffu));
+  __hip_atomic_store(&d->gen, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Non-leader blocks, thread 0, at a round boundary: waits until every word
+// of the round record names `epoch` (r receives it).  Each poll reads the
+// record and `abort` in one round trip.  False on abort or time-out.
+__device__ bool wait_round(const ServeArgs &a, uint32_t epoch, uint64_t limit_ticks,
+                           uint64_t (&r)[4]) {
+  ServeDev *d = a.dev;
+  const uint64_t tag = epoch & 0xffffu;
+  const uint64_t t0 = now_ticks();
+  for (uint64_t it = 0;; ++it) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      r[k] = __hip_atomic_load(&d->rec[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t ab = poll32(&d->abort);
+    if (ab) return false;
+    if ((r[0] >> 48) == tag && (r[1] >> 48) == tag && (r[2] >> 48) == tag && (r[3] >> 48) == tag)
+      return true;
+    if (now_ticks() - t0 > limit_ticks || it > kMaxSpins) {
+      set_abort(d);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
 }
 
 // Leader: releases `epoch` to the waiting blocks.
@@ -612,10 +661,22 @@ __device__ bool phase_barrier(const ServeArgs &a, uint32_t epoch, uint32_t phase
 // its ranges).
 template <uint32_t MODE, bool TIMED>
 __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
+  // the round's ranges [l0, l1), [i0, i1), [d0, d1), time and scan flag;
+  // the other blocks keep the last round's ends here between rounds
   __shared__ uint64_t s_range[8];
   __shared__ uint32_t s_cmd, s_ok;
   const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
   ServeDev *d = a.dev;
+  if (threadIdx.x == 0) {
+    // the ends of the last launch's last round (the leader writes them only
+    // after every block has arrived at the first boundary)
+    auto get = [](const uint64_t *p) {
+      return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    s_range[0] = s_range[1] = get(&d->lk1);
+    s_range[2] = s_range[3] = get(&d->in1);
+    s_range[4] = s_range[5] = get(&d->de1);
+  }
   // epochs continue from the last launch's (nothing writes gen until every
   // block of this launch has arrived at its first barrier)
   uint32_t epoch = poll32(&d->gen);
@@ -647,48 +708,54 @@ __global__ void __launch_bounds__(kBlock) serve_loop(ServeArgs a) {
                                              __HIP_MEMORY_SCOPE_AGENT)) {
             // some deletes of the round wait for its inserts, which are all
             // done now: run them before the round is published complete
-            d->deferred = 0u;
+            // (a device-coherent store: blocks set the flag with atomics)
+            __hip_atomic_store(&d->deferred, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             cmd = kCmdDeferred;
           } else {
             cmd = ok ? leader_next_round(a, ran) : kCmdExit;
           }
-          d->cmd = cmd;
+          const uint32_t scan = TIMED && cmd == kCmdRun ? d->scan : 0u;
+          const uint32_t tnow = TIMED ? d->now : 0u;
           const uint64_t tr = now_ticks();
           d->t_boundary += (tr - tg) - (d->t_wait - w0);
           d->t_mark = tr;
-          release_epoch(d, epoch);
+          publish_round(d, epoch, cmd, scan, tnow);
           s_cmd = cmd;
+          // the leader's own ranges (its own writes)
+          s_range[0] = d->lk0;
+          s_range[1] = d->lk1;
+          s_range[2] = d->in0;
+          s_range[3] = d->in1;
+          s_range[4] = d->de0;
+          s_range[5] = d->de1;
+          s_range[6] = tnow;
+          s_range[7] = scan;
         }
       }
     } else if (threadIdx.x == 0) {
-      // released: the command itself is read below
-      s_cmd = wait_release(a, epoch, a.idle_ticks + kPhaseMs * kTicksPerMs) ? kCmdRun : kCmdExit;
+      uint64_t r[4];
+      s_cmd = wait_round(a, epoch, a.idle_ticks + kPhaseMs * kTicksPerMs, r)
+                  ? (uint32_t)(r[0] >> 32) & 0xffffu
+                  : kCmdExit;
+      if (s_cmd == kCmdRun) {
+        // full ends from their low 48 bits and the last round's ends (a
+        // round's operations of a kind are fewer than 2^48)
+        const uint64_t m = kLow48;
+        s_range[0] = s_range[1];
+        s_range[1] += (r[1] - s_range[1]) & m;
+        s_range[2] = s_range[3];
+        s_range[3] += (r[2] - s_range[3]) & m;
+        s_range[4] = s_range[5];
+        s_range[5] += (r[3] - s_range[5]) & m;
+      }
+      // a deferred round keeps the last round's ranges
+      s_range[6] = r[0] & 0xffffu;
+      s_range[7] = s_cmd == kCmdRun ? (r[0] >> 16) & 1u : 0u;
     }
     if (threadIdx.x == 0) {
-      // the command, the abort flag and the round's ranges and time, which
-      // the leader wrote before its release, in one round trip
-      // (device-coherent loads, issued after the release was seen)
-      const uint32_t cmd = __hip_atomic_load(&d->cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t ab = poll32(&d->abort);
-      auto get = [](const uint64_t *p) {
-        return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      };
-      const uint64_t r[6] = {get(&d->lk0), get(&d->lk1), get(&d->in0),
-                             get(&d->in1), get(&d->de0), get(&d->de1)};
-      const uint32_t tnow = TIMED ? poll32(&d->now) : 0u;
-      const uint32_t tscan = TIMED ? poll32(&d->scan) : 0u;
       // the round's ring entries were written by the host or a copy engine
       // while the kernel ran: drop any cached copy of them
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-      // (the leader's own block keeps the command it decided)
-      if (ab) s_cmd = kCmdExit;
-      else if (s_cmd != kCmdExit && blockIdx.x != 0u) s_cmd = cmd;
-      if (s_cmd == kCmdRun || s_cmd == kCmdDeferred) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) s_range[k] = r[k];
-        s_range[6] = tnow;
-        s_range[7] = s_cmd == kCmdRun ? tscan : 0u;
-      }
     }
     __syncthreads();
     if (s_cmd != kCmdRun && s_cmd != kCmdDeferred) break;
