@@ -346,9 +346,14 @@ __device__ bool wait_round(const ServeArgs &a, uint32_t epoch, uint64_t limit_ti
   }
 }
 
-// Leader: releases `epoch` to the waiting blocks.
+// Leader, at a barrier inside a round: releases `epoch` to the waiting
+// blocks.  What they read after it was written with device-coherent
+// accesses (table words, set entries) or written through (results), all
+// done before the blocks arrived, so the release is a relaxed store: a
+// release store would write back this XCD's L2 cache.
 __device__ __forceinline__ void release_epoch(ServeDev *d, uint32_t epoch) {
-  __hip_atomic_store(&d->gen, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  __builtin_amdgcn_s_waitcnt(0);
+  __hip_atomic_store(&d->gen, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // The burst that the last staged burst's tagged tails (w) name, if both
