@@ -229,9 +229,10 @@ __device__ __forceinline__ uint32_t poll_sys32(const uint32_t *p) {
 // (with one system-scope release per block per round, for the host, at the
 // time) took the update phase at 25% offered load from 49 to 35 us per
 // round.  The results for the host now need no write-back either: they are
-// written through (put_result, reg_pass_to's SYS stores).  The
-// leader's release of `gen` stays: the round's ranges it publishes are
-// plain stores.
+// written through (put_result, reg_pass_to's SYS stores).  The leader
+// writes back nothing either: at a round boundary it publishes a tagged
+// record with device-coherent stores (publish_round), and at a barrier
+// inside a round nothing it wrote is read (release_epoch).
 __device__ __forceinline__ void block_arrive(const ServeArgs &a, uint32_t epoch) {
   __builtin_amdgcn_s_waitcnt(0);
   __hip_atomic_store(a.arrive + (uint64_t)blockIdx.x * kFlagStride, epoch, __ATOMIC_RELAXED,
