@@ -103,12 +103,16 @@ constexpr uint32_t kScanUnroll = 16;
 constexpr uint32_t kScanBit = 16, kTimeIndexShift = 24;
 // latest[] of the last staged burst b, in one 16-byte block that the host
 // writes with one store and the loop reads with one load: latest[0] holds
-// the low 48 bits of b's lookup tail, latest[1] the low 24 bits of its
-// insert tail (bits 24..47) and of its delete tail (bits 0..23); bits 48..63
-// of both hold the tag kTagValid | (b mod 2^15).  The loop uses a block only
-// when both tags agree, and only on servers whose budget is under 2^24 ops
-// of a kind, so that a round's tails follow from these bits.
+// the low 24 bits of b's lookup tail (bits 24..47) and of its insert tail
+// (bits 0..23), latest[1] the low 24 bits of its delete tail (bits 24..47)
+// and those of f (bits 0..23), a burst no later than the first one of b's
+// time index (tables with timers; f = max(that burst, b - 8192), so that f
+// is older than every burst in flight when the index is older still); bits
+// 48..63 of both hold the tag kTagValid | (b mod 2^15).  The loop uses a
+// block only when both tags agree, and only on servers whose budget is
+// under 2^24 ops of a kind, so that a round's tails follow from these bits.
 constexpr uint64_t kLow48 = (1ull << 48) - 1u, kLow24 = (1ull << 24) - 1u;
+constexpr uint64_t kIndexFirstWindow = 2ull * kQueue;
 constexpr uint64_t kFastTailsBudget = 1ull << 24;
 constexpr uint32_t kTagValid = 0x8000u, kTagMask = 0x7fffu;
 struct ServeHost {
@@ -178,7 +182,7 @@ struct ServeArgs {
   uint32_t *set_tag;  // entry in use by the round whose tag it holds
   uint64_t set_mask;  // entries - 1
   uint32_t timed;     // the table has timers
-  uint32_t fast_tails;  // no timers and a budget under 2^24: tails come with the poll
+  uint32_t fast_tails;  // a budget under 2^24: tails come with the poll
   uint32_t ttl;       // entry lifetime in time units (timers)
   uint32_t refresh;   // lookups that find an entry set its expiration time
   uint64_t nb;        // buckets
@@ -393,9 +397,14 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
     if (a.fast_tails && s > d->done) {
       // submitted work is waiting: the round takes the bursts up to the
       // last staged one (the last submitted one or a later one whose
-      // operations are in the rings too), whose tails came with the poll
+      // operations are in the rings too), whose tails came with the poll;
+      // on a table with timers only while that burst's time index began
+      // before this round (then every burst of the round has the last
+      // round's time, and none starts a scan, which begins a new index)
       const uint64_t b = latest_burst(w, d->done);
-      if (b != ~0ull && b + 1u >= s) {
+      const uint64_t since = (d->done - w.y) & kLow24;  // done - f, mod 2^24
+      const bool same_time = !a.timed || (since >= 1u && since < (1ull << 23));
+      if (b != ~0ull && b + 1u >= s && same_time) {
         s = b + 1u;
         have_tails = true;
         break;
@@ -420,13 +429,15 @@ __device__ uint32_t leader_next_round(const ServeArgs &a, bool ran_round) {
   d->t_wait += now_ticks() - t0;
   if (have_tails) {
     // full tails from their low bits: a round's operations of a kind are
-    // in flight together, at most the budget, under 2^24
+    // in flight together, at most the budget, under 2^24 (a table with
+    // timers keeps the last round's time)
+    d->scan = 0u;
     d->lk0 = d->lk1;
     d->in0 = d->in1;
     d->de0 = d->de1;
-    d->lk1 += (w.x - d->lk1) & kLow48;
-    d->in1 += ((w.y >> 24) - d->in1) & kLow24;
-    d->de1 += (w.y - d->de1) & kLow24;
+    d->lk1 += ((w.x >> 24) - d->lk1) & kLow24;
+    d->in1 += (w.x - d->in1) & kLow24;
+    d->de1 += ((w.y >> 24) - d->de1) & kLow24;
     d->done = s;
     return kCmdRun;
   }
@@ -858,6 +869,7 @@ struct ckpp_server {
   uint16_t now;
   uint16_t last_scan;
   uint64_t time_index;
+  uint64_t index_first;  // the first burst staged at the current time index
   bool time_set;
 };
 
@@ -1031,7 +1043,7 @@ int ckpp_server_create(ckpp_server **out, ckpp_table *t, const ckpp_server_confi
   a.set_tag = s->set_tag;
   a.set_mask = set_entries - 1u;
   a.timed = timed ? 1u : 0u;
-  a.fast_tails = !timed && c.budget < ckpp::kFastTailsBudget ? 1u : 0u;
+  a.fast_tails = c.budget < ckpp::kFastTailsBudget ? 1u : 0u;
   a.ttl = timed ? ttl : 0u;
   a.refresh = timed && (c.ttl & CKPP_SERVER_REFRESH) ? 1u : 0u;
   a.nb = 1ull << t->log2_buckets;
@@ -1159,8 +1171,10 @@ int stage_burst(ckpp_server *s, uint64_t done, uint32_t n_lookup, uint32_t n_ins
   // takes a staged burst early only while submitted ones wait)
   if (s->args.fast_tails) {
     const uint64_t tag = (uint64_t)(ckpp::kTagValid | (uint32_t)(b & ckpp::kTagMask)) << 48;
-    const uint64_t w0 = tag | (nt[0] & ckpp::kLow48);
-    const uint64_t w1 = tag | (nt[1] & ckpp::kLow24) << 24 | (nt[2] & ckpp::kLow24);
+    const uint64_t win = b >= ckpp::kIndexFirstWindow ? b - ckpp::kIndexFirstWindow : 0u;
+    const uint64_t f = s->index_first > win ? s->index_first : win;
+    const uint64_t w0 = tag | (nt[0] & ckpp::kLow24) << 24 | (nt[1] & ckpp::kLow24);
+    const uint64_t w1 = tag | (nt[2] & ckpp::kLow24) << 24 | (f & ckpp::kLow24);
     // one aligned 16-byte store (single-copy atomic on x86-64 processors
     // with AVX; the tags catch a torn read anyway), after the stores above
     std::atomic_thread_fence(std::memory_order_release);
@@ -1206,12 +1220,15 @@ int ckpp_server_set_time(ckpp_server *s, uint16_t now) {
   const uint64_t old_index = s->time_index;
   s->now = now;
   s->time_index += 1;
+  const uint64_t old_first = s->index_first;
+  s->index_first = s->submitted;
   if (scan) {
     const uint64_t done = host_u64(&s->host->completed)->load(std::memory_order_acquire);
     const int rc = stage_burst(s, done, 0u, 0u, 0u, true);
     if (rc != CKPP_OK) {
       s->now = old_now;
       s->time_index = old_index;
+      s->index_first = old_first;
       return rc;
     }
     s->last_scan = now;
