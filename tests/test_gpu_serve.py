@@ -252,6 +252,35 @@ def test_server_many_small_bursts_past_the_tag_wrap():
     t.close()
 
 
+def test_server_budget_of_2_24_reads_the_tail_records():
+    """A server whose budget is 2^24 ops of a kind does not use the tagged
+    tails block (its low bits could not tell such a round's tails): the
+    leader reads each round's tails from the tail records.  Bursts alone and
+    back to back equal the oracle."""
+    from paper_1712_09624_amd.ckpp import Server
+    ref_a, t_a, keys = oracle_and_table(12, 0.8, 41)
+    ref_b, t_b, _ = oracle_and_table(12, 0.8, 41)
+    bursts = make_bursts(keys, 16, 42)
+    want = oracle_run(ref_a, bursts)
+    del ref_b
+    say("server with a 2^24 budget: 16 bursts one by one, then back to back")
+    with Server(t_a, capacity=1 << 24, budget=1 << 24, idle_ms=500) as srv:
+        for i, b in enumerate(bursts):
+            counts, first = put(srv, b)
+            bid = srv.submit(*counts)
+            srv.wait(bid, 10000)
+            check(fetch(srv, counts, first), want[i], f"alone burst {i}")
+    with Server(t_b, capacity=1 << 24, budget=1 << 24, idle_ms=500) as srv:
+        placed = [put(srv, b) for b in bursts]
+        ids = [srv.submit(*c) for c, _ in placed]
+        assert None not in ids
+        srv.wait(ids[-1], 10000)
+        for i, (c, f) in enumerate(placed):
+            check(fetch(srv, c, f), want[i], f"mixed burst {i}")
+    t_a.close()
+    t_b.close()
+
+
 def test_server_insert_and_delete_of_one_key_in_a_round():
     """A burst that inserts keys and deletes some of them: the deletes wait
     for the round's inserts (they are deferred past them), report found, and
