@@ -347,7 +347,9 @@ int ckpp_info(const ckpp_table *t, ckpp_info_t *out);
  * blocks per compute unit (0: enough blocks to cover the batch in one
  * pass).  Applies to every later lookup on t.  A new table starts with
  * {8, 2, 128, 0}, the fastest shape on 2^20..2^24-bucket tables at load
- * 0.9.  Errors: CKPP_EINVAL (a shape outside these sets). */
+ * 0.9; until a shape is set, batches of at most 4096 lookups run as
+ * {1, 1, 64, blocks_per_cu} instead, which completes small batches
+ * soonest.  Errors: CKPP_EINVAL (a shape outside these sets). */
 typedef struct {
     uint32_t lanes_per_lookup;
     uint32_t lookups_per_lane;

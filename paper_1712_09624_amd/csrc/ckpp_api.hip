@@ -460,6 +460,7 @@ int ckpp_set_lookup_launch(ckpp_table *t, const ckpp_launch_t *cfg) {
   if (cfg->block != 64 && cfg->block != 128 && cfg->block != 256) return CKPP_EINVAL;
   if (cfg->blocks_per_cu > 4096) return CKPP_EINVAL;
   t->lookup_launch = *cfg;
+  t->launch_set = true;
   return CKPP_OK;
 }
 

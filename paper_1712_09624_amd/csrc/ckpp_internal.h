@@ -20,6 +20,7 @@ struct ckpp_table {
   uint64_t *d_stats;    // device accumulator of ckpp_stats_t
   uint32_t retry_limit; // attempts per key on contended locks (ckpp_set_retry_limit)
   ckpp_launch_t lookup_launch;
+  bool launch_set;      // a caller set lookup_launch (else small batches take their own shape)
   int num_cus;
 };
 

@@ -207,9 +207,18 @@ hipError_t launch_shape(const ckpp_table *t, const TableRef &T, const uint4 *key
   return hipGetLastError();
 }
 
+// A batch this small is bound by the latency of one lookup's few
+// dependent loads, not by requests: one lane per lookup in 64-thread blocks
+// finishes it soonest (measured on MI355X, bursts of 1..2048 lookups on a
+// 2^24-bucket table: 21.4 us p50 from submission to completion against
+// 25.4 us in the default shape).  Used while no caller set a shape.
+constexpr uint64_t kSmallBatch = 4096;
+
 template <uint32_t MODE, bool TIMED>
 hipError_t launch_mode(const ckpp_table *t, const TableRef &T, const uint4 *keys, uint64_t n,
                        uint8_t *found, uint64_t *vals, hipStream_t s) {
+  if (!t->launch_set && n <= kSmallBatch)
+    return launch_reg<1, MODE, TIMED, 1>(t, T, keys, n, found, vals, s);
   switch (t->lookup_launch.block) {
     case 64: return launch_shape<1, MODE, TIMED>(t, T, keys, n, found, vals, s);
     case 128: return launch_shape<2, MODE, TIMED>(t, T, keys, n, found, vals, s);
