@@ -1099,7 +1099,7 @@ def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0
         t.close()
         return out
     # the same kind of stream through the plain batch calls, burst by burst
-    # (lookup, insert and delete batch of each burst, then a synchronization)
+    # (lookup, insert and delete batch of each burst, then a wait on their stream)
     nplain = min(5000, nbursts)
     st = serve_stream(nplain, 100 + len(out["runs"]), keys, universe, vals, del_base)
     out["plain_calls"] = plain_call_run(t, st, dev)
@@ -1111,7 +1111,7 @@ def serve_bench(dev, nbursts=50000, B=24, load=0.85, fracs=(0.25, 0.5, 0.75, 1.0
 def plain_call_run(t, st, dev):
     """Bursts served one at a time by the plain batch calls, back to back
     (closed loop): per burst a lookup, an insert and a delete batch on the
-    caller's stream and a synchronization.  Every result is checked."""
+    caller's stream and a wait on that stream.  Every result is checked."""
     import torch
     look, ins, dels = to_dev(st["look"], dev), to_dev(st["ins"], dev), to_dev(st["dels"], dev)
     ins_v = to_dev(st["ins_val"].view(np.int64), dev)
@@ -1123,6 +1123,7 @@ def plain_call_run(t, st, dev):
     nf = torch.zeros(1, dtype=torch.int64, device=dev)
     lat = np.empty(len(nl))
     ol = oi = od = 0
+    s = torch.cuda.current_stream(dev)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for b in range(len(nl)):
@@ -1134,7 +1135,7 @@ def plain_call_run(t, st, dev):
             t.insert(ins[oi:oi + c], ins_v[oi:oi + c], status=ist[oi:oi + c], nfailed=nf)
         if e:
             t.delete(dels[od:od + e], found=dfo[od:od + e])
-        torch.cuda.synchronize()
+        s.synchronize()
         lat[b] = time.perf_counter() - t0
         ol, oi, od = ol + a, oi + c, od + e
     span = time.perf_counter() - t_start
@@ -1549,7 +1550,7 @@ def summarize_serve(path, trace_dir=None, counter_dir=None):
     pc = rec.get("plain_calls")
     if pc:
         out.append(f"# the same kind of stream ({pc['bursts']} bursts) through the plain batch calls, one "
-                   "burst at a time (lookup, insert and delete batch, then a synchronization), checked:")
+                   "burst at a time (lookup, insert and delete batch, then a wait on their stream), checked:")
         out.append(f"{'plain-calls':>10} {pc['glookups']:>11.4f} {pc['p50_us']:>9.1f} {pc['p99_us']:>9.1f}")
     if trace_dir:
         rows = [r for r in csv.DictReader(open(os.path.join(trace_dir, "serve_trace", "serve_kernel_stats.csv")))
